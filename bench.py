@@ -1,0 +1,222 @@
+"""KmerCo on one MI355X: k-mer insertions/s of the full hot path.
+
+One step = one KmerCo pass over the workload with its reads already resident
+in HBM: clear the countBF, insertion phase (ingest, first-seen claims +
+saturating increments, resolve, ordered distinct output) and classification
+phase (Query-II per distinct k-mer, ordered trustworthy / erroneous split).
+The metric counts one insertion per valid k-mer window, as the paper's
+insertions-per-second figure does (number of insertions / insertion time).
+
+Prints one JSON line.  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bacterial]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bacterial", choices=["tiny", "bacterial"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
+    ap.add_argument("--no-verify", action="store_true")
+    return ap.parse_args()
+
+
+def sha(t) -> str:
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(t.cpu().numpy().view(np.uint64)).tobytes()).hexdigest()
+
+
+def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int) -> float:
+    """Bytes a launch of `phase` must move by its definition (logical
+    accesses, not cache lines): see the per-kernel table in the design notes."""
+    if phase == "claim_increment":   # cell RMW + first-seen entry RMW per slot, packed input
+        return n_windows * k_h * (16 + 8) + n_bases * 0.5
+    if phase == "claim":             # cell read + entry RMW per slot
+        return n_windows * k_h * (8 + 8) + n_bases * 0.5
+    if phase == "increment":         # cell RMW per slot
+        return n_windows * k_h * 16 + n_bases * 0.5
+    if phase == "resolve":           # entry read per slot, winner reset, flags
+        return n_windows * k_h * 4 + n_distinct * 4 + n_bases * (0.5 + 0.125)
+    if phase == "ingest":            # ASCII in, packed codes + bitmaps out
+        return n_bases * 1.5
+    if phase == "scatter":           # flags + packed input, keys out
+        return n_bases * (0.5 + 0.125) + n_distinct * 8
+    if phase == "classify_mark":     # key + cell per slot, mask out
+        return n_distinct * (8 + 8 * k_h + 0.125)
+    if phase == "classify_scatter":  # key in, key out, mask
+        return n_distinct * (16 + 0.125)
+    return 0.0
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if one
+    exists for this kernel and workload and the kernel sources have not
+    changed since; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2305_07545_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(rs, X, Y, n_sample_reads):
+    """The oracle, as it is, on the first reads of the same workload with the
+    same countBF dimensions, on one host core."""
+    import oracle
+    oracle.build(force=False)
+    n = min(n_sample_reads, rs.n_reads)
+    sub = rs.subset(0, n)
+    t = time.perf_counter()
+    _, _, _, _, nw = oracle.run_kmerco(sub.reads, sub.offsets, rs.k, rs.tau, X, Y)
+    secs = time.perf_counter() - t
+    return {"value": nw / secs, "unit": "insertions/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {rs.n_reads} reads ({nw} k-mers), insert + classify, "
+                      f"countBF {X}x{Y}, single-threaded C oracle, {secs:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "--gpus must be 1 (no multi-GPU path is built)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2305_07545_amd as P
+    import synth
+
+    P.load_library()  # fails loudly when the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    rs = synth.config(args.workload)
+    X, Y = P.dims(rs.n_items)
+    k_h, alpha = 1, 8
+    reads = torch.from_numpy(rs.reads).to(dev)
+    offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
+    n_bases = rs.n_bases
+    cap = n_bases
+    distinct = torch.empty(cap, dtype=torch.int64, device=dev)
+    trust = torch.empty(cap, dtype=torch.int64, device=dev)
+    err = torch.empty(cap, dtype=torch.int64, device=dev)
+    counters = torch.zeros(4, dtype=torch.int64, device=dev)  # distinct, windows, trust, err
+    nd, nw, nt, ne = (counters[i:i + 1] for i in range(4))
+    bf = P.CountBF(X, Y, alpha, k_h, device=dev)
+    bf.reserve(n_bases)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        bf.reset(stream)
+        counters.zero_()
+        bf.insert(reads, offs, rs.k, distinct=distinct, n_distinct=nd, n_windows=nw,
+                  stream=stream)
+        bf.classify(distinct, nd, rs.tau, trust=trust, err=err, n_trust=nt, n_err=ne,
+                    keys_cap=cap, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    bf.sync()
+    torch.cuda.synchronize()
+
+    bf.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = bf.profile_read()
+    bf.profile(False)
+    bf.sync()
+
+    n_distinct, n_windows, n_trust, n_err = (int(x) for x in counters.cpu().tolist())
+    verified = None
+    if not args.no_verify:
+        ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_digests.json")
+        if os.path.exists(ref_path):
+            ref = json.load(open(ref_path))
+            verified = (ref["X"] == X and ref["Y"] == Y and ref["n_windows"] == n_windows
+                        and ref["n_distinct"] == n_distinct and ref["n_trust"] == n_trust
+                        and sha(bf.words) == ref["words_sha256"]
+                        and sha(distinct[:n_distinct]) == ref["distinct_sha256"]
+                        and sha(trust[:n_trust]) == ref["trust_sha256"]
+                        and sha(err[:n_err]) == ref["err_sha256"])
+
+    ms_step = elapsed * 1e3 / args.steps
+    value = n_windows * args.steps / elapsed
+    per_phase = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()}
+    dom = max(phases, key=lambda k: phases[k][0]) if phases else None
+    roofline = None
+    if dom:
+        avg_s = phases[dom][0] / phases[dom][1] / 1e3
+        nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h)
+        achieved = nbytes / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic_for(dom, args.workload), "kernel": dom,
+                    "algorithmic_bytes_per_launch": nbytes,
+                    "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+    out = {
+        "metric": "k-mer insertions/s",
+        "value": value,
+        "unit": "insertions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_reads": rs.n_reads, "n_bases": n_bases,
+                   "k": rs.k, "tau": rs.tau, "X": X, "Y": Y, "alpha": alpha, "k_h": k_h,
+                   "countbf_bytes": X * Y * 8, "n_windows": n_windows,
+                   "n_distinct": n_distinct, "n_trust": n_trust, "n_err": n_err,
+                   "parallelism": "single GPU"},
+        "verified_vs_oracle_digests": verified,
+        "phases": per_phase,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(rs, X, Y, args.cpu_sample_reads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

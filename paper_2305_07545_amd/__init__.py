@@ -1,0 +1,16 @@
+"""MI355X (gfx950) KmerCo: countBF insertion and threshold classification.
+
+The compute lives in ``libkmerco_hip.so`` (hand-written HIP kernels behind the
+C ABI of ``include/kmerco.h``); this package is its Python binding.
+"""
+from .kmerco import (  # noqa: F401
+    CountBF,
+    KmercoError,
+    LIB_PATH,
+    SIGNATURES,
+    dims,
+    eta,
+    load_library,
+    run_kmerco,
+    strerror,
+)

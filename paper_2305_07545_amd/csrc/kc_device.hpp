@@ -1,0 +1,212 @@
+// Device-side building blocks of the gfx950 KmerCo kernels.
+//
+// Packed read layout produced by the ingest kernel (one per insert call):
+//   codes[m]  uint32, bases 16m .. 16m+15 as 2-bit codes, base 16m in bits
+//             31..30 (A=0 C=1 G=2 T=3; invalid bases stored as 0)
+//   inv[b]    uint32, bit q%32 of word q/32 set when base q is not A/C/G/T;
+//             positions past the end of the reads are set (invalid)
+//   rs[b]     uint32, bit set at every read start offset
+// A window of K bases starting at p is valid iff bases p..p+K-1 are valid
+// and no read starts at p+1..p+K-1 (Algorithm 1 visits windows inside one
+// read; windows holding a non-ACGT byte are skipped).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+constexpr uint32_t kIdle = 0xFFFFFFFFu;  // first-seen scratch entry with no claimant
+
+// Filter parameters handed to every kernel by value.
+struct FilterArgs {
+    uint64_t *words;      // X*Y cells
+    uint32_t *aux;        // X*Y*eta first-seen entries (kIdle when unused)
+    uint64_t X, Y;
+    uint64_t mX, mY;      // floor((2^64-1)/X), floor((2^64-1)/Y)
+    uint64_t mEta;        // floor((2^64-1)/eta)
+    uint32_t eta;
+    uint32_t alpha;
+    uint32_t k_h;
+    uint32_t eta_pow2;    // eta is a power of two (then l = h & (eta-1))
+    uint64_t field_max;   // 2^alpha - 1
+};
+
+// Packed reads of one insert call.
+struct ReadsArgs {
+    const uint32_t *codes;
+    const uint32_t *inv;
+    const uint32_t *rs;
+    uint64_t n_bases;
+    uint32_t k;
+};
+
+// ----------------------------------------------------------------------------
+// MurmurHash3_x86_32 of an 8-byte little-endian key, split so that the two
+// block mixes (which do not depend on the seed) are shared between seeds.
+// ----------------------------------------------------------------------------
+// The arithmetic helpers below are __host__ __device__ so that host-side
+// tests can check them on the CPU; only two primitives differ by side.
+#define KC_HD __host__ __device__ __forceinline__
+
+KC_HD uint32_t rotl32(uint32_t x, uint32_t r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(x, x, 32u - r);
+#else
+    return (x << r) | (x >> (32u - r));
+#endif
+}
+
+KC_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+KC_HD uint32_t mm3_block(uint32_t k) {
+    k *= 0xcc9e2d51u;
+    k = rotl32(k, 15);
+    return k * 0x1b873593u;
+}
+
+KC_HD uint32_t mm3_seeded(uint32_t b0, uint32_t b1, uint32_t seed) {
+    uint32_t h = seed ^ b0;
+    h = rotl32(h, 13) * 5u + 0xe6546b64u;
+    h ^= b1;
+    h = rotl32(h, 13) * 5u + 0xe6546b64u;
+    h ^= 8u;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// H_a(key) for a = 1..8: seeds 2a-2 (high word) and 2a-1 (low word).
+KC_HD uint64_t hash_a(uint32_t b0, uint32_t b1, uint32_t a) {
+    uint32_t hi = mm3_seeded(b0, b1, 2u * a - 2u);
+    uint32_t lo = mm3_seeded(b0, b1, 2u * a - 1u);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+KC_HD void key_blocks(uint64_t key, uint32_t &b0, uint32_t &b1) {
+    b0 = mm3_block((uint32_t)key);
+    b1 = mm3_block((uint32_t)(key >> 32));
+}
+
+// ----------------------------------------------------------------------------
+// Exact h mod d with a precomputed reciprocal m = floor((2^64-1)/d):
+// q = floor(h*m / 2^64) is floor(h/d) or one less, so one correction step
+// gives the exact remainder for every 64-bit h and every d >= 1.
+// ----------------------------------------------------------------------------
+KC_HD uint64_t mod_by(uint64_t h, uint64_t d, uint64_t m) {
+    uint64_t q = mulhi64(h, m);
+    uint64_t r = h - q * d;
+    return r >= d ? r - d : r;
+}
+
+// Counter index (word * eta + l) of hash value h.
+KC_HD void slot_of(const FilterArgs &F, uint64_t h, uint64_t &word,
+                                        uint32_t &l) {
+    uint64_t i = mod_by(h, F.X, F.mX);
+    uint64_t j = mod_by(h, F.Y, F.mY);
+    l = F.eta_pow2 ? (uint32_t)(h & (uint64_t)(F.eta - 1)) : (uint32_t)mod_by(h, F.eta, F.mEta);
+    word = i * F.Y + j;
+}
+
+// ----------------------------------------------------------------------------
+// Base codes: A=0x41 C=0x43 G=0x47 T=0x54 -> 0 1 2 3; any other byte invalid
+// ----------------------------------------------------------------------------
+KC_HD uint32_t base_code(uint32_t b) { return ((b >> 1) ^ (b >> 2)) & 3u; }
+
+KC_HD bool base_valid(uint32_t b, uint32_t code) {
+    return b == ((0x54474341u >> (8u * code)) & 0xFFu);
+}
+
+// ----------------------------------------------------------------------------
+// Window extraction from the packed layout
+// ----------------------------------------------------------------------------
+
+// 2-bit reverse complement of a K-base key (K <= 32): complement every code
+// (x ^ 3 == ~x on 2 bits), reverse the order of the 32 2-bit groups, drop the
+// 32-K groups that came from the unused high end.
+KC_HD uint64_t revcomp_key(uint64_t x, uint32_t K) {
+    x = ~x;
+    x = ((x >> 2) & 0x3333333333333333ull) | ((x & 0x3333333333333333ull) << 2);
+    x = ((x >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((x & 0x0F0F0F0F0F0F0F0Full) << 4);
+    x = __builtin_bswap64(x);
+    return x >> (64u - 2u * K);
+}
+
+// Forward key of the K-base window starting at p (first base most
+// significant).  Needs codes[p/16 + 2] to exist.
+KC_HD uint64_t window_key(const uint32_t *__restrict__ codes, uint64_t p,
+                                               uint32_t K) {
+    uint64_t m = p >> 4;
+    uint32_t s = 2u * (uint32_t)(p & 15u);
+    uint64_t hi = ((uint64_t)codes[m] << 32) | codes[m + 1];
+    uint64_t top = s ? ((hi << s) | ((uint64_t)codes[m + 2] >> (32u - s))) : hi;
+    return top >> (64u - 2u * K);
+}
+
+// Window validity (see the layout note above).  Needs inv/rs[p/32 + 1].
+KC_HD bool window_valid(const ReadsArgs &R, uint64_t p) {
+    if (p + R.k > R.n_bases)
+        return false;
+    uint64_t b = p >> 5;
+    uint32_t o = (uint32_t)(p & 31u);
+    uint64_t kmask = (R.k >= 64u) ? ~0ull : ((1ull << R.k) - 1ull);
+    uint64_t iv = ((((uint64_t)R.inv[b + 1]) << 32) | R.inv[b]) >> o;
+    uint64_t st = ((((uint64_t)R.rs[b + 1]) << 32) | R.rs[b]) >> o;
+    return ((iv & kmask) | (st & kmask & ~1ull)) == 0;
+}
+
+// Canonical key and its H_1 value (Sec. 2.3: the strand with the smaller
+// hash; a tie keeps the reverse complement), plus the key's MM3 blocks for
+// the remaining hash functions.
+struct Canon {
+    uint64_t key;
+    uint64_t h1;
+    uint32_t b0, b1;
+};
+
+KC_HD Canon canonical(uint64_t fwd, uint32_t K) {
+    uint64_t rc = revcomp_key(fwd, K);
+    uint32_t f0, f1, r0, r1;
+    key_blocks(fwd, f0, f1);
+    key_blocks(rc, r0, r1);
+    uint64_t hf = hash_a(f0, f1, 1);
+    uint64_t hr = hash_a(r0, r1, 1);
+    Canon c;
+    if (hf < hr) {
+        c.key = fwd; c.h1 = hf; c.b0 = f0; c.b1 = f1;
+    } else {
+        c.key = rc; c.h1 = hr; c.b0 = r0; c.b1 = r1;
+    }
+    return c;
+}
+
+// Saturating increment of counter l of a cell (64-bit CAS loop).  Returns
+// nothing; a saturated counter is left unchanged.
+__device__ __forceinline__ void saturating_increment(uint64_t *cell, uint32_t shift,
+                                                     uint64_t field_max) {
+    const uint64_t fmask = field_max << shift;
+    const uint64_t inc = 1ull << shift;
+    uint64_t old = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((old & fmask) != fmask) {
+        uint64_t assumed = old;
+        old = atomicCAS((unsigned long long *)cell, (unsigned long long)assumed,
+                        (unsigned long long)(assumed + inc));
+        if (old == assumed)
+            break;
+    }
+}
+
+__device__ __forceinline__ uint64_t read_counter(const FilterArgs &F, uint64_t word, uint32_t l) {
+    return (F.words[word] >> (F.alpha * l)) & F.field_max;
+}
+
+}  // namespace kc

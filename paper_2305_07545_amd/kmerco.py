@@ -1,0 +1,256 @@
+"""ctypes binding of the gfx950 KmerCo library (``include/kmerco.h``).
+
+Argument marshalling only: torch tensors supply device memory and streams;
+every step of the insertion and classification phases runs in the library's
+HIP kernels.  The library must be built (``paper_2305_07545_amd.build``); there
+is no fallback path.
+
+64-bit keys, words and offsets travel as ``torch.int64`` tensors holding the
+unsigned bit patterns.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmerco_hip.so")
+
+KC_OK, KC_EINVAL, KC_ENOMEM, KC_ERANGE, KC_EDEVICE, KC_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class KmercoError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class kc_layout(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_uint64), ("Y", ctypes.c_uint64),
+                ("alpha", ctypes.c_uint32), ("k_h", ctypes.c_uint32)]
+
+
+_lib = None
+
+# every symbol include/kmerco.h declares, with (restype, argtypes)
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_i = ctypes.c_int
+SIGNATURES = {
+    "kc_strerror": (ctypes.c_char_p, [_i]),
+    "kc_version": (_i, []),
+    "kc_dims": (_i, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "kc_eta": (_u32, [_u32]),
+    "kc_create": (_i, [ctypes.POINTER(kc_layout), _vp, _i, _vp, ctypes.POINTER(_vp)]),
+    "kc_destroy": (None, [_vp]),
+    "kc_reserve": (_i, [_vp, _u64]),
+    "kc_insert": (_i, [_vp, _vp, _vp, _u64, _u64, _u32, _vp, _u64, _vp, _vp, _vp]),
+    "kc_classify": (_i, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "kc_query": (_i, [_vp, _vp, _u64, _vp, _vp]),
+    "kc_sync": (_i, [_vp]),
+    "kc_get_layout": (_i, [_vp, ctypes.POINTER(kc_layout)]),
+    "kc_reset": (_i, [_vp, _vp]),
+    "kc_profile": (_i, [_vp, _i]),
+    "kc_profile_read": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64), _u32]),
+    "kc_phase_name": (ctypes.c_char_p, [_u32]),
+}
+
+PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
+          "classify_mark", "classify_scatter", "query", "reset"]
+
+
+def load_library():
+    """Load the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"KmerCo HIP library not built ({LIB_PATH}); "
+                               "run paper_2305_07545_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return load_library().kc_strerror(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != KC_OK:
+        raise KmercoError(status, what)
+
+
+def dims(n_items: float, fpp: float = 0.001):
+    """Eq. (1) countBF dimensions (X, Y)."""
+    X = ctypes.c_uint64(0)
+    Y = ctypes.c_uint64(0)
+    _check(load_library().kc_dims(float(n_items), float(fpp), ctypes.byref(X), ctypes.byref(Y)),
+           "kc_dims")
+    return int(X.value), int(Y.value)
+
+
+def eta(alpha: int) -> int:
+    return int(load_library().kc_eta(alpha))
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class CountBF:
+    """A countBF resident in device memory, driven by the HIP library.
+
+    ``words`` (int64[X*Y]) is allocated here unless given; with ``zero=True``
+    the library clears it and the filter starts empty."""
+
+    def __init__(self, X: int, Y: int, alpha: int = 8, k_h: int = 1, words=None,
+                 zero: bool = True, device=None, stream=None):
+        self.lib = load_library()
+        self.layout = kc_layout(X, Y, alpha, k_h)
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        if words is None:
+            words = torch.empty(X * Y, dtype=torch.int64, device=dev)
+        _require(words, torch.int64, "words")
+        if words.numel() != X * Y:
+            raise ValueError("words must hold X*Y cells")
+        self.words = words
+        self.device = words.device
+        h = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_create(ctypes.byref(self.layout), _ptr(words), int(zero),
+                                      _stream_ptr(stream), ctypes.byref(h)), "kc_create")
+        self._h = h
+        self.n_distinct = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.n_windows = torch.zeros(1, dtype=torch.int64, device=self.device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.kc_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def reserve(self, max_bases: int):
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_reserve(self._h, int(max_bases)), "kc_reserve")
+
+    def insert(self, reads, offsets, k: int, distinct=None, distinct_cap=None,
+               n_distinct=None, n_windows=None, stream=None):
+        """Insertion phase over one read batch (async).  Appends this call's
+        distinct keys to ``distinct`` at ``n_distinct`` (device counters)."""
+        _require(reads, torch.uint8, "reads")
+        _require(offsets, torch.int64, "offsets")
+        n_reads = offsets.numel() - 1
+        n_bases = reads.numel()
+        if n_reads < 0:
+            raise ValueError("offsets needs n_reads + 1 entries")
+        if distinct is None:
+            distinct = torch.empty(max(1, n_bases), dtype=torch.int64, device=self.device)
+        _require(distinct, torch.int64, "distinct")
+        cap = distinct.numel() if distinct_cap is None else int(distinct_cap)
+        n_distinct = self.n_distinct if n_distinct is None else n_distinct
+        n_windows = self.n_windows if n_windows is None else n_windows
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_insert(self._h, _ptr(reads), _ptr(offsets), n_reads, n_bases, k,
+                                      _ptr(distinct), cap, _ptr(n_distinct), _ptr(n_windows),
+                                      _stream_ptr(stream)), "kc_insert")
+        return distinct
+
+    def classify(self, keys, n_keys, tau: int, trust=None, err=None, n_trust=None, n_err=None,
+                 keys_cap=None, stream=None):
+        """Classification phase (async); returns (trust, n_trust, err, n_err)
+        device tensors."""
+        _require(keys, torch.int64, "keys")
+        cap = keys.numel() if keys_cap is None else int(keys_cap)
+        if trust is None:
+            trust = torch.empty(max(1, cap), dtype=torch.int64, device=self.device)
+        if err is None:
+            err = torch.empty(max(1, cap), dtype=torch.int64, device=self.device)
+        if n_trust is None:
+            n_trust = torch.zeros(1, dtype=torch.int64, device=self.device)
+        if n_err is None:
+            n_err = torch.zeros(1, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_classify(self._h, _ptr(keys), _ptr(n_keys), cap, int(tau),
+                                        _ptr(trust), _ptr(n_trust), _ptr(err), _ptr(n_err),
+                                        _stream_ptr(stream)), "kc_classify")
+        return trust, n_trust, err, n_err
+
+    def query(self, keys, freq=None, stream=None):
+        _require(keys, torch.int64, "keys")
+        if freq is None:
+            freq = torch.empty(max(1, keys.numel()), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_query(self._h, _ptr(keys), keys.numel(), _ptr(freq),
+                                     _stream_ptr(stream)), "kc_query")
+        return freq[:keys.numel()]
+
+    def reset(self, stream=None):
+        """Clear the countBF (async): empty filter, k unset."""
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_reset(self._h, _stream_ptr(stream)), "kc_reset")
+
+    def profile(self, enable: bool = True):
+        _check(self.lib.kc_profile(self._h, int(enable)), "kc_profile")
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} of the kernels recorded since the
+        last read (waits for them)."""
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_uint64 * n)()
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_profile_read(self._h, ms, cnt, n), "kc_profile_read")
+        return {PHASES[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
+
+    def sync(self):
+        """Wait for the filter's work; raises on a sticky device error."""
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_sync(self._h), "kc_sync")
+
+
+def run_kmerco(reads, offsets, k: int, tau: int, X: int, Y: int, alpha: int = 8, k_h: int = 1,
+               stream=None):
+    """Both phases on a fresh countBF.  Returns host numpy arrays
+    (words, distinct, trust, err, n_windows) as uint64."""
+    bf = CountBF(X, Y, alpha, k_h, stream=stream)
+    distinct = bf.insert(reads, offsets, k, stream=stream)
+    trust, n_trust, err, n_err = bf.classify(distinct, bf.n_distinct, tau, stream=stream)
+    bf.sync()
+    nd = int(bf.n_distinct.item())
+    nt = int(n_trust.item())
+    ne = int(n_err.item())
+    u = lambda t: t.cpu().numpy().view("uint64")  # noqa: E731
+    out = (u(bf.words), u(distinct[:nd]), u(trust[:nt]), u(err[:ne]), int(bf.n_windows.item()))
+    bf.close()
+    return out

@@ -1,0 +1,52 @@
+// Host build of the GPU path's arithmetic helpers, for CPU tests (no kernel
+// is launched).  Exposes them through a small C interface for ctypes.
+#include <stdint.h>
+
+#include "kc_device.hpp"
+
+extern "C" {
+
+uint64_t kch_mod_by(uint64_t h, uint64_t d) { return kc::mod_by(h, d, UINT64_MAX / d); }
+
+uint64_t kch_revcomp(uint64_t x, uint32_t K) { return kc::revcomp_key(x, K); }
+
+uint64_t kch_window_key(const uint32_t *codes, uint64_t p, uint32_t K) {
+    return kc::window_key(codes, p, K);
+}
+
+int kch_window_valid(const uint32_t *codes, const uint32_t *inv, const uint32_t *rs,
+                     uint64_t n_bases, uint32_t k, uint64_t p) {
+    kc::ReadsArgs R{codes, inv, rs, n_bases, k};
+    return kc::window_valid(R, p) ? 1 : 0;
+}
+
+uint64_t kch_hash(uint64_t key, uint32_t a) {
+    uint32_t b0, b1;
+    kc::key_blocks(key, b0, b1);
+    return kc::hash_a(b0, b1, a);
+}
+
+uint64_t kch_canonical(uint64_t fwd, uint32_t K, uint64_t *h1) {
+    kc::Canon c = kc::canonical(fwd, K);
+    *h1 = c.h1;
+    return c.key;
+}
+
+void kch_slot(uint64_t X, uint64_t Y, uint32_t alpha, uint64_t h, uint64_t *word, uint32_t *l) {
+    kc::FilterArgs F{};
+    F.X = X;
+    F.Y = Y;
+    F.mX = UINT64_MAX / X;
+    F.mY = UINT64_MAX / Y;
+    F.alpha = alpha;
+    F.eta = 64u / alpha;
+    F.mEta = UINT64_MAX / F.eta;
+    F.eta_pow2 = (F.eta & (F.eta - 1)) == 0;
+    kc::slot_of(F, h, *word, *l);
+}
+
+int kch_base(uint32_t b, uint32_t *code) {
+    *code = kc::base_code(b);
+    return kc::base_valid(b, *code) ? 1 : 0;
+}
+}

@@ -1,0 +1,50 @@
+"""Write SHA-256 digests of the oracle's outputs on the full-size workloads.
+
+Calls only ``oracle`` and ``synth``; the GPU parity tests compare the HIP
+path's outputs against these stored digests.  Usage:
+
+    python tests/golden/make_digests.py tiny bacterial
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+
+def sha(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
+
+
+def digests(name: str, scale: float = 1.0) -> dict:
+    rs = synth.config(name, scale)
+    X, Y = oracle.dims(rs.n_items, 0.001)
+    t = time.time()
+    words, distinct, trust, err, nw = oracle.run_kmerco(rs.reads, rs.offsets, rs.k, rs.tau, X, Y)
+    secs = time.time() - t
+    return {
+        "workload": name, "scale": scale, "k": rs.k, "tau": rs.tau, "X": X, "Y": Y,
+        "alpha": 8, "k_h": 1, "n_reads": rs.n_reads, "n_bases": rs.n_bases,
+        "n_windows": nw, "n_distinct": len(distinct), "n_trust": len(trust), "n_err": len(err),
+        "words_sha256": sha(words), "distinct_sha256": sha(distinct),
+        "trust_sha256": sha(trust), "err_sha256": sha(err),
+        "oracle_seconds": round(secs, 2),
+    }
+
+
+if __name__ == "__main__":
+    oracle.build(force=False)
+    for name in sys.argv[1:] or ["tiny", "bacterial"]:
+        d = digests(name)
+        path = os.path.join(HERE, f"{name}_digests.json")
+        with open(path, "w") as f:
+            json.dump(d, f, indent=1)
+        print(path, d)

@@ -1,0 +1,71 @@
+"""The C ABI library loads on the CPU and exports every symbol the header
+declares; host-only entry points behave as documented (no GPU calls)."""
+import ctypes
+import re
+import os
+
+import pytest
+
+import paper_2305_07545_amd as P
+from paper_2305_07545_amd import kmerco
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kmerco.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    assert "kc_insert" in names and "kc_classify" in names and "kc_create" in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(kmerco.SIGNATURES)
+
+
+def test_dims_matches_oracle(oracle_lib):
+    for n in [1, 10, 1000, 5.5e5, 6.1e7, 20484059 / 2, 163872472 / 2, 8.9e9]:
+        assert P.dims(n) == oracle_lib.dims(n)
+
+
+def test_dims_errors():
+    for bad in [(0, 0.001), (10, 0.0), (10, 1.0), (-1, 0.5)]:
+        with pytest.raises(P.KmercoError):
+            P.dims(*bad)
+
+
+def test_eta_and_strings():
+    assert [P.eta(a) for a in (1, 5, 8, 16, 32, 64, 0, 65)] == [64, 12, 8, 4, 2, 1, 0, 0]
+    assert P.strerror(0) == "ok"
+    assert "capacity" in P.strerror(-3)
+    assert P.load_library().kc_version() >= 1
+
+
+def test_create_rejects_bad_layouts_without_touching_the_device():
+    lib = P.load_library()
+    h = ctypes.c_void_p(None)
+    bad = [(0, 5, 8, 1), (5, 0, 8, 1), (5, 7, 0, 1), (5, 7, 33, 1), (5, 7, 8, 0), (5, 7, 8, 9)]
+    for X, Y, a, kh in bad:
+        L = kmerco.kc_layout(X, Y, a, kh)
+        st = lib.kc_create(ctypes.byref(L), ctypes.c_void_p(0x1000), 1, None, ctypes.byref(h))
+        assert st == kmerco.KC_EINVAL
+    L = kmerco.kc_layout(5, 7, 8, 1)
+    assert lib.kc_create(ctypes.byref(L), None, 1, None, ctypes.byref(h)) == kmerco.KC_EINVAL
+
+
+def test_null_handle_calls_are_rejected():
+    lib = P.load_library()
+    assert lib.kc_insert(None, None, None, 0, 0, 21, None, 0, None, None, None) == kmerco.KC_EINVAL
+    assert lib.kc_classify(None, None, None, 0, 2, None, None, None, None, None) == kmerco.KC_EINVAL
+    assert lib.kc_query(None, None, 0, None, None) == kmerco.KC_EINVAL
+    assert lib.kc_sync(None) == kmerco.KC_EINVAL
+    assert lib.kc_reserve(None, 10) == kmerco.KC_EINVAL
+    lib.kc_destroy(None)

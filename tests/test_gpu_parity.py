@@ -1,0 +1,268 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every GPU output -- countBF words, distinct list (order included),
+trustworthy / erroneous lists and the inserted-window count -- must equal
+the oracle's exactly: all outputs are integers and the readings taken make
+each of them unique."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2305_07545_amd")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    P.load_library()
+
+
+def dev(rs):
+    reads = torch.from_numpy(rs.reads).cuda()
+    offs = torch.from_numpy(rs.offsets.view(np.int64)).cuda()
+    return reads, offs
+
+
+def gpu_run(rs, X, Y, alpha=8, k_h=1, k=None, tau=None):
+    reads, offs = dev(rs)
+    return P.run_kmerco(reads, offs, rs.k if k is None else k, rs.tau if tau is None else tau,
+                        X, Y, alpha, k_h)
+
+
+def cpu_run(rs, X, Y, alpha=8, k_h=1, k=None, tau=None):
+    return oracle.run_kmerco(rs.reads, rs.offsets, rs.k if k is None else k,
+                             rs.tau if tau is None else tau, X, Y, alpha, k_h)
+
+
+def assert_same(g, c, what=""):
+    names = ["words", "distinct", "trust", "err"]
+    for n, a, b in zip(names, g[:4], c[:4]):
+        a = np.asarray(a, dtype=np.uint64)
+        b = np.asarray(b, dtype=np.uint64)
+        assert a.shape == b.shape, f"{what} {n}: shape {a.shape} != {b.shape}"
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{what} {n}: {len(bad)} mismatches, first at {bad[:5]}: "
+                                 f"gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+    assert g[4] == c[4], f"{what} n_windows {g[4]} != {c[4]}"
+
+
+def check(rs, X, Y, alpha=8, k_h=1, k=None, tau=None, what=""):
+    print(f"case {what}: {rs.name} X={X} Y={Y} alpha={alpha} k_h={k_h} k={k or rs.k} "
+          f"bases={rs.n_bases}", flush=True)
+    g = gpu_run(rs, X, Y, alpha, k_h, k, tau)
+    c = cpu_run(rs, X, Y, alpha, k_h, k, tau)
+    assert_same(g, c, what)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def test_tiny_full_size():
+    rs = synth.config("tiny")
+    X, Y = oracle.dims(rs.n_items)
+    g = check(rs, X, Y, what="tiny")
+    ref = json.load(open(os.path.join(GOLDEN, "tiny_digests.json")))
+    assert (X, Y) == (ref["X"], ref["Y"])
+    assert hashlib.sha256(g[0].tobytes()).hexdigest() == ref["words_sha256"]
+
+
+def test_bacterial_small_scale():
+    rs = synth.config("bacterial", scale=0.02)
+    X, Y = oracle.dims(rs.n_items)
+    check(rs, X, Y, what="bacterial x0.02")
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
+
+
+def test_bacterial_full_size_digests():
+    """The benchmark's workload at full size, in the launch configuration the
+    benchmark times, against digests written by tests/golden/make_digests.py
+    from the oracle."""
+    ref = json.load(open(os.path.join(GOLDEN, "bacterial_digests.json")))
+    rs = synth.config("bacterial")
+    X, Y = oracle.dims(rs.n_items)
+    assert (X, Y) == (ref["X"], ref["Y"]) and rs.n_bases == ref["n_bases"]
+    print(f"case bacterial full: X={X} Y={Y} bases={rs.n_bases}", flush=True)
+    words, distinct, trust, err, nw = gpu_run(rs, X, Y)
+    assert nw == ref["n_windows"]
+    assert len(distinct) == ref["n_distinct"]
+    assert len(trust) == ref["n_trust"] and len(err) == ref["n_err"]
+    assert _sha(words) == ref["words_sha256"]
+    assert _sha(distinct) == ref["distinct_sha256"]
+    assert _sha(trust) == ref["trust_sha256"]
+    assert _sha(err) == ref["err_sha256"]
+
+
+# ---------------------------------------------------------------------------
+# shapes, k, layouts, collisions
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [1, 2, 7, 16, 21, 31, 32])
+def test_ragged_reads_all_k(k):
+    rs = synth.random_reads(100 + k, 700, 1, 400, k=k, tau=2, p_n=0.01, p_other=0.005)
+    check(rs, 257, 263, k=k, what=f"ragged k={k}")
+
+
+@pytest.mark.parametrize("alpha,k_h", [(8, 1), (8, 2), (8, 3), (4, 1), (4, 3), (5, 2), (7, 1),
+                                       (12, 2), (16, 1), (21, 1), (32, 2), (1, 1), (3, 8)])
+def test_heavy_collisions(alpha, k_h):
+    """A 3 x 5 filter: every cell is hit thousands of times (CAS contention,
+    saturation, first-seen between colliding k-mers)."""
+    rs = synth.random_reads(200 + alpha * 10 + k_h, 300, 20, 200, k=9, tau=3, p_n=0.01)
+    check(rs, 3, 5, alpha=alpha, k_h=k_h, what=f"collide a={alpha} kh={k_h}")
+
+
+@pytest.mark.parametrize("alpha,k_h", [(8, 2), (6, 3), (16, 4), (10, 1)])
+def test_medium_filters_multi_hash(alpha, k_h):
+    rs = synth.random_reads(300 + alpha + k_h, 2000, 50, 300, k=25, tau=2, p_n=0.002)
+    check(rs, 211, 223, alpha=alpha, k_h=k_h, what=f"medium a={alpha} kh={k_h}")
+
+
+def test_low_complexity_saturation():
+    """Two-letter reads: few distinct k-mers, counters saturate."""
+    rs = synth.random_reads(401, 3000, 100, 250, k=11, tau=5, alphabet=b"AC")
+    check(rs, 101, 103, what="AC alphabet")
+    homo = synth.reads_from_strings(["A" * 1000, "T" * 700, "ACGT" * 200], k=21, tau=3)
+    check(homo, 7, 11, what="homopolymers")
+
+
+def test_multi_chunk(monkeypatch):
+    """First-seen resolved in many chunks (chunk size forced small)."""
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "2048")
+    rs = synth.random_reads(501, 500, 30, 300, k=13, tau=2, alphabet=b"ACGT", p_n=0.01)
+    check(rs, 31, 37, k_h=2, what="chunk 2048")
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "1024")
+    check(rs, 97, 101, what="chunk 1024")
+
+
+def test_unaligned_reads_pointer():
+    rs = synth.random_reads(601, 400, 10, 200, k=17, p_n=0.01)
+    reads_pad = torch.zeros(rs.n_bases + 1, dtype=torch.uint8, device="cuda")
+    reads_pad[1:] = torch.from_numpy(rs.reads).cuda()
+    reads = reads_pad[1:]  # 1-byte offset: the ingest kernel's unaligned path
+    offs = torch.from_numpy(rs.offsets.view(np.int64)).cuda()
+    g = P.run_kmerco(reads, offs, 17, 2, 59, 61)
+    c = cpu_run(rs, 59, 61)
+    assert_same(g, c, "unaligned")
+
+
+# ---------------------------------------------------------------------------
+# calls and edge cases
+# ---------------------------------------------------------------------------
+
+def test_incremental_equals_concatenated():
+    parts = [synth.random_reads(700 + i, 200 + 50 * i, 15, 180, k=19, p_n=0.01) for i in range(3)]
+    whole = synth.concat_reads(parts)
+    X, Y = 61, 67
+    bf = P.CountBF(X, Y, 8, 2)
+    distinct = torch.empty(whole.n_bases, dtype=torch.int64, device="cuda")
+    for p in parts:
+        r, o = dev(p)
+        bf.insert(r, o, 19, distinct=distinct)
+    trust, nt, err, ne = bf.classify(distinct, bf.n_distinct, 2)
+    bf.sync()
+    nd = int(bf.n_distinct.item())
+    u = lambda t: t.cpu().numpy().view(np.uint64)  # noqa: E731
+    g = (u(bf.words), u(distinct[:nd]), u(trust[:int(nt.item())]), u(err[:int(ne.item())]),
+         int(bf.n_windows.item()))
+    c = oracle.run_kmerco(whole.reads, whole.offsets, 19, 2, X, Y, 8, 2)
+    assert_same(g, c, "incremental")
+
+
+def test_resume_from_existing_words():
+    """kc_create with zero=0 continues an existing countBF (general claim path)."""
+    a = synth.random_reads(801, 300, 30, 150, k=15)
+    b = synth.random_reads(802, 300, 30, 150, k=15)
+    X, Y = 41, 43
+    cpu = oracle.CountBF(X, Y, 8, 1)
+    cpu.insert(a.reads, a.offsets, 15)
+    words = torch.from_numpy(cpu.words.view(np.int64)).cuda()
+    bf = P.CountBF(X, Y, 8, 1, words=words, zero=False)
+    r, o = dev(b)
+    distinct = bf.insert(r, o, 15)
+    bf.sync()
+    db, _ = cpu.insert(b.reads, b.offsets, 15)
+    nd = int(bf.n_distinct.item())
+    assert np.array_equal(bf.words.cpu().numpy().view(np.uint64), cpu.words)
+    assert np.array_equal(distinct[:nd].cpu().numpy().view(np.uint64), db)
+
+
+def test_empty_and_degenerate_inputs():
+    X, Y = 13, 17
+    # no bases at all
+    bf = P.CountBF(X, Y)
+    r = torch.empty(0, dtype=torch.uint8, device="cuda")
+    o = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bf.insert(r, o, 21)
+    bf.sync()
+    assert int(bf.n_distinct.item()) == 0 and int(bf.n_windows.item()) == 0
+    assert int(bf.words.abs().sum().item()) == 0
+    # reads shorter than k, all-N reads, empty reads in between
+    rs = synth.reads_from_strings(["ACG", "", "NNNNNNNNNNNNNNNNNNNNNNNN", "ACGTACGTAC", "",
+                                   "acgtacgtacgtacgtacgtacgt", "ACGTNACGTACGT"], k=11)
+    check(rs, X, Y, what="degenerate")
+
+
+def test_query_matches_oracle():
+    rs = synth.random_reads(901, 500, 30, 200, k=21, p_n=0.01)
+    X, Y = 101, 103
+    cpu = oracle.CountBF(X, Y, 8, 3)
+    d, _ = cpu.insert(rs.reads, rs.offsets, 21)
+    rng = np.random.default_rng(3)
+    keys = np.concatenate([d, rng.integers(0, 2**42, 500, dtype=np.int64).astype(np.uint64)])
+    bf = P.CountBF(X, Y, 8, 3)
+    r, o = dev(rs)
+    bf.insert(r, o, 21)
+    f = bf.query(torch.from_numpy(keys.view(np.int64)).cuda())
+    bf.sync()
+    assert np.array_equal(f.cpu().numpy().astype(np.uint64), cpu.query(keys))
+
+
+@pytest.mark.parametrize("tau", [0, 1, 2, 5, 254, 255, 1000])
+def test_classify_thresholds(tau):
+    rs = synth.random_reads(1001, 800, 30, 200, k=9, alphabet=b"ACGT")
+    check(rs, 53, 59, tau=tau, what=f"tau={tau}")
+
+
+def test_errors_and_capacity():
+    rs = synth.random_reads(1101, 100, 30, 100, k=21)
+    r, o = dev(rs)
+    bf = P.CountBF(29, 31)
+    small = torch.empty(5, dtype=torch.int64, device="cuda")
+    bf.insert(r, o, 21, distinct=small)
+    with pytest.raises(P.KmercoError) as e:
+        bf.sync()
+    assert e.value.status == -3
+    c = cpu_run(rs, 29, 31)
+    assert int(bf.n_distinct.item()) == len(c[1])  # the count reports the need
+    assert np.array_equal(small.cpu().numpy().view(np.uint64), c[1][:5])
+    with pytest.raises(P.KmercoError) as e:
+        bf.insert(r, o, 23)  # k differs from the first insert
+    assert e.value.status == -5
+    bf.sync()  # sticky status was cleared
+
+
+def test_repeatable():
+    rs = synth.random_reads(1201, 1000, 50, 250, k=31, p_n=0.01)
+    a = gpu_run(rs, 89, 97, k_h=2)
+    b = gpu_run(rs, 89, 97, k_h=2)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
