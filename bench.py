@@ -1,9 +1,10 @@
 """KmerCo on one MI355X: k-mer insertions/s of the full hot path.
 
 One step = one KmerCo pass over the workload with its reads already resident
-in HBM: clear the countBF, insertion phase (ingest, first-seen claims +
-saturating increments, resolve, ordered distinct output) and classification
-phase (Query-II per distinct k-mer, ordered trustworthy / erroneous split).
+in HBM: clear the countBF, then kc_insert_classify: the insertion phase
+(ingest, binned counting + first-seen in LDS, ordered distinct output) and the
+classification phase (Query-II of each distinct k-mer against the final
+countBF, ordered trustworthy / erroneous split).
 The metric counts one insertion per valid k-mer window, as the paper's
 insertions-per-second figure does (number of insertions / insertion time).
 
@@ -42,9 +43,19 @@ def sha(t) -> str:
     return hashlib.sha256(np.ascontiguousarray(t.cpu().numpy().view(np.uint64)).tobytes()).hexdigest()
 
 
-def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int) -> float:
+def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
+                      n_words: int) -> float:
     """Bytes a launch of `phase` must move by its definition (logical
     accesses, not cache lines): see the per-kernel table in the design notes."""
+    entries = n_windows * k_h
+    if phase == "bin_count":         # packed input (codes 2 bits + 2 mask bits per base)
+        return n_bases * 0.5
+    if phase == "bin_write":         # packed input, one 8-byte entry per (window, hash fn)
+        return n_bases * 0.5 + entries * 8
+    if phase == "region":            # entries in, countBF cells read + written, flags
+        return entries * 8 + n_words * 16 + n_distinct
+    if phase == "tile_count":        # flag byte + packed input per position
+        return n_bases * 1.5
     if phase == "claim_increment":   # cell RMW + first-seen entry RMW per slot, packed input
         return n_windows * k_h * (16 + 8) + n_bases * 0.5
     if phase == "claim":             # cell read + entry RMW per slot
@@ -55,8 +66,8 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_windows * k_h * 4 + n_distinct * 4 + n_bases * (0.5 + 0.125)
     if phase == "ingest":            # ASCII in, packed codes + bitmaps out
         return n_bases * 1.5
-    if phase == "scatter":           # flags + packed input, keys out
-        return n_bases * (0.5 + 0.125) + n_distinct * 8
+    if phase == "scatter":           # flag byte + packed input, keys out (distinct + split)
+        return n_bases * 1.5 + n_distinct * 16
     if phase == "classify_mark":     # key + cell per slot, mask out
         return n_distinct * (8 + 8 * k_h + 0.125)
     if phase == "classify_scatter":  # key in, key out, mask
@@ -142,10 +153,8 @@ def main():
     def step():
         bf.reset(stream)
         counters.zero_()
-        bf.insert(reads, offs, rs.k, distinct=distinct, n_distinct=nd, n_windows=nw,
-                  stream=stream)
-        bf.classify(distinct, nd, rs.tau, trust=trust, err=err, n_trust=nt, n_err=ne,
-                    keys_cap=cap, stream=stream)
+        bf.insert_classify(reads, offs, rs.k, rs.tau, distinct=distinct, trust=trust, err=err,
+                           n_distinct=nd, n_windows=nw, n_trust=nt, n_err=ne, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -183,7 +192,7 @@ def main():
     roofline = None
     if dom:
         avg_s = phases[dom][0] / phases[dom][1] / 1e3
-        nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h)
+        nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, X * Y)
         achieved = nbytes / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

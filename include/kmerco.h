@@ -124,6 +124,22 @@ kc_status kc_insert(kc_filter *f, const uint8_t *reads_dev, const uint64_t *offs
                     uint64_t *distinct_dev, uint64_t distinct_cap, uint64_t *n_distinct_dev,
                     uint64_t *n_windows_dev, void *stream);
 
+/* Both phases of KmerCo for one read batch (the pipeline of Sec. 3: insert
+ * every k-mer, then classify the distinct ones), async on `stream`.
+ * Insertion is exactly kc_insert (same arguments, same distinct output).
+ * This call's distinct k-mers are then split by Query-II against the countBF
+ * as it stands after the call: frequency > tau -> trust_dev, else err_dev,
+ * both in distinct order, class_cap keys of room each; *n_trust_dev and
+ * *n_err_dev are overwritten with the counts (a count above class_cap drops
+ * the excess and records KC_ERANGE, returned by kc_sync).  Identical to
+ * kc_insert followed by kc_classify of the keys the insert appended. */
+kc_status kc_insert_classify(kc_filter *f, const uint8_t *reads_dev, const uint64_t *offsets_dev,
+                             uint64_t n_reads, uint64_t n_bases, uint32_t k, uint32_t tau,
+                             uint64_t *distinct_dev, uint64_t distinct_cap,
+                             uint64_t *n_distinct_dev, uint64_t *n_windows_dev,
+                             uint64_t *trust_dev, uint64_t *n_trust_dev, uint64_t *err_dev,
+                             uint64_t *n_err_dev, uint64_t class_cap, void *stream);
+
 /* Classification phase (Algorithm 2 with Query-II / Algorithm 5), async.
  * keys_dev / n_keys_dev: the k-mers to classify (typically the distinct list
  * and its device count); n = min(*n_keys_dev, keys_cap) keys are used.
@@ -161,17 +177,21 @@ kc_status kc_reset(kc_filter *f, void *stream);
  * ---------------------------------------------------------------------- */
 typedef enum {
     KC_PHASE_INGEST = 0,          /* ASCII -> 2-bit codes + base/read-start bitmaps */
-    KC_PHASE_CLAIM = 1,           /* first-seen claims (filter not empty) */
-    KC_PHASE_INCREMENT = 2,       /* saturating counter increments */
-    KC_PHASE_CLAIM_INCREMENT = 3, /* claims + increments (filter empty) */
-    KC_PHASE_RESOLVE = 4,         /* first-seen winners -> distinct flags */
+    KC_PHASE_CLAIM = 1,           /* direct path: first-seen claims (filter not empty) */
+    KC_PHASE_INCREMENT = 2,       /* direct path: saturating counter increments */
+    KC_PHASE_CLAIM_INCREMENT = 3, /* direct path: claims + increments (filter empty) */
+    KC_PHASE_RESOLVE = 4,         /* direct path: first-seen winners -> distinct flags */
     KC_PHASE_SCAN = 5,            /* per-tile offsets (insert and classify) */
     KC_PHASE_SCATTER = 6,         /* ordered distinct-key output */
     KC_PHASE_CLASSIFY_MARK = 7,   /* Query-II + threshold per key */
     KC_PHASE_CLASSIFY_SCATTER = 8,/* ordered trustworthy / erroneous output */
     KC_PHASE_QUERY = 9,           /* kc_query */
     KC_PHASE_RESET = 10,          /* kc_reset / kc_create clears */
-    KC_PHASE_COUNT = 11
+    KC_PHASE_BIN_COUNT = 11,      /* binned path: per-region entry counts */
+    KC_PHASE_BIN_WRITE = 12,      /* binned path: (occurrence, counter) entries by region */
+    KC_PHASE_REGION = 13,         /* binned path: LDS counting + first-seen per region */
+    KC_PHASE_TILE_COUNT = 14,     /* per-tile distinct / trustworthy / window counts */
+    KC_PHASE_COUNT = 15
 } kc_phase;
 
 kc_status kc_profile(kc_filter *f, int enable);

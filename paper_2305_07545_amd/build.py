@@ -9,7 +9,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkmerco_hip.so")
-SOURCES = ["kc_kernels.hip", "kc_api.hip"]
+SOURCES = ["kc_kernels.hip", "kc_binned.hip", "kc_scan.hip", "kc_api.hip"]
+MICROBENCH_LIB = os.path.join(HERE, "libkmerco_microbench.so")
+MICROBENCH_SOURCES = ["kc_microbench.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,16 +26,24 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 into the in-tree shared library."""
-    tmp = LIB + ".tmp"
+def _compile(sources, out, verbose):
+    tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+           *[os.path.join(CSRC, s) for s in sources], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {out}:\n{r.stdout}")
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source for gfx950: the KmerCo library and the
+    memory-system microbenchmarks."""
+    _compile(MICROBENCH_SOURCES, MICROBENCH_LIB, verbose)
+    return _compile(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":

@@ -4,10 +4,17 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 
 #include "kc_kernels.hpp"
 #include "kmerco.h"
+
+namespace {
+
+enum class Path { Auto, Direct, Binned };
+
+}  // namespace
 
 struct kc_filter {
     kc_layout layout;
@@ -18,7 +25,9 @@ struct kc_filter {
     uint32_t k;            // k of the first insert, 0 before it
     uint32_t *status;      // device: sticky status bits (kc::kStatus*)
     hipStream_t last;      // stream of the last enqueued call
-    uint64_t chunk;        // positions resolved per first-seen chunk
+    uint64_t chunk;        // direct path: positions per first-seen chunk
+    uint64_t bin_chunk;    // binned path: positions per chunk
+    Path path;
     kc::Profiler prof;     // optional per-kernel timing
 };
 
@@ -54,61 +63,160 @@ bool valid_layout(const kc_layout *L) {
     return true;
 }
 
-void free_workspace(kc::Workspace &W) {
-    (void)hipFree(W.codes);
-    (void)hipFree(W.inv);
-    (void)hipFree(W.rs);
-    (void)hipFree(W.flags);
-    (void)hipFree(W.tile_a);
-    (void)hipFree(W.tile_b);
-    (void)hipFree(W.tile_off);
-    (void)hipFree(W.totals);
-    W = kc::Workspace{};
-}
-
 template <typename T>
 bool dev_alloc(T **p, uint64_t count) {
     return hipMalloc((void **)p, (count ? count : 1) * sizeof(T)) == hipSuccess;
 }
 
-// Grow the per-call workspace to hold `n` positions.  Waits for the
-// handle's outstanding work before releasing old buffers.
-kc_status ensure_workspace(kc_filter *f, uint64_t n) {
-    if (n <= f->W.cap && f->W.codes)
+template <typename T>
+void dev_free(T *&p) {
+    (void)hipFree(p);
+    p = nullptr;
+}
+
+void wait_idle(kc_filter *f) { (void)hipStreamSynchronize(f->last); }
+
+// per-position buffers for inserts of up to n bases
+kc_status ensure_positions(kc_filter *f, uint64_t n) {
+    kc::Workspace &W = f->W;
+    if (W.codes && n <= W.cap)
         return KC_OK;
-    if (f->W.codes)
-        (void)hipStreamSynchronize(f->last);
-    free_workspace(f->W);
-    uint64_t cap = n < 65536 ? 65536 : n + n / 8;  // headroom for slowly growing calls
-    kc::Workspace W;
-    W.cap = cap;
-    bool ok = dev_alloc(&W.codes, kc::code_words(cap)) && dev_alloc(&W.inv, kc::mask_words(cap)) &&
-              dev_alloc(&W.rs, kc::mask_words(cap)) && dev_alloc(&W.flags, kc::flag_words(cap)) &&
-              dev_alloc(&W.tile_a, kc::tiles(cap)) && dev_alloc(&W.tile_b, kc::tiles(cap)) &&
-              dev_alloc(&W.tile_off, kc::tiles(cap)) && dev_alloc(&W.totals, 2);
-    if (!ok) {
-        free_workspace(W);
+    wait_idle(f);
+    dev_free(W.codes);
+    dev_free(W.inv);
+    dev_free(W.rs);
+    dev_free(W.flags8);
+    uint64_t cap = n < 65536 ? 65536 : n + n / 8;
+    W.cap = 0;
+    if (!dev_alloc(&W.codes, kc::code_words(cap)) || !dev_alloc(&W.inv, kc::mask_words(cap)) ||
+        !dev_alloc(&W.rs, kc::mask_words(cap)) || !dev_alloc(&W.flags8, kc::tiles(cap) * kc::kTile))
         return KC_ENOMEM;
-    }
-    f->W = W;
+    W.cap = cap;
     return KC_OK;
 }
 
-// Positions per first-seen chunk: kc::kChunk, or KMERCO_CHUNK_POSITIONS
-// (rounded down to a multiple of kc::kTile, at least one tile) so that small
-// inputs can exercise the multi-chunk path.
-uint64_t chunk_from_env() {
-    const char *e = std::getenv("KMERCO_CHUNK_POSITIONS");
+// per-tile buffers for n positions or keys
+kc_status ensure_tiles(kc_filter *f, uint64_t n) {
+    kc::Workspace &W = f->W;
+    uint64_t nt = kc::tiles(n) + 1;
+    if (W.tile_a && nt <= W.tile_cap)
+        return KC_OK;
+    wait_idle(f);
+    dev_free(W.tile_a);
+    dev_free(W.tile_b);
+    dev_free(W.tile_c);
+    dev_free(W.off_a);
+    dev_free(W.off_b);
+    dev_free(W.off_c);
+    dev_free(W.tmask);
+    dev_free(W.partial64);
+    uint64_t cap = nt < 64 ? 64 : nt + nt / 8;
+    W.tile_cap = 0;
+    if (!dev_alloc(&W.tile_a, cap) || !dev_alloc(&W.tile_b, cap) || !dev_alloc(&W.tile_c, cap) ||
+        !dev_alloc(&W.off_a, cap) || !dev_alloc(&W.off_b, cap) || !dev_alloc(&W.off_c, cap) ||
+        !dev_alloc(&W.tmask, cap * (kc::kTile / 64)) ||
+        !dev_alloc(&W.partial64, kc::scan_partials(cap)))
+        return KC_ENOMEM;
+    W.tile_cap = cap;
+    return KC_OK;
+}
+
+// binned-path buffers for one chunk of the given plan
+kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
+    kc::Workspace &W = f->W;
+    uint64_t n_mat = (uint64_t)B.n_regions * B.G;
+    uint64_t n_ent = chunk_positions * f->layout.k_h;
+    if (W.matrix && n_mat <= W.matrix_cap && W.entries && n_ent <= W.entries_cap)
+        return KC_OK;
+    wait_idle(f);
+    if (!W.matrix || n_mat > W.matrix_cap) {
+        dev_free(W.matrix);
+        dev_free(W.partial32);
+        W.matrix_cap = 0;
+        if (!dev_alloc(&W.matrix, n_mat) || !dev_alloc(&W.partial32, kc::scan_partials(n_mat)))
+            return KC_ENOMEM;
+        W.matrix_cap = n_mat;
+    }
+    if (!W.entries || n_ent > W.entries_cap) {
+        dev_free(W.entries);
+        W.entries_cap = 0;
+        uint64_t cap = n_ent + n_ent / 8;
+        if (!dev_alloc(&W.entries, cap))
+            return KC_ENOMEM;
+        W.entries_cap = cap;
+    }
+    return KC_OK;
+}
+
+kc_status ensure_scalars(kc_filter *f) {
+    if (f->W.totals)
+        return KC_OK;
+    if (!dev_alloc(&f->W.totals, 8) || !dev_alloc(&f->W.n_entries, 1))
+        return KC_ENOMEM;
+    return KC_OK;
+}
+
+// first-seen workspace of the direct path: one entry per counter
+kc_status ensure_aux(kc_filter *f, hipStream_t s) {
+    if (f->F.aux)
+        return KC_OK;
+    uint64_t n_aux = f->layout.X * f->layout.Y * f->F.eta;
+    if (!dev_alloc(&f->F.aux, n_aux))
+        return KC_ENOMEM;
+    return kc::fill_u32(f->F.aux, n_aux, kc::kIdle, s) == hipSuccess ? KC_OK : KC_EDEVICE;
+}
+
+void free_all(kc_filter *f) {
+    kc::Workspace &W = f->W;
+    dev_free(W.codes);
+    dev_free(W.inv);
+    dev_free(W.rs);
+    dev_free(W.flags8);
+    dev_free(W.tile_a);
+    dev_free(W.tile_b);
+    dev_free(W.tile_c);
+    dev_free(W.off_a);
+    dev_free(W.off_b);
+    dev_free(W.off_c);
+    dev_free(W.tmask);
+    dev_free(W.partial64);
+    dev_free(W.matrix);
+    dev_free(W.partial32);
+    dev_free(W.entries);
+    dev_free(W.totals);
+    dev_free(W.n_entries);
+    dev_free(f->F.aux);
+    dev_free(f->status);
+}
+
+uint64_t env_u64(const char *name, uint64_t dflt) {
+    const char *e = std::getenv(name);
     if (!e || !*e)
-        return kc::kChunk;
+        return dflt;
     char *end = nullptr;
     unsigned long long v = std::strtoull(e, &end, 10);
-    if (end == e)
-        return kc::kChunk;
-    uint64_t c = (uint64_t)v / kc::kTile * kc::kTile;
+    return end == e ? dflt : (uint64_t)v;
+}
+
+// Chunk sizes: the defaults, or KMERCO_CHUNK_POSITIONS (rounded down to a
+// multiple of kc::kTile, at least one tile) so that small inputs can
+// exercise the multi-chunk paths.
+uint64_t chunk_size(uint64_t dflt) {
+    uint64_t c = env_u64("KMERCO_CHUNK_POSITIONS", dflt) / kc::kTile * kc::kTile;
     if (c < (uint64_t)kc::kTile)
         c = kc::kTile;
-    return c > kc::kChunk ? kc::kChunk : c;
+    return c > dflt ? dflt : c;
+}
+
+// Insertion path: binned unless the filter is too large for one level of
+// regions; KMERCO_PATH=direct|binned forces one (tests compare both).
+Path path_from_env() {
+    const char *e = std::getenv("KMERCO_PATH");
+    if (e && std::strcmp(e, "direct") == 0)
+        return Path::Direct;
+    if (e && std::strcmp(e, "binned") == 0)
+        return Path::Binned;
+    return Path::Auto;
 }
 
 uint64_t next_prime_after(uint64_t n) {
@@ -124,6 +232,72 @@ uint64_t next_prime_after(uint64_t n) {
         if (prime)
             return p;
     }
+}
+
+// Both phases for one call.  trust == nullptr: insertion only.
+kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offsets,
+                      uint64_t n_reads, uint64_t n_bases, uint32_t k, uint64_t *distinct,
+                      uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows, uint32_t tau,
+                      uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                      uint64_t cap_te, hipStream_t s) {
+    const bool split = trust != nullptr;
+    f->last = s;
+    f->k = k;
+    kc_status st = ensure_scalars(f);
+    if (st != KC_OK)
+        return st;
+    if (n_bases == 0) {
+        if (split && (kc::fill_u64(n_trust, 1, 0, s) != hipSuccess ||
+                      kc::fill_u64(n_err, 1, 0, s) != hipSuccess))
+            return KC_EDEVICE;
+        return KC_OK;
+    }
+    if ((st = ensure_positions(f, n_bases)) != KC_OK || (st = ensure_tiles(f, n_bases)) != KC_OK)
+        return st;
+    kc::BinPlan plan{};
+    const uint64_t bchunk = n_bases < f->bin_chunk ? n_bases : f->bin_chunk;
+    bool binned = f->path != Path::Direct && kc::bin_plan(f->F, bchunk, plan);
+    if (f->path == Path::Binned && !binned)
+        return KC_EINVAL;  // forced binned path but the filter does not fit it
+    if (binned) {
+        if ((st = ensure_binned(f, plan, bchunk)) != KC_OK)
+            return st;
+    } else if ((st = ensure_aux(f, s)) != KC_OK) {
+        return st;
+    }
+    hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, f->W, s, &f->prof);
+    if (e != hipSuccess)
+        return KC_EDEVICE;
+    kc::ReadsArgs R{f->W.codes, f->W.inv, f->W.rs, n_bases, k};
+    const uint64_t chunk = binned ? bchunk : f->chunk;
+    // this call's classification can be taken from the region pass when the
+    // final counter of each distinct k-mer's single slot is known there
+    const bool fused = split && binned && f->F.k_h == 1 && n_bases <= chunk;
+    for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk) {
+        uint64_t c1 = c0 + chunk < n_bases ? c0 + chunk : n_bases;
+        if (binned)
+            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, f->W, fused, tau, s, &f->prof);
+        else
+            e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, f->W, s, &f->prof);
+        if (e != hipSuccess)
+            return KC_EDEVICE;
+        f->zero = false;
+    }
+    e = kc::launch_distinct(R, f->W, distinct, cap_d, n_distinct, n_windows,
+                            fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status, s,
+                            &f->prof);
+    if (e != hipSuccess)
+        return KC_EDEVICE;
+    if (split && !fused) {
+        // classify the keys this call appended: distinct[base .. *n_distinct),
+        // base saved by the distinct output step
+        e = kc::launch_classify(f->F, distinct, n_distinct, f->W.totals + 3, n_bases, cap_d, tau,
+                                trust, n_trust, err, n_err, cap_te, f->status, f->W, s,
+                                &f->prof);
+        if (e != hipSuccess)
+            return KC_EDEVICE;
+    }
+    return KC_OK;
 }
 
 }  // namespace
@@ -142,7 +316,7 @@ const char *kc_strerror(int status) {
     }
 }
 
-int kc_version(void) { return 1; }
+int kc_version(void) { return 2; }
 
 uint32_t kc_eta(uint32_t alpha) { return (alpha >= 1 && alpha <= 64) ? 64u / alpha : 0u; }
 
@@ -178,9 +352,12 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     f->zero = zero != 0;
     f->k = 0;
     f->last = (hipStream_t)stream;
-    f->chunk = chunk_from_env();
+    f->chunk = chunk_size(kc::kChunk);
+    f->bin_chunk = chunk_size(kc::kBinChunk);
+    f->path = path_from_env();
     kc::FilterArgs &F = f->F;
     F.words = words_dev;
+    F.aux = nullptr;
     F.X = layout->X;
     F.Y = layout->Y;
     F.mX = UINT64_MAX / layout->X;
@@ -191,24 +368,17 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     F.eta_pow2 = (F.eta & (F.eta - 1)) == 0;
     F.k_h = layout->k_h;
     F.field_max = (layout->alpha >= 64) ? ~0ull : ((1ull << layout->alpha) - 1ull);
-    uint64_t n_words = layout->X * layout->Y;
-    uint64_t n_aux = n_words * F.eta;
     hipStream_t s = (hipStream_t)stream;
-    if (!dev_alloc(&F.aux, n_aux) || !dev_alloc(&f->status, 1)) {
-        (void)hipFree(F.aux);
-        (void)hipFree(f->status);
+    if (!dev_alloc(&f->status, 1)) {
         delete f;
         return KC_ENOMEM;
     }
-    hipError_t e = kc::fill_u32(F.aux, n_aux, kc::kIdle, s);
-    if (e == hipSuccess)
-        e = kc::fill_u32(f->status, 1, 0u, s);
+    hipError_t e = kc::fill_u32(f->status, 1, 0u, s);
     if (e == hipSuccess && zero)
-        e = kc::fill_u64(words_dev, n_words, 0ull, s);
+        e = kc::fill_u64(words_dev, layout->X * layout->Y, 0ull, s);
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(s);
-        (void)hipFree(F.aux);
-        (void)hipFree(f->status);
+        free_all(f);
         delete f;
         return KC_EDEVICE;
     }
@@ -222,9 +392,7 @@ void kc_destroy(kc_filter *f) {
     DeviceGuard g(f->device);
     (void)hipDeviceSynchronize();
     f->prof.release();
-    free_workspace(f->W);
-    (void)hipFree(f->F.aux);
-    (void)hipFree(f->status);
+    free_all(f);
     delete f;
 }
 
@@ -234,7 +402,18 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases) {
     DeviceGuard g(f->device);
     if (!g.ok)
         return KC_EDEVICE;
-    return ensure_workspace(f, max_bases);
+    kc_status st = ensure_scalars(f);
+    if (st == KC_OK)
+        st = ensure_positions(f, max_bases);
+    if (st == KC_OK)
+        st = ensure_tiles(f, max_bases);
+    if (st != KC_OK || max_bases == 0)
+        return st;
+    kc::BinPlan plan{};
+    const uint64_t bchunk = max_bases < f->bin_chunk ? max_bases : f->bin_chunk;
+    if (f->path != Path::Direct && kc::bin_plan(f->F, bchunk, plan))
+        return ensure_binned(f, plan, bchunk);
+    return ensure_aux(f, f->last);
 }
 
 kc_status kc_get_layout(const kc_filter *f, kc_layout *out) {
@@ -259,28 +438,34 @@ kc_status kc_insert(kc_filter *f, const uint8_t *reads_dev, const uint64_t *offs
     DeviceGuard g(f->device);
     if (!g.ok)
         return KC_EDEVICE;
-    hipStream_t s = (hipStream_t)stream;
-    f->last = s;
-    f->k = k;
-    if (n_bases == 0)
-        return KC_OK;
-    kc_status st = ensure_workspace(f, n_bases);
-    if (st != KC_OK)
-        return st;
-    hipError_t e = kc::launch_ingest(reads_dev, n_bases, offsets_dev, n_reads, f->W, s, &f->prof);
-    if (e != hipSuccess)
+    return insert_impl(f, reads_dev, offsets_dev, n_reads, n_bases, k, distinct_dev, distinct_cap,
+                       n_distinct_dev, n_windows_dev, 0, nullptr, nullptr, nullptr, nullptr, 0,
+                       (hipStream_t)stream);
+}
+
+kc_status kc_insert_classify(kc_filter *f, const uint8_t *reads_dev, const uint64_t *offsets_dev,
+                             uint64_t n_reads, uint64_t n_bases, uint32_t k, uint32_t tau,
+                             uint64_t *distinct_dev, uint64_t distinct_cap,
+                             uint64_t *n_distinct_dev, uint64_t *n_windows_dev,
+                             uint64_t *trust_dev, uint64_t *n_trust_dev, uint64_t *err_dev,
+                             uint64_t *n_err_dev, uint64_t class_cap, void *stream) {
+    if (!f || k < 1 || k > 32 || !n_distinct_dev || !n_trust_dev || !n_err_dev)
+        return KC_EINVAL;
+    if (n_bases > 0 && (!reads_dev || !offsets_dev))
+        return KC_EINVAL;
+    if ((distinct_cap > 0 && !distinct_dev) || (class_cap > 0 && (!trust_dev || !err_dev)))
+        return KC_EINVAL;
+    if (f->k != 0 && f->k != k)
+        return KC_ESTATE;
+    DeviceGuard g(f->device);
+    if (!g.ok)
         return KC_EDEVICE;
-    kc::ReadsArgs R{f->W.codes, f->W.inv, f->W.rs, n_bases, k};
-    for (uint64_t c0 = 0; c0 < n_bases; c0 += f->chunk) {
-        uint64_t c1 = c0 + f->chunk < n_bases ? c0 + f->chunk : n_bases;
-        e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, f->W, s, &f->prof);
-        if (e != hipSuccess)
-            return KC_EDEVICE;
-        f->zero = false;
-    }
-    e = kc::launch_distinct(R, f->W, distinct_dev, distinct_cap, n_distinct_dev, n_windows_dev,
-                            f->status, s, &f->prof);
-    return e == hipSuccess ? KC_OK : KC_EDEVICE;
+    // a non-null marker selects the classification outputs even at capacity 0
+    uint64_t *trust = trust_dev ? trust_dev : n_trust_dev;
+    uint64_t *err = err_dev ? err_dev : n_err_dev;
+    return insert_impl(f, reads_dev, offsets_dev, n_reads, n_bases, k, distinct_dev, distinct_cap,
+                       n_distinct_dev, n_windows_dev, tau, trust, n_trust_dev, err, n_err_dev,
+                       class_cap, (hipStream_t)stream);
 }
 
 kc_status kc_classify(kc_filter *f, const uint64_t *keys_dev, const uint64_t *n_keys_dev,
@@ -295,11 +480,14 @@ kc_status kc_classify(kc_filter *f, const uint64_t *keys_dev, const uint64_t *n_
         return KC_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     f->last = s;
-    kc_status st = ensure_workspace(f, keys_cap);
+    kc_status st = ensure_scalars(f);
+    if (st == KC_OK)
+        st = ensure_tiles(f, keys_cap);
     if (st != KC_OK)
         return st;
-    hipError_t e = kc::launch_classify(f->F, keys_dev, n_keys_dev, keys_cap, tau, trust_dev,
-                                       n_trust_dev, err_dev, n_err_dev, f->W, s, &f->prof);
+    hipError_t e = kc::launch_classify(f->F, keys_dev, n_keys_dev, nullptr, keys_cap, keys_cap,
+                                       tau, trust_dev, n_trust_dev, err_dev, n_err_dev, keys_cap,
+                                       nullptr, f->W, s, &f->prof);
     return e == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
@@ -312,7 +500,8 @@ kc_status kc_query(kc_filter *f, const uint64_t *keys_dev, uint64_t n, uint32_t 
         return KC_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     f->last = s;
-    return kc::launch_query(f->F, keys_dev, n, freq_dev, s, &f->prof) == hipSuccess ? KC_OK : KC_EDEVICE;
+    return kc::launch_query(f->F, keys_dev, n, freq_dev, s, &f->prof) == hipSuccess ? KC_OK
+                                                                                    : KC_EDEVICE;
 }
 
 kc_status kc_sync(kc_filter *f) {
@@ -348,7 +537,7 @@ kc_status kc_reset(kc_filter *f, void *stream) {
     f->prof.end(s);
     if (e != hipSuccess)
         return KC_EDEVICE;
-    // the first-seen workspace is back to idle after every insert
+    // the direct path's first-seen workspace is idle again after every insert
     f->zero = true;
     f->k = 0;
     return KC_OK;
@@ -375,7 +564,8 @@ kc_status kc_profile_read(kc_filter *f, double *ms, uint64_t *launches, uint32_t
 const char *kc_phase_name(uint32_t phase) {
     static const char *names[kc::kPhCount] = {
         "ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
-        "classify_mark", "classify_scatter", "query", "reset"};
+        "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_write",
+        "region", "tile_count"};
     return phase < (uint32_t)kc::kPhCount ? names[phase] : "unknown";
 }
 

@@ -189,6 +189,98 @@ KC_HD Canon canonical(uint64_t fwd, uint32_t K) {
     return c;
 }
 
+// Same choice with one MurmurHash3 call fewer: the high words (seed 0) of
+// both strands decide unless they are equal; only the chosen strand's low
+// word (seed 1) is then needed.  Identical result to canonical().
+KC_HD Canon canonical_fast(uint64_t fwd, uint32_t K) {
+    uint64_t rc = revcomp_key(fwd, K);
+    uint32_t f0, f1, r0, r1;
+    key_blocks(fwd, f0, f1);
+    key_blocks(rc, r0, r1);
+    uint32_t hf = mm3_seeded(f0, f1, 0u);
+    uint32_t hr = mm3_seeded(r0, r1, 0u);
+    Canon c;
+    if (hf != hr) {
+        bool take_fwd = hf < hr;
+        c.key = take_fwd ? fwd : rc;
+        c.b0 = take_fwd ? f0 : r0;
+        c.b1 = take_fwd ? f1 : r1;
+        c.h1 = ((uint64_t)(take_fwd ? hf : hr) << 32) | mm3_seeded(c.b0, c.b1, 1u);
+    } else {
+        uint64_t Hf = ((uint64_t)hf << 32) | mm3_seeded(f0, f1, 1u);
+        uint64_t Hr = ((uint64_t)hr << 32) | mm3_seeded(r0, r1, 1u);
+        bool take_fwd = Hf < Hr;
+        c.key = take_fwd ? fwd : rc;
+        c.b0 = take_fwd ? f0 : r0;
+        c.b1 = take_fwd ? f1 : r1;
+        c.h1 = take_fwd ? Hf : Hr;
+    }
+    return c;
+}
+
+// ----------------------------------------------------------------------------
+// Wavefront-level window extraction.  A wavefront handles 64 consecutive
+// positions pb .. pb+63 (pb a multiple of 64).  The packed words they need
+// (6 code words, 3 invalid-base words, 3 read-start words) are the same for
+// every lane, so they are loaded once per wavefront (scalar loads when pb is
+// wave-uniform) and each lane selects its own.
+// ----------------------------------------------------------------------------
+struct WaveWords {
+    uint32_t c[6];
+    uint32_t iv[3];
+    uint32_t st[3];
+};
+
+KC_HD void wave_load(const ReadsArgs &R, uint64_t pb, WaveWords &w) {
+    const uint32_t *cp = R.codes + (pb >> 4);
+    const uint32_t *ip = R.inv + (pb >> 5);
+    const uint32_t *sp = R.rs + (pb >> 5);
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+        w.c[i] = cp[i];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        w.iv[i] = ip[i];
+        w.st[i] = sp[i];
+    }
+}
+
+KC_HD uint32_t pick4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t i) {
+    uint32_t lo = (i & 1u) ? a1 : a0;
+    uint32_t hi = (i & 1u) ? a3 : a2;
+    return (i & 2u) ? hi : lo;
+}
+
+// low 32 bits of (hi:lo) >> s, s in [0, 31]
+KC_HD uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t s) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(hi, lo, s);
+#else
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
+#endif
+}
+
+// Window at position pb + lane (lane < 64): validity and forward key.
+KC_HD bool wave_window(const WaveWords &w, uint64_t pb, uint32_t lane, uint32_t K,
+                       uint64_t n_bases, uint64_t &fwd) {
+    const uint32_t mo = lane >> 4;
+    const uint32_t w0 = pick4(w.c[0], w.c[1], w.c[2], w.c[3], mo);
+    const uint32_t w1 = pick4(w.c[1], w.c[2], w.c[3], w.c[4], mo);
+    const uint32_t w2 = pick4(w.c[2], w.c[3], w.c[4], w.c[5], mo);
+    const uint32_t s = 2u * (lane & 15u);
+    // 64 bits starting at base (lane & 15) of w0: (w0:w1:w2) << s
+    const uint32_t top_hi = s ? funnel32(w0, w1, 32u - s) : w0;
+    const uint32_t top_lo = s ? funnel32(w1, w2, 32u - s) : w1;
+    fwd = (((uint64_t)top_hi << 32) | top_lo) >> (64u - 2u * K);
+    // 32 mask bits starting at the window's first base
+    const bool upper = (lane & 32u) != 0;
+    const uint32_t o = lane & 31u;
+    const uint32_t iv = funnel32(upper ? w.iv[2] : w.iv[1], upper ? w.iv[1] : w.iv[0], o);
+    const uint32_t st = funnel32(upper ? w.st[2] : w.st[1], upper ? w.st[1] : w.st[0], o);
+    const uint32_t kmask = K >= 32u ? 0xFFFFFFFFu : ((1u << K) - 1u);
+    return (pb + lane + K <= n_bases) && ((iv & kmask) | (st & kmask & ~1u)) == 0;
+}
+
 // Saturating increment of counter l of a cell (64-bit CAS loop).  Returns
 // nothing; a saturated counter is left unchanged.
 __device__ __forceinline__ void saturating_increment(uint64_t *cell, uint32_t shift,

@@ -136,150 +136,161 @@ __global__ void __launch_bounds__(kWG) k_insert_phase(FilterArgs F, ReadsArgs R,
 }
 
 __global__ void __launch_bounds__(kWG) k_resolve(FilterArgs F, ReadsArgs R, uint64_t c0,
-                                                 uint64_t c1, uint64_t *__restrict__ flags,
-                                                 uint32_t *__restrict__ tile_distinct,
-                                                 uint32_t *__restrict__ tile_valid) {
-    __shared__ uint32_t s_cnt[2][kWG / 64];
-    const uint64_t tile = c0 / kTile + blockIdx.x;
-    const uint64_t tile0 = tile * kTile;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    uint32_t n_dist = 0, n_valid = 0;
+                                                 uint64_t c1, uint8_t *__restrict__ flags) {
+    const uint64_t tile0 = c0 + (uint64_t)blockIdx.x * kTile;
 #pragma unroll 1
     for (int j = 0; j < kTile / kWG; j++) {
         uint64_t p = tile0 + (uint64_t)j * kWG + threadIdx.x;
-        bool valid = p < c1 && window_valid(R, p);
+        if (p >= c1 || !window_valid(R, p))
+            continue;
+        uint64_t fwd = window_key(R.codes, p, R.k);
+        Canon c = canonical(fwd, R.k);
+        uint32_t t = (uint32_t)(p - c0);
         bool win = false;
-        if (valid) {
-            uint64_t fwd = window_key(R.codes, p, R.k);
-            Canon c = canonical(fwd, R.k);
-            uint32_t t = (uint32_t)(p - c0);
-            for (uint32_t a = 1; a <= F.k_h; a++) {
-                uint64_t h = (a == 1) ? c.h1 : hash_a(c.b0, c.b1, a);
-                uint64_t word;
-                uint32_t l;
-                slot_of(F, h, word, l);
-                uint64_t idx = word * F.eta + l;
-                if (F.aux[idx] == t) {
-                    win = true;
-                    F.aux[idx] = kIdle;
-                }
+        for (uint32_t a = 1; a <= F.k_h; a++) {
+            uint64_t h = (a == 1) ? c.h1 : hash_a(c.b0, c.b1, a);
+            uint64_t word;
+            uint32_t l;
+            slot_of(F, h, word, l);
+            uint64_t idx = word * F.eta + l;
+            if (F.aux[idx] == t) {
+                win = true;
+                F.aux[idx] = kIdle;
             }
         }
-        uint64_t wmask = __ballot(win);
-        uint64_t vmask = __ballot(valid);
-        if (lane == 0) {
-            flags[(tile0 + (uint64_t)j * kWG) / 64 + wave] = wmask;
-            n_dist += (uint32_t)__popcll(wmask);
-            n_valid += (uint32_t)__popcll(vmask);
-        }
-    }
-    if (lane == 0) {
-        s_cnt[0][wave] = n_dist;
-        s_cnt[1][wave] = n_valid;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t a = 0, b = 0;
-        for (int w = 0; w < kWG / 64; w++) {
-            a += s_cnt[0][w];
-            b += s_cnt[1][w];
-        }
-        tile_distinct[tile] = a;
-        tile_valid[tile] = b;
+        if (win)
+            flags[p] = 1;
     }
 }
 
 // ---------------------------------------------------------------------------
-// single-workgroup exclusive scan of per-block counts
-//   off[i] = (base ? *base : 0) + sum(cnt[0..i)),  totals[0] = sum(cnt),
-//   totals[1] = sum(cnt2) when cnt2 is given
+// ordered output of the distinct k-mers (and optionally of their
+// trustworthy / erroneous split): flag byte per position, 1 = distinct,
+// 3 = distinct and trustworthy
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kScanWG) k_scan(const uint32_t *__restrict__ cnt,
-                                                  const uint32_t *__restrict__ cnt2, uint64_t nb,
-                                                  uint64_t *__restrict__ off,
-                                                  const uint64_t *__restrict__ base,
-                                                  uint64_t *__restrict__ totals) {
-    __shared__ uint64_t s_sum[kScanWG];
-    __shared__ uint64_t s_sum2[kScanWG];
-    const uint64_t per = (nb + kScanWG - 1) / kScanWG;
-    const uint64_t lo = per * threadIdx.x;
-    const uint64_t hi = lo + per < nb ? lo + per : nb;
-    uint64_t sum = 0, sum2 = 0;
-    for (uint64_t i = lo; i < hi; i++) {
-        sum += cnt[i];
-        if (cnt2)
-            sum2 += cnt2[i];
-    }
-    s_sum[threadIdx.x] = sum;
-    s_sum2[threadIdx.x] = sum2;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the per-thread sums
-    for (int d = 1; d < kScanWG; d <<= 1) {
-        uint64_t v = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
-        uint64_t v2 = threadIdx.x >= (unsigned)d ? s_sum2[threadIdx.x - d] : 0;
-        __syncthreads();
-        s_sum[threadIdx.x] += v;
-        s_sum2[threadIdx.x] += v2;
-        __syncthreads();
-    }
-    uint64_t run = (base ? *base : 0) + s_sum[threadIdx.x] - sum;
-    for (uint64_t i = lo; i < hi; i++) {
-        off[i] = run;
-        run += cnt[i];
-    }
-    if (threadIdx.x == kScanWG - 1) {
-        totals[0] = s_sum[kScanWG - 1];
-        totals[1] = s_sum2[kScanWG - 1];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// ordered scatter of the distinct keys
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWG) k_scatter_distinct(ReadsArgs R, uint64_t first_tile,
-                                                          const uint64_t *__restrict__ flags,
-                                                          const uint64_t *__restrict__ tile_off,
-                                                          uint64_t *__restrict__ out,
-                                                          uint64_t cap) {
-    const uint64_t tile = first_tile + blockIdx.x;
-    const uint64_t tile0 = tile * kTile;
+__global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *__restrict__ flags,
+                                                    uint32_t *__restrict__ tile_d,
+                                                    uint32_t *__restrict__ tile_t,
+                                                    uint32_t *__restrict__ tile_v) {
+    __shared__ uint32_t s_cnt[3][kWG / 64];
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    constexpr int kWords = kTile / 64;
-    const uint64_t *fw = flags + tile0 / 64;
-    uint64_t base = tile_off[tile];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t nd = 0, nt = 0, nv = 0;
 #pragma unroll 1
     for (int j = 0; j < kTile / kWG; j++) {
-        int widx = j * (kWG / 64) + wave;
-        uint64_t word = fw[widx];
-        if (((word >> lane) & 1ull) == 0)
-            continue;
-        uint64_t before = 0;
-        for (int w = 0; w < widx; w++)
-            before += (uint64_t)__popcll(fw[w]);
-        before += (uint64_t)__popcll(word & ((1ull << lane) - 1ull));
-        uint64_t p = tile0 + (uint64_t)j * kWG + threadIdx.x;
-        uint64_t fwd = window_key(R.codes, p, R.k);
-        uint64_t key = canonical(fwd, R.k).key;
-        uint64_t dst = base + before;
-        if (dst < cap)
-            out[dst] = key;
+        const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
+        WaveWords w;
+        wave_load(R, pb, w);
+        uint64_t fwd;
+        bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd);
+        uint32_t f = valid ? flags[pb + lane] : 0u;
+        nd += (uint32_t)__popcll(__ballot(f != 0));
+        nt += (uint32_t)__popcll(__ballot(f == 3));
+        nv += (uint32_t)__popcll(__ballot(valid));
     }
-    (void)kWords;
+    if (lane == 0) {
+        s_cnt[0][wave] = nd;
+        s_cnt[1][wave] = nt;
+        s_cnt[2][wave] = nv;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t a = 0;
+        for (int w = 0; w < kWG / 64; w++)
+            a += s_cnt[threadIdx.x][w];
+        uint32_t *dst = threadIdx.x == 0 ? tile_d : threadIdx.x == 1 ? tile_t : tile_v;
+        dst[blockIdx.x] = a;
+    }
 }
 
+__global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__restrict__ flags,
+                                                 const uint64_t *__restrict__ off_d,
+                                                 const uint64_t *__restrict__ off_t,
+                                                 const uint64_t *__restrict__ call_base,
+                                                 uint64_t *__restrict__ distinct, uint64_t cap_d,
+                                                 uint64_t *__restrict__ trust,
+                                                 uint64_t *__restrict__ err, uint64_t cap_te,
+                                                 int split) {
+    constexpr int kWaves = kTile / 64;
+    __shared__ uint64_t s_md[kWaves];
+    __shared__ uint64_t s_mt[kWaves];
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t f[kTile / kWG];
+    uint64_t key_fwd[kTile / kWG];
+#pragma unroll
+    for (int j = 0; j < kTile / kWG; j++) {
+        const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
+        WaveWords w;
+        wave_load(R, pb, w);
+        bool valid = wave_window(w, pb, lane, R.k, R.n_bases, key_fwd[j]);
+        f[j] = valid ? flags[pb + lane] : 0u;
+        uint64_t md = __ballot(f[j] != 0);
+        uint64_t mt = __ballot(f[j] == 3);
+        if (lane == 0) {
+            s_md[j * (kWG / 64) + wave] = md;
+            s_mt[j * (kWG / 64) + wave] = mt;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int j = 0; j < kTile / kWG; j++) {
+        if (f[j] == 0)
+            continue;
+        const int widx = j * (kWG / 64) + (int)wave;
+        uint64_t rd = 0, rt = 0;
+        for (int q = 0; q < widx; q++) {
+            rd += (uint64_t)__popcll(s_md[q]);
+            rt += (uint64_t)__popcll(s_mt[q]);
+        }
+        rd += (uint64_t)__popcll(s_md[widx] & lt);
+        rt += (uint64_t)__popcll(s_mt[widx] & lt);
+        const uint64_t key = canonical_fast(key_fwd[j], R.k).key;
+        const uint64_t d = off_d[blockIdx.x] + rd;
+        if (d < cap_d)
+            distinct[d] = key;
+        if (split) {
+            const uint64_t ti = off_t[blockIdx.x] + rt;  // trustworthy keys before this one
+            const uint64_t ei = (d - *call_base) - ti;   // erroneous keys before this one
+            if (f[j] == 3) {
+                if (ti < cap_te)
+                    trust[ti] = key;
+            } else if (ei < cap_te) {
+                err[ei] = key;
+            }
+        }
+    }
+}
+
+// totals[0] distinct, [1] trustworthy, [2] valid windows of this call
 __global__ void k_finish_insert(uint64_t *__restrict__ n_distinct, uint64_t *__restrict__ n_windows,
-                                const uint64_t *__restrict__ totals, uint64_t cap,
-                                uint32_t *__restrict__ status) {
+                                uint64_t *__restrict__ n_trust, uint64_t *__restrict__ n_err,
+                                const uint64_t *__restrict__ totals, uint64_t cap_d,
+                                uint64_t cap_te, uint32_t *__restrict__ status) {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
-    uint64_t nd = *n_distinct + totals[0];
+    const uint64_t nd = *n_distinct + totals[0];
     *n_distinct = nd;
     if (n_windows)
-        *n_windows += totals[1];
-    if (nd > cap)
+        *n_windows += totals[2];
+    bool over = nd > cap_d;
+    if (n_trust) {
+        *n_trust = totals[1];
+        *n_err = totals[0] - totals[1];
+        over = over || totals[1] > cap_te || totals[0] - totals[1] > cap_te;
+    }
+    if (over)
         atomicOr(status, kStatusRange);
+}
+
+// copies *src to *dst (device scalars), so that a later kernel sees a value
+// as it was at this point of the stream
+__global__ void k_copy_u64(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dst = *src;
 }
 
 // ---------------------------------------------------------------------------
@@ -301,13 +312,24 @@ __device__ __forceinline__ uint64_t query_key(const FilterArgs &F, uint64_t key)
     return best;
 }
 
+// keys used: keys[b .. e), b = *key_base (0 when null), e = min(*n_keys, limit)
+__device__ __forceinline__ uint64_t key_count(const uint64_t *n_keys, const uint64_t *key_base,
+                                              uint64_t limit, uint64_t &b) {
+    b = key_base ? *key_base : 0;
+    const uint64_t e = *n_keys < limit ? *n_keys : limit;
+    return e > b ? e - b : 0;
+}
+
 __global__ void __launch_bounds__(kWG) k_classify_mark(FilterArgs F, const uint64_t *__restrict__ keys,
                                                        const uint64_t *__restrict__ n_keys,
+                                                       const uint64_t *__restrict__ key_base,
                                                        uint64_t cap, uint32_t tau,
                                                        uint64_t *__restrict__ tmask,
                                                        uint32_t *__restrict__ tile_trust) {
     __shared__ uint32_t s_cnt[kWG / 64];
-    const uint64_t n = *n_keys < cap ? *n_keys : cap;
+    uint64_t b;
+    const uint64_t n = key_count(n_keys, key_base, cap, b);
+    keys += b;
     const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
@@ -342,12 +364,16 @@ __global__ void __launch_bounds__(kWG) k_classify_mark(FilterArgs F, const uint6
 
 __global__ void __launch_bounds__(kWG) k_classify_scatter(const uint64_t *__restrict__ keys,
                                                           const uint64_t *__restrict__ n_keys,
+                                                          const uint64_t *__restrict__ key_base,
                                                           uint64_t cap,
                                                           const uint64_t *__restrict__ tmask,
                                                           const uint64_t *__restrict__ tile_off,
                                                           uint64_t *__restrict__ trust,
-                                                          uint64_t *__restrict__ err) {
-    const uint64_t n = *n_keys < cap ? *n_keys : cap;
+                                                          uint64_t *__restrict__ err,
+                                                          uint64_t cap_out) {
+    uint64_t b;
+    const uint64_t n = key_count(n_keys, key_base, cap, b);
+    keys += b;
     const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     if (tile0 >= n)
         return;
@@ -367,21 +393,28 @@ __global__ void __launch_bounds__(kWG) k_classify_scatter(const uint64_t *__rest
             before += (uint64_t)__popcll(fw[w]);
         before += (uint64_t)__popcll(word & ((1ull << lane) - 1ull));
         uint64_t t_idx = base + before;  // trustworthy keys before i
-        if ((word >> lane) & 1ull)
-            trust[t_idx] = keys[i];
-        else
+        if ((word >> lane) & 1ull) {
+            if (t_idx < cap_out)
+                trust[t_idx] = keys[i];
+        } else if (i - t_idx < cap_out) {
             err[i - t_idx] = keys[i];
+        }
     }
 }
 
-__global__ void k_finish_classify(const uint64_t *__restrict__ n_keys, uint64_t cap,
+__global__ void k_finish_classify(const uint64_t *__restrict__ n_keys,
+                                  const uint64_t *__restrict__ key_base, uint64_t cap,
                                   const uint64_t *__restrict__ totals,
-                                  uint64_t *__restrict__ n_trust, uint64_t *__restrict__ n_err) {
+                                  uint64_t *__restrict__ n_trust, uint64_t *__restrict__ n_err,
+                                  uint64_t cap_out, uint32_t *__restrict__ status) {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
-    const uint64_t n = *n_keys < cap ? *n_keys : cap;
+    uint64_t b;
+    const uint64_t n = key_count(n_keys, key_base, cap, b);
     *n_trust = totals[0];
     *n_err = n - totals[0];
+    if (status && (totals[0] > cap_out || n - totals[0] > cap_out))
+        atomicOr(status, kStatusRange);
 }
 
 __global__ void k_query(FilterArgs F, const uint64_t *__restrict__ keys, uint64_t n,
@@ -437,6 +470,8 @@ hipError_t launch_ingest(const uint8_t *reads, uint64_t n_bases, const uint64_t 
     if (P)
         P->begin(kPhIngest, s);
     hipError_t e = fill_u32(W.rs, n_mask, 0u, s);
+    if (e == hipSuccess)  // flag bytes of every tile of the call
+        e = fill_u32((uint32_t *)W.flags8, tiles(n_bases) * (kTile / 4), 0u, s);
     if (e == hipSuccess) {
         int aligned = ((uintptr_t)reads & 15u) == 0;
         hipLaunchKernelGGL(k_ingest, dim3(grid_for(n_mask, 256)), dim3(256), 0, s, reads,
@@ -466,49 +501,71 @@ hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     }
     if (e != hipSuccess)
         return e;
-    return launch(P, kPhResolve, k_resolve, grid, block, s, F, R, c0, c1, W.flags, W.tile_a,
-                  W.tile_b);
+    return launch(P, kPhResolve, k_resolve, grid, block, s, F, R, c0, c1, W.flags8);
 }
 
 hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *distinct,
-                           uint64_t cap, uint64_t *n_distinct, uint64_t *n_windows,
-                           uint32_t *status, hipStream_t s, Profiler *P) {
-    uint64_t n_tiles = (R.n_bases + kTile - 1) / kTile;
-    hipError_t e = launch(P, kPhScan, k_scan, dim3(1), dim3(kScanWG), s,
-                          (const uint32_t *)W.tile_a, (const uint32_t *)W.tile_b, n_tiles,
-                          W.tile_off, (const uint64_t *)n_distinct, W.totals);
+                           uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows,
+                           uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                           uint64_t cap_te, uint32_t *status, hipStream_t s, Profiler *P) {
+    const uint64_t n_tiles = tiles(R.n_bases);
+    const bool split = trust != nullptr;
+    hipError_t e = launch(P, kPhTileCount, k_tile_count, dim3((unsigned)n_tiles), dim3(kWG), s, R,
+                          (const uint8_t *)W.flags8, W.tile_a, W.tile_b, W.tile_c);
+    if (P)
+        P->begin(kPhScan, s);
     if (e == hipSuccess)
-        e = launch(P, kPhScatter, k_scatter_distinct, dim3((unsigned)n_tiles), dim3(kWG), s, R,
-                   (uint64_t)0, (const uint64_t *)W.flags, (const uint64_t *)W.tile_off, distinct,
-                   cap);
+        e = scan_u32_u64(W.tile_a, W.off_a, n_tiles, n_distinct, W.totals + 0, W.partial64, s);
+    if (e == hipSuccess && split)
+        e = scan_u32_u64(W.tile_b, W.off_b, n_tiles, nullptr, W.totals + 1, W.partial64, s);
+    if (e == hipSuccess)
+        e = scan_u32_u64(W.tile_c, W.off_c, n_tiles, nullptr, W.totals + 2, W.partial64, s);
+    if (e == hipSuccess) {  // the call's first distinct index, before k_finish_insert moves it
+        hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, (const uint64_t *)n_distinct,
+                           W.totals + 3);
+        e = hipGetLastError();
+    }
+    if (P)
+        P->end(s);
+    if (e == hipSuccess)
+        e = launch(P, kPhScatter, k_compact, dim3((unsigned)n_tiles), dim3(kWG), s, R,
+                   (const uint8_t *)W.flags8, (const uint64_t *)W.off_a,
+                   (const uint64_t *)W.off_b, (const uint64_t *)(W.totals + 3), distinct, cap_d,
+                   trust, err, cap_te, split ? 1 : 0);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_finish_insert, dim3(1), dim3(64), 0, s, n_distinct, n_windows,
-                           (const uint64_t *)W.totals, cap, status);
+                           split ? n_trust : (uint64_t *)nullptr, n_err,
+                           (const uint64_t *)W.totals, cap_d, cap_te, status);
         e = hipGetLastError();
     }
     return e;
 }
 
 hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint64_t *n_keys,
-                           uint64_t cap, uint32_t tau, uint64_t *trust, uint64_t *n_trust,
-                           uint64_t *err, uint64_t *n_err, const Workspace &W, hipStream_t s,
-                           Profiler *P) {
-    uint64_t n_tiles = (cap + kTile - 1) / kTile;
+                           const uint64_t *key_base, uint64_t grid_cap, uint64_t cap,
+                           uint32_t tau, uint64_t *trust, uint64_t *n_trust, uint64_t *err,
+                           uint64_t *n_err, uint64_t cap_out, uint32_t *status,
+                           const Workspace &W, hipStream_t s, Profiler *P) {
+    // `cap` bounds the key buffer (keys[.. cap)); grid_cap >= the number of
+    // keys classified sizes the grid
+    uint64_t n_tiles = (grid_cap + kTile - 1) / kTile;
     if (n_tiles == 0)
         n_tiles = 1;
     hipError_t e = launch(P, kPhClassifyMark, k_classify_mark, dim3((unsigned)n_tiles), dim3(kWG),
-                          s, F, keys, n_keys, cap, tau, W.flags, W.tile_a);
+                          s, F, keys, n_keys, key_base, cap, tau, W.tmask, W.tile_a);
+    if (P)
+        P->begin(kPhScan, s);
     if (e == hipSuccess)
-        e = launch(P, kPhScan, k_scan, dim3(1), dim3(kScanWG), s, (const uint32_t *)W.tile_a,
-                   (const uint32_t *)nullptr, n_tiles, W.tile_off, (const uint64_t *)nullptr,
-                   W.totals);
+        e = scan_u32_u64(W.tile_a, W.off_a, n_tiles, nullptr, W.totals + 4, W.partial64, s);
+    if (P)
+        P->end(s);
     if (e == hipSuccess)
         e = launch(P, kPhClassifyScatter, k_classify_scatter, dim3((unsigned)n_tiles), dim3(kWG),
-                   s, keys, n_keys, cap, (const uint64_t *)W.flags,
-                   (const uint64_t *)W.tile_off, trust, err);
+                   s, keys, n_keys, key_base, cap, (const uint64_t *)W.tmask,
+                   (const uint64_t *)W.off_a, trust, err, cap_out);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_finish_classify, dim3(1), dim3(64), 0, s, n_keys, cap,
-                           (const uint64_t *)W.totals, n_trust, n_err);
+        hipLaunchKernelGGL(k_finish_classify, dim3(1), dim3(64), 0, s, n_keys, key_base, cap,
+                           (const uint64_t *)(W.totals + 4), n_trust, n_err, cap_out, status);
         e = hipGetLastError();
     }
     return e;

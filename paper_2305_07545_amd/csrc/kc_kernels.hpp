@@ -10,53 +10,92 @@
 
 namespace kc {
 
-constexpr int kTile = 1024;    // positions (or keys) per workgroup
-constexpr int kWG = 256;       // threads per workgroup (4 wavefronts of 64)
-constexpr int kScanWG = 1024;  // threads of the single-workgroup scan
+constexpr int kTile = 1024;    // positions (or keys) per workgroup of the tile kernels
+constexpr int kWG = 256;       // threads per workgroup of the tile kernels
 constexpr uint32_t kStatusRange = 1u;  // sticky device status: an output overflowed
 
-// Largest chunk of positions resolved at once: occurrence indices t = p - c0
-// must stay below kIdle.  A multiple of kTile.
+// Direct path: positions resolved per first-seen chunk (t = p - c0 < 2^32).
 constexpr uint64_t kChunk = 1ull << 31;
 
-// Per-call workspace (device memory owned by the handle).
+// Binned path
+constexpr int kBinWG = 512;                  // threads per bin workgroup
+constexpr uint64_t kBinTileMin = 65536;      // positions per bin workgroup (at least)
+constexpr int kRegionWG = 1024;              // threads per region workgroup
+constexpr int kRegionCounters = 16384;       // counters per region: hits + first = 128 KiB LDS
+constexpr uint32_t kMaxRegions = 16384;      // LDS histogram of the bin kernels: 64 KiB
+constexpr uint64_t kMaxMatrix = 1ull << 25;  // (region, bin workgroup) counts per chunk
+constexpr uint64_t kBinChunk = 1ull << 28;   // positions per binned chunk (entries < 2^31)
+
+struct BinPlan {
+    uint32_t region_shift;  // log2(words per region)
+    uint32_t n_regions;
+    uint32_t G;             // bin workgroups of the chunk
+    uint64_t tile;          // positions per bin workgroup (multiple of kBinWG)
+    uint64_t entries_cap;   // capacity of the entry list
+};
+
+// Per-handle workspace (device memory owned by the handle).
 struct Workspace {
+    // per-position buffers of an insert call (cap positions)
     uint32_t *codes = nullptr;    // code_words(cap) 2-bit packed bases
     uint32_t *inv = nullptr;      // mask_words(cap) invalid-base bits
     uint32_t *rs = nullptr;       // mask_words(cap) read-start bits
-    uint64_t *flags = nullptr;    // flag_words(cap) distinct / trustworthy bits
-    uint32_t *tile_a = nullptr;   // tiles(cap) per-tile counts
-    uint32_t *tile_b = nullptr;   // tiles(cap) per-tile counts
-    uint64_t *tile_off = nullptr; // tiles(cap) scanned offsets
-    uint64_t *totals = nullptr;   // 2 scan totals
-    uint64_t cap = 0;             // positions (bases or keys) the buffers hold
+    uint8_t *flags8 = nullptr;    // tiles(cap)*kTile flag bytes
+    uint64_t cap = 0;
+    // per-tile buffers (tile_cap tiles of positions or keys)
+    uint32_t *tile_a = nullptr, *tile_b = nullptr, *tile_c = nullptr;
+    uint64_t *off_a = nullptr, *off_b = nullptr, *off_c = nullptr;
+    uint64_t *tmask = nullptr;    // tile_cap * kTile / 64 classification bits
+    uint64_t *partial64 = nullptr;
+    uint64_t tile_cap = 0;
+    // binned path (per chunk)
+    uint32_t *matrix = nullptr;   // matrix_cap counts, scanned in place to offsets
+    uint32_t *partial32 = nullptr;
+    uint64_t matrix_cap = 0;
+    uint64_t *entries = nullptr;  // entries_cap (t << 32 | local counter)
+    uint64_t entries_cap = 0;
+    // scalars
+    uint64_t *totals = nullptr;   // 8 scan totals / saved counters
+    uint32_t *n_entries = nullptr;
 };
 
 inline uint64_t tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
 inline uint64_t mask_words(uint64_t n) { return tiles(n) * (kTile / 32) + 2; }
 inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
-inline uint64_t flag_words(uint64_t n) { return tiles(n) * (kTile / 64); }
-
-hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
-hipError_t fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
 // Phase ids for the profiler (same values as kc_phase in kmerco.h).
 enum Phase {
     kPhIngest = 0, kPhClaim, kPhIncrement, kPhClaimIncrement, kPhResolve, kPhScan, kPhScatter,
-    kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhCount
+    kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhBinCount, kPhBinWrite, kPhRegion,
+    kPhTileCount, kPhCount
 };
+
+hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+
+uint64_t scan_partials(uint64_t n);
+hipError_t scan_u32_u64(const uint32_t *in, uint64_t *out, uint64_t n, const uint64_t *base,
+                        uint64_t *total, uint64_t *partial, hipStream_t s);
+hipError_t scan_u32_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total,
+                        uint32_t *partial, hipStream_t s);
 
 hipError_t launch_ingest(const uint8_t *reads, uint64_t n_bases, const uint64_t *offsets,
                          uint64_t n_reads, const Workspace &W, hipStream_t s, Profiler *P);
 hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                bool zero_filter, const Workspace &W, hipStream_t s, Profiler *P);
+bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B);
+hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
+                               const BinPlan &plan, const Workspace &W, bool classify,
+                               uint32_t tau, hipStream_t s, Profiler *P);
 hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *distinct,
-                           uint64_t cap, uint64_t *n_distinct, uint64_t *n_windows,
-                           uint32_t *status, hipStream_t s, Profiler *P);
+                           uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows,
+                           uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                           uint64_t cap_te, uint32_t *status, hipStream_t s, Profiler *P);
 hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint64_t *n_keys,
-                           uint64_t cap, uint32_t tau, uint64_t *trust, uint64_t *n_trust,
-                           uint64_t *err, uint64_t *n_err, const Workspace &W, hipStream_t s,
-                           Profiler *P);
+                           const uint64_t *key_base, uint64_t grid_cap, uint64_t cap,
+                           uint32_t tau, uint64_t *trust, uint64_t *n_trust, uint64_t *err,
+                           uint64_t *n_err, uint64_t cap_out, uint32_t *status,
+                           const Workspace &W, hipStream_t s, Profiler *P);
 hipError_t launch_query(const FilterArgs &F, const uint64_t *keys, uint64_t n, uint32_t *freq,
                         hipStream_t s, Profiler *P);
 

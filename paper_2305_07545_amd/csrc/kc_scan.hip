@@ -1,0 +1,138 @@
+// Multi-workgroup exclusive prefix sums (reduce -> scan of block sums ->
+// rescan with block offsets) used for the ordered outputs and the bin
+// offsets.
+#include <hip/hip_runtime.h>
+
+#include "kc_kernels.hpp"
+
+namespace kc {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanBlock = kScanThreads * kScanPer;  // elements per workgroup
+constexpr int kTopThreads = 1024;
+
+template <typename T>
+__device__ __forceinline__ T wg_exclusive_sum(T v, T *s_tmp, T &total) {
+    // s_tmp: kScanThreads entries.  Hillis-Steele over the workgroup.
+    const int tid = threadIdx.x;
+    s_tmp[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        T add = tid >= d ? s_tmp[tid - d] : (T)0;
+        __syncthreads();
+        s_tmp[tid] += add;
+        __syncthreads();
+    }
+    total = s_tmp[kScanThreads - 1];
+    T incl = s_tmp[tid];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename TIn, typename TOut>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const TIn *__restrict__ in, uint64_t n,
+                                                             TOut *__restrict__ partial) {
+    __shared__ TOut s[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+    TOut sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; i++)
+        if (base + i < n)
+            sum += (TOut)in[base + i];
+    TOut total;
+    (void)wg_exclusive_sum<TOut>(sum, s, total);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = total;
+}
+
+// One workgroup: partial[b] <- base + sum(partial[0..b)), *total <- sum.
+template <typename TOut>
+__global__ void __launch_bounds__(kTopThreads) k_scan_top(TOut *__restrict__ partial, uint64_t nb,
+                                                         const TOut *__restrict__ base,
+                                                         TOut *__restrict__ total) {
+    __shared__ TOut s[kTopThreads];
+    const uint64_t per = (nb + kTopThreads - 1) / kTopThreads;
+    const uint64_t lo = per * threadIdx.x;
+    const uint64_t hi = lo + per < nb ? lo + per : nb;
+    TOut sum = 0;
+    for (uint64_t i = lo; i < hi; i++)
+        sum += partial[i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < kTopThreads; d <<= 1) {
+        TOut add = threadIdx.x >= (unsigned)d ? s[threadIdx.x - d] : (TOut)0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    TOut run = (base ? *base : (TOut)0) + s[threadIdx.x] - sum;
+    for (uint64_t i = lo; i < hi; i++) {
+        TOut v = partial[i];
+        partial[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == kTopThreads - 1 && total)
+        *total = s[kTopThreads - 1];
+}
+
+template <typename TIn, typename TOut>
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(const TIn *__restrict__ in, uint64_t n,
+                                                           const TOut *__restrict__ partial,
+                                                           TOut *__restrict__ out) {
+    __shared__ TOut s[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+    TOut v[kScanPer];
+    TOut sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; i++) {
+        v[i] = base + i < n ? (TOut)in[base + i] : (TOut)0;
+        sum += v[i];
+    }
+    TOut total;
+    TOut run = partial[blockIdx.x] + wg_exclusive_sum<TOut>(sum, s, total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; i++) {
+        if (base + i < n)
+            out[base + i] = run;
+        run += v[i];
+    }
+}
+
+template <typename TIn, typename TOut>
+hipError_t scan_impl(const TIn *in, TOut *out, uint64_t n, const TOut *base, TOut *total,
+                     TOut *partial, hipStream_t s) {
+    uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 0)
+        nb = 1;
+    hipLaunchKernelGGL((k_scan_reduce<TIn, TOut>), dim3((unsigned)nb), dim3(kScanThreads), 0, s,
+                       in, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_scan_top<TOut>), dim3(1), dim3(kTopThreads), 0, s, partial, nb, base,
+                       total);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_scan_down<TIn, TOut>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
+                       n, (const TOut *)partial, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint64_t scan_partials(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+hipError_t scan_u32_u64(const uint32_t *in, uint64_t *out, uint64_t n, const uint64_t *base,
+                        uint64_t *total, uint64_t *partial, hipStream_t s) {
+    return scan_impl<uint32_t, uint64_t>(in, out, n, base, total, partial, s);
+}
+
+hipError_t scan_u32_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total,
+                        uint32_t *partial, hipStream_t s) {
+    return scan_impl<uint32_t, uint32_t>(in, out, n, (const uint32_t *)nullptr, total, partial, s);
+}
+
+}  // namespace kc

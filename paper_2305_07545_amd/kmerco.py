@@ -49,6 +49,8 @@ SIGNATURES = {
     "kc_reserve": (_i, [_vp, _u64]),
     "kc_insert": (_i, [_vp, _vp, _vp, _u64, _u64, _u32, _vp, _u64, _vp, _vp, _vp]),
     "kc_classify": (_i, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "kc_insert_classify": (_i, [_vp, _vp, _vp, _u64, _u64, _u32, _u32, _vp, _u64, _vp, _vp,
+                                _vp, _vp, _vp, _vp, _u64, _vp]),
     "kc_query": (_i, [_vp, _vp, _u64, _vp, _vp]),
     "kc_sync": (_i, [_vp]),
     "kc_get_layout": (_i, [_vp, ctypes.POINTER(kc_layout)]),
@@ -59,7 +61,8 @@ SIGNATURES = {
 }
 
 PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
-          "classify_mark", "classify_scatter", "query", "reset"]
+          "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_write",
+          "region", "tile_count"]
 
 
 def load_library():
@@ -186,6 +189,42 @@ class CountBF:
                                       _stream_ptr(stream)), "kc_insert")
         return distinct
 
+    def insert_classify(self, reads, offsets, k: int, tau: int, distinct=None, trust=None,
+                        err=None, n_distinct=None, n_windows=None, n_trust=None, n_err=None,
+                        class_cap=None, stream=None):
+        """Both phases for one read batch (async): insertion, then the split
+        of this call's distinct keys at tau.  Returns (distinct, trust,
+        n_trust, err, n_err)."""
+        _require(reads, torch.uint8, "reads")
+        _require(offsets, torch.int64, "offsets")
+        n_reads = offsets.numel() - 1
+        n_bases = reads.numel()
+        if n_reads < 0:
+            raise ValueError("offsets needs n_reads + 1 entries")
+        room = max(1, n_bases)
+        if distinct is None:
+            distinct = torch.empty(room, dtype=torch.int64, device=self.device)
+        if trust is None:
+            trust = torch.empty(room, dtype=torch.int64, device=self.device)
+        if err is None:
+            err = torch.empty(room, dtype=torch.int64, device=self.device)
+        for t, nm in ((distinct, "distinct"), (trust, "trust"), (err, "err")):
+            _require(t, torch.int64, nm)
+        cap_te = min(trust.numel(), err.numel()) if class_cap is None else int(class_cap)
+        n_distinct = self.n_distinct if n_distinct is None else n_distinct
+        n_windows = self.n_windows if n_windows is None else n_windows
+        if n_trust is None:
+            n_trust = torch.zeros(1, dtype=torch.int64, device=self.device)
+        if n_err is None:
+            n_err = torch.zeros(1, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_insert_classify(
+                self._h, _ptr(reads), _ptr(offsets), n_reads, n_bases, k, int(tau),
+                _ptr(distinct), distinct.numel(), _ptr(n_distinct), _ptr(n_windows),
+                _ptr(trust), _ptr(n_trust), _ptr(err), _ptr(n_err), cap_te,
+                _stream_ptr(stream)), "kc_insert_classify")
+        return distinct, trust, n_trust, err, n_err
+
     def classify(self, keys, n_keys, tau: int, trust=None, err=None, n_trust=None, n_err=None,
                  keys_cap=None, stream=None):
         """Classification phase (async); returns (trust, n_trust, err, n_err)
@@ -240,12 +279,17 @@ class CountBF:
 
 
 def run_kmerco(reads, offsets, k: int, tau: int, X: int, Y: int, alpha: int = 8, k_h: int = 1,
-               stream=None):
+               stream=None, fused: bool = True):
     """Both phases on a fresh countBF.  Returns host numpy arrays
-    (words, distinct, trust, err, n_windows) as uint64."""
+    (words, distinct, trust, err, n_windows) as uint64.  fused: one
+    kc_insert_classify call; else kc_insert then kc_classify."""
     bf = CountBF(X, Y, alpha, k_h, stream=stream)
-    distinct = bf.insert(reads, offsets, k, stream=stream)
-    trust, n_trust, err, n_err = bf.classify(distinct, bf.n_distinct, tau, stream=stream)
+    if fused:
+        distinct, trust, n_trust, err, n_err = bf.insert_classify(reads, offsets, k, tau,
+                                                                  stream=stream)
+    else:
+        distinct = bf.insert(reads, offsets, k, stream=stream)
+        trust, n_trust, err, n_err = bf.classify(distinct, bf.n_distinct, tau, stream=stream)
     bf.sync()
     nd = int(bf.n_distinct.item())
     nt = int(n_trust.item())

@@ -50,3 +50,21 @@ int kch_base(uint32_t b, uint32_t *code) {
     return kc::base_valid(b, *code) ? 1 : 0;
 }
 }
+
+extern "C" {
+
+int kch_wave_window(const uint32_t *codes, const uint32_t *inv, const uint32_t *rs,
+                    uint64_t n_bases, uint32_t k, uint64_t p, uint64_t *fwd) {
+    kc::ReadsArgs R{codes, inv, rs, n_bases, k};
+    const uint64_t pb = p & ~63ull;
+    kc::WaveWords w;
+    kc::wave_load(R, pb, w);
+    return kc::wave_window(w, pb, (uint32_t)(p - pb), k, n_bases, *fwd) ? 1 : 0;
+}
+
+uint64_t kch_canonical_fast(uint64_t fwd, uint32_t K, uint64_t *h1) {
+    kc::Canon c = kc::canonical_fast(fwd, K);
+    *h1 = c.h1;
+    return c.key;
+}
+}

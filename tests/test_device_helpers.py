@@ -34,6 +34,10 @@ def H(tmp_path_factory):
     L.kch_slot.argtypes = [u64, u64, u32, u64, ctypes.POINTER(u64), ctypes.POINTER(u32)]
     L.kch_slot.restype = None
     L.kch_base.argtypes = [u32, ctypes.POINTER(u32)]; L.kch_base.restype = ctypes.c_int
+    L.kch_wave_window.argtypes = [p32, p32, p32, u64, u32, u64, ctypes.POINTER(u64)]
+    L.kch_wave_window.restype = ctypes.c_int
+    L.kch_canonical_fast.argtypes = [u64, u32, ctypes.POINTER(u64)]
+    L.kch_canonical_fast.restype = u64
     return L
 
 
@@ -90,6 +94,9 @@ def test_revcomp_and_canonical(H):
             h1 = ctypes.c_uint64()
             assert H.kch_canonical(f, K, ctypes.byref(h1)) == brute.canonical_str(s)
             assert h1.value == min(brute.h64(f), brute.h64(r)) or f == r
+            h1f = ctypes.c_uint64()
+            assert H.kch_canonical_fast(f, K, ctypes.byref(h1f)) == brute.canonical_str(s)
+            assert h1f.value == h1.value
 
 
 def _pack(seq: bytes, starts):
@@ -134,3 +141,8 @@ def test_window_extraction_matches_brute_force(H):
             assert v == (p in valid), (K, p)
             if v:
                 assert H.kch_window_key(P(codes), p, K) == brute.key_of(buf[p:p + K].decode())
+            fw = ctypes.c_uint64()
+            wv = H.kch_wave_window(P(codes), P(inv), P(rs), len(buf), K, p, ctypes.byref(fw))
+            assert wv == v, (K, p)
+            if v:
+                assert fw.value == brute.key_of(buf[p:p + K].decode())

@@ -36,10 +36,10 @@ def dev(rs):
     return reads, offs
 
 
-def gpu_run(rs, X, Y, alpha=8, k_h=1, k=None, tau=None):
+def gpu_run(rs, X, Y, alpha=8, k_h=1, k=None, tau=None, fused=True):
     reads, offs = dev(rs)
     return P.run_kmerco(reads, offs, rs.k if k is None else k, rs.tau if tau is None else tau,
-                        X, Y, alpha, k_h)
+                        X, Y, alpha, k_h, fused=fused)
 
 
 def cpu_run(rs, X, Y, alpha=8, k_h=1, k=None, tau=None):
@@ -60,13 +60,21 @@ def assert_same(g, c, what=""):
     assert g[4] == c[4], f"{what} n_windows {g[4]} != {c[4]}"
 
 
-def check(rs, X, Y, alpha=8, k_h=1, k=None, tau=None, what=""):
+def check(rs, X, Y, alpha=8, k_h=1, k=None, tau=None, what="", fused=True):
     print(f"case {what}: {rs.name} X={X} Y={Y} alpha={alpha} k_h={k_h} k={k or rs.k} "
-          f"bases={rs.n_bases}", flush=True)
-    g = gpu_run(rs, X, Y, alpha, k_h, k, tau)
+          f"bases={rs.n_bases} path={os.environ.get('KMERCO_PATH', 'auto')} fused={fused}",
+          flush=True)
+    g = gpu_run(rs, X, Y, alpha, k_h, k, tau, fused)
     c = cpu_run(rs, X, Y, alpha, k_h, k, tau)
     assert_same(g, c, what)
     return g
+
+
+@pytest.fixture(params=["binned", "direct"])
+def path(request, monkeypatch):
+    """Insertion path forced for the handles created in the test."""
+    monkeypatch.setenv("KMERCO_PATH", request.param)
+    return request.param
 
 
 # ---------------------------------------------------------------------------
@@ -116,27 +124,28 @@ def test_bacterial_full_size_digests():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("k", [1, 2, 7, 16, 21, 31, 32])
-def test_ragged_reads_all_k(k):
+def test_ragged_reads_all_k(k, path):
     rs = synth.random_reads(100 + k, 700, 1, 400, k=k, tau=2, p_n=0.01, p_other=0.005)
     check(rs, 257, 263, k=k, what=f"ragged k={k}")
+    check(rs, 257, 263, k=k, what=f"ragged k={k} unfused", fused=False)
 
 
 @pytest.mark.parametrize("alpha,k_h", [(8, 1), (8, 2), (8, 3), (4, 1), (4, 3), (5, 2), (7, 1),
                                        (12, 2), (16, 1), (21, 1), (32, 2), (1, 1), (3, 8)])
-def test_heavy_collisions(alpha, k_h):
-    """A 3 x 5 filter: every cell is hit thousands of times (CAS contention,
+def test_heavy_collisions(alpha, k_h, path):
+    """A 3 x 5 filter: every cell is hit thousands of times (contention,
     saturation, first-seen between colliding k-mers)."""
     rs = synth.random_reads(200 + alpha * 10 + k_h, 300, 20, 200, k=9, tau=3, p_n=0.01)
     check(rs, 3, 5, alpha=alpha, k_h=k_h, what=f"collide a={alpha} kh={k_h}")
 
 
 @pytest.mark.parametrize("alpha,k_h", [(8, 2), (6, 3), (16, 4), (10, 1)])
-def test_medium_filters_multi_hash(alpha, k_h):
+def test_medium_filters_multi_hash(alpha, k_h, path):
     rs = synth.random_reads(300 + alpha + k_h, 2000, 50, 300, k=25, tau=2, p_n=0.002)
     check(rs, 211, 223, alpha=alpha, k_h=k_h, what=f"medium a={alpha} kh={k_h}")
 
 
-def test_low_complexity_saturation():
+def test_low_complexity_saturation(path):
     """Two-letter reads: few distinct k-mers, counters saturate."""
     rs = synth.random_reads(401, 3000, 100, 250, k=11, tau=5, alphabet=b"AC")
     check(rs, 101, 103, what="AC alphabet")
@@ -144,13 +153,16 @@ def test_low_complexity_saturation():
     check(homo, 7, 11, what="homopolymers")
 
 
-def test_multi_chunk(monkeypatch):
-    """First-seen resolved in many chunks (chunk size forced small)."""
+def test_multi_chunk(monkeypatch, path):
+    """First-seen resolved in many chunks (chunk size forced small); the
+    split of a multi-chunk call is classified after the insert."""
     monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "2048")
     rs = synth.random_reads(501, 500, 30, 300, k=13, tau=2, alphabet=b"ACGT", p_n=0.01)
     check(rs, 31, 37, k_h=2, what="chunk 2048")
     monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "1024")
     check(rs, 97, 101, what="chunk 1024")
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "5000")
+    check(rs, 211, 223, what="chunk 4096")
 
 
 def test_unaligned_reads_pointer():
@@ -168,7 +180,7 @@ def test_unaligned_reads_pointer():
 # calls and edge cases
 # ---------------------------------------------------------------------------
 
-def test_incremental_equals_concatenated():
+def test_incremental_equals_concatenated(path):
     parts = [synth.random_reads(700 + i, 200 + 50 * i, 15, 180, k=19, p_n=0.01) for i in range(3)]
     whole = synth.concat_reads(parts)
     X, Y = 61, 67
@@ -187,7 +199,7 @@ def test_incremental_equals_concatenated():
     assert_same(g, c, "incremental")
 
 
-def test_resume_from_existing_words():
+def test_resume_from_existing_words(path):
     """kc_create with zero=0 continues an existing countBF (general claim path)."""
     a = synth.random_reads(801, 300, 30, 150, k=15)
     b = synth.random_reads(802, 300, 30, 150, k=15)
@@ -205,7 +217,7 @@ def test_resume_from_existing_words():
     assert np.array_equal(distinct[:nd].cpu().numpy().view(np.uint64), db)
 
 
-def test_empty_and_degenerate_inputs():
+def test_empty_and_degenerate_inputs(path):
     X, Y = 13, 17
     # no bases at all
     bf = P.CountBF(X, Y)
@@ -240,6 +252,25 @@ def test_query_matches_oracle():
 def test_classify_thresholds(tau):
     rs = synth.random_reads(1001, 800, 30, 200, k=9, alphabet=b"ACGT")
     check(rs, 53, 59, tau=tau, what=f"tau={tau}")
+    check(rs, 53, 59, tau=tau, what=f"tau={tau} unfused", fused=False)
+
+
+def test_large_filter_uses_direct_path():
+    """A countBF beyond the binned path's region limit (33.6 M cells) is
+    filled by the direct path automatically."""
+    rs = synth.random_reads(1050, 300, 50, 200, k=21, p_n=0.01)
+    check(rs, 5801, 5807, what="large filter auto")
+
+
+def test_paths_agree_on_bacterial_sample(monkeypatch):
+    rs = synth.config("bacterial", scale=0.01)
+    X, Y = oracle.dims(rs.n_items)
+    monkeypatch.setenv("KMERCO_PATH", "direct")
+    a = gpu_run(rs, X, Y)
+    monkeypatch.setenv("KMERCO_PATH", "binned")
+    b = gpu_run(rs, X, Y)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
 
 
 def test_errors_and_capacity():
