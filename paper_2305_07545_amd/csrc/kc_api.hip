@@ -124,26 +124,39 @@ kc_status ensure_tiles(kc_filter *f, uint64_t n) {
 // binned-path buffers for one chunk of the given plan
 kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
     kc::Workspace &W = f->W;
-    uint64_t n_mat = (uint64_t)B.n_regions * B.G;
-    uint64_t n_ent = chunk_positions * f->layout.k_h;
-    if (W.matrix && n_mat <= W.matrix_cap && W.entries && n_ent <= W.entries_cap)
+    const uint64_t n_mat = (uint64_t)B.n_regions * B.G;
+    const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
+    const uint64_t n_slots = chunk_positions * f->layout.k_h;
+    const uint64_t n_ent = n_slots;
+    if (W.matrix && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap && n_slots <= W.slots_cap &&
+        n_ent <= W.entries_cap)
         return KC_OK;
     wait_idle(f);
-    if (!W.matrix || n_mat > W.matrix_cap) {
+    if (!W.matrix || n_mat > W.matrix_cap || n_coarse > W.coarse_cap) {
         dev_free(W.matrix);
+        dev_free(W.coarse);
         dev_free(W.partial32);
-        W.matrix_cap = 0;
-        if (!dev_alloc(&W.matrix, n_mat) || !dev_alloc(&W.partial32, kc::scan_partials(n_mat)))
+        W.matrix_cap = W.coarse_cap = 0;
+        if (!dev_alloc(&W.matrix, n_mat) || !dev_alloc(&W.coarse, n_coarse) ||
+            !dev_alloc(&W.partial32, kc::scan_partials(n_mat)))
             return KC_ENOMEM;
         W.matrix_cap = n_mat;
+        W.coarse_cap = n_coarse;
+    }
+    if (!W.slots || n_slots > W.slots_cap) {
+        dev_free(W.slots);
+        W.slots_cap = 0;
+        if (!dev_alloc(&W.slots, n_slots))
+            return KC_ENOMEM;
+        W.slots_cap = n_slots;
     }
     if (!W.entries || n_ent > W.entries_cap) {
         dev_free(W.entries);
+        dev_free(W.bucketed);
         W.entries_cap = 0;
-        uint64_t cap = n_ent + n_ent / 8;
-        if (!dev_alloc(&W.entries, cap))
+        if (!dev_alloc(&W.entries, n_ent) || !dev_alloc(&W.bucketed, n_ent))
             return KC_ENOMEM;
-        W.entries_cap = cap;
+        W.entries_cap = n_ent;
     }
     return KC_OK;
 }
@@ -151,7 +164,7 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
 kc_status ensure_scalars(kc_filter *f) {
     if (f->W.totals)
         return KC_OK;
-    if (!dev_alloc(&f->W.totals, 8) || !dev_alloc(&f->W.n_entries, 1))
+    if (!dev_alloc(&f->W.totals, 8) || !dev_alloc(&f->W.n_entries, 2))
         return KC_ENOMEM;
     return KC_OK;
 }
@@ -181,7 +194,10 @@ void free_all(kc_filter *f) {
     dev_free(W.tmask);
     dev_free(W.partial64);
     dev_free(W.matrix);
+    dev_free(W.coarse);
     dev_free(W.partial32);
+    dev_free(W.slots);
+    dev_free(W.bucketed);
     dev_free(W.entries);
     dev_free(W.totals);
     dev_free(W.n_entries);
@@ -266,6 +282,8 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         return st;
     }
     hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, f->W, s, &f->prof);
+    if (e == hipSuccess && binned)  // valid windows, accumulated by the bin passes
+        e = kc::fill_u64(f->W.totals + 5, 1, 0ull, s);
     if (e != hipSuccess)
         return KC_EDEVICE;
     kc::ReadsArgs R{f->W.codes, f->W.inv, f->W.rs, n_bases, k};
@@ -284,8 +302,8 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         f->zero = false;
     }
     e = kc::launch_distinct(R, f->W, distinct, cap_d, n_distinct, n_windows,
-                            fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status, s,
-                            &f->prof);
+                            fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status,
+                            binned, s, &f->prof);
     if (e != hipSuccess)
         return KC_EDEVICE;
     if (split && !fused) {

@@ -1,19 +1,27 @@
 // Binned insertion: the countBF update and the first-seen resolution done in
-// LDS, one workgroup per filter region, with no global atomics.
+// LDS, one workgroup per filter region, with no global atomics on counters.
 //
-// For one chunk of positions [c0, c1) (t = p - c0):
-//   bin_count   hash every valid window; per-workgroup LDS histogram of the
-//               regions its slots fall in -> count matrix [region][workgroup]
-//   (scan)      exclusive scan of the matrix in region-major order: the
-//               offset of every (region, workgroup) segment of the entry list
-//   bin_write   hash again; append (t, local counter) entries to the segments
+// A filter region is 2^shift consecutive cells whose eta*2^shift counters fit
+// the LDS arrays; a bucket is 2^bshift consecutive regions (at most 64
+// buckets).  For one chunk of positions [c0, c1) (t = p - c0):
+//   bin_count   hash every valid window once; store its slot id
+//               (region << 14 | local counter) per (position, hash function);
+//               per-workgroup LDS histograms of regions and of buckets
+//   (scans)     region-major scan of the region counts -> the offset of every
+//               (region, bin workgroup) segment of the final entry list;
+//               bucket-major scan of the bucket counts -> the same for the
+//               intermediate bucket list
+//   bin_bucket  read the slot ids; batches are counting-sorted by bucket in
+//               LDS and written as contiguous runs: entry = t << 32 | slot id
+//   bin_region  one workgroup per (bucket, slice of bin workgroups): move the
+//               slice's entries to their regions' segments
 //   region      one workgroup per region: in LDS, hits[c] += 1 and
 //               first[c] = min(first[c], t) over the region's entries; then
 //               counter = min(2^alpha - 1, old + hits) per counter, and the
 //               occurrence first[c] is distinct when the counter was zero
 //               before the chunk (the sequential Query-I result)
-// The order of entries inside a segment does not matter: sums and minima
-// are order-independent, so the outputs are deterministic.
+// Entry order inside a segment never matters: sums and minima are order-
+// independent, so the outputs are deterministic.
 #include <hip/hip_runtime.h>
 
 #include "kc_device.hpp"
@@ -27,72 +35,178 @@ __device__ __forceinline__ uint32_t wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
+constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
+
 }  // namespace
 
 __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                       uint64_t c1, BinPlan B,
-                                                      uint32_t *__restrict__ matrix) {
-    extern __shared__ uint32_t hist[];
-    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
-        hist[i] = 0;
+                                                      uint32_t *__restrict__ slots,
+                                                      uint32_t *__restrict__ fine,
+                                                      uint32_t *__restrict__ coarse,
+                                                      unsigned long long *__restrict__ n_valid) {
+    extern __shared__ uint32_t s_hist[];  // n_regions region counts, then kMaxBuckets
+    uint32_t *s_bucket = s_hist + B.n_regions;
+    __shared__ uint32_t s_valid;
+    for (uint32_t i = threadIdx.x; i < B.n_regions + kMaxBuckets; i += kBinWG)
+        s_hist[i] = 0;
+    if (threadIdx.x == 0)
+        s_valid = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t shift = B.region_shift;
+    const uint32_t bshift = B.bucket_shift;
+    const uint64_t len = c1 - c0;
     const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
     const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
+    const uint64_t smask = (1ull << shift) - 1ull;
+    uint32_t nv = 0;
     for (uint64_t pb = g0 + 64u * wave_id(); pb < g1; pb += kBinWG) {
         WaveWords w;
         wave_load(R, pb, w);
         uint64_t fwd;
-        bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd) && pb + lane < g1;
+        const uint64_t p = pb + lane;
+        const bool in = p < g1;
+        const bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd) && in;
         if (valid) {
+            nv++;
             const Canon c = canonical_fast(fwd, R.k);
             for (uint32_t a = 1; a <= F.k_h; a++) {
                 uint64_t word;
                 uint32_t l;
                 slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
-                atomicAdd(&hist[(uint32_t)(word >> shift)], 1u);
+                const uint32_t r = (uint32_t)(word >> shift);
+                const uint32_t id = (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
+                slots[(uint64_t)(a - 1) * len + (p - c0)] = id;
+                atomicAdd(&s_hist[r], 1u);
+                atomicAdd(&s_bucket[r >> bshift], 1u);
             }
+        } else if (in) {
+            for (uint32_t a = 1; a <= F.k_h; a++)
+                slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
         }
     }
+    atomicAdd(&s_valid, nv);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
-        matrix[(uint64_t)i * B.G + blockIdx.x] = hist[i];
+        fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
+    for (uint32_t i = threadIdx.x; i < B.n_buckets; i += kBinWG)
+        coarse[(uint64_t)i * B.G + blockIdx.x] = s_bucket[i];
+    if (threadIdx.x == 0)
+        atomicAdd(n_valid, (unsigned long long)s_valid);
 }
 
-__global__ void __launch_bounds__(kBinWG) k_bin_write(FilterArgs F, ReadsArgs R, uint64_t c0,
-                                                      uint64_t c1, BinPlan B,
-                                                      const uint32_t *__restrict__ offsets,
-                                                      uint64_t *__restrict__ entries) {
-    extern __shared__ uint32_t cursor[];
-    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
-        cursor[i] = offsets[(uint64_t)i * B.G + blockIdx.x];
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
-    const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
-    const uint32_t shift = B.region_shift;
-    const uint64_t smask = (1ull << shift) - 1ull;
+// Level 1: slot ids of this workgroup's positions -> runs of the bucket list.
+__global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1, uint32_t k_h,
+                                                       BinPlan B,
+                                                       const uint32_t *__restrict__ slots,
+                                                       const uint32_t *__restrict__ coarse_off,
+                                                       uint64_t *__restrict__ bucketed) {
+    __shared__ uint64_t s_stage[kStage];
+    __shared__ uint32_t s_cnt[kMaxBuckets];
+    __shared__ uint32_t s_start[kMaxBuckets];
+    __shared__ uint32_t s_fill[kMaxBuckets];
+    __shared__ uint32_t s_cursor[kMaxBuckets];
+    const uint32_t bshift = B.bucket_shift + kLocalBits;
+    const uint64_t len = c1 - c0;
+    const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;  // chunk-relative
+    const uint64_t g1 = g0 + B.tile < len ? g0 + B.tile : len;
+    const uint64_t batch = kStage / k_h;                   // positions per batch
     const uint64_t cap = B.entries_cap;
-    for (uint64_t pb = g0 + 64u * wave_id(); pb < g1; pb += kBinWG) {
-        WaveWords w;
-        wave_load(R, pb, w);
-        uint64_t fwd;
-        bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd) && pb + lane < g1;
-        if (valid) {
-            const Canon c = canonical_fast(fwd, R.k);
-            const uint64_t t = pb + lane - c0;
-            for (uint32_t a = 1; a <= F.k_h; a++) {
-                uint64_t word;
-                uint32_t l;
-                slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
-                uint32_t r = (uint32_t)(word >> shift);
-                uint32_t local = (l << shift) | (uint32_t)(word & smask);
-                uint32_t pos = atomicAdd(&cursor[r], 1u);
-                if (pos < cap)
-                    entries[pos] = (t << 32) | local;
+    for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
+        s_cursor[i] = i < B.n_buckets ? coarse_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
+        s_cnt[i] = 0;
+        s_fill[i] = 0;
+    }
+    __syncthreads();
+    for (uint64_t q0 = g0; q0 < g1; q0 += batch) {
+        const uint64_t q1 = q0 + batch < g1 ? q0 + batch : g1;
+        // count entries per bucket
+        for (uint64_t q = q0 + threadIdx.x; q < q1; q += kBinWG)
+            for (uint32_t a = 0; a < k_h; a++) {
+                const uint32_t id = slots[(uint64_t)a * len + q];
+                if (id != kNoSlot)
+                    atomicAdd(&s_cnt[id >> bshift], 1u);
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (uint32_t b = 0; b < kMaxBuckets; b++) {
+                s_start[b] = run;
+                run += s_cnt[b];
             }
         }
+        __syncthreads();
+        // stage the entries sorted by bucket
+        for (uint64_t q = q0 + threadIdx.x; q < q1; q += kBinWG)
+            for (uint32_t a = 0; a < k_h; a++) {
+                const uint32_t id = slots[(uint64_t)a * len + q];
+                if (id != kNoSlot) {
+                    const uint32_t b = id >> bshift;
+                    const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
+                    s_stage[j] = (q << 32) | id;
+                }
+            }
+        __syncthreads();
+        // write each bucket's run contiguously
+        const uint32_t n_stage = s_start[kMaxBuckets - 1] + s_cnt[kMaxBuckets - 1];
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+            const uint64_t e = s_stage[j];
+            const uint32_t b = (uint32_t)e >> bshift;
+            const uint64_t dst = (uint64_t)s_cursor[b] + (j - s_start[b]);
+            if (dst < cap)
+                bucketed[dst] = e;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
+            s_cursor[i] += s_cnt[i];
+            s_cnt[i] = 0;
+            s_fill[i] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Level 2: the entries of bucket b written by bin workgroups [s*slice,
+// (s+1)*slice) -> their regions' segments for those workgroups.
+__global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
+                                                       const uint32_t *__restrict__ coarse_off,
+                                                       const uint32_t *__restrict__ n_entries,
+                                                       const uint32_t *__restrict__ fine_off,
+                                                       const uint64_t *__restrict__ bucketed,
+                                                       uint64_t *__restrict__ entries) {
+    __shared__ uint32_t s_cursor[kMaxRegionsPerBucket];
+    const uint32_t b = blockIdx.x / B.n_slices;
+    const uint32_t s = blockIdx.x % B.n_slices;
+    const uint32_t gs0 = s * B.slice;
+    if (gs0 >= B.G)
+        return;
+    const uint32_t gs1 = gs0 + B.slice < B.G ? gs0 + B.slice : B.G;
+    const uint32_t r0 = b << B.bucket_shift;
+    const uint32_t nr = (r0 + (1u << B.bucket_shift) <= B.n_regions) ? (1u << B.bucket_shift)
+                                                                      : B.n_regions - r0;
+    for (uint32_t i = threadIdx.x; i < nr; i += kBinWG)
+        s_cursor[i] = fine_off[(uint64_t)(r0 + i) * B.G + gs0];
+    __syncthreads();
+    const uint64_t e0 = coarse_off[(uint64_t)b * B.G + gs0];
+    uint64_t e1;
+    if (gs1 < B.G)
+        e1 = coarse_off[(uint64_t)b * B.G + gs1];
+    else
+        e1 = b + 1 < B.n_buckets ? coarse_off[(uint64_t)(b + 1) * B.G] : *n_entries;
+    const uint64_t cap = B.entries_cap;
+    if (e1 > cap)
+        e1 = cap;
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBinWG) {
+        const uint64_t v = bucketed[e];
+        const uint32_t r = ((uint32_t)v >> kLocalBits) & ((1u << kLocalBits) - 1u);
+        const uint32_t i = r - r0;
+        if (i >= nr)
+            continue;  // cannot happen for entries written by k_bin_bucket
+        const uint32_t pos = atomicAdd(&s_cursor[i], 1u);
+        if (pos < cap)
+            entries[pos] = v;
     }
 }
 
@@ -117,8 +231,8 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     if (e1 > B.entries_cap)
         e1 = B.entries_cap;
     for (uint64_t e = e0 + threadIdx.x; e < e1; e += kRegionWG) {
-        uint64_t v = entries[e];
-        uint32_t local = (uint32_t)v & (kRegionCounters - 1);
+        const uint64_t v = entries[e];
+        const uint32_t local = (uint32_t)v & (kRegionCounters - 1);
         atomicAdd(&hits[local], 1u);
         atomicMin(&first[local], (uint32_t)(v >> 32));
     }
@@ -134,11 +248,11 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             const uint64_t h = hits[idx];
             if (h == 0)
                 continue;
-            const uint32_t shift = F.alpha * l;
-            const uint64_t pf = (pre >> shift) & F.field_max;
+            const uint32_t sh = F.alpha * l;
+            const uint64_t pf = (pre >> sh) & F.field_max;
             const uint64_t room = F.field_max - pf;
             const uint64_t nf = pf + (h < room ? h : room);
-            next = (next & ~(F.field_max << shift)) | (nf << shift);
+            next = (next & ~(F.field_max << sh)) | (nf << sh);
             if (pf == 0) {
                 uint8_t flag = 1;
                 if (classify && nf > (uint64_t)tau)
@@ -155,25 +269,32 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
 // launcher
 // ---------------------------------------------------------------------------
 bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B) {
-    // largest power-of-two word count whose eta counters fit the LDS arrays
+    // largest power-of-two cell count whose eta counters fit the LDS arrays
     uint32_t shift = 0;
     while (((2ull << shift) * F.eta) <= (uint64_t)kRegionCounters)
         shift++;
     if (((1ull << shift) * F.eta) > (uint64_t)kRegionCounters)
         return false;
-    uint64_t n_words = F.X * F.Y;
-    uint64_t n_regions = (n_words + (1ull << shift) - 1) >> shift;
+    const uint64_t n_words = F.X * F.Y;
+    const uint64_t n_regions = (n_words + (1ull << shift) - 1) >> shift;
     if (n_regions > kMaxRegions)
         return false;
     B.region_shift = shift;
     B.n_regions = (uint32_t)n_regions;
-    // positions per bin workgroup: enough to amortise the histogram, and a
-    // matrix of at most kMaxMatrix counts
+    uint32_t bshift = 0;
+    while (((n_regions + (1ull << bshift) - 1) >> bshift) > kMaxBuckets)
+        bshift++;
+    B.bucket_shift = bshift;
+    B.n_buckets = (uint32_t)((n_regions + (1ull << bshift) - 1) >> bshift);
+    // positions per bin workgroup: enough to amortise the histograms, and a
+    // region matrix of at most kMaxMatrix counts
     uint64_t tile = kBinTileMin;
     while ((chunk_positions + tile - 1) / tile * n_regions > kMaxMatrix)
         tile *= 2;
     B.tile = tile;
     B.G = (uint32_t)((chunk_positions + tile - 1) / tile);
+    B.slice = kSlice;
+    B.n_slices = (B.G + B.slice - 1) / B.slice;
     return true;
 }
 
@@ -182,12 +303,15 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
                                uint32_t tau, hipStream_t s, Profiler *P) {
     BinPlan B = plan;
     B.G = (uint32_t)((c1 - c0 + B.tile - 1) / B.tile);
+    B.n_slices = (B.G + B.slice - 1) / B.slice;
     B.entries_cap = W.entries_cap;
-    const size_t lds = (size_t)B.n_regions * sizeof(uint32_t);
-    const uint64_t n_mat = (uint64_t)B.n_regions * B.G;
+    const size_t lds = (size_t)(B.n_regions + kMaxBuckets) * sizeof(uint32_t);
+    const uint64_t n_fine = (uint64_t)B.n_regions * B.G;
+    const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
     if (P)
         P->begin(kPhBinCount, s);
-    hipLaunchKernelGGL(k_bin_count, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.matrix);
+    hipLaunchKernelGGL(k_bin_count, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots,
+                       W.matrix, W.coarse, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -195,18 +319,27 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhScan, s);
-    e = scan_u32_u32(W.matrix, W.matrix, n_mat, W.n_entries, W.partial32, s);
+    e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+    if (e == hipSuccess)
+        e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
     if (P)
         P->end(s);
     if (e != hipSuccess)
         return e;
     if (P)
         P->begin(kPhBinWrite, s);
-    hipLaunchKernelGGL(k_bin_write, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
-                       (const uint32_t *)W.matrix, W.entries);
+    hipLaunchKernelGGL(k_bin_bucket, dim3(B.G), dim3(kBinWG), 0, s, c0, c1, F.k_h, B,
+                       (const uint32_t *)W.slots, (const uint32_t *)W.coarse, W.bucketed);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_bin_region, dim3(B.n_buckets * B.n_slices), dim3(kBinWG), 0, s, B,
+                           (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
+                           (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
+        e = hipGetLastError();
+    }
     if (P)
         P->end(s);
-    if ((e = hipGetLastError()) != hipSuccess)
+    if (e != hipSuccess)
         return e;
     if (P)
         P->begin(kPhRegion, s);

@@ -169,42 +169,53 @@ __global__ void __launch_bounds__(kWG) k_resolve(FilterArgs F, ReadsArgs R, uint
 // 3 = distinct and trustworthy
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *__restrict__ flags,
+                                                    uint64_t n_tiles, int count_valid,
                                                     uint32_t *__restrict__ tile_d,
                                                     uint32_t *__restrict__ tile_t,
                                                     uint32_t *__restrict__ tile_v) {
     __shared__ uint32_t s_cnt[3][kWG / 64];
-    const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint32_t nd = 0, nt = 0, nv = 0;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t tile0 = tile * kTile;
+        uint32_t nd = 0, nt = 0, nv = 0;
 #pragma unroll 1
-    for (int j = 0; j < kTile / kWG; j++) {
-        const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
-        WaveWords w;
-        wave_load(R, pb, w);
-        uint64_t fwd;
-        bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd);
-        uint32_t f = valid ? flags[pb + lane] : 0u;
-        nd += (uint32_t)__popcll(__ballot(f != 0));
-        nt += (uint32_t)__popcll(__ballot(f == 3));
-        nv += (uint32_t)__popcll(__ballot(valid));
-    }
-    if (lane == 0) {
-        s_cnt[0][wave] = nd;
-        s_cnt[1][wave] = nt;
-        s_cnt[2][wave] = nv;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        uint32_t a = 0;
-        for (int w = 0; w < kWG / 64; w++)
-            a += s_cnt[threadIdx.x][w];
-        uint32_t *dst = threadIdx.x == 0 ? tile_d : threadIdx.x == 1 ? tile_t : tile_v;
-        dst[blockIdx.x] = a;
+        for (int j = 0; j < kTile / kWG; j++) {
+            const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
+            uint32_t f;
+            if (count_valid) {
+                WaveWords w;
+                wave_load(R, pb, w);
+                uint64_t fwd;
+                const bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd);
+                f = valid ? flags[pb + lane] : 0u;
+                nv += (uint32_t)__popcll(__ballot(valid));
+            } else {
+                // flags are only ever set at valid windows, and zero past n_bases
+                f = flags[pb + lane];
+            }
+            nd += (uint32_t)__popcll(__ballot(f != 0));
+            nt += (uint32_t)__popcll(__ballot(f == 3));
+        }
+        if (lane == 0) {
+            s_cnt[0][wave] = nd;
+            s_cnt[1][wave] = nt;
+            s_cnt[2][wave] = nv;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            uint32_t a = 0;
+            for (int w = 0; w < kWG / 64; w++)
+                a += s_cnt[threadIdx.x][w];
+            uint32_t *dst = threadIdx.x == 0 ? tile_d : threadIdx.x == 1 ? tile_t : tile_v;
+            dst[tile] = a;
+        }
+        __syncthreads();
     }
 }
 
 __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__restrict__ flags,
+                                                 uint64_t n_tiles,
                                                  const uint64_t *__restrict__ off_d,
                                                  const uint64_t *__restrict__ off_t,
                                                  const uint64_t *__restrict__ call_base,
@@ -215,67 +226,75 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
     constexpr int kWaves = kTile / 64;
     __shared__ uint64_t s_md[kWaves];
     __shared__ uint64_t s_mt[kWaves];
-    const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint32_t f[kTile / kWG];
-    uint64_t key_fwd[kTile / kWG];
-#pragma unroll
-    for (int j = 0; j < kTile / kWG; j++) {
-        const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
-        WaveWords w;
-        wave_load(R, pb, w);
-        bool valid = wave_window(w, pb, lane, R.k, R.n_bases, key_fwd[j]);
-        f[j] = valid ? flags[pb + lane] : 0u;
-        uint64_t md = __ballot(f[j] != 0);
-        uint64_t mt = __ballot(f[j] == 3);
-        if (lane == 0) {
-            s_md[j * (kWG / 64) + wave] = md;
-            s_mt[j * (kWG / 64) + wave] = mt;
-        }
-    }
-    __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
+    const uint64_t base = split ? *call_base : 0;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t tile0 = tile * kTile;
+        uint32_t f[kTile / kWG];
 #pragma unroll
-    for (int j = 0; j < kTile / kWG; j++) {
-        if (f[j] == 0)
-            continue;
-        const int widx = j * (kWG / 64) + (int)wave;
-        uint64_t rd = 0, rt = 0;
-        for (int q = 0; q < widx; q++) {
-            rd += (uint64_t)__popcll(s_md[q]);
-            rt += (uint64_t)__popcll(s_mt[q]);
-        }
-        rd += (uint64_t)__popcll(s_md[widx] & lt);
-        rt += (uint64_t)__popcll(s_mt[widx] & lt);
-        const uint64_t key = canonical_fast(key_fwd[j], R.k).key;
-        const uint64_t d = off_d[blockIdx.x] + rd;
-        if (d < cap_d)
-            distinct[d] = key;
-        if (split) {
-            const uint64_t ti = off_t[blockIdx.x] + rt;  // trustworthy keys before this one
-            const uint64_t ei = (d - *call_base) - ti;   // erroneous keys before this one
-            if (f[j] == 3) {
-                if (ti < cap_te)
-                    trust[ti] = key;
-            } else if (ei < cap_te) {
-                err[ei] = key;
+        for (int j = 0; j < kTile / kWG; j++) {
+            const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
+            f[j] = flags[pb + lane];  // set only at valid windows
+            const uint64_t md = __ballot(f[j] != 0);
+            const uint64_t mt = __ballot(f[j] == 3);
+            if (lane == 0) {
+                s_md[j * (kWG / 64) + wave] = md;
+                s_mt[j * (kWG / 64) + wave] = mt;
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kTile / kWG; j++) {
+            const int widx = j * (kWG / 64) + (int)wave;
+            const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
+            if (s_md[widx] == 0)
+                continue;  // wave-uniform: nothing flagged in these 64 positions
+            WaveWords w;
+            wave_load(R, pb, w);
+            uint64_t fwd;
+            (void)wave_window(w, pb, lane, R.k, R.n_bases, fwd);
+            if (f[j] == 0)
+                continue;
+            uint64_t rd = 0, rt = 0;
+            for (int q = 0; q < widx; q++) {
+                rd += (uint64_t)__popcll(s_md[q]);
+                rt += (uint64_t)__popcll(s_mt[q]);
+            }
+            rd += (uint64_t)__popcll(s_md[widx] & lt);
+            rt += (uint64_t)__popcll(s_mt[widx] & lt);
+            const uint64_t key = canonical_fast(fwd, R.k).key;
+            const uint64_t d = off_d[tile] + rd;
+            if (d < cap_d)
+                distinct[d] = key;
+            if (split) {
+                const uint64_t ti = off_t[tile] + rt;  // trustworthy keys before this one
+                const uint64_t ei = (d - base) - ti;   // erroneous keys before this one
+                if (f[j] == 3) {
+                    if (ti < cap_te)
+                        trust[ti] = key;
+                } else if (ei < cap_te) {
+                    err[ei] = key;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
-// totals[0] distinct, [1] trustworthy, [2] valid windows of this call
+// totals[0] distinct, [1] trustworthy, [2] valid windows counted by the tile
+// pass, [5] valid windows counted by the insert passes
 __global__ void k_finish_insert(uint64_t *__restrict__ n_distinct, uint64_t *__restrict__ n_windows,
                                 uint64_t *__restrict__ n_trust, uint64_t *__restrict__ n_err,
-                                const uint64_t *__restrict__ totals, uint64_t cap_d,
-                                uint64_t cap_te, uint32_t *__restrict__ status) {
+                                const uint64_t *__restrict__ totals, int windows_counted,
+                                uint64_t cap_d, uint64_t cap_te, uint32_t *__restrict__ status) {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
     const uint64_t nd = *n_distinct + totals[0];
     *n_distinct = nd;
     if (n_windows)
-        *n_windows += totals[2];
+        *n_windows += windows_counted ? totals[5] : totals[2];
     bool over = nd > cap_d;
     if (n_trust) {
         *n_trust = totals[1];
@@ -507,18 +526,21 @@ hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
 hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *distinct,
                            uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows,
                            uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
-                           uint64_t cap_te, uint32_t *status, hipStream_t s, Profiler *P) {
+                           uint64_t cap_te, uint32_t *status, bool windows_counted,
+                           hipStream_t s, Profiler *P) {
     const uint64_t n_tiles = tiles(R.n_bases);
     const bool split = trust != nullptr;
-    hipError_t e = launch(P, kPhTileCount, k_tile_count, dim3((unsigned)n_tiles), dim3(kWG), s, R,
-                          (const uint8_t *)W.flags8, W.tile_a, W.tile_b, W.tile_c);
+    const dim3 grid((unsigned)(n_tiles < (uint64_t)kTileGrid ? n_tiles : kTileGrid));
+    hipError_t e = launch(P, kPhTileCount, k_tile_count, grid, dim3(kWG), s, R,
+                          (const uint8_t *)W.flags8, n_tiles, windows_counted ? 0 : 1, W.tile_a,
+                          W.tile_b, W.tile_c);
     if (P)
         P->begin(kPhScan, s);
     if (e == hipSuccess)
         e = scan_u32_u64(W.tile_a, W.off_a, n_tiles, n_distinct, W.totals + 0, W.partial64, s);
     if (e == hipSuccess && split)
         e = scan_u32_u64(W.tile_b, W.off_b, n_tiles, nullptr, W.totals + 1, W.partial64, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !windows_counted)
         e = scan_u32_u64(W.tile_c, W.off_c, n_tiles, nullptr, W.totals + 2, W.partial64, s);
     if (e == hipSuccess) {  // the call's first distinct index, before k_finish_insert moves it
         hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, (const uint64_t *)n_distinct,
@@ -528,14 +550,15 @@ hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *dis
     if (P)
         P->end(s);
     if (e == hipSuccess)
-        e = launch(P, kPhScatter, k_compact, dim3((unsigned)n_tiles), dim3(kWG), s, R,
-                   (const uint8_t *)W.flags8, (const uint64_t *)W.off_a,
-                   (const uint64_t *)W.off_b, (const uint64_t *)(W.totals + 3), distinct, cap_d,
-                   trust, err, cap_te, split ? 1 : 0);
+        e = launch(P, kPhScatter, k_compact, grid, dim3(kWG), s, R, (const uint8_t *)W.flags8,
+                   n_tiles, (const uint64_t *)W.off_a, (const uint64_t *)W.off_b,
+                   (const uint64_t *)(W.totals + 3), distinct, cap_d, trust, err, cap_te,
+                   split ? 1 : 0);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_finish_insert, dim3(1), dim3(64), 0, s, n_distinct, n_windows,
                            split ? n_trust : (uint64_t *)nullptr, n_err,
-                           (const uint64_t *)W.totals, cap_d, cap_te, status);
+                           (const uint64_t *)W.totals, windows_counted ? 1 : 0, cap_d, cap_te,
+                           status);
         e = hipGetLastError();
     }
     return e;

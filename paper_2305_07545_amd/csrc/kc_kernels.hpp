@@ -25,13 +25,22 @@ constexpr int kRegionCounters = 16384;       // counters per region: hits + firs
 constexpr uint32_t kMaxRegions = 16384;      // LDS histogram of the bin kernels: 64 KiB
 constexpr uint64_t kMaxMatrix = 1ull << 25;  // (region, bin workgroup) counts per chunk
 constexpr uint64_t kBinChunk = 1ull << 28;   // positions per binned chunk (entries < 2^31)
+constexpr uint32_t kMaxBuckets = 64;         // level-1 buckets (groups of regions)
+constexpr uint32_t kMaxRegionsPerBucket = kMaxRegions / kMaxBuckets;
+constexpr int kStage = 8192;                 // level-1 entries staged per batch: 64 KiB LDS
+constexpr uint32_t kSlice = 32;              // bin workgroups per level-2 workgroup
+constexpr int kTileGrid = 2048;              // workgroups of the persistent tile kernels
 
 struct BinPlan {
-    uint32_t region_shift;  // log2(words per region)
+    uint32_t region_shift;  // log2(cells per region)
     uint32_t n_regions;
+    uint32_t bucket_shift;  // log2(regions per bucket)
+    uint32_t n_buckets;
     uint32_t G;             // bin workgroups of the chunk
+    uint32_t slice;         // bin workgroups per level-2 workgroup
+    uint32_t n_slices;
     uint64_t tile;          // positions per bin workgroup (multiple of kBinWG)
-    uint64_t entries_cap;   // capacity of the entry list
+    uint64_t entries_cap;   // capacity of each entry list
 };
 
 // Per-handle workspace (device memory owned by the handle).
@@ -49,14 +58,18 @@ struct Workspace {
     uint64_t *partial64 = nullptr;
     uint64_t tile_cap = 0;
     // binned path (per chunk)
-    uint32_t *matrix = nullptr;   // matrix_cap counts, scanned in place to offsets
+    uint32_t *matrix = nullptr;   // matrix_cap region counts, scanned in place to offsets
+    uint32_t *coarse = nullptr;   // coarse_cap bucket counts, scanned in place to offsets
     uint32_t *partial32 = nullptr;
-    uint64_t matrix_cap = 0;
-    uint64_t *entries = nullptr;  // entries_cap (t << 32 | local counter)
+    uint64_t matrix_cap = 0, coarse_cap = 0;
+    uint32_t *slots = nullptr;    // slots_cap slot ids (position-major per hash function)
+    uint64_t slots_cap = 0;
+    uint64_t *bucketed = nullptr; // entries_cap entries grouped by bucket
+    uint64_t *entries = nullptr;  // entries_cap entries grouped by region
     uint64_t entries_cap = 0;
     // scalars
     uint64_t *totals = nullptr;   // 8 scan totals / saved counters
-    uint32_t *n_entries = nullptr;
+    uint32_t *n_entries = nullptr;  // 2 entry totals
 };
 
 inline uint64_t tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
@@ -87,10 +100,13 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B);
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
                                uint32_t tau, hipStream_t s, Profiler *P);
+// windows_counted: the insert passes already added this call's valid-window
+// count to W.totals[5] (else the tile pass counts them)
 hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *distinct,
                            uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows,
                            uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
-                           uint64_t cap_te, uint32_t *status, hipStream_t s, Profiler *P);
+                           uint64_t cap_te, uint32_t *status, bool windows_counted,
+                           hipStream_t s, Profiler *P);
 hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint64_t *n_keys,
                            const uint64_t *key_base, uint64_t grid_cap, uint64_t cap,
                            uint32_t tau, uint64_t *trust, uint64_t *n_trust, uint64_t *err,
