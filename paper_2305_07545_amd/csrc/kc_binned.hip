@@ -37,6 +37,9 @@ __device__ __forceinline__ uint32_t wave_id() {
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
 constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
+constexpr uint32_t kStageLog = 12;         // kStage == 1 << kStageLog
+static_assert(kStage == (1 << kStageLog), "stage size");
+static_assert(kRegionCounters == (1 << kLocalBits), "region size");
 
 }  // namespace
 
@@ -44,19 +47,16 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                                                       uint64_t c1, BinPlan B,
                                                       uint32_t *__restrict__ slots,
                                                       uint32_t *__restrict__ fine,
-                                                      uint32_t *__restrict__ coarse,
                                                       unsigned long long *__restrict__ n_valid) {
-    extern __shared__ uint32_t s_hist[];  // n_regions region counts, then kMaxBuckets
-    uint32_t *s_bucket = s_hist + B.n_regions;
+    extern __shared__ uint32_t s_hist[];  // n_regions region counts
     __shared__ uint32_t s_valid;
-    for (uint32_t i = threadIdx.x; i < B.n_regions + kMaxBuckets; i += kBinWG)
+    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
         s_hist[i] = 0;
     if (threadIdx.x == 0)
         s_valid = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t shift = B.region_shift;
-    const uint32_t bshift = B.bucket_shift;
     const uint64_t len = c1 - c0;
     const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
     const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
@@ -80,7 +80,6 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                 const uint32_t id = (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
                 slots[(uint64_t)(a - 1) * len + (p - c0)] = id;
                 atomicAdd(&s_hist[r], 1u);
-                atomicAdd(&s_bucket[r >> bshift], 1u);
             }
         } else if (in) {
             for (uint32_t a = 1; a <= F.k_h; a++)
@@ -91,18 +90,36 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
         fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
-    for (uint32_t i = threadIdx.x; i < B.n_buckets; i += kBinWG)
-        coarse[(uint64_t)i * B.G + blockIdx.x] = s_bucket[i];
     if (threadIdx.x == 0)
         atomicAdd(n_valid, (unsigned long long)s_valid);
 }
 
+// Bucket counts: coarse[b][g] = sum of fine[r][g] over the regions r of b.
+__global__ void k_bucket_counts(BinPlan B, const uint32_t *__restrict__ fine,
+                                uint32_t *__restrict__ coarse) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)B.n_buckets * B.G)
+        return;
+    const uint32_t b = (uint32_t)(i / B.G);
+    const uint32_t g = (uint32_t)(i % B.G);
+    const uint32_t r0 = b << B.bucket_shift;
+    const uint32_t r1 = (r0 + (1u << B.bucket_shift)) < B.n_regions ? r0 + (1u << B.bucket_shift)
+                                                                     : B.n_regions;
+    uint32_t sum = 0;
+    for (uint32_t r = r0; r < r1; r++)
+        sum += fine[(uint64_t)r * B.G + g];
+    coarse[i] = sum;
+}
+
 // Level 1: slot ids of this workgroup's positions -> runs of the bucket list.
+// A batch holds kStage entries: the thread's kPer entries stay in registers
+// between counting, staging and writing.
 __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1, uint32_t k_h,
                                                        BinPlan B,
                                                        const uint32_t *__restrict__ slots,
                                                        const uint32_t *__restrict__ coarse_off,
                                                        uint64_t *__restrict__ bucketed) {
+    constexpr int kPer = kStage / kBinWG;
     __shared__ uint64_t s_stage[kStage];
     __shared__ uint32_t s_cnt[kMaxBuckets];
     __shared__ uint32_t s_start[kMaxBuckets];
@@ -112,7 +129,12 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
     const uint64_t len = c1 - c0;
     const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;  // chunk-relative
     const uint64_t g1 = g0 + B.tile < len ? g0 + B.tile : len;
-    const uint64_t batch = kStage / k_h;                   // positions per batch
+    // positions per batch: a power of two with batch * k_h <= kStage
+    uint32_t bl = 0;
+    while ((1u << bl) < k_h)
+        bl++;
+    const uint32_t batch_log = kStageLog - bl;
+    const uint64_t batch = 1ull << batch_log;
     const uint64_t cap = B.entries_cap;
     for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
         s_cursor[i] = i < B.n_buckets ? coarse_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
@@ -120,36 +142,44 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
         s_fill[i] = 0;
     }
     __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
     for (uint64_t q0 = g0; q0 < g1; q0 += batch) {
-        const uint64_t q1 = q0 + batch < g1 ? q0 + batch : g1;
-        // count entries per bucket
-        for (uint64_t q = q0 + threadIdx.x; q < q1; q += kBinWG)
-            for (uint32_t a = 0; a < k_h; a++) {
-                const uint32_t id = slots[(uint64_t)a * len + q];
-                if (id != kNoSlot)
-                    atomicAdd(&s_cnt[id >> bshift], 1u);
-            }
+        const uint64_t nq = (q0 + batch < g1 ? q0 + batch : g1) - q0;
+        uint32_t id[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            // entry i of the batch: hash function i / batch, position i % batch
+            const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
+            const uint64_t a = i >> batch_log;
+            const uint64_t q = q0 + (i & (batch - 1));
+            id[u] = (a < k_h && q - q0 < nq) ? slots[a * len + q] : kNoSlot;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (id[u] != kNoSlot)
+                atomicAdd(&s_cnt[id[u] >> bshift], 1u);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (uint32_t b = 0; b < kMaxBuckets; b++) {
-                s_start[b] = run;
-                run += s_cnt[b];
+        if (threadIdx.x < 64) {  // one wavefront scans the 64 bucket counts
+            uint32_t v = s_cnt[lane];
+            uint32_t incl = v;
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= d)
+                    incl += o;
             }
+            s_start[lane] = incl - v;
         }
         __syncthreads();
-        // stage the entries sorted by bucket
-        for (uint64_t q = q0 + threadIdx.x; q < q1; q += kBinWG)
-            for (uint32_t a = 0; a < k_h; a++) {
-                const uint32_t id = slots[(uint64_t)a * len + q];
-                if (id != kNoSlot) {
-                    const uint32_t b = id >> bshift;
-                    const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
-                    s_stage[j] = (q << 32) | id;
-                }
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (id[u] != kNoSlot) {
+                const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
+                const uint64_t q = q0 + (i & (batch - 1));
+                const uint32_t b = id[u] >> bshift;
+                const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
+                s_stage[j] = (q << 32) | id[u];
             }
         __syncthreads();
-        // write each bucket's run contiguously
         const uint32_t n_stage = s_start[kMaxBuckets - 1] + s_cnt[kMaxBuckets - 1];
         for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
             const uint64_t e = s_stage[j];
@@ -169,14 +199,21 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
 }
 
 // Level 2: the entries of bucket b written by bin workgroups [s*slice,
-// (s+1)*slice) -> their regions' segments for those workgroups.
+// (s+1)*slice) -> their regions' segments for those workgroups.  Batches of
+// kStage entries are counting-sorted by region in LDS and written as runs.
 __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
                                                        const uint32_t *__restrict__ coarse_off,
                                                        const uint32_t *__restrict__ n_entries,
                                                        const uint32_t *__restrict__ fine_off,
                                                        const uint64_t *__restrict__ bucketed,
                                                        uint64_t *__restrict__ entries) {
+    constexpr int kPer = kStage / kBinWG;
+    __shared__ uint64_t s_stage[kStage];
     __shared__ uint32_t s_cursor[kMaxRegionsPerBucket];
+    __shared__ uint32_t s_cnt[kMaxRegionsPerBucket];
+    __shared__ uint32_t s_start[kMaxRegionsPerBucket];
+    __shared__ uint32_t s_fill[kMaxRegionsPerBucket];
+    __shared__ uint32_t s_wave[kBinWG / 64];
     const uint32_t b = blockIdx.x / B.n_slices;
     const uint32_t s = blockIdx.x % B.n_slices;
     const uint32_t gs0 = s * B.slice;
@@ -186,8 +223,11 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
     const uint32_t r0 = b << B.bucket_shift;
     const uint32_t nr = (r0 + (1u << B.bucket_shift) <= B.n_regions) ? (1u << B.bucket_shift)
                                                                       : B.n_regions - r0;
-    for (uint32_t i = threadIdx.x; i < nr; i += kBinWG)
-        s_cursor[i] = fine_off[(uint64_t)(r0 + i) * B.G + gs0];
+    for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kBinWG) {
+        s_cursor[i] = i < nr ? fine_off[(uint64_t)(r0 + i) * B.G + gs0] : 0u;
+        s_cnt[i] = 0;
+        s_fill[i] = 0;
+    }
     __syncthreads();
     const uint64_t e0 = coarse_off[(uint64_t)b * B.G + gs0];
     uint64_t e1;
@@ -198,15 +238,65 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
     const uint64_t cap = B.entries_cap;
     if (e1 > cap)
         e1 = cap;
-    for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBinWG) {
-        const uint64_t v = bucketed[e];
-        const uint32_t r = ((uint32_t)v >> kLocalBits) & ((1u << kLocalBits) - 1u);
-        const uint32_t i = r - r0;
-        if (i >= nr)
-            continue;  // cannot happen for entries written by k_bin_bucket
-        const uint32_t pos = atomicAdd(&s_cursor[i], 1u);
-        if (pos < cap)
-            entries[pos] = v;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    for (uint64_t q0 = e0; q0 < e1; q0 += kStage) {
+        uint64_t v[kPer];
+        uint32_t ri[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
+            v[u] = x < e1 ? bucketed[x] : ~0ull;
+            const uint32_t r = ((uint32_t)v[u] >> kLocalBits) & ((1u << kLocalBits) - 1u);
+            ri[u] = (v[u] != ~0ull && r - r0 < nr) ? r - r0 : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (ri[u] != 0xFFFFFFFFu)
+                atomicAdd(&s_cnt[ri[u]], 1u);
+        __syncthreads();
+        // exclusive scan of the region counts (kMaxRegionsPerBucket <= kBinWG)
+        {
+            const uint32_t c = threadIdx.x < kMaxRegionsPerBucket ? s_cnt[threadIdx.x] : 0u;
+            uint32_t incl = c;
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= d)
+                    incl += o;
+            }
+            if (lane == 63)
+                s_wave[wave] = incl;
+            __syncthreads();
+            uint32_t before = 0;
+            for (uint32_t w = 0; w < wave; w++)
+                before += s_wave[w];
+            if (threadIdx.x < kMaxRegionsPerBucket)
+                s_start[threadIdx.x] = before + incl - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (ri[u] != 0xFFFFFFFFu) {
+                const uint32_t j = s_start[ri[u]] + atomicAdd(&s_fill[ri[u]], 1u);
+                s_stage[j] = v[u];
+            }
+        __syncthreads();
+        const uint32_t n_stage =
+            s_start[kMaxRegionsPerBucket - 1] + s_cnt[kMaxRegionsPerBucket - 1];
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+            const uint64_t e = s_stage[j];
+            const uint32_t r = (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0;
+            const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
+            if (dst < cap)
+                entries[dst] = e;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kBinWG) {
+            s_cursor[i] += s_cnt[i];
+            s_cnt[i] = 0;
+            s_fill[i] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -230,11 +320,22 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     uint64_t e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
     if (e1 > B.entries_cap)
         e1 = B.entries_cap;
-    for (uint64_t e = e0 + threadIdx.x; e < e1; e += kRegionWG) {
-        const uint64_t v = entries[e];
-        const uint32_t local = (uint32_t)v & (kRegionCounters - 1);
-        atomicAdd(&hits[local], 1u);
-        atomicMin(&first[local], (uint32_t)(v >> 32));
+    constexpr int kUnroll = 8;
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += (uint64_t)kUnroll * kRegionWG) {
+        uint64_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint64_t x = e + (uint64_t)u * kRegionWG;
+            v[u] = x < e1 ? entries[x] : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            if (v[u] == ~0ull)
+                continue;
+            const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+            atomicAdd(&hits[local], 1u);
+            atomicMin(&first[local], (uint32_t)(v[u] >> 32));
+        }
     }
     __syncthreads();
     const uint64_t wbase = (uint64_t)r << B.region_shift;
@@ -305,13 +406,13 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     B.G = (uint32_t)((c1 - c0 + B.tile - 1) / B.tile);
     B.n_slices = (B.G + B.slice - 1) / B.slice;
     B.entries_cap = W.entries_cap;
-    const size_t lds = (size_t)(B.n_regions + kMaxBuckets) * sizeof(uint32_t);
+    const size_t lds = (size_t)B.n_regions * sizeof(uint32_t);
     const uint64_t n_fine = (uint64_t)B.n_regions * B.G;
     const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
     if (P)
         P->begin(kPhBinCount, s);
     hipLaunchKernelGGL(k_bin_count, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots,
-                       W.matrix, W.coarse, (unsigned long long *)(W.totals + 5));
+                       W.matrix, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -319,7 +420,11 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhScan, s);
-    e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+    hipLaunchKernelGGL(k_bucket_counts, dim3((unsigned)((n_coarse + 255) / 256)), dim3(256), 0, s,
+                       B, (const uint32_t *)W.matrix, W.coarse);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
     if (e == hipSuccess)
         e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
     if (P)

@@ -168,52 +168,102 @@ __global__ void __launch_bounds__(kWG) k_resolve(FilterArgs F, ReadsArgs R, uint
 // trustworthy / erroneous split): flag byte per position, 1 = distinct,
 // 3 = distinct and trustworthy
 // ---------------------------------------------------------------------------
+// exclusive sum over the workgroup (kWG threads) and the total
+__device__ __forceinline__ uint32_t wg_exclusive_u32(uint32_t v, uint32_t *s_wave,
+                                                     uint32_t &total) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
+    }
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (uint32_t w = 0; w < kWG / 64; w++) {
+        const uint32_t t = s_wave[w];
+        if (w < wave)
+            before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + incl - v;
+}
+
+// Per tile: distinct flags (bit 0 of a flag byte), trustworthy flags (bit 1)
+// and, when asked, valid windows.  kSuper tiles per iteration; one 32-bit
+// word (4 flag bytes) per thread and tile.
 __global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *__restrict__ flags,
                                                     uint64_t n_tiles, int count_valid,
                                                     uint32_t *__restrict__ tile_d,
                                                     uint32_t *__restrict__ tile_t,
                                                     uint32_t *__restrict__ tile_v) {
-    __shared__ uint32_t s_cnt[3][kWG / 64];
+    static_assert(kTile == 4 * kWG, "one flag word per thread and tile");
+    __shared__ uint32_t s_cnt[3 * kSuper];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t tile0 = tile * kTile;
-        uint32_t nd = 0, nt = 0, nv = 0;
-#pragma unroll 1
-        for (int j = 0; j < kTile / kWG; j++) {
-            const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
-            uint32_t f;
-            if (count_valid) {
-                WaveWords w;
-                wave_load(R, pb, w);
-                uint64_t fwd;
-                const bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd);
-                f = valid ? flags[pb + lane] : 0u;
-                nv += (uint32_t)__popcll(__ballot(valid));
-            } else {
-                // flags are only ever set at valid windows, and zero past n_bases
-                f = flags[pb + lane];
-            }
-            nd += (uint32_t)__popcll(__ballot(f != 0));
-            nt += (uint32_t)__popcll(__ballot(f == 3));
+    const uint32_t *f32 = reinterpret_cast<const uint32_t *>(flags);
+    const uint64_t n_super = (n_tiles + kSuper - 1) / kSuper;
+    for (uint64_t st = blockIdx.x; st < n_super; st += gridDim.x) {
+        if (threadIdx.x < 3 * kSuper)
+            s_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t x[kSuper];
+#pragma unroll
+        for (int u = 0; u < kSuper; u++) {
+            const uint64_t tile = st * kSuper + u;
+            x[u] = tile < n_tiles ? f32[tile * kWG + threadIdx.x] : 0u;
         }
-        if (lane == 0) {
-            s_cnt[0][wave] = nd;
-            s_cnt[1][wave] = nt;
-            s_cnt[2][wave] = nv;
+#pragma unroll
+        for (int u = 0; u < kSuper; u++) {
+            const uint64_t tile = st * kSuper + u;
+            uint32_t nd = (uint32_t)__popc(x[u] & 0x01010101u);
+            uint32_t nt = (uint32_t)__popc(x[u] & 0x02020202u);
+            uint32_t nv = 0;
+            if (count_valid && tile < n_tiles) {
+#pragma unroll 1
+                for (int j = 0; j < kTile / kWG; j++) {
+                    const uint64_t pb = tile * kTile + (uint64_t)j * kWG + 64u * wave;
+                    WaveWords w;
+                    wave_load(R, pb, w);
+                    uint64_t fwd;
+                    nv += (uint32_t)__popcll(
+                        __ballot(wave_window(w, pb, lane, R.k, R.n_bases, fwd)));
+                }
+                if (lane != 0)
+                    nv = 0;
+            }
+            for (uint32_t d = 32; d >= 1; d >>= 1) {
+                nd += __shfl_down(nd, d, 64);
+                nt += __shfl_down(nt, d, 64);
+            }
+            if (lane == 0) {
+                atomicAdd(&s_cnt[3 * u], nd);
+                atomicAdd(&s_cnt[3 * u + 1], nt);
+                atomicAdd(&s_cnt[3 * u + 2], nv);
+            }
         }
         __syncthreads();
-        if (threadIdx.x < 3) {
-            uint32_t a = 0;
-            for (int w = 0; w < kWG / 64; w++)
-                a += s_cnt[threadIdx.x][w];
-            uint32_t *dst = threadIdx.x == 0 ? tile_d : threadIdx.x == 1 ? tile_t : tile_v;
-            dst[tile] = a;
+        if (threadIdx.x < kSuper) {
+            const uint64_t tile = st * kSuper + threadIdx.x;
+            if (tile < n_tiles) {
+                tile_d[tile] = s_cnt[3 * threadIdx.x];
+                tile_t[tile] = s_cnt[3 * threadIdx.x + 1];
+                tile_v[tile] = s_cnt[3 * threadIdx.x + 2];
+            }
         }
         __syncthreads();
     }
 }
 
+// Ordered output.  Per super-tile (kSuper tiles), the flagged positions are
+// first gathered into a dense list in position order (so that hashing is done
+// only for them), then each listed window's canonical key goes to the
+// distinct list and, when split, to the trustworthy or erroneous list.
 __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__restrict__ flags,
                                                  uint64_t n_tiles,
                                                  const uint64_t *__restrict__ off_d,
@@ -223,59 +273,62 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
                                                  uint64_t *__restrict__ trust,
                                                  uint64_t *__restrict__ err, uint64_t cap_te,
                                                  int split) {
-    constexpr int kWaves = kTile / 64;
-    __shared__ uint64_t s_md[kWaves];
-    __shared__ uint64_t s_mt[kWaves];
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t lt = (1ull << lane) - 1ull;
+    constexpr int kSuperPos = kSuper * kTile;  // positions per super-tile
+    constexpr int kWords = kSuperPos / 4 / kWG; // flag words per thread
+    static_assert(kSuperPos <= 32768, "list entries are 15-bit");
+    __shared__ uint32_t s_wave[2][kWG / 64];
+    __shared__ uint16_t s_pos[kSuperPos];  // super-tile position of the i-th flagged window
+    __shared__ uint16_t s_tb[kSuperPos];   // trustworthy windows before it; bit 15: it is one
+    const uint32_t *f32 = reinterpret_cast<const uint32_t *>(flags);
     const uint64_t base = split ? *call_base : 0;
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t tile0 = tile * kTile;
-        uint32_t f[kTile / kWG];
+    const uint64_t n_super = (n_tiles + kSuper - 1) / kSuper;
+    const uint64_t n_words = n_tiles * kWG;
+    for (uint64_t st = blockIdx.x; st < n_super; st += gridDim.x) {
+        const uint64_t w0 = st * (kSuperPos / 4) + (uint64_t)threadIdx.x * kWords;
+        uint32_t x[kWords];
+        uint32_t cd = 0, ct = 0;
 #pragma unroll
-        for (int j = 0; j < kTile / kWG; j++) {
-            const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
-            f[j] = flags[pb + lane];  // set only at valid windows
-            const uint64_t md = __ballot(f[j] != 0);
-            const uint64_t mt = __ballot(f[j] == 3);
-            if (lane == 0) {
-                s_md[j * (kWG / 64) + wave] = md;
-                s_mt[j * (kWG / 64) + wave] = mt;
+        for (int u = 0; u < kWords; u++) {
+            x[u] = w0 + u < n_words ? f32[w0 + u] : 0u;
+            cd += (uint32_t)__popc(x[u] & 0x01010101u);
+            ct += (uint32_t)__popc(x[u] & 0x02020202u);
+        }
+        uint32_t tot_d, tot_t;
+        uint32_t rd = wg_exclusive_u32(cd, s_wave[0], tot_d);
+        uint32_t rt = wg_exclusive_u32(ct, s_wave[1], tot_t);
+#pragma unroll
+        for (int u = 0; u < kWords; u++) {
+#pragma unroll
+            for (uint32_t sub = 0; sub < 4; sub++) {
+                const uint32_t fb = (x[u] >> (8u * sub)) & 0xFFu;
+                if (fb) {
+                    s_pos[rd] = (uint16_t)(4u * (threadIdx.x * kWords + u) + sub);
+                    s_tb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
+                    rd++;
+                    rt += fb == 3;
+                }
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kTile / kWG; j++) {
-            const int widx = j * (kWG / 64) + (int)wave;
-            const uint64_t pb = tile0 + (uint64_t)j * kWG + 64u * wave;
-            if (s_md[widx] == 0)
-                continue;  // wave-uniform: nothing flagged in these 64 positions
-            WaveWords w;
-            wave_load(R, pb, w);
-            uint64_t fwd;
-            (void)wave_window(w, pb, lane, R.k, R.n_bases, fwd);
-            if (f[j] == 0)
-                continue;
-            uint64_t rd = 0, rt = 0;
-            for (int q = 0; q < widx; q++) {
-                rd += (uint64_t)__popcll(s_md[q]);
-                rt += (uint64_t)__popcll(s_mt[q]);
-            }
-            rd += (uint64_t)__popcll(s_md[widx] & lt);
-            rt += (uint64_t)__popcll(s_mt[widx] & lt);
-            const uint64_t key = canonical_fast(fwd, R.k).key;
-            const uint64_t d = off_d[tile] + rd;
+        const uint64_t pos0 = st * kSuperPos;
+        const uint64_t od = off_d[st * kSuper];
+        const uint64_t ot = split ? off_t[st * kSuper] : 0;
+        for (uint32_t i = threadIdx.x; i < tot_d; i += kWG) {
+            const uint64_t p = pos0 + s_pos[i];
+            const uint64_t key = canonical_fast(window_key(R.codes, p, R.k), R.k).key;
+            const uint64_t d = od + i;
             if (d < cap_d)
                 distinct[d] = key;
             if (split) {
-                const uint64_t ti = off_t[tile] + rt;  // trustworthy keys before this one
-                const uint64_t ei = (d - base) - ti;   // erroneous keys before this one
-                if (f[j] == 3) {
+                const uint32_t tb = s_tb[i];
+                const uint64_t ti = ot + (tb & 0x7FFFu);  // trustworthy keys before this one
+                if (tb & 0x8000u) {
                     if (ti < cap_te)
                         trust[ti] = key;
-                } else if (ei < cap_te) {
-                    err[ei] = key;
+                } else {
+                    const uint64_t ei = (d - base) - ti;  // erroneous keys before this one
+                    if (ei < cap_te)
+                        err[ei] = key;
                 }
             }
         }

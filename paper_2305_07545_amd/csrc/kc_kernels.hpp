@@ -27,9 +27,10 @@ constexpr uint64_t kMaxMatrix = 1ull << 25;  // (region, bin workgroup) counts p
 constexpr uint64_t kBinChunk = 1ull << 28;   // positions per binned chunk (entries < 2^31)
 constexpr uint32_t kMaxBuckets = 64;         // level-1 buckets (groups of regions)
 constexpr uint32_t kMaxRegionsPerBucket = kMaxRegions / kMaxBuckets;
-constexpr int kStage = 8192;                 // level-1 entries staged per batch: 64 KiB LDS
+constexpr int kStage = 4096;                 // level-1 entries staged per batch: 32 KiB LDS
 constexpr uint32_t kSlice = 32;              // bin workgroups per level-2 workgroup
 constexpr int kTileGrid = 2048;              // workgroups of the persistent tile kernels
+constexpr int kSuper = 4;                    // tiles per iteration of the tile kernels
 
 struct BinPlan {
     uint32_t region_shift;  // log2(cells per region)
