@@ -48,10 +48,12 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
     """Bytes a launch of `phase` must move by its definition (logical
     accesses, not cache lines): see the per-kernel table in the design notes."""
     entries = n_windows * k_h
-    if phase == "bin_count":         # packed input (codes 2 bits + 2 mask bits per base)
-        return n_bases * 0.5
-    if phase == "bin_write":         # packed input, one 8-byte entry per (window, hash fn)
-        return n_bases * 0.5 + entries * 8
+    if phase == "bin_count":         # packed input, one 4-byte slot id per (position, hash fn)
+        return n_bases * (0.5 + 4 * k_h)
+    if phase == "bin_bucket":        # slot ids in, one 8-byte entry per (window, hash fn) out
+        return n_bases * 4 * k_h + entries * 8
+    if phase == "bin_region":        # entries in and out
+        return entries * 16
     if phase == "region":            # entries in, countBF cells read + written, flags
         return entries * 8 + n_words * 16 + n_distinct
     if phase == "tile_count":        # flag byte + packed input per position

@@ -188,10 +188,11 @@ typedef enum {
     KC_PHASE_QUERY = 9,           /* kc_query */
     KC_PHASE_RESET = 10,          /* kc_reset / kc_create clears */
     KC_PHASE_BIN_COUNT = 11,      /* binned path: per-region entry counts */
-    KC_PHASE_BIN_WRITE = 12,      /* binned path: (occurrence, counter) entries by region */
+    KC_PHASE_BIN_BUCKET = 12,     /* binned path: entries grouped by bucket of regions */
     KC_PHASE_REGION = 13,         /* binned path: LDS counting + first-seen per region */
     KC_PHASE_TILE_COUNT = 14,     /* per-tile distinct / trustworthy / window counts */
-    KC_PHASE_COUNT = 15
+    KC_PHASE_BIN_REGION = 15,     /* binned path: bucket slices -> region segments */
+    KC_PHASE_COUNT = 16
 } kc_phase;
 
 kc_status kc_profile(kc_filter *f, int enable);

@@ -582,8 +582,8 @@ kc_status kc_profile_read(kc_filter *f, double *ms, uint64_t *launches, uint32_t
 const char *kc_phase_name(uint32_t phase) {
     static const char *names[kc::kPhCount] = {
         "ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
-        "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_write",
-        "region", "tile_count"};
+        "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
+        "region", "tile_count", "bin_region"};
     return phase < (uint32_t)kc::kPhCount ? names[phase] : "unknown";
 }
 

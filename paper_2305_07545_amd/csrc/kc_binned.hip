@@ -432,18 +432,22 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (e != hipSuccess)
         return e;
     if (P)
-        P->begin(kPhBinWrite, s);
+        P->begin(kPhBinBucket, s);
     hipLaunchKernelGGL(k_bin_bucket, dim3(B.G), dim3(kBinWG), 0, s, c0, c1, F.k_h, B,
                        (const uint32_t *)W.slots, (const uint32_t *)W.coarse, W.bucketed);
+    if (P)
+        P->end(s);
     e = hipGetLastError();
     if (e == hipSuccess) {
+        if (P)
+            P->begin(kPhBinRegion, s);
         hipLaunchKernelGGL(k_bin_region, dim3(B.n_buckets * B.n_slices), dim3(kBinWG), 0, s, B,
                            (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
                            (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
+        if (P)
+            P->end(s);
         e = hipGetLastError();
     }
-    if (P)
-        P->end(s);
     if (e != hipSuccess)
         return e;
     if (P)

@@ -80,8 +80,8 @@ inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 // Phase ids for the profiler (same values as kc_phase in kmerco.h).
 enum Phase {
     kPhIngest = 0, kPhClaim, kPhIncrement, kPhClaimIncrement, kPhResolve, kPhScan, kPhScatter,
-    kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhBinCount, kPhBinWrite, kPhRegion,
-    kPhTileCount, kPhCount
+    kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhBinCount, kPhBinBucket, kPhRegion,
+    kPhTileCount, kPhBinRegion, kPhCount
 };
 
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);

@@ -61,8 +61,8 @@ SIGNATURES = {
 }
 
 PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
-          "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_write",
-          "region", "tile_count"]
+          "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
+          "region", "tile_count", "bin_region"]
 
 
 def load_library():

@@ -42,6 +42,12 @@ def rate(kind: str, footprint: int, ops: int) -> float:
 
 def main(argv):
     import torch  # noqa: F401 - initialises the HIP runtime the same way the library sees it
+    if argv and argv[0] == "--copy":
+        # one streaming copy of a known size (calibrates traffic counters):
+        # reads and writes argv[1] bytes
+        n = int(argv[1]) if len(argv) > 1 else 1 << 30
+        print(json.dumps({"copy_bytes_each_way": n, "bytes_per_s": rate("copy64", n, n // 8)}))
+        return
     sizes = [int(x) for x in argv] if argv else [
         512 << 10, 4 << 20, 32 << 20, 128 << 20, 512 << 20, 2 << 30, 8 << 30]
     ops = 1 << 27
