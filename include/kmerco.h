@@ -199,6 +199,60 @@ kc_status kc_profile(kc_filter *f, int enable);
 kc_status kc_profile_read(kc_filter *f, double *ms, uint64_t *launches, uint32_t n_phases);
 const char *kc_phase_name(uint32_t phase);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent read sets, each with its own countBF, k and
+ * tau, inserted (and classified) together by one launch per phase.  The
+ * result for every set is identical to kc_insert_classify (or kc_insert when
+ * trust_dev is NULL) on that set's reads alone.
+ *
+ * All sets' reads live in one buffer (reads_dev, offsets_dev as for
+ * kc_insert, n_bases bytes in total).  Set i owns bases
+ * [first_base, first_base + n_bases) of it, which must hold whole reads:
+ * first_base a multiple of 4096, sets sorted by first_base and disjoint
+ * (padding between sets must be reads of invalid bases, e.g. 'N', which add
+ * no k-mer).  Each set has its own filter handle (at most one set per
+ * handle), created on the batch's device; its countBF may span at most 2048
+ * regions of 16384 counters (about 16 MB at alpha = 8) and hold at most
+ * 2^28 bases; larger sets go through kc_insert.  The total number of
+ * (base, hash function) pairs must stay below 2^32.  Outputs per set have the
+ * meaning of kc_insert_classify; distinct capacity overflows are sticky in
+ * the set's filter (kc_sync on it).
+ * ---------------------------------------------------------------------- */
+typedef struct kc_batch kc_batch;
+
+typedef struct {
+    kc_filter *filter;
+    uint64_t first_base, n_bases;
+    uint32_t k, tau;
+    uint64_t *distinct_dev;
+    uint64_t distinct_cap;
+    uint64_t *n_distinct_dev;   /* in/out, appended at */
+    uint64_t *n_windows_dev;    /* in/out, may be NULL */
+    uint64_t *trust_dev;        /* NULL: insertion only */
+    uint64_t *n_trust_dev;
+    uint64_t *err_dev;
+    uint64_t *n_err_dev;
+    uint64_t class_cap;
+} kc_set;
+
+/* kc_batch_insert flags */
+#define KC_BATCH_RESET 1u  /* first clear every set's countBF and zero its distinct/window counters */
+#define KC_BATCH_GRAPH 2u  /* capture the launches into a HIP graph; a later call with the same
+                              arguments replays it (stream must not be the null stream) */
+#define KC_BATCH_TUNE 4u   /* time the candidate work-item sizes on this input, keep the fastest */
+
+kc_status kc_batch_create(kc_batch **out);
+void kc_batch_destroy(kc_batch *b);
+kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
+                          const uint8_t *reads_dev, const uint64_t *offsets_dev, uint64_t n_reads,
+                          uint64_t n_bases, uint32_t flags, void *stream);
+/* work-item size (positions per binning workgroup) in use / to use */
+kc_status kc_batch_get_tile(const kc_batch *b, uint64_t *tile);
+kc_status kc_batch_set_tile(kc_batch *b, uint64_t tile);
+kc_status kc_batch_profile(kc_batch *b, int enable);
+kc_status kc_batch_profile_read(kc_batch *b, double *ms, uint64_t *launches, uint32_t n_phases);
+kc_status kc_batch_sync(kc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@ The compute lives in ``libkmerco_hip.so`` (hand-written HIP kernels behind the
 C ABI of ``include/kmerco.h``); this package is its Python binding.
 """
 from .kmerco import (  # noqa: F401
+    Batch,
     CountBF,
     KmercoError,
     LIB_PATH,
@@ -11,6 +12,7 @@ from .kmerco import (  # noqa: F401
     dims,
     eta,
     load_library,
+    pack_read_sets,
     run_kmerco,
     strerror,
 )

@@ -10,47 +10,25 @@
 #include "kc_kernels.hpp"
 #include "kmerco.h"
 
-namespace {
+#include "kc_handle.hpp"
 
-enum class Path { Auto, Direct, Binned };
-
-}  // namespace
-
-struct kc_filter {
-    kc_layout layout;
-    kc::FilterArgs F;
-    kc::Workspace W;
-    int device;
-    bool zero;             // every counter of the filter is zero
-    uint32_t k;            // k of the first insert, 0 before it
-    uint32_t *status;      // device: sticky status bits (kc::kStatus*)
-    hipStream_t last;      // stream of the last enqueued call
-    uint64_t chunk;        // direct path: positions per first-seen chunk
-    uint64_t bin_chunk;    // binned path: positions per chunk
-    Path path;
-    kc::Profiler prof;     // optional per-kernel timing
-};
-
-namespace {
+namespace kcapi {
 
 // Make the handle's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) {
-            ok = false;
-            return;
-        }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess)
-            ok = false;
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+        ok = false;
+        return;
     }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
-            (void)hipSetDevice(prev);
-    }
-};
+    if (prev != dev && hipSetDevice(dev) != hipSuccess)
+        ok = false;
+}
+
+DeviceGuard::~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+        (void)hipSetDevice(prev);
+}
 
 bool valid_layout(const kc_layout *L) {
     if (!L)
@@ -63,25 +41,14 @@ bool valid_layout(const kc_layout *L) {
     return true;
 }
 
-template <typename T>
-bool dev_alloc(T **p, uint64_t count) {
-    return hipMalloc((void **)p, (count ? count : 1) * sizeof(T)) == hipSuccess;
-}
-
-template <typename T>
-void dev_free(T *&p) {
-    (void)hipFree(p);
-    p = nullptr;
-}
-
 void wait_idle(kc_filter *f) { (void)hipStreamSynchronize(f->last); }
 
-// per-position buffers for inserts of up to n bases
-kc_status ensure_positions(kc_filter *f, uint64_t n) {
-    kc::Workspace &W = f->W;
+// per-position buffers for inserts of up to n bases (waits for `wait_on`
+// before releasing smaller ones)
+kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
     if (W.codes && n <= W.cap)
         return KC_OK;
-    wait_idle(f);
+    (void)hipStreamSynchronize(wait_on);
     dev_free(W.codes);
     dev_free(W.inv);
     dev_free(W.rs);
@@ -96,12 +63,11 @@ kc_status ensure_positions(kc_filter *f, uint64_t n) {
 }
 
 // per-tile buffers for n positions or keys
-kc_status ensure_tiles(kc_filter *f, uint64_t n) {
-    kc::Workspace &W = f->W;
+kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
     uint64_t nt = kc::tiles(n) + 1;
     if (W.tile_a && nt <= W.tile_cap)
         return KC_OK;
-    wait_idle(f);
+    (void)hipStreamSynchronize(wait_on);
     dev_free(W.tile_a);
     dev_free(W.tile_b);
     dev_free(W.tile_c);
@@ -120,6 +86,9 @@ kc_status ensure_tiles(kc_filter *f, uint64_t n) {
     W.tile_cap = cap;
     return KC_OK;
 }
+
+kc_status ensure_positions(kc_filter *f, uint64_t n) { return ensure_positions(f->W, f->last, n); }
+kc_status ensure_tiles(kc_filter *f, uint64_t n) { return ensure_tiles(f->W, f->last, n); }
 
 // binned-path buffers for one chunk of the given plan
 kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
@@ -161,13 +130,15 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     return KC_OK;
 }
 
-kc_status ensure_scalars(kc_filter *f) {
-    if (f->W.totals)
+kc_status ensure_scalars(kc::Workspace &W) {
+    if (W.totals)
         return KC_OK;
-    if (!dev_alloc(&f->W.totals, 8) || !dev_alloc(&f->W.n_entries, 2))
+    if (!dev_alloc(&W.totals, 8) || !dev_alloc(&W.n_entries, 2))
         return KC_ENOMEM;
     return KC_OK;
 }
+
+kc_status ensure_scalars(kc_filter *f) { return ensure_scalars(f->W); }
 
 // first-seen workspace of the direct path: one entry per counter
 kc_status ensure_aux(kc_filter *f, hipStream_t s) {
@@ -179,8 +150,7 @@ kc_status ensure_aux(kc_filter *f, hipStream_t s) {
     return kc::fill_u32(f->F.aux, n_aux, kc::kIdle, s) == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
-void free_all(kc_filter *f) {
-    kc::Workspace &W = f->W;
+void free_workspace(kc::Workspace &W) {
     dev_free(W.codes);
     dev_free(W.inv);
     dev_free(W.rs);
@@ -201,6 +171,10 @@ void free_all(kc_filter *f) {
     dev_free(W.entries);
     dev_free(W.totals);
     dev_free(W.n_entries);
+}
+
+void free_all(kc_filter *f) {
+    free_workspace(f->W);
     dev_free(f->F.aux);
     dev_free(f->status);
 }
@@ -226,13 +200,13 @@ uint64_t chunk_size(uint64_t dflt) {
 
 // Insertion path: binned unless the filter is too large for one level of
 // regions; KMERCO_PATH=direct|binned forces one (tests compare both).
-Path path_from_env() {
+KcPath path_from_env() {
     const char *e = std::getenv("KMERCO_PATH");
     if (e && std::strcmp(e, "direct") == 0)
-        return Path::Direct;
+        return KcPath::Direct;
     if (e && std::strcmp(e, "binned") == 0)
-        return Path::Binned;
-    return Path::Auto;
+        return KcPath::Binned;
+    return KcPath::Auto;
 }
 
 uint64_t next_prime_after(uint64_t n) {
@@ -249,6 +223,11 @@ uint64_t next_prime_after(uint64_t n) {
             return p;
     }
 }
+
+}  // namespace kcapi
+
+namespace {
+using namespace kcapi;
 
 // Both phases for one call.  trust == nullptr: insertion only.
 kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offsets,
@@ -272,8 +251,8 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         return st;
     kc::BinPlan plan{};
     const uint64_t bchunk = n_bases < f->bin_chunk ? n_bases : f->bin_chunk;
-    bool binned = f->path != Path::Direct && kc::bin_plan(f->F, bchunk, plan);
-    if (f->path == Path::Binned && !binned)
+    bool binned = f->path != KcPath::Direct && kc::bin_plan(f->F, bchunk, plan);
+    if (f->path == KcPath::Binned && !binned)
         return KC_EINVAL;  // forced binned path but the filter does not fit it
     if (binned) {
         if ((st = ensure_binned(f, plan, bchunk)) != KC_OK)
@@ -429,7 +408,7 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases) {
         return st;
     kc::BinPlan plan{};
     const uint64_t bchunk = max_bases < f->bin_chunk ? max_bases : f->bin_chunk;
-    if (f->path != Path::Direct && kc::bin_plan(f->F, bchunk, plan))
+    if (f->path != KcPath::Direct && kc::bin_plan(f->F, bchunk, plan))
         return ensure_binned(f, plan, bchunk);
     return ensure_aux(f, f->last);
 }

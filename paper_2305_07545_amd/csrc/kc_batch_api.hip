@@ -1,0 +1,492 @@
+// C ABI of the batched form (declared in include/kmerco.h): many read sets,
+// each with its own countBF, inserted (and classified) by one launch per
+// phase; optional HIP-graph capture and replay; work-item size autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kc_batched.hpp"
+#include "kc_handle.hpp"
+#include "kc_kernels.hpp"
+#include "kmerco.h"
+
+using namespace kcapi;
+
+struct kc_batch {
+    int device = 0;
+    kc::Workspace W;
+    kc::BatchBuffers B;
+    uint64_t cap_sets = 0, cap_items = 0, cap_regions = 0, cap_tiles = 0, cap_slots = 0,
+             cap_matrix = 0, cap_entries = 0;
+    std::vector<kc::SetDesc> h_sets;
+    std::vector<uint32_t> h_items, h_regions, h_tiles;
+    uint64_t tile = 65536;           // positions per work item (autotuned)
+    hipStream_t last = nullptr;
+    // graph of the last KC_BATCH_GRAPH call and the arguments it was built for
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint8_t> graph_key;
+    kc::Profiler prof;
+};
+
+namespace {
+
+constexpr uint64_t kTileCandidates[] = {16384, 32768, 65536, 131072, 262144};
+
+void free_batch_buffers(kc_batch *b) {
+    kc::BatchBuffers &B = b->B;
+    dev_free(B.sets);
+    dev_free(B.item_set);
+    dev_free(B.region_set);
+    dev_free(B.tile_set);
+    dev_free(B.slots);
+    dev_free(B.matrix);
+    dev_free(B.partial32);
+    dev_free(B.n_entries);
+    dev_free(B.entries);
+    dev_free(B.valid);
+    dev_free(B.saved);
+    b->cap_sets = b->cap_items = b->cap_regions = b->cap_tiles = b->cap_slots = b->cap_matrix =
+        b->cap_entries = 0;
+}
+
+void drop_graph(kc_batch *b) {
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_key.clear();
+}
+
+template <typename T>
+kc_status grow(T **p, uint64_t &cap, uint64_t need) {
+    if (*p && need <= cap)
+        return KC_OK;
+    dev_free(*p);
+    cap = 0;
+    uint64_t n = need + need / 8 + 16;
+    if (!dev_alloc(p, n))
+        return KC_ENOMEM;
+    cap = n;
+    return KC_OK;
+}
+
+// Plan of a batch for work-item size `tile`: descriptors, work items, regions,
+// tile owners, sizes.
+kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64_t n_bases,
+                        uint64_t tile) {
+    kc::BatchPlan P{};
+    P.tile = tile;
+    P.n_tiles = kc::tiles(n_bases);
+    b->h_sets.clear();
+    b->h_items.clear();
+    b->h_regions.clear();
+    b->h_tiles.assign(P.n_tiles + kc::kSuper, kc::kNoSet);
+    uint64_t mat = 0, slot = 0;
+    uint32_t reg = 0, item = 0;
+    for (uint32_t i = 0; i < n_sets; i++) {
+        const kc_set &q = sets[i];
+        if (q.n_bases == 0)
+            continue;
+        kc_filter *f = q.filter;
+        kc::BinPlan bp{};
+        (void)kc::bin_plan(f->F, q.n_bases, bp);  // validated by the caller
+        kc::SetDesc d{};
+        d.F = f->F;
+        d.base = q.first_base;
+        d.n_bases = q.n_bases;
+        d.slot_base = slot;
+        d.mat_base = mat;
+        d.k = q.k;
+        d.tau = q.tau;
+        d.region_shift = bp.region_shift;
+        d.n_regions = bp.n_regions;
+        d.region_base = reg;
+        d.G = (uint32_t)((q.n_bases + tile - 1) / tile);
+        d.item_base = item;
+        d.fused = (q.trust_dev && f->F.k_h == 1) ? 1u : 0u;
+        d.distinct = q.distinct_dev;
+        d.cap_d = q.distinct_cap;
+        d.n_distinct = q.n_distinct_dev;
+        d.n_windows = q.n_windows_dev;
+        d.trust = q.trust_dev;
+        d.n_trust = q.n_trust_dev;
+        d.err = q.err_dev;
+        d.n_err = q.n_err_dev;
+        d.cap_te = q.class_cap;
+        d.status = f->status;
+        const uint32_t s = (uint32_t)b->h_sets.size();
+        b->h_sets.push_back(d);
+        for (uint32_t j = 0; j < d.G; j++)
+            b->h_items.push_back(s);
+        for (uint32_t r = 0; r < d.n_regions; r++)
+            b->h_regions.push_back(s);
+        const uint64_t t0 = q.first_base / kc::kTile;
+        const uint64_t t1 = kc::tiles(q.first_base + q.n_bases);
+        for (uint64_t t = t0; t < t1; t++)
+            b->h_tiles[t] = s;
+        item += d.G;
+        reg += d.n_regions;
+        mat += (uint64_t)d.n_regions * d.G;
+        slot += q.n_bases * f->F.k_h;
+    }
+    P.n_sets = (uint32_t)b->h_sets.size();
+    P.n_items = item;
+    P.n_regions = reg;
+    P.n_matrix = mat;
+    P.n_slots = slot;
+    P.entries_cap = slot;
+    return P;
+}
+
+kc_status ensure_batch(kc_batch *b, const kc::BatchPlan &P, hipStream_t s) {
+    kc::BatchBuffers &B = b->B;
+    if (B.sets && P.n_sets <= b->cap_sets && P.n_items <= b->cap_items &&
+        P.n_regions <= b->cap_regions && b->h_tiles.size() <= b->cap_tiles &&
+        P.n_slots <= b->cap_slots && P.n_matrix <= b->cap_matrix && P.entries_cap <= b->cap_entries)
+        return KC_OK;
+    (void)hipStreamSynchronize(s);
+    drop_graph(b);
+    kc_status st = KC_OK;
+    uint64_t c_sets = b->cap_sets, c_tmp;
+    if ((st = grow(&B.sets, c_sets, P.n_sets)) != KC_OK)
+        return st;
+    c_tmp = c_sets;
+    dev_free(B.valid);
+    dev_free(B.saved);
+    if (!dev_alloc(&B.valid, c_tmp) || !dev_alloc(&B.saved, c_tmp))
+        return KC_ENOMEM;
+    b->cap_sets = c_sets;
+    if ((st = grow(&B.item_set, b->cap_items, P.n_items)) != KC_OK ||
+        (st = grow(&B.region_set, b->cap_regions, P.n_regions)) != KC_OK ||
+        (st = grow(&B.tile_set, b->cap_tiles, b->h_tiles.size())) != KC_OK ||
+        (st = grow(&B.slots, b->cap_slots, P.n_slots)) != KC_OK ||
+        (st = grow(&B.entries, b->cap_entries, P.entries_cap)) != KC_OK)
+        return st;
+    if (!B.matrix || P.n_matrix > b->cap_matrix) {
+        dev_free(B.matrix);
+        dev_free(B.partial32);
+        b->cap_matrix = 0;
+        uint64_t n = P.n_matrix + P.n_matrix / 8 + 16;
+        if (!dev_alloc(&B.matrix, n) || !dev_alloc(&B.partial32, kc::scan_partials(n)))
+            return KC_ENOMEM;
+        b->cap_matrix = n;
+    }
+    if (!B.n_entries && !dev_alloc(&B.n_entries, 2))
+        return KC_ENOMEM;
+    return KC_OK;
+}
+
+kc_status upload(kc_batch *b, const kc::BatchPlan &P, hipStream_t s) {
+    kc::BatchBuffers &B = b->B;
+    hipError_t e = hipMemcpyAsync(B.sets, b->h_sets.data(), P.n_sets * sizeof(kc::SetDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && P.n_items)
+        e = hipMemcpyAsync(B.item_set, b->h_items.data(), P.n_items * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && P.n_regions)
+        e = hipMemcpyAsync(B.region_set, b->h_regions.data(), P.n_regions * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B.tile_set, b->h_tiles.data(), b->h_tiles.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)  // the host vectors may change on the next call
+        e = hipStreamSynchronize(s);
+    return e == hipSuccess ? KC_OK : KC_EDEVICE;
+}
+
+// Launch sequence of one call (ingest, batch pipeline, per-set split for
+// sets the region pass cannot classify).
+kc_status launch_all(kc_batch *b, const kc::BatchPlan &P, const kc_set *sets, uint32_t n_sets,
+                     const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads,
+                     uint64_t n_bases, bool reset, hipStream_t s, kc::Profiler *prof) {
+    hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, b->W, s, prof);
+    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0};
+    if (e == hipSuccess && P.n_sets)
+        e = kc::launch_batch(P, b->B, R, reset, s, prof);
+    if (e != hipSuccess)
+        return KC_EDEVICE;
+    uint32_t di = 0;
+    for (uint32_t i = 0; i < n_sets; i++) {
+        const kc_set &q = sets[i];
+        if (q.n_bases == 0) {
+            if (q.trust_dev && (kc::fill_u64(q.n_trust_dev, 1, 0, s) != hipSuccess ||
+                                kc::fill_u64(q.n_err_dev, 1, 0, s) != hipSuccess))
+                return KC_EDEVICE;
+            continue;
+        }
+        const kc::SetDesc &d = b->h_sets[di++];
+        if (q.trust_dev && !d.fused) {
+            // split of the keys this set appended: distinct[saved .. *n_distinct)
+            e = kc::launch_classify(q.filter->F, q.distinct_dev, q.n_distinct_dev,
+                                    b->B.saved + (di - 1), q.n_bases, q.distinct_cap, q.tau,
+                                    q.trust_dev, q.n_trust_dev, q.err_dev, q.n_err_dev,
+                                    q.class_cap, q.filter->status, b->W, s, prof);
+            if (e != hipSuccess)
+                return KC_EDEVICE;
+        }
+    }
+    return KC_OK;
+}
+
+// Fastest work-item size for this input, timed on the binning kernels only
+// (they do not modify any countBF).
+kc_status autotune(kc_batch *b, const kc_set *sets, uint32_t n_sets, const uint8_t *reads,
+                   const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases, hipStream_t s) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return KC_EDEVICE;
+    kc_status st = KC_OK;
+    if (kc::launch_ingest(reads, n_bases, offsets, n_reads, b->W, s, nullptr) != hipSuccess)
+        st = KC_EDEVICE;
+    float best = 1e30f;
+    uint64_t best_tile = b->tile;
+    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0};
+    for (uint64_t tile : kTileCandidates) {
+        if (st != KC_OK)
+            break;
+        kc::BatchPlan P = make_plan(b, sets, n_sets, n_bases, tile);
+        if ((st = ensure_batch(b, P, s)) != KC_OK || (st = upload(b, P, s)) != KC_OK)
+            break;
+        float t_min = 1e30f;
+        for (int rep = 0; rep < 3 && st == KC_OK; rep++) {
+            (void)hipEventRecord(e0, s);
+            if (kc::launch_batch_bins(P, b->B, R, s, nullptr) != hipSuccess)
+                st = KC_EDEVICE;
+            (void)hipEventRecord(e1, s);
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = KC_EDEVICE;
+            if (rep > 0)
+                t_min = std::min(t_min, ms);
+        }
+        if (st == KC_OK && t_min < best) {
+            best = t_min;
+            best_tile = tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == KC_OK)
+        b->tile = best_tile;
+    return st;
+}
+
+// Everything a captured graph depends on: the arguments, the work-item size
+// and the workspace addresses baked into its kernels.
+std::vector<uint8_t> call_key(const kc_batch *b, const kc_set *sets, uint32_t n_sets,
+                              const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads,
+                              uint64_t n_bases, uint32_t flags, hipStream_t s) {
+    const kc::Workspace &W = b->W;
+    const uint64_t tail[] = {(uint64_t)(uintptr_t)reads, (uint64_t)(uintptr_t)offsets, n_reads,
+                             n_bases, flags & ~(uint32_t)KC_BATCH_TUNE, (uint64_t)(uintptr_t)s,
+                             b->tile, n_sets,
+                             (uint64_t)(uintptr_t)W.codes, (uint64_t)(uintptr_t)W.inv,
+                             (uint64_t)(uintptr_t)W.rs, (uint64_t)(uintptr_t)W.flags8,
+                             (uint64_t)(uintptr_t)W.tile_a, (uint64_t)(uintptr_t)W.off_a,
+                             (uint64_t)(uintptr_t)W.partial64, (uint64_t)(uintptr_t)W.totals,
+                             (uint64_t)(uintptr_t)W.tmask};
+    std::vector<uint8_t> k(n_sets * sizeof(kc_set) + sizeof tail);
+    std::memcpy(k.data(), sets, n_sets * sizeof(kc_set));
+    std::memcpy(k.data() + n_sets * sizeof(kc_set), tail, sizeof tail);
+    return k;
+}
+
+kc_status validate(const kc_set *sets, uint32_t n_sets, const uint8_t *reads,
+                   const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases, int device) {
+    if (!sets || n_sets == 0)
+        return KC_EINVAL;
+    if (n_bases > 0 && (!reads || !offsets || n_reads == 0))
+        return KC_EINVAL;
+    uint64_t end = 0, entries = 0;
+    for (uint32_t i = 0; i < n_sets; i++) {
+        const kc_set &q = sets[i];
+        kc_filter *f = q.filter;
+        if (!f || f->device != device || q.k < 1 || q.k > 32 || !q.n_distinct_dev)
+            return KC_EINVAL;
+        if (f->k != 0 && f->k != q.k)
+            return KC_ESTATE;
+        if (q.first_base % kc::kSetAlign != 0 || q.first_base < end ||
+            q.first_base + q.n_bases > n_bases)
+            return KC_EINVAL;  // sets must be aligned, sorted and disjoint
+        if (q.distinct_cap > 0 && !q.distinct_dev)
+            return KC_EINVAL;
+        if (q.trust_dev && (!q.n_trust_dev || !q.err_dev || !q.n_err_dev))
+            return KC_EINVAL;
+        for (uint32_t j = 0; j < i; j++)
+            if (sets[j].filter == f)
+                return KC_EINVAL;  // one filter per set
+        if (q.n_bases > 0) {
+            kc::BinPlan bp{};
+            if (q.n_bases > kc::kBinChunk || !kc::bin_plan(f->F, q.n_bases, bp) ||
+                bp.n_regions > kc::kBatchMaxRegions)
+                return KC_EINVAL;  // too large for the batched form: use kc_insert
+        }
+        entries += q.n_bases * f->F.k_h;
+        end = q.first_base + q.n_bases;
+    }
+    if (entries >= (1ull << 32))
+        return KC_EINVAL;
+    return KC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kc_status kc_batch_create(kc_batch **out) {
+    if (!out)
+        return KC_EINVAL;
+    *out = nullptr;
+    kc_batch *b = new (std::nothrow) kc_batch();
+    if (!b)
+        return KC_ENOMEM;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return KC_EDEVICE;
+    }
+    b->B.W = &b->W;
+    *out = b;
+    return KC_OK;
+}
+
+void kc_batch_destroy(kc_batch *b) {
+    if (!b)
+        return;
+    DeviceGuard g(b->device);
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    b->prof.release();
+    free_batch_buffers(b);
+    free_workspace(b->W);
+    delete b;
+}
+
+kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
+                          const uint8_t *reads_dev, const uint64_t *offsets_dev, uint64_t n_reads,
+                          uint64_t n_bases, uint32_t flags, void *stream) {
+    if (!b)
+        return KC_EINVAL;
+    kc_status st = validate(sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, b->device);
+    if (st != KC_OK)
+        return st;
+    DeviceGuard g(b->device);
+    if (!g.ok)
+        return KC_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const bool graph = (flags & KC_BATCH_GRAPH) != 0;
+    const bool reset = (flags & KC_BATCH_RESET) != 0;
+    if (graph && !s)
+        return KC_EINVAL;  // the null stream cannot be captured
+    b->last = s;
+    if ((st = ensure_scalars(b->W)) != KC_OK || (st = ensure_positions(b->W, s, n_bases)) != KC_OK ||
+        (st = ensure_tiles(b->W, s, n_bases)) != KC_OK)
+        return st;
+    if (flags & KC_BATCH_TUNE) {
+        drop_graph(b);  // tuning rewrites the device descriptor table
+        if ((st = autotune(b, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, s)) != KC_OK)
+            return st;
+    }
+    std::vector<uint8_t> key;
+    if (graph) {
+        key = call_key(b, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, flags, s);
+        if (b->exec && key == b->graph_key) {
+            if (hipGraphLaunch(b->exec, s) != hipSuccess)
+                return KC_EDEVICE;
+            for (uint32_t i = 0; i < n_sets; i++) {
+                sets[i].filter->zero = false;
+                sets[i].filter->k = sets[i].k;
+                sets[i].filter->last = s;
+            }
+            return KC_OK;
+        }
+    }
+    // a new descriptor table invalidates any captured graph
+    drop_graph(b);
+    kc::BatchPlan P = make_plan(b, sets, n_sets, n_bases, b->tile);
+    if ((st = ensure_batch(b, P, s)) != KC_OK || (st = upload(b, P, s)) != KC_OK)
+        return st;
+    if (graph) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess)
+            return KC_EDEVICE;
+        st = launch_all(b, P, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, reset, s,
+                        nullptr);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &gr);
+        if (st != KC_OK || e != hipSuccess) {
+            if (gr)
+                (void)hipGraphDestroy(gr);
+            return st != KC_OK ? st : KC_EDEVICE;
+        }
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiateWithFlags(&ex, gr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            return KC_EDEVICE;
+        }
+        b->graph = gr;
+        b->exec = ex;
+        b->graph_key = key;
+        if (hipGraphLaunch(ex, s) != hipSuccess)
+            return KC_EDEVICE;
+    } else {
+        st = launch_all(b, P, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, reset, s,
+                        &b->prof);
+        if (st != KC_OK)
+            return st;
+    }
+    for (uint32_t i = 0; i < n_sets; i++) {
+        sets[i].filter->zero = false;
+        sets[i].filter->k = sets[i].k;
+        sets[i].filter->last = s;
+    }
+    return KC_OK;
+}
+
+kc_status kc_batch_get_tile(const kc_batch *b, uint64_t *tile) {
+    if (!b || !tile)
+        return KC_EINVAL;
+    *tile = b->tile;
+    return KC_OK;
+}
+
+kc_status kc_batch_set_tile(kc_batch *b, uint64_t tile) {
+    if (!b || tile < (uint64_t)kc::kBinWG || tile % kc::kBinWG != 0 || tile > kc::kBinChunk)
+        return KC_EINVAL;
+    b->tile = tile;
+    return KC_OK;
+}
+
+kc_status kc_batch_profile(kc_batch *b, int enable) {
+    if (!b)
+        return KC_EINVAL;
+    b->prof.collect(nullptr, nullptr, 0);
+    b->prof.on = enable != 0;
+    return KC_OK;
+}
+
+kc_status kc_batch_profile_read(kc_batch *b, double *ms, uint64_t *launches, uint32_t n_phases) {
+    if (!b || (n_phases > 0 && (!ms || !launches)))
+        return KC_EINVAL;
+    DeviceGuard g(b->device);
+    if (!g.ok)
+        return KC_EDEVICE;
+    b->prof.collect(ms, launches, n_phases);
+    return KC_OK;
+}
+
+kc_status kc_batch_sync(kc_batch *b) {
+    if (!b)
+        return KC_EINVAL;
+    DeviceGuard g(b->device);
+    if (!g.ok)
+        return KC_EDEVICE;
+    return hipStreamSynchronize(b->last) == hipSuccess ? KC_OK : KC_EDEVICE;
+}
+
+}  // extern "C"

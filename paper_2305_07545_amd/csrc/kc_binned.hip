@@ -37,7 +37,6 @@ __device__ __forceinline__ uint32_t wave_id() {
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
 constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
-constexpr uint32_t kStageLog = 12;         // kStage == 1 << kStageLog
 static_assert(kStage == (1 << kStageLog), "stage size");
 static_assert(kRegionCounters == (1 << kLocalBits), "region size");
 

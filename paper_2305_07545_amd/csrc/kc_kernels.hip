@@ -168,32 +168,6 @@ __global__ void __launch_bounds__(kWG) k_resolve(FilterArgs F, ReadsArgs R, uint
 // trustworthy / erroneous split): flag byte per position, 1 = distinct,
 // 3 = distinct and trustworthy
 // ---------------------------------------------------------------------------
-// exclusive sum over the workgroup (kWG threads) and the total
-__device__ __forceinline__ uint32_t wg_exclusive_u32(uint32_t v, uint32_t *s_wave,
-                                                     uint32_t &total) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d)
-            incl += o;
-    }
-    if (lane == 63)
-        s_wave[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0;
-    total = 0;
-    for (uint32_t w = 0; w < kWG / 64; w++) {
-        const uint32_t t = s_wave[w];
-        if (w < wave)
-            before += t;
-        total += t;
-    }
-    __syncthreads();
-    return before + incl - v;
-}
-
 // Per tile: distinct flags (bit 0 of a flag byte), trustworthy flags (bit 1)
 // and, when asked, valid windows.  kSuper tiles per iteration; one 32-bit
 // word (4 flag bytes) per thread and tile.
@@ -574,6 +548,14 @@ hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (e != hipSuccess)
         return e;
     return launch(P, kPhResolve, k_resolve, grid, block, s, F, R, c0, c1, W.flags8);
+}
+
+hipError_t launch_tile_count(const ReadsArgs &R, const Workspace &W, uint64_t n_tiles,
+                             hipStream_t s) {
+    const dim3 grid((unsigned)(n_tiles < (uint64_t)kTileGrid ? n_tiles : kTileGrid));
+    hipLaunchKernelGGL(k_tile_count, grid, dim3(kWG), 0, s, R, (const uint8_t *)W.flags8, n_tiles,
+                       0, W.tile_a, W.tile_b, W.tile_c);
+    return hipGetLastError();
 }
 
 hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *distinct,

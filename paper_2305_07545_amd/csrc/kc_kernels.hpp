@@ -27,7 +27,8 @@ constexpr uint64_t kMaxMatrix = 1ull << 25;  // (region, bin workgroup) counts p
 constexpr uint64_t kBinChunk = 1ull << 28;   // positions per binned chunk (entries < 2^31)
 constexpr uint32_t kMaxBuckets = 64;         // level-1 buckets (groups of regions)
 constexpr uint32_t kMaxRegionsPerBucket = kMaxRegions / kMaxBuckets;
-constexpr int kStage = 4096;                 // level-1 entries staged per batch: 32 KiB LDS
+constexpr int kStage = 4096;                 // entries staged per batch in LDS: 32 KiB
+constexpr uint32_t kStageLog = 12;           // kStage == 1 << kStageLog
 constexpr uint32_t kSlice = 32;              // bin workgroups per level-2 workgroup
 constexpr int kTileGrid = 2048;              // workgroups of the persistent tile kernels
 constexpr int kSuper = 4;                    // tiles per iteration of the tile kernels
@@ -74,6 +75,33 @@ struct Workspace {
 };
 
 inline uint64_t tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
+
+// Exclusive sum over a workgroup of kWG threads; `total` receives the sum.
+// Every thread of the workgroup must call it (it synchronises).
+__device__ __forceinline__ uint32_t wg_exclusive_u32(uint32_t v, uint32_t *s_wave,
+                                                     uint32_t &total) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
+    }
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (uint32_t w = 0; w < kWG / 64; w++) {
+        const uint32_t t = s_wave[w];
+        if (w < wave)
+            before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + incl - v;
+}
 inline uint64_t mask_words(uint64_t n) { return tiles(n) * (kTile / 32) + 2; }
 inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 

@@ -32,6 +32,20 @@ class kc_layout(ctypes.Structure):
                 ("alpha", ctypes.c_uint32), ("k_h", ctypes.c_uint32)]
 
 
+class kc_set(ctypes.Structure):
+    _fields_ = [("filter", ctypes.c_void_p),
+                ("first_base", ctypes.c_uint64), ("n_bases", ctypes.c_uint64),
+                ("k", ctypes.c_uint32), ("tau", ctypes.c_uint32),
+                ("distinct_dev", ctypes.c_void_p), ("distinct_cap", ctypes.c_uint64),
+                ("n_distinct_dev", ctypes.c_void_p), ("n_windows_dev", ctypes.c_void_p),
+                ("trust_dev", ctypes.c_void_p), ("n_trust_dev", ctypes.c_void_p),
+                ("err_dev", ctypes.c_void_p), ("n_err_dev", ctypes.c_void_p),
+                ("class_cap", ctypes.c_uint64)]
+
+
+KC_BATCH_RESET, KC_BATCH_GRAPH, KC_BATCH_TUNE = 1, 2, 4
+SET_ALIGN = 4096
+
 _lib = None
 
 # every symbol include/kmerco.h declares, with (restype, argtypes)
@@ -58,6 +72,14 @@ SIGNATURES = {
     "kc_profile": (_i, [_vp, _i]),
     "kc_profile_read": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64), _u32]),
     "kc_phase_name": (ctypes.c_char_p, [_u32]),
+    "kc_batch_create": (_i, [ctypes.POINTER(_vp)]),
+    "kc_batch_destroy": (None, [_vp]),
+    "kc_batch_insert": (_i, [_vp, ctypes.POINTER(kc_set), _u32, _vp, _vp, _u64, _u64, _u32, _vp]),
+    "kc_batch_get_tile": (_i, [_vp, ctypes.POINTER(_u64)]),
+    "kc_batch_set_tile": (_i, [_vp, _u64]),
+    "kc_batch_profile": (_i, [_vp, _i]),
+    "kc_batch_profile_read": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64), _u32]),
+    "kc_batch_sync": (_i, [_vp]),
 }
 
 PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
@@ -298,3 +320,113 @@ def run_kmerco(reads, offsets, k: int, tau: int, X: int, Y: int, alpha: int = 8,
     out = (u(bf.words), u(distinct[:nd]), u(trust[:nt]), u(err[:ne]), int(bf.n_windows.item()))
     bf.close()
     return out
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+def pack_read_sets(sets):
+    """Concatenate read sets [(reads uint8, offsets uint64), ...] into one
+    buffer in which every set starts at a multiple of SET_ALIGN bases; the
+    gaps are filled with one read of 'N' bases (no valid k-mer).  Returns
+    (reads, offsets, [(first_base, n_bases, first_read, n_reads)])."""
+    import numpy as np
+    parts, offs, spans = [], [np.zeros(1, dtype=np.uint64)], []
+    pos = 0
+    n_reads = 0
+    for reads, offsets in sets:
+        reads = np.asarray(reads, dtype=np.uint8)
+        offsets = np.asarray(offsets, dtype=np.uint64)
+        pad = (-pos) % SET_ALIGN
+        if pad:
+            parts.append(np.full(pad, ord("N"), dtype=np.uint8))
+            offs.append(np.array([pos + pad], dtype=np.uint64))
+            pos += pad
+            n_reads += 1
+        nb = int(offsets[-1])
+        nr = len(offsets) - 1
+        spans.append((pos, nb, n_reads, nr))
+        parts.append(reads[:nb])
+        if nr:
+            offs.append(offsets[1:] + np.uint64(pos))
+        pos += nb
+        n_reads += nr
+    reads = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint8)
+    return reads, np.concatenate(offs).astype(np.uint64), spans
+
+
+class Batch:
+    """kc_batch: insert many read sets, each into its own CountBF, with one
+    launch per phase."""
+
+    def __init__(self):
+        self.lib = load_library()
+        h = ctypes.c_void_p(None)
+        _check(self.lib.kc_batch_create(ctypes.byref(h)), "kc_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.kc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    @property
+    def tile(self) -> int:
+        t = ctypes.c_uint64(0)
+        _check(self.lib.kc_batch_get_tile(self._h, ctypes.byref(t)), "kc_batch_get_tile")
+        return int(t.value)
+
+    @tile.setter
+    def tile(self, value: int):
+        _check(self.lib.kc_batch_set_tile(self._h, int(value)), "kc_batch_set_tile")
+
+    def insert(self, entries, reads, offsets, reset=False, graph=False, tune=False, stream=None):
+        """entries: list of dicts with keys filter (CountBF), first_base,
+        n_bases, k, tau, distinct, n_distinct, n_windows, and optionally
+        trust, n_trust, err, n_err (device tensors)."""
+        _require(reads, torch.uint8, "reads")
+        _require(offsets, torch.int64, "offsets")
+        arr = (kc_set * len(entries))()
+        for i, e in enumerate(entries):
+            q = arr[i]
+            q.filter = e["filter"].handle
+            q.first_base = int(e["first_base"])
+            q.n_bases = int(e["n_bases"])
+            q.k = int(e["k"])
+            q.tau = int(e.get("tau", 0))
+            q.distinct_dev = e["distinct"].data_ptr()
+            q.distinct_cap = int(e.get("distinct_cap", e["distinct"].numel()))
+            q.n_distinct_dev = e["n_distinct"].data_ptr()
+            q.n_windows_dev = e["n_windows"].data_ptr() if e.get("n_windows") is not None else None
+            if e.get("trust") is not None:
+                q.trust_dev = e["trust"].data_ptr()
+                q.n_trust_dev = e["n_trust"].data_ptr()
+                q.err_dev = e["err"].data_ptr()
+                q.n_err_dev = e["n_err"].data_ptr()
+                q.class_cap = int(e.get("class_cap", min(e["trust"].numel(), e["err"].numel())))
+        flags = (KC_BATCH_RESET if reset else 0) | (KC_BATCH_GRAPH if graph else 0) | \
+                (KC_BATCH_TUNE if tune else 0)
+        with torch.cuda.device(reads.device):
+            _check(self.lib.kc_batch_insert(self._h, arr, len(entries), _ptr(reads), _ptr(offsets),
+                                            offsets.numel() - 1, reads.numel(), flags,
+                                            _stream_ptr(stream)), "kc_batch_insert")
+
+    def profile(self, enable: bool = True):
+        _check(self.lib.kc_batch_profile(self._h, int(enable)), "kc_batch_profile")
+
+    def profile_read(self):
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_uint64 * n)()
+        _check(self.lib.kc_batch_profile_read(self._h, ms, cnt, n), "kc_batch_profile_read")
+        return {PHASES[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
+
+    def sync(self):
+        _check(self.lib.kc_batch_sync(self._h), "kc_batch_sync")
