@@ -29,7 +29,7 @@ class BatchRun:
     """Filters, outputs and packed reads for a list of
     (ReadSet, (X, Y, alpha, k_h), split) cases."""
 
-    def __init__(self, cases, stream=None):
+    def __init__(self, cases, stream=None, extra=0):
         self.cases = cases
         self.stream = stream
         reads, offs, self.spans = P.pack_read_sets([(rs.reads, rs.offsets) for rs, _, _ in cases])
@@ -38,7 +38,7 @@ class BatchRun:
         self.entries = []
         for (rs, (X, Y, a, kh), split), (base, nb, _, _) in zip(cases, self.spans):
             f = P.CountBF(X, Y, a, kh, stream=stream)
-            room = 4 * nb + 4096  # room for later incremental calls too
+            room = nb + extra + 64  # distinct <= windows <= bases
             e = {"filter": f, "first_base": base, "n_bases": nb, "k": rs.k, "tau": rs.tau,
                  "distinct": torch.empty(room, dtype=torch.int64, device="cuda"),
                  "n_distinct": torch.zeros(1, dtype=torch.int64, device="cuda"),
@@ -148,7 +148,8 @@ def test_incremental_batches():
     # insert-only so that distinct lists concatenate across the two calls
     a = [(rs, lay, False) for rs, lay, _ in a]
     bb = [(rs, lay, False) for rs, lay, _ in bb]
-    run_a = BatchRun(a)
+    # the second call brings at most 300 * 200 more windows per set
+    run_a = BatchRun(a, extra=300 * 200)
     batch = P.Batch()
     batch.insert(run_a.entries, run_a.reads, run_a.offs, reset=True)
     reads_b, offs_b, spans_b = P.pack_read_sets([(rs.reads, rs.offsets) for rs, _, _ in bb])
