@@ -8,8 +8,14 @@ countBF, ordered trustworthy / erroneous split).
 The metric counts one insertion per valid k-mer window, as the paper's
 insertions-per-second figure does (number of insertions / insertion time).
 
+The same line carries the batched form measured against the plain kernel on
+the 256-set workload (each set with its own countBF): one step inserts and
+classifies every set, either as 256 plain calls in sequence or as one batched
+call captured in a HIP graph; both are checked against the oracle's digests.
+
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bacterial]
+                    [--forms batched|none]
 """
 from __future__ import annotations
 
@@ -35,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--forms", default="batched",
+                    help="comma list of extra forms to measure: batched, or none")
+    ap.add_argument("--form-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -118,6 +127,156 @@ def cpu_baseline(rs, X, Y, n_sample_reads):
                       f"countBF {X}x{Y}, single-threaded C oracle, {secs:.1f} s"}
 
 
+def roofline_of(phases, n_bases, n_windows, n_distinct, k_h, n_words, workload):
+    """HBM roofline of the phase with the largest total time."""
+    if not phases:
+        return None
+    dom = max(phases, key=lambda k: phases[k][0])
+    avg_s = phases[dom][0] / phases[dom][1] / 1e3
+    nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words)
+    achieved = nbytes / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, workload), "kernel": dom,
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+
+def batched_leg(args, dev):
+    """The 256-set workload, plain (one kc_insert_classify per set, in
+    sequence on one stream) against batched (one kc_batch_insert, autotuned
+    once, then replayed from a HIP graph).  Same filters, same outputs."""
+    import numpy as np
+    import torch
+
+    import paper_2305_07545_amd as P
+    import synth
+
+    t_gen = time.perf_counter()
+    sets = synth.config("batched")
+    t_gen = time.perf_counter() - t_gen
+    n = len(sets)
+    # graph capture needs a non-default stream; the plain calls use it too
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        return _batched_leg(args, dev, sets, stream, t_gen)
+
+
+def _batched_leg(args, dev, sets, stream, t_gen):
+    import numpy as np
+    import torch
+
+    import paper_2305_07545_amd as P
+    n = len(sets)
+    packed, poffs, spans = P.pack_read_sets([(rs.reads, rs.offsets) for rs in sets])
+    reads = torch.from_numpy(packed).to(dev)
+    offs = torch.from_numpy(poffs.view(np.int64)).to(dev)
+    # plain calls take each set's own buffers
+    own = [(torch.from_numpy(rs.reads).to(dev), torch.from_numpy(rs.offsets.view(np.int64)).to(dev))
+           for rs in sets]
+    bases = [rs.n_bases for rs in sets]
+    starts = np.concatenate([[0], np.cumsum(bases)]).astype(np.int64)
+    total = int(starts[-1])
+    out = {name: torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+           for name in ("distinct", "trust", "err")}
+    counters = torch.zeros((n, 4), dtype=torch.int64, device=dev)
+    filters, entries = [], []
+    for i, (rs, (base, nb, _, _)) in enumerate(zip(sets, spans)):
+        X, Y = P.dims(rs.n_items)
+        f = P.CountBF(X, Y, 8, 1, device=dev)
+        filters.append(f)
+        sl = slice(int(starts[i]), int(starts[i + 1]))
+        e = {"filter": f, "first_base": base, "n_bases": nb, "k": rs.k, "tau": rs.tau,
+             "n_distinct": counters[i, 0:1], "n_windows": counters[i, 1:2],
+             "n_trust": counters[i, 2:3], "n_err": counters[i, 3:4]}
+        e.update({name: out[name][sl] for name in out})
+        entries.append(e)
+
+    def plain_step():
+        counters.zero_()
+        for e, (r, o) in zip(entries, own):
+            e["filter"].reset(stream)
+            e["filter"].insert_classify(r, o, e["k"], e["tau"], distinct=e["distinct"],
+                                        trust=e["trust"], err=e["err"],
+                                        n_distinct=e["n_distinct"], n_windows=e["n_windows"],
+                                        n_trust=e["n_trust"], n_err=e["n_err"], stream=stream)
+
+    batch = P.Batch()
+
+    def batch_step(tune=False):
+        counters.zero_()
+        batch.insert(entries, reads, offs, reset=True, graph=not tune, tune=tune, stream=stream)
+
+    def timed(step, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def check():
+        import json as _json
+        ref_path = os.path.join(ROOT, "tests", "golden", "batched_digests.json")
+        if args.no_verify or not os.path.exists(ref_path):
+            return None
+        ref = _json.load(open(ref_path))["sets"]
+        c = counters.cpu().numpy()
+        for i, (e, r) in enumerate(zip(entries, ref)):
+            nd, nw, nt, ne = (int(x) for x in c[i])
+            if (nd, nw, nt, ne) != (r["n_distinct"], r["n_windows"], r["n_trust"], r["n_err"]):
+                return False
+            if (sha(e["filter"].words) != r["words_sha256"]
+                    or sha(e["distinct"][:nd]) != r["distinct_sha256"]
+                    or sha(e["trust"][:nt]) != r["trust_sha256"]
+                    or sha(e["err"][:ne]) != r["err_sha256"]):
+                return False
+        return True
+
+    steps = max(1, args.form_steps)
+    plain_step()
+    plain_step()
+    plain_s = timed(plain_step, steps)
+    plain_ok = check()
+    for f in filters:
+        f.sync()
+    n_windows = int(counters[:, 1].sum().item())
+
+    batch_step(tune=True)
+    batch_step()
+    batch_step()
+    batch_s = timed(batch_step, steps)
+    batch.sync()
+    batch_ok = check()
+    # per-phase times come from eager launches (events are not recorded
+    # inside graph replays)
+    batch.profile(True)
+    eager_s = timed(lambda: batch.insert(entries, reads, offs, reset=True, stream=stream), steps)
+    phases = batch.profile_read()
+    batch.profile(False)
+    batch.sync()
+    n_distinct = int(counters[:, 0].sum().item())
+    n_words = sum(int(f.layout.X) * int(f.layout.Y) for f in filters)
+    res = {
+        "workload": "batched: 256 read sets, own countBF each",
+        "n_sets": n, "n_reads": sum(rs.n_reads for rs in sets), "n_bases": total,
+        "n_windows": n_windows, "n_distinct": n_distinct,
+        "countbf_bytes_total": n_words * 8,
+        "value": n_windows / batch_s, "plain_value": n_windows / plain_s,
+        "unit": "insertions/s", "speedup_vs_plain": plain_s / batch_s,
+        "ms_per_step": batch_s * 1e3, "plain_ms_per_step": plain_s * 1e3,
+        "eager_ms_per_step": eager_s * 1e3,
+        "steps": steps, "tile": batch.tile, "graph": True,
+        "verified_vs_oracle_digests": {"batched": batch_ok, "plain": plain_ok},
+        "phases": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()},
+        "roofline": roofline_of(phases, total, n_windows, n_distinct, 1, n_words, "batched"),
+        "input_generation_s": round(t_gen, 1),
+    }
+    for f in filters:
+        f.close()
+    batch.close()
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -190,17 +349,7 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     value = n_windows * args.steps / elapsed
     per_phase = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()}
-    dom = max(phases, key=lambda k: phases[k][0]) if phases else None
-    roofline = None
-    if dom:
-        avg_s = phases[dom][0] / phases[dom][1] / 1e3
-        nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, X * Y)
-        achieved = nbytes / avg_s / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic_for(dom, args.workload), "kernel": dom,
-                    "algorithmic_bytes_per_launch": nbytes,
-                    "avg_launch_ms": round(avg_s * 1e3, 4)}
+    roofline = roofline_of(phases, n_bases, n_windows, n_distinct, k_h, X * Y, args.workload)
 
     out = {
         "metric": "k-mer insertions/s",
@@ -224,6 +373,11 @@ def main():
         "phases": per_phase,
         "roofline": roofline,
     }
+    bf.close()
+    del reads, offs, distinct, trust, err
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if "batched" in forms:
+        out["batched"] = batched_leg(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rs, X, Y, args.cpu_sample_reads)
     print(json.dumps(out), flush=True)

@@ -3,10 +3,14 @@
 Calls only ``oracle`` and ``synth``; the GPU parity tests compare the HIP
 path's outputs against these stored digests.  Usage:
 
-    python tests/golden/make_digests.py tiny bacterial
+    python tests/golden/make_digests.py tiny bacterial batched
+
+The batched workload (256 independent read sets, each with its own countBF)
+is stored set by set; its sets run in parallel host processes.
 """
 import hashlib
 import json
+import multiprocessing
 import os
 import sys
 import time
@@ -40,11 +44,36 @@ def digests(name: str, scale: float = 1.0) -> dict:
     }
 
 
+_SETS = []
+
+
+def _one_set(i: int) -> dict:
+    rs = _SETS[i]
+    X, Y = oracle.dims(rs.n_items, 0.001)
+    words, distinct, trust, err, nw = oracle.run_kmerco(rs.reads, rs.offsets, rs.k, rs.tau, X, Y)
+    return {"set": i, "k": rs.k, "tau": rs.tau, "X": X, "Y": Y, "n_reads": rs.n_reads,
+            "n_bases": rs.n_bases, "n_windows": nw, "n_distinct": len(distinct),
+            "n_trust": len(trust), "n_err": len(err), "words_sha256": sha(words),
+            "distinct_sha256": sha(distinct), "trust_sha256": sha(trust),
+            "err_sha256": sha(err)}
+
+
+def batched_digests(scale: float = 1.0, workers: int = 8) -> dict:
+    _SETS[:] = synth.config("batched", scale)
+    t = time.time()
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        per_set = pool.map(_one_set, range(len(_SETS)), chunksize=1)
+    return {"workload": "batched", "scale": scale, "alpha": 8, "k_h": 1,
+            "n_sets": len(per_set), "n_windows": sum(d["n_windows"] for d in per_set),
+            "oracle_seconds_wall": round(time.time() - t, 2), "oracle_processes": workers,
+            "sets": per_set}
+
+
 if __name__ == "__main__":
     oracle.build(force=False)
     for name in sys.argv[1:] or ["tiny", "bacterial"]:
-        d = digests(name)
+        d = batched_digests() if name == "batched" else digests(name)
         path = os.path.join(HERE, f"{name}_digests.json")
         with open(path, "w") as f:
             json.dump(d, f, indent=1)
-        print(path, d)
+        print(path, {k: v for k, v in d.items() if k != "sets"})

@@ -56,11 +56,11 @@ class BatchRun:
         for e in self.entries:
             e["filter"].sync()
             nd = int(e["n_distinct"].item())
-            r = {"words": u(e["filter"].words), "distinct": u(e["distinct"])[:nd].copy(),
+            r = {"words": u(e["filter"].words), "distinct": u(e["distinct"][:nd]),
                  "nw": int(e["n_windows"].item())}
             if "trust" in e:
-                r["trust"] = u(e["trust"])[:int(e["n_trust"].item())].copy()
-                r["err"] = u(e["err"])[:int(e["n_err"].item())].copy()
+                r["trust"] = u(e["trust"][:int(e["n_trust"].item())])
+                r["err"] = u(e["err"][:int(e["n_err"].item())])
             out.append(r)
         return out
 
@@ -201,3 +201,34 @@ def test_batch_argument_errors():
         b.insert(big, run.reads, run.offs)
     with pytest.raises(P.KmercoError):
         b.insert(run.entries, run.reads, run.offs, graph=True, stream=torch.cuda.default_stream())
+
+
+def test_batched_workload_full_size_digests():
+    """All 256 sets of the batched workload at full size in one graph-captured
+    batched call, against the oracle's per-set digests."""
+    import hashlib
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "batched_digests.json")))["sets"]
+    sets = synth.config("batched")
+    cases = [(rs, (r["X"], r["Y"], 8, 1), True) for rs, r in zip(sets, ref)]
+    print(f"case batched workload full size: {len(cases)} sets", flush=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        run = BatchRun(cases, stream=stream)
+        b = P.Batch()
+        b.insert(run.entries, run.reads, run.offs, reset=True, tune=True, stream=stream)
+        b.insert(run.entries, run.reads, run.offs, reset=True, graph=True, stream=stream)
+        got = run.results()
+
+    def h(a):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
+
+    for i, (g, r) in enumerate(zip(got, ref)):
+        assert g["nw"] == r["n_windows"], f"set {i} windows"
+        assert len(g["distinct"]) == r["n_distinct"], f"set {i} distinct count"
+        assert h(g["words"]) == r["words_sha256"], f"set {i} words"
+        assert h(g["distinct"]) == r["distinct_sha256"], f"set {i} distinct"
+        assert h(g["trust"]) == r["trust_sha256"], f"set {i} trust"
+        assert h(g["err"]) == r["err_sha256"], f"set {i} err"
