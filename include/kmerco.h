@@ -212,8 +212,9 @@ const char *kc_phase_name(uint32_t phase);
  * (padding between sets must be reads of invalid bases, e.g. 'N', which add
  * no k-mer).  Each set has its own filter handle (at most one set per
  * handle), created on the batch's device; its countBF may span at most 2048
- * regions of 16384 counters (about 16 MB at alpha = 8) and hold at most
- * 2^28 bases; larger sets go through kc_insert.  The total number of
+ * regions (a region is the largest power-of-two number of cells whose
+ * counters number at most 16384: 2048 cells at alpha = 8, so at most 32 MB
+ * of countBF) and hold at most 2^28 bases; larger sets go through kc_insert.  The total number of
  * (base, hash function) pairs must stay below 2^32.  Outputs per set have the
  * meaning of kc_insert_classify; distinct capacity overflows are sticky in
  * the set's filter (kc_sync on it).
@@ -252,6 +253,124 @@ kc_status kc_batch_set_tile(kc_batch *b, uint64_t tile);
 kc_status kc_batch_profile(kc_batch *b, int enable);
 kc_status kc_batch_profile_read(kc_batch *b, double *ms, uint64_t *launches, uint32_t n_phases);
 kc_status kc_batch_sync(kc_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Serving form: a request loop over device-resident countBFs.
+ *
+ * A session is one countBF with its k and its distinct list, kept on the
+ * device across requests; a request inserts a read set into a session
+ * (continuing the session's sequential order, so that a session's requests
+ * together equal one kc_insert of their concatenated reads) and/or
+ * classifies the session's whole distinct list at a threshold (Algorithm 2
+ * with Query-II).  Sessions are admitted by device memory: a session opened
+ * while the budget is spent waits, with its requests, until closed sessions
+ * have released enough; admission is in order of kc_server_open.
+ *
+ * kc_server_pump() runs the loop once without blocking: it retires finished
+ * batches, admits waiting sessions, and issues new batches while a staging
+ * lane is free.  A batch takes queued requests in arrival order, at most one
+ * per session (a session's requests run in submission order), copies their
+ * reads to the lane on a copy stream and runs them on a compute stream:
+ * the requests whose countBF and size fit the batched form go through one
+ * kc_batch_insert call, the others through kc_insert, then the classify
+ * requests through kc_classify.  With two or more lanes, requests that
+ * arrive while a batch runs are copied in meanwhile and form the next one.
+ * A request's outputs do not depend on which other requests share its batch.
+ *
+ * Memory: the server allocates, and frees on close/destroy, each session's
+ * countBF (8*X*Y bytes), distinct list (8*distinct_cap bytes) and the
+ * per-counter first-seen entries of countBFs too large for the binned path
+ * (4 bytes per counter); these count against memory_budget.  Staging lanes and the shared
+ * scratch of the insert calls are the server's own and do not.
+ * Host memory passed in a request (reads, offsets) must stay valid and
+ * unchanged until the request is done; pinned memory lets the copies run
+ * asynchronously.  Not thread-safe: one host thread drives a server.
+ * ---------------------------------------------------------------------- */
+typedef struct kc_server kc_server;
+
+typedef struct {
+    uint64_t memory_budget;  /* device bytes for admitted sessions */
+    uint64_t lane_bases;     /* staging room of one lane in bases: the largest request */
+    uint64_t lane_reads;     /* staging room of one lane in reads */
+    uint32_t lane_requests;  /* most requests in one batch (1..4096) */
+    uint32_t lanes;          /* batches in flight, 1..8 */
+} kc_server_config;
+
+/* request operations (bit set) */
+#define KC_OP_INSERT 1u
+#define KC_OP_CLASSIFY 2u
+
+typedef struct {
+    uint32_t session;
+    uint32_t op;                   /* KC_OP_INSERT, KC_OP_CLASSIFY or both (insert first) */
+    uint32_t tau;                  /* classification threshold: frequency > tau -> trustworthy */
+    uint32_t reserved;             /* 0 */
+    const uint8_t *reads_host;     /* ASCII bases; host memory */
+    const uint64_t *offsets_host;  /* n_reads + 1 CSR offsets, offsets[0] == 0, non-decreasing */
+    uint64_t n_reads;
+    uint64_t *trust_dev;           /* classify: device outputs, class_cap keys of room each */
+    uint64_t *err_dev;
+    uint64_t class_cap;
+} kc_request;
+
+typedef struct {
+    int32_t status;          /* KC_OK, or KC_ERANGE when the session's distinct list or
+                                class_cap overflowed, KC_ENOMEM when the session could not be
+                                allocated, KC_EDEVICE on a device error */
+    uint32_t done;           /* 1 once the outputs are final */
+    uint64_t n_windows;      /* k-mers inserted (valid windows) */
+    uint64_t distinct_first; /* this request's first-seen k-mers are the session's distinct */
+    uint64_t n_new;          /* keys [distinct_first, distinct_first + n_new) */
+    uint64_t n_trust, n_err; /* classify: counts written to trust_dev / err_dev */
+    double t_submit, t_issue, t_done;  /* seconds since kc_server_create */
+} kc_result;
+
+typedef struct {
+    uint64_t session_bytes;      /* admitted sessions' device bytes */
+    uint64_t staging_bytes;      /* the lanes' device staging */
+    uint32_t sessions_open;      /* admitted */
+    uint32_t sessions_waiting;   /* opened, waiting for memory */
+    uint64_t requests_done;
+    uint64_t batches;            /* lanes issued */
+    uint64_t batched_requests;   /* requests inserted through kc_batch_insert */
+    uint64_t plain_requests;     /* requests inserted through kc_insert */
+    uint32_t max_batch;          /* most requests in one issued lane */
+    uint32_t reserved;
+} kc_server_stats;
+
+/* Create a server on the current device.  KC_EINVAL for a bad config. */
+kc_status kc_server_create(const kc_server_config *cfg, kc_server **out);
+/* Wait for all work, free every session and the staging. */
+void kc_server_destroy(kc_server *s);
+/* Open a session for a countBF of this layout and k-mer length k, with room
+ * for distinct_cap distinct k-mers; *session receives its id at once, and
+ * the session is admitted when its bytes fit the budget.  KC_ENOMEM if they
+ * exceed the whole budget, KC_EINVAL for a bad layout or k. */
+kc_status kc_server_open(kc_server *s, const kc_layout *layout, uint32_t k,
+                         uint64_t distinct_cap, uint32_t *session);
+/* Close a session: after its submitted requests are done its memory is
+ * released; further submits to it fail with KC_ESTATE. */
+kc_status kc_server_close(kc_server *s, uint32_t session);
+/* Queue a request; *ticket identifies it.  Validates the request on the host
+ * (offsets monotone and within the staging room, outputs present) and
+ * returns KC_EINVAL / KC_ERANGE without queuing it otherwise. */
+kc_status kc_server_submit(kc_server *s, const kc_request *req, uint64_t *ticket);
+/* Run the loop once without blocking; *n_done (may be NULL) receives the
+ * number of requests retired by this call. */
+kc_status kc_server_pump(kc_server *s, uint32_t *n_done);
+/* Pump until the ticket's request is done (ticket 0: until all are). */
+kc_status kc_server_wait(kc_server *s, uint64_t ticket);
+/* The ticket's result so far (done == 0 while queued or running). */
+kc_status kc_server_result(const kc_server *s, uint64_t ticket, kc_result *out);
+/* Copy n keys of a session's distinct list, from index first, to host
+ * memory (waits for the session's issued work).  KC_ERANGE past the end. */
+kc_status kc_server_read_distinct(kc_server *s, uint32_t session, uint64_t first, uint64_t n,
+                                  uint64_t *dst_host);
+/* Copy a session's countBF cells (8*X*Y bytes) to host memory (waits). */
+kc_status kc_server_read_words(kc_server *s, uint32_t session, uint64_t *dst_host);
+kc_status kc_server_stats_get(const kc_server *s, kc_server_stats *out);
+/* Seconds since kc_server_create on the server's clock. */
+double kc_server_now(const kc_server *s);
 
 #ifdef __cplusplus
 }

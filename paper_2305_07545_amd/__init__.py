@@ -9,6 +9,7 @@ from .kmerco import (  # noqa: F401
     KmercoError,
     LIB_PATH,
     SIGNATURES,
+    Server,
     dims,
     eta,
     load_library,

@@ -87,12 +87,12 @@ kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
     return KC_OK;
 }
 
-kc_status ensure_positions(kc_filter *f, uint64_t n) { return ensure_positions(f->W, f->last, n); }
-kc_status ensure_tiles(kc_filter *f, uint64_t n) { return ensure_tiles(f->W, f->last, n); }
+kc_status ensure_positions(kc_filter *f, uint64_t n) { return ensure_positions(*f->W, f->last, n); }
+kc_status ensure_tiles(kc_filter *f, uint64_t n) { return ensure_tiles(*f->W, f->last, n); }
 
 // binned-path buffers for one chunk of the given plan
 kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
-    kc::Workspace &W = f->W;
+    kc::Workspace &W = *f->W;
     const uint64_t n_mat = (uint64_t)B.n_regions * B.G;
     const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
     const uint64_t n_slots = chunk_positions * f->layout.k_h;
@@ -138,7 +138,7 @@ kc_status ensure_scalars(kc::Workspace &W) {
     return KC_OK;
 }
 
-kc_status ensure_scalars(kc_filter *f) { return ensure_scalars(f->W); }
+kc_status ensure_scalars(kc_filter *f) { return ensure_scalars(*f->W); }
 
 // first-seen workspace of the direct path: one entry per counter
 kc_status ensure_aux(kc_filter *f, hipStream_t s) {
@@ -174,7 +174,7 @@ void free_workspace(kc::Workspace &W) {
 }
 
 void free_all(kc_filter *f) {
-    free_workspace(f->W);
+    free_workspace(f->own);
     dev_free(f->F.aux);
     dev_free(f->status);
 }
@@ -224,6 +224,19 @@ uint64_t next_prime_after(uint64_t n) {
     }
 }
 
+void share_workspace(kc_filter *f, kc::Workspace *W) { f->W = W ? W : &f->own; }
+
+uint64_t filter_private_bytes(const kc_layout &layout) {
+    kc::FilterArgs F{};
+    F.X = layout.X;
+    F.Y = layout.Y;
+    F.eta = 64u / layout.alpha;
+    kc::BinPlan plan{};
+    if (path_from_env() != KcPath::Direct && kc::bin_plan(F, 1u << 16, plan))
+        return 0;
+    return layout.X * layout.Y * F.eta * sizeof(uint32_t);
+}
+
 }  // namespace kcapi
 
 namespace {
@@ -260,12 +273,12 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     } else if ((st = ensure_aux(f, s)) != KC_OK) {
         return st;
     }
-    hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, f->W, s, &f->prof);
+    hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, *f->W, s, &f->prof);
     if (e == hipSuccess && binned)  // valid windows, accumulated by the bin passes
-        e = kc::fill_u64(f->W.totals + 5, 1, 0ull, s);
+        e = kc::fill_u64(f->W->totals + 5, 1, 0ull, s);
     if (e != hipSuccess)
         return KC_EDEVICE;
-    kc::ReadsArgs R{f->W.codes, f->W.inv, f->W.rs, n_bases, k};
+    kc::ReadsArgs R{f->W->codes, f->W->inv, f->W->rs, n_bases, k};
     const uint64_t chunk = binned ? bchunk : f->chunk;
     // this call's classification can be taken from the region pass when the
     // final counter of each distinct k-mer's single slot is known there
@@ -273,14 +286,14 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk) {
         uint64_t c1 = c0 + chunk < n_bases ? c0 + chunk : n_bases;
         if (binned)
-            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, f->W, fused, tau, s, &f->prof);
+            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, *f->W, fused, tau, s, &f->prof);
         else
-            e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, f->W, s, &f->prof);
+            e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, *f->W, s, &f->prof);
         if (e != hipSuccess)
             return KC_EDEVICE;
         f->zero = false;
     }
-    e = kc::launch_distinct(R, f->W, distinct, cap_d, n_distinct, n_windows,
+    e = kc::launch_distinct(R, *f->W, distinct, cap_d, n_distinct, n_windows,
                             fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status,
                             binned, s, &f->prof);
     if (e != hipSuccess)
@@ -288,8 +301,8 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     if (split && !fused) {
         // classify the keys this call appended: distinct[base .. *n_distinct),
         // base saved by the distinct output step
-        e = kc::launch_classify(f->F, distinct, n_distinct, f->W.totals + 3, n_bases, cap_d, tau,
-                                trust, n_trust, err, n_err, cap_te, f->status, f->W, s,
+        e = kc::launch_classify(f->F, distinct, n_distinct, f->W->totals + 3, n_bases, cap_d, tau,
+                                trust, n_trust, err, n_err, cap_te, f->status, *f->W, s,
                                 &f->prof);
         if (e != hipSuccess)
             return KC_EDEVICE;
@@ -345,6 +358,7 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     if (!f)
         return KC_ENOMEM;
     f->layout = *layout;
+    f->W = &f->own;
     f->device = dev;
     f->zero = zero != 0;
     f->k = 0;
@@ -484,7 +498,7 @@ kc_status kc_classify(kc_filter *f, const uint64_t *keys_dev, const uint64_t *n_
         return st;
     hipError_t e = kc::launch_classify(f->F, keys_dev, n_keys_dev, nullptr, keys_cap, keys_cap,
                                        tau, trust_dev, n_trust_dev, err_dev, n_err_dev, keys_cap,
-                                       nullptr, f->W, s, &f->prof);
+                                       nullptr, *f->W, s, &f->prof);
     return e == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 

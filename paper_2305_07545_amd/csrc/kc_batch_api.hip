@@ -338,6 +338,11 @@ kc_status validate(const kc_set *sets, uint32_t n_sets, const uint8_t *reads,
 
 }  // namespace
 
+bool kcapi::batchable(const kc_filter *f) {
+    kc::BinPlan bp{};
+    return kc::bin_plan(f->F, kc::kBinChunk, bp) && bp.n_regions <= kc::kBatchMaxRegions;
+}
+
 extern "C" {
 
 kc_status kc_batch_create(kc_batch **out) {

@@ -11,7 +11,10 @@ enum class KcPath { Auto, Direct, Binned };
 struct kc_filter {
     kc_layout layout;
     kc::FilterArgs F;
-    kc::Workspace W;
+    kc::Workspace own;     // scratch of this handle's calls
+    kc::Workspace *W;      // &own, or a workspace shared by handles whose calls
+                           // are all ordered on one stream
+
     int device;
     bool zero;             // every counter of the filter is zero
     uint32_t k;            // k of the first insert, 0 before it
@@ -44,9 +47,21 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
+bool valid_layout(const kc_layout *L);
 kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n);
 kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n);
 kc_status ensure_scalars(kc::Workspace &W);
 void free_workspace(kc::Workspace &W);
+
+// Use W (owned by the caller, outliving f) instead of the handle's own
+// scratch.  Every call on every handle sharing W must be enqueued on one
+// stream, which is then also the stream waited on before W grows.
+void share_workspace(kc_filter *f, kc::Workspace *W);
+// Device bytes a handle of this layout allocates for itself on first insert
+// besides the shared scratch (the direct path's per-counter first-seen
+// entries), 0 for layouts that take the binned path.
+uint64_t filter_private_bytes(const kc_layout &layout);
+// Whether a handle can be a set of a kc_batch_insert call.
+bool batchable(const kc_filter *f);
 
 }  // namespace kcapi

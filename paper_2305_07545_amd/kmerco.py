@@ -46,6 +46,39 @@ class kc_set(ctypes.Structure):
 KC_BATCH_RESET, KC_BATCH_GRAPH, KC_BATCH_TUNE = 1, 2, 4
 SET_ALIGN = 4096
 
+
+class kc_server_config(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_uint64), ("lane_bases", ctypes.c_uint64),
+                ("lane_reads", ctypes.c_uint64), ("lane_requests", ctypes.c_uint32),
+                ("lanes", ctypes.c_uint32)]
+
+
+class kc_request(ctypes.Structure):
+    _fields_ = [("session", ctypes.c_uint32), ("op", ctypes.c_uint32),
+                ("tau", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("reads_host", ctypes.c_void_p), ("offsets_host", ctypes.c_void_p),
+                ("n_reads", ctypes.c_uint64), ("trust_dev", ctypes.c_void_p),
+                ("err_dev", ctypes.c_void_p), ("class_cap", ctypes.c_uint64)]
+
+
+class kc_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("done", ctypes.c_uint32),
+                ("n_windows", ctypes.c_uint64), ("distinct_first", ctypes.c_uint64),
+                ("n_new", ctypes.c_uint64), ("n_trust", ctypes.c_uint64),
+                ("n_err", ctypes.c_uint64), ("t_submit", ctypes.c_double),
+                ("t_issue", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class kc_server_stats(ctypes.Structure):
+    _fields_ = [("session_bytes", ctypes.c_uint64), ("staging_bytes", ctypes.c_uint64),
+                ("sessions_open", ctypes.c_uint32), ("sessions_waiting", ctypes.c_uint32),
+                ("requests_done", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("batched_requests", ctypes.c_uint64), ("plain_requests", ctypes.c_uint64),
+                ("max_batch", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+KC_OP_INSERT, KC_OP_CLASSIFY = 1, 2
+
 _lib = None
 
 # every symbol include/kmerco.h declares, with (restype, argtypes)
@@ -80,6 +113,18 @@ SIGNATURES = {
     "kc_batch_profile": (_i, [_vp, _i]),
     "kc_batch_profile_read": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64), _u32]),
     "kc_batch_sync": (_i, [_vp]),
+    "kc_server_create": (_i, [ctypes.POINTER(kc_server_config), ctypes.POINTER(_vp)]),
+    "kc_server_destroy": (None, [_vp]),
+    "kc_server_open": (_i, [_vp, ctypes.POINTER(kc_layout), _u32, _u64, ctypes.POINTER(_u32)]),
+    "kc_server_close": (_i, [_vp, _u32]),
+    "kc_server_submit": (_i, [_vp, ctypes.POINTER(kc_request), ctypes.POINTER(_u64)]),
+    "kc_server_pump": (_i, [_vp, ctypes.POINTER(_u32)]),
+    "kc_server_wait": (_i, [_vp, _u64]),
+    "kc_server_result": (_i, [_vp, _u64, ctypes.POINTER(kc_result)]),
+    "kc_server_read_distinct": (_i, [_vp, _u32, _u64, _u64, _vp]),
+    "kc_server_read_words": (_i, [_vp, _u32, _vp]),
+    "kc_server_stats_get": (_i, [_vp, ctypes.POINTER(kc_server_stats)]),
+    "kc_server_now": (ctypes.c_double, [_vp]),
 }
 
 PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
@@ -430,3 +475,117 @@ class Batch:
 
     def sync(self):
         _check(self.lib.kc_batch_sync(self._h), "kc_batch_sync")
+
+
+def _host_ptr(a):
+    """Address of a host buffer: a numpy array or a CPU torch tensor."""
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda or not a.is_contiguous():
+            raise ValueError("request buffers must be contiguous host memory")
+        return a.data_ptr()
+    import numpy as np
+    if not isinstance(a, np.ndarray) or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("request buffers must be contiguous host memory")
+    return a.ctypes.data
+
+
+class Server:
+    """kc_server: sessions of device-resident countBFs served by a request
+    loop with continuous batching (see the kc_server entry points)."""
+
+    def __init__(self, memory_budget: int, lane_bases: int, lane_reads: int,
+                 lane_requests: int = 64, lanes: int = 2):
+        self.lib = load_library()
+        cfg = kc_server_config(int(memory_budget), int(lane_bases), int(lane_reads),
+                               int(lane_requests), int(lanes))
+        h = ctypes.c_void_p(None)
+        _check(self.lib.kc_server_create(ctypes.byref(cfg), ctypes.byref(h)), "kc_server_create")
+        self._h = h
+        self._keep = {}  # ticket -> host buffers the request reads from
+
+    def close_server(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.kc_server_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close_server()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def open(self, X: int, Y: int, k: int, distinct_cap: int, alpha: int = 8, k_h: int = 1) -> int:
+        sid = ctypes.c_uint32(0)
+        lay = kc_layout(int(X), int(Y), int(alpha), int(k_h))
+        _check(self.lib.kc_server_open(self._h, ctypes.byref(lay), int(k), int(distinct_cap),
+                                       ctypes.byref(sid)), "kc_server_open")
+        return int(sid.value)
+
+    def close(self, session: int):
+        _check(self.lib.kc_server_close(self._h, int(session)), "kc_server_close")
+
+    def submit(self, session: int, reads=None, offsets=None, classify: bool = False,
+               insert: bool = True, tau: int = 0, trust=None, err=None) -> int:
+        """reads: uint8 host buffer, offsets: uint64 host CSR (offsets[0] == 0);
+        trust/err: device int64 tensors for a classify request."""
+        q = kc_request()
+        q.session = int(session)
+        q.op = (KC_OP_INSERT if insert else 0) | (KC_OP_CLASSIFY if classify else 0)
+        q.tau = int(tau)
+        keep = []
+        if insert:
+            q.reads_host = _host_ptr(reads)
+            q.offsets_host = _host_ptr(offsets)
+            q.n_reads = (offsets.numel() if isinstance(offsets, torch.Tensor) else len(offsets)) - 1
+            keep += [reads, offsets]
+        if classify:
+            _require(trust, torch.int64, "trust")
+            _require(err, torch.int64, "err")
+            q.trust_dev = trust.data_ptr()
+            q.err_dev = err.data_ptr()
+            q.class_cap = min(trust.numel(), err.numel())
+            keep += [trust, err]
+        t = ctypes.c_uint64(0)
+        _check(self.lib.kc_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)),
+               "kc_server_submit")
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def pump(self) -> int:
+        n = ctypes.c_uint32(0)
+        _check(self.lib.kc_server_pump(self._h, ctypes.byref(n)), "kc_server_pump")
+        return int(n.value)
+
+    def wait(self, ticket: int = 0):
+        _check(self.lib.kc_server_wait(self._h, int(ticket)), "kc_server_wait")
+
+    def result(self, ticket: int) -> dict:
+        r = kc_result()
+        _check(self.lib.kc_server_result(self._h, int(ticket), ctypes.byref(r)),
+               "kc_server_result")
+        if r.done:
+            self._keep.pop(int(ticket), None)
+        return {f: getattr(r, f) for f, _ in kc_result._fields_}
+
+    def read_distinct(self, session: int, first: int, n: int):
+        import numpy as np
+        out = np.zeros(max(int(n), 1), dtype=np.uint64)
+        _check(self.lib.kc_server_read_distinct(self._h, int(session), int(first), int(n),
+                                                out.ctypes.data), "kc_server_read_distinct")
+        return out[:int(n)]
+
+    def read_words(self, session: int, n_words: int):
+        import numpy as np
+        out = np.zeros(int(n_words), dtype=np.uint64)
+        _check(self.lib.kc_server_read_words(self._h, int(session), out.ctypes.data),
+               "kc_server_read_words")
+        return out
+
+    def stats(self) -> dict:
+        st = kc_server_stats()
+        _check(self.lib.kc_server_stats_get(self._h, ctypes.byref(st)), "kc_server_stats_get")
+        return {f: getattr(st, f) for f, _ in kc_server_stats._fields_}
+
+    def now(self) -> float:
+        return float(self.lib.kc_server_now(self._h))

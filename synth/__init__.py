@@ -13,3 +13,4 @@ from .reads import (  # noqa: F401
     random_reads,
     reads_from_strings,
 )
+from .serving import Request, ServingWorkload, sample_reads_fast, serving_workload  # noqa: F401
