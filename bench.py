@@ -41,8 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--forms", default="batched",
-                    help="comma list of extra forms to measure: batched, or none")
+    ap.add_argument("--forms", default="batched,serving",
+                    help="comma list of extra forms to measure: batched, serving, or none")
+    ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--form-steps", type=int, default=5)
     return ap.parse_args()
 
@@ -277,6 +278,106 @@ def _batched_leg(args, dev, sets, stream, t_gen):
     return res
 
 
+def serving_leg(args, dev):
+    """The serving trace replayed in real time: Poisson arrivals (50/s) of
+    insert / insert+classify requests on 16 device-resident sessions under a
+    200 GB budget.  Latency = completion - submission on the server clock;
+    throughput = k-mers inserted / (last completion - first submission)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2305_07545_amd as P
+    from paper_2305_07545_amd import serve
+    import synth
+
+    t_gen = time.perf_counter()
+    w = synth.serving_workload(duration_s=args.serving_seconds)
+    n = len(w.requests)
+    # pinned host copies: the requests' reads are runs of these pools
+    pools = [torch.from_numpy(r).pin_memory() for r, _ in w.pools]
+    n_off = sum(q.n_reads + 1 for q in w.requests)
+    offs_all = torch.empty(n_off, dtype=torch.int64).pin_memory()
+    bufs, pos, expect_windows = [], 0, 0
+    for i, q in enumerate(w.requests):
+        _, o = w.request_reads(i)
+        lo = int(w.pools[q.genome][1][q.first_read])
+        view = offs_all[pos:pos + len(o)]
+        view.copy_(torch.from_numpy(o.view(np.int64)))
+        bufs.append((pools[q.genome][lo:lo + int(o[-1])], view))
+        pos += len(o)
+        lens = np.diff(o.astype(np.int64))
+        expect_windows += int(np.maximum(lens - w.ks[q.genome] + 1, 0).sum())
+    t_gen = time.perf_counter() - t_gen
+
+    budget = 200 * 10**9
+    server = P.Server(memory_budget=budget,
+                      lane_bases=max(w.request_bases(i) for i in range(n)),
+                      lane_reads=max(q.n_reads for q in w.requests), lane_requests=64, lanes=2)
+    caps = [int(math.ceil(1.2 * d)) + 4096 for d in w.expected_distinct]
+    dims = [P.dims(x) for x in w.n_items]
+    sessions = [server.open(X, Y, w.ks[g], caps[g]) for g, (X, Y) in enumerate(dims)]
+    outs = [(torch.empty(c, dtype=torch.int64, device=dev), torch.empty(c, dtype=torch.int64,
+                                                                         device=dev))
+            for c in caps]
+
+    def submit(i):
+        q = w.requests[i]
+        reads, offs = bufs[i]
+        kw = {}
+        if q.classify:
+            kw = {"classify": True, "tau": q.tau, "trust": outs[q.genome][0],
+                  "err": outs[q.genome][1]}
+        return server.submit(sessions[q.genome], reads, offs, **kw)
+
+    res = serve.replay(server, [q.t for q in w.requests], submit)
+    st = server.stats()
+    server.close_server()
+
+    # capacity: the same requests all submitted at once to fresh sessions
+    sat = P.Server(memory_budget=budget,
+                   lane_bases=max(w.request_bases(i) for i in range(n)),
+                   lane_reads=max(q.n_reads for q in w.requests), lane_requests=64, lanes=2)
+    server = sat  # submit() now targets the fresh server and its sessions
+    sessions[:] = [sat.open(X, Y, w.ks[g], caps[g]) for g, (X, Y) in enumerate(dims)]
+    res_sat = serve.replay(sat, [0.0] * n, submit)
+    sat_span = max(r["t_done"] for r in res_sat) - min(r["t_submit"] for r in res_sat)
+    sat_ok = [r["n_windows"] for r in res_sat] == [r["n_windows"] for r in res] and \
+        [r["n_new"] for r in res_sat] == [r["n_new"] for r in res] and \
+        all(r["status"] == 0 for r in res_sat)
+    sat_st = sat.stats()
+    ok = all(r["status"] == 0 for r in res)
+    windows = sum(r["n_windows"] for r in res)
+    nxt = [0] * len(sessions)
+    for i, q in enumerate(w.requests):  # each request continues its session's list
+        ok &= res[i]["distinct_first"] == nxt[q.genome]
+        nxt[q.genome] += res[i]["n_new"]
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    out = {
+        "workload": "serving: 16 sessions, Poisson 50 req/s, 10k-2M reads per request",
+        "requests": n, "duration_s": args.serving_seconds,
+        "classify_requests": sum(q.classify for q in w.requests),
+        "n_bases": sum(w.request_bases(i) for i in range(n)),
+        "n_windows": windows, "value": windows / span, "unit": "insertions/s",
+        "latency": serve.latency_summary(res),
+        "checks": {"statuses_ok_and_lists_contiguous": bool(ok),
+                   "windows_equal_sum_of_L_minus_k_plus_1": windows == expect_windows},
+        "memory_budget_bytes": budget, "session_bytes": st["session_bytes"],
+        "staging_bytes": st["staging_bytes"], "batches": st["batches"],
+        "batched_requests": st["batched_requests"], "plain_requests": st["plain_requests"],
+        "max_batch": st["max_batch"],
+        "saturated": {"value": windows / sat_span, "unit": "insertions/s",
+                      "makespan_s": sat_span, "latency": serve.latency_summary(res_sat),
+                      "batches": sat_st["batches"], "max_batch": sat_st["max_batch"],
+                      "same_counts_as_paced_run": bool(sat_ok)},
+        "countbf_bytes": [X * Y * 8 for X, Y in dims],
+        "input_generation_s": round(t_gen, 1),
+    }
+    sat.close_server()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -378,6 +479,8 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if "batched" in forms:
         out["batched"] = batched_leg(args, dev)
+    if "serving" in forms:
+        out["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rs, X, Y, args.cpu_sample_reads)
     print(json.dumps(out), flush=True)
