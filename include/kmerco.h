@@ -192,7 +192,9 @@ typedef enum {
     KC_PHASE_REGION = 13,         /* binned path: LDS counting + first-seen per region */
     KC_PHASE_TILE_COUNT = 14,     /* per-tile distinct / trustworthy / window counts */
     KC_PHASE_BIN_REGION = 15,     /* binned path: bucket slices -> region segments */
-    KC_PHASE_COUNT = 16
+    KC_PHASE_BIN_PART = 16,       /* partitioned path: entries grouped by partition */
+    KC_PHASE_PART_COUNT = 17,     /* partitioned path: per-partition region counts */
+    KC_PHASE_COUNT = 18
 } kc_phase;
 
 kc_status kc_profile(kc_filter *f, int enable);

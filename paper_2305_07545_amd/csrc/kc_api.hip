@@ -114,6 +114,9 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     }
     if (!W.slots || n_slots > W.slots_cap) {
         dev_free(W.slots);
+        // the partitioned path's arrays are sized with the slots: drop them
+        dev_free(W.parts);
+        dev_free(W.plist);
         W.slots_cap = 0;
         if (!dev_alloc(&W.slots, n_slots))
             return KC_ENOMEM;
@@ -130,10 +133,66 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     return KC_OK;
 }
 
+// partitioned binned-path buffers for one chunk of the given plan
+kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
+    kc::Workspace &W = *f->W;
+    const uint64_t n_slots = chunk_positions * f->layout.k_h;
+    const uint64_t n_pmat = (uint64_t)B.n_parts * B.G;
+    const uint64_t n_mat = kc::kMaxMatrix;  // a pass: regions x list workgroups
+    const uint64_t n_coarse = (uint64_t)kc::kMaxBuckets * kc::kMaxListTiles;
+    const uint64_t n_scan = n_pmat > n_mat ? n_pmat : n_mat;
+    if (W.plist && W.pbounds && n_slots <= W.slots_cap && n_slots <= W.entries_cap &&
+        n_pmat <= W.pmat_cap && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap &&
+        n_scan <= W.matrix_cap)
+        return KC_OK;
+    wait_idle(f);
+    if (!W.pbounds && (!dev_alloc(&W.pbounds, kc::kMaxParts + 1) ||
+                       hipHostMalloc((void **)&W.pbounds_host, (kc::kMaxParts + 1) * sizeof(uint32_t),
+                                     hipHostMallocDefault) != hipSuccess))
+        return KC_ENOMEM;
+    if (!W.matrix || n_scan > W.matrix_cap || n_coarse > W.coarse_cap) {
+        dev_free(W.matrix);
+        dev_free(W.coarse);
+        dev_free(W.partial32);
+        W.matrix_cap = W.coarse_cap = 0;
+        if (!dev_alloc(&W.matrix, n_scan) || !dev_alloc(&W.coarse, n_coarse) ||
+            !dev_alloc(&W.partial32, kc::scan_partials(n_scan)))
+            return KC_ENOMEM;
+        W.matrix_cap = n_scan;
+        W.coarse_cap = n_coarse;
+    }
+    if (!W.pmat || n_pmat > W.pmat_cap) {
+        dev_free(W.pmat);
+        W.pmat_cap = 0;
+        if (!dev_alloc(&W.pmat, n_pmat))
+            return KC_ENOMEM;
+        W.pmat_cap = n_pmat;
+    }
+    if (!W.slots || !W.plist || n_slots > W.slots_cap) {
+        dev_free(W.slots);
+        dev_free(W.parts);
+        dev_free(W.plist);
+        W.slots_cap = 0;
+        if (!dev_alloc(&W.slots, n_slots) || !dev_alloc(&W.parts, n_slots) ||
+            !dev_alloc(&W.plist, n_slots))
+            return KC_ENOMEM;
+        W.slots_cap = n_slots;
+    }
+    if (!W.entries || n_slots > W.entries_cap) {
+        dev_free(W.entries);
+        dev_free(W.bucketed);
+        W.entries_cap = 0;
+        if (!dev_alloc(&W.entries, n_slots) || !dev_alloc(&W.bucketed, n_slots))
+            return KC_ENOMEM;
+        W.entries_cap = n_slots;
+    }
+    return KC_OK;
+}
+
 kc_status ensure_scalars(kc::Workspace &W) {
     if (W.totals)
         return KC_OK;
-    if (!dev_alloc(&W.totals, 8) || !dev_alloc(&W.n_entries, 2))
+    if (!dev_alloc(&W.totals, 8) || !dev_alloc(&W.n_entries, 4))
         return KC_ENOMEM;
     return KC_OK;
 }
@@ -169,6 +228,14 @@ void free_workspace(kc::Workspace &W) {
     dev_free(W.slots);
     dev_free(W.bucketed);
     dev_free(W.entries);
+    dev_free(W.parts);
+    dev_free(W.plist);
+    dev_free(W.pmat);
+    dev_free(W.pbounds);
+    if (W.pbounds_host)
+        (void)hipHostFree(W.pbounds_host);
+    W.pbounds_host = nullptr;
+    W.slots_cap = W.entries_cap = W.matrix_cap = W.coarse_cap = W.pmat_cap = 0;
     dev_free(W.totals);
     dev_free(W.n_entries);
 }
@@ -209,6 +276,32 @@ KcPath path_from_env() {
     return KcPath::Auto;
 }
 
+// Partition size of the partitioned binned path: kc::kPartLog regions, or
+// fewer with KMERCO_PART_LOG (so that small countBFs can exercise it).
+uint32_t part_log_from_env() {
+    uint64_t v = env_u64("KMERCO_PART_LOG", kc::kPartLog);
+    return v > kc::kPartLog ? kc::kPartLog : (uint32_t)v;
+}
+
+// The binned plan and chunk size for an insert of n_bases positions; false
+// when the direct path is taken.
+bool choose_plan(const kc_filter *f, uint64_t n_bases, kc::BinPlan &plan, uint64_t &chunk) {
+    if (f->path == KcPath::Direct)
+        return false;
+    chunk = n_bases < f->bin_chunk ? n_bases : f->bin_chunk;
+    if (!kc::bin_plan(f->F, chunk, plan, f->part_log))
+        return false;
+    if (plan.n_parts) {
+        chunk = n_bases < f->part_chunk ? n_bases : f->part_chunk;
+        return kc::bin_plan(f->F, chunk, plan, f->part_log);
+    }
+    return true;
+}
+
+kc_status ensure_plan(kc_filter *f, const kc::BinPlan &plan, uint64_t chunk) {
+    return plan.n_parts ? ensure_parts(f, plan, chunk) : ensure_binned(f, plan, chunk);
+}
+
 uint64_t next_prime_after(uint64_t n) {
     for (uint64_t p = n + 1;; p++) {
         if (p < 2)
@@ -232,7 +325,7 @@ uint64_t filter_private_bytes(const kc_layout &layout) {
     F.Y = layout.Y;
     F.eta = 64u / layout.alpha;
     kc::BinPlan plan{};
-    if (path_from_env() != KcPath::Direct && kc::bin_plan(F, 1u << 16, plan))
+    if (path_from_env() != KcPath::Direct && kc::bin_plan(F, 1u << 16, plan, part_log_from_env()))
         return 0;
     return layout.X * layout.Y * F.eta * sizeof(uint32_t);
 }
@@ -263,12 +356,12 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     if ((st = ensure_positions(f, n_bases)) != KC_OK || (st = ensure_tiles(f, n_bases)) != KC_OK)
         return st;
     kc::BinPlan plan{};
-    const uint64_t bchunk = n_bases < f->bin_chunk ? n_bases : f->bin_chunk;
-    bool binned = f->path != KcPath::Direct && kc::bin_plan(f->F, bchunk, plan);
+    uint64_t bchunk = 0;
+    const bool binned = choose_plan(f, n_bases, plan, bchunk);
     if (f->path == KcPath::Binned && !binned)
         return KC_EINVAL;  // forced binned path but the filter does not fit it
     if (binned) {
-        if ((st = ensure_binned(f, plan, bchunk)) != KC_OK)
+        if ((st = ensure_plan(f, plan, bchunk)) != KC_OK)
             return st;
     } else if ((st = ensure_aux(f, s)) != KC_OK) {
         return st;
@@ -365,6 +458,8 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     f->last = (hipStream_t)stream;
     f->chunk = chunk_size(kc::kChunk);
     f->bin_chunk = chunk_size(kc::kBinChunk);
+    f->part_chunk = chunk_size(kc::kPartChunk);
+    f->part_log = part_log_from_env();
     f->path = path_from_env();
     kc::FilterArgs &F = f->F;
     F.words = words_dev;
@@ -421,9 +516,9 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases) {
     if (st != KC_OK || max_bases == 0)
         return st;
     kc::BinPlan plan{};
-    const uint64_t bchunk = max_bases < f->bin_chunk ? max_bases : f->bin_chunk;
-    if (f->path != KcPath::Direct && kc::bin_plan(f->F, bchunk, plan))
-        return ensure_binned(f, plan, bchunk);
+    uint64_t bchunk = 0;
+    if (choose_plan(f, max_bases, plan, bchunk))
+        return ensure_plan(f, plan, bchunk);
     return ensure_aux(f, f->last);
 }
 
@@ -576,7 +671,7 @@ const char *kc_phase_name(uint32_t phase) {
     static const char *names[kc::kPhCount] = {
         "ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
         "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
-        "region", "tile_count", "bin_region"};
+        "region", "tile_count", "bin_region", "bin_part", "part_count"};
     return phase < (uint32_t)kc::kPhCount ? names[phase] : "unknown";
 }
 

@@ -39,17 +39,24 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
 constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
 static_assert(kStage == (1 << kStageLog), "stage size");
 static_assert(kRegionCounters == (1 << kLocalBits), "region size");
+static_assert(kMaxRegions == (1u << kPartLog), "partition size");
+static_assert(kMaxParts <= 256, "partition ids are bytes");
 
 }  // namespace
 
+// kParts: the partitioned path; the slot id holds the region within its
+// partition, parts[] the partition, and the histogram counts partitions.
+template <bool kParts>
 __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                       uint64_t c1, BinPlan B,
                                                       uint32_t *__restrict__ slots,
+                                                      uint8_t *__restrict__ parts,
                                                       uint32_t *__restrict__ fine,
                                                       unsigned long long *__restrict__ n_valid) {
-    extern __shared__ uint32_t s_hist[];  // n_regions region counts
+    extern __shared__ uint32_t s_hist[];  // n_regions region (n_parts partition) counts
     __shared__ uint32_t s_valid;
-    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
+    const uint32_t n_keys = kParts ? B.n_parts : B.n_regions;
+    for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
         s_hist[i] = 0;
     if (threadIdx.x == 0)
         s_valid = 0;
@@ -76,9 +83,16 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                 uint32_t l;
                 slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
                 const uint32_t r = (uint32_t)(word >> shift);
-                const uint32_t id = (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
-                slots[(uint64_t)(a - 1) * len + (p - c0)] = id;
-                atomicAdd(&s_hist[r], 1u);
+                const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
+                const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
+                const uint64_t at = (uint64_t)(a - 1) * len + (p - c0);
+                slots[at] = id;
+                if (kParts) {
+                    parts[at] = (uint8_t)(r >> B.part_log);
+                    atomicAdd(&s_hist[r >> B.part_log], 1u);
+                } else {
+                    atomicAdd(&s_hist[r], 1u);
+                }
             }
         } else if (in) {
             for (uint32_t a = 1; a <= F.k_h; a++)
@@ -87,7 +101,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
+    for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
         fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
     if (threadIdx.x == 0)
         atomicAdd(n_valid, (unsigned long long)s_valid);
@@ -299,6 +313,218 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
     }
 }
 
+// ---------------------------------------------------------------------------
+// partitioned path: countBFs of more than kMaxRegions regions
+// ---------------------------------------------------------------------------
+
+// bounds[p] = start of partition p in the partition list (the scanned
+// partition-major matrix), bounds[n_parts] = total
+__global__ void k_part_bounds(const uint32_t *__restrict__ pmat, uint32_t G, uint32_t n_parts,
+                              const uint32_t *__restrict__ total, uint32_t *__restrict__ bounds) {
+    for (uint32_t p = threadIdx.x; p <= n_parts; p += blockDim.x)
+        bounds[p] = p < n_parts ? pmat[(uint64_t)p * G] : *total;
+}
+
+// Slot ids of this workgroup's positions -> runs of the partition list
+// (entry = t << 32 | slot id), counting-sorted by partition in LDS batches of
+// kStage entries like the level-1 pass.
+__global__ void __launch_bounds__(kBinWG) k_part_scatter(uint64_t c0, uint64_t c1, uint32_t k_h,
+                                                         BinPlan B,
+                                                         const uint32_t *__restrict__ slots,
+                                                         const uint8_t *__restrict__ parts,
+                                                         const uint32_t *__restrict__ pmat_off,
+                                                         uint64_t *__restrict__ plist) {
+    constexpr int kPer = kStage / kBinWG;
+    __shared__ uint64_t s_stage[kStage];
+    __shared__ uint8_t s_tag[kStage];  // partition of each staged entry
+    __shared__ uint32_t s_cnt[kMaxParts];
+    __shared__ uint32_t s_start[kMaxParts];
+    __shared__ uint32_t s_fill[kMaxParts];
+    __shared__ uint32_t s_cursor[kMaxParts];
+    __shared__ uint32_t s_wave[kBinWG / 64];
+    static_assert(kMaxParts <= kBinWG, "one thread per partition count");
+    const uint64_t len = c1 - c0;
+    const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;
+    const uint64_t g1 = g0 + B.tile < len ? g0 + B.tile : len;
+    uint32_t bl = 0;
+    while ((1u << bl) < k_h)
+        bl++;
+    const uint32_t batch_log = kStageLog - bl;
+    const uint64_t batch = 1ull << batch_log;
+    const uint64_t cap = B.entries_cap;
+    for (uint32_t i = threadIdx.x; i < kMaxParts; i += kBinWG) {
+        s_cursor[i] = i < B.n_parts ? pmat_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
+        s_cnt[i] = 0;
+        s_fill[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    for (uint64_t q0 = g0; q0 < g1; q0 += batch) {
+        const uint64_t nq = (q0 + batch < g1 ? q0 + batch : g1) - q0;
+        uint32_t id[kPer];
+        uint32_t pt[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
+            const uint64_t a = i >> batch_log;
+            const uint64_t q = q0 + (i & (batch - 1));
+            const bool ok = a < k_h && q - q0 < nq;
+            id[u] = ok ? slots[a * len + q] : kNoSlot;
+            pt[u] = (id[u] != kNoSlot) ? (uint32_t)parts[a * len + q] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (id[u] != kNoSlot)
+                atomicAdd(&s_cnt[pt[u]], 1u);
+        __syncthreads();
+        {
+            const uint32_t c = threadIdx.x < kMaxParts ? s_cnt[threadIdx.x] : 0u;
+            uint32_t incl = c;
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= d)
+                    incl += o;
+            }
+            if (lane == 63)
+                s_wave[wave] = incl;
+            __syncthreads();
+            uint32_t before = 0;
+            for (uint32_t w = 0; w < wave; w++)
+                before += s_wave[w];
+            if (threadIdx.x < kMaxParts)
+                s_start[threadIdx.x] = before + incl - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (id[u] != kNoSlot) {
+                const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
+                const uint64_t q = q0 + (i & (batch - 1));
+                const uint32_t j = s_start[pt[u]] + atomicAdd(&s_fill[pt[u]], 1u);
+                s_stage[j] = (q << 32) | id[u];
+                s_tag[j] = (uint8_t)pt[u];
+            }
+        __syncthreads();
+        const uint32_t n_stage = s_start[kMaxParts - 1] + s_cnt[kMaxParts - 1];
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+            const uint32_t pj = s_tag[j];
+            const uint64_t dst = (uint64_t)s_cursor[pj] + (j - s_start[pj]);
+            if (dst < cap)
+                plist[dst] = s_stage[j];
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kMaxParts; i += kBinWG) {
+            s_cursor[i] += s_cnt[i];
+            s_cnt[i] = 0;
+            s_fill[i] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Region counts of one partition's list, per list workgroup of B.tile
+// entries: fine[r][g] (region-major), as k_bin_count produces them for the
+// single-level path.
+__global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restrict__ list,
+                                                       uint64_t n, BinPlan B,
+                                                       uint32_t *__restrict__ fine) {
+    extern __shared__ uint32_t s_hist[];
+    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
+        s_hist[i] = 0;
+    __syncthreads();
+    const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;
+    const uint64_t g1 = g0 + B.tile < n ? g0 + B.tile : n;
+    constexpr int kUnroll = 8;
+    for (uint64_t e = g0 + threadIdx.x; e < g1; e += (uint64_t)kUnroll * kBinWG) {
+        uint32_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint64_t x = e + (uint64_t)u * kBinWG;
+            v[u] = x < g1 ? (uint32_t)list[x] : kNoSlot;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            if (v[u] != kNoSlot)
+                atomicAdd(&s_hist[(v[u] >> kLocalBits) & (kMaxRegions - 1u)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
+        fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
+}
+
+// Level 1 over one partition's list: entries of list workgroup g -> runs of
+// the bucket list, as k_bin_bucket does for slot ids.
+__global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__restrict__ list,
+                                                            uint64_t n, BinPlan B,
+                                                            const uint32_t *__restrict__ coarse_off,
+                                                            uint64_t *__restrict__ bucketed) {
+    constexpr int kPer = kStage / kBinWG;
+    __shared__ uint64_t s_stage[kStage];
+    __shared__ uint32_t s_cnt[kMaxBuckets];
+    __shared__ uint32_t s_start[kMaxBuckets];
+    __shared__ uint32_t s_fill[kMaxBuckets];
+    __shared__ uint32_t s_cursor[kMaxBuckets];
+    const uint32_t bshift = B.bucket_shift + kLocalBits;
+    const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;
+    const uint64_t g1 = g0 + B.tile < n ? g0 + B.tile : n;
+    const uint64_t cap = B.entries_cap;
+    for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
+        s_cursor[i] = i < B.n_buckets ? coarse_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
+        s_cnt[i] = 0;
+        s_fill[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint64_t q0 = g0; q0 < g1; q0 += kStage) {
+        uint64_t v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
+            v[u] = x < g1 ? list[x] : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (v[u] != ~0ull)
+                atomicAdd(&s_cnt[(uint32_t)v[u] >> bshift], 1u);
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            uint32_t c = s_cnt[lane];
+            uint32_t incl = c;
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= d)
+                    incl += o;
+            }
+            s_start[lane] = incl - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            if (v[u] != ~0ull) {
+                const uint32_t b = (uint32_t)v[u] >> bshift;
+                const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
+                s_stage[j] = v[u];
+            }
+        __syncthreads();
+        const uint32_t n_stage = s_start[kMaxBuckets - 1] + s_cnt[kMaxBuckets - 1];
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+            const uint64_t e = s_stage[j];
+            const uint32_t b = (uint32_t)e >> bshift;
+            const uint64_t dst = (uint64_t)s_cursor[b] + (j - s_start[b]);
+            if (dst < cap)
+                bucketed[dst] = e;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
+            s_cursor[i] += s_cnt[i];
+            s_cnt[i] = 0;
+            s_fill[i] = 0;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
@@ -337,7 +563,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         }
     }
     __syncthreads();
-    const uint64_t wbase = (uint64_t)r << B.region_shift;
+    const uint64_t wbase = (uint64_t)(B.region0 + r) << B.region_shift;
     const uint64_t n_words = F.X * F.Y;
     const uint32_t nw = wbase + S <= n_words ? S : (uint32_t)(n_words - wbase);
     for (uint32_t w = threadIdx.x; w < nw; w += kRegionWG) {
@@ -368,18 +594,37 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B) {
+bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_t part_log) {
     // largest power-of-two cell count whose eta counters fit the LDS arrays
     uint32_t shift = 0;
     while (((2ull << shift) * F.eta) <= (uint64_t)kRegionCounters)
         shift++;
     if (((1ull << shift) * F.eta) > (uint64_t)kRegionCounters)
         return false;
+    if (part_log > kPartLog)
+        part_log = kPartLog;
     const uint64_t n_words = F.X * F.Y;
     const uint64_t n_regions = (n_words + (1ull << shift) - 1) >> shift;
-    if (n_regions > kMaxRegions)
-        return false;
+    B = BinPlan{};
     B.region_shift = shift;
+    B.slice = kSlice;
+    if (n_regions > (1ull << part_log)) {
+        // partitioned: bin workgroups count partitions, passes over each
+        // partition's list bin its regions as the single-level path does
+        const uint64_t np = (n_regions + (1ull << part_log) - 1) >> part_log;
+        if (np > kMaxParts)
+            return false;
+        B.n_regions = (uint32_t)n_regions;
+        B.n_parts = (uint32_t)np;
+        B.part_log = part_log;
+        uint64_t tile = kBinTileMin;
+        while ((chunk_positions + tile - 1) / tile * np > kMaxMatrix)
+            tile *= 2;
+        B.tile = tile;
+        B.G = (uint32_t)((chunk_positions + tile - 1) / tile);
+        B.n_slices = (B.G + B.slice - 1) / B.slice;
+        return true;
+    }
     B.n_regions = (uint32_t)n_regions;
     uint32_t bshift = 0;
     while (((n_regions + (1ull << bshift) - 1) >> bshift) > kMaxBuckets)
@@ -393,14 +638,149 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B) {
         tile *= 2;
     B.tile = tile;
     B.G = (uint32_t)((chunk_positions + tile - 1) / tile);
-    B.slice = kSlice;
     B.n_slices = (B.G + B.slice - 1) / B.slice;
     return true;
 }
 
+namespace {
+
+// The plan of one partition's pass over its n entries of the list.
+BinPlan part_pass(const BinPlan &B, uint32_t p, uint64_t n, uint64_t entries_cap) {
+    BinPlan Q = B;
+    Q.n_parts = 0;
+    Q.region0 = p << B.part_log;
+    const uint32_t per = 1u << B.part_log;
+    Q.n_regions = B.n_regions - Q.region0 < per ? B.n_regions - Q.region0 : per;
+    uint32_t bshift = 0;
+    while (((Q.n_regions + (1u << bshift) - 1) >> bshift) > kMaxBuckets)
+        bshift++;
+    Q.bucket_shift = bshift;
+    Q.n_buckets = (Q.n_regions + (1u << bshift) - 1) >> bshift;
+    uint64_t tile = kBinTileMin;
+    while ((n + tile - 1) / tile > kMaxListTiles)
+        tile *= 2;
+    Q.tile = tile;
+    Q.G = (uint32_t)((n + tile - 1) / tile);
+    Q.n_slices = (Q.G + Q.slice - 1) / Q.slice;
+    Q.entries_cap = entries_cap;
+    return Q;
+}
+
+hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
+                              const BinPlan &plan, const Workspace &W, bool classify,
+                              uint32_t tau, hipStream_t s, Profiler *P) {
+    BinPlan B = plan;
+    B.G = (uint32_t)((c1 - c0 + B.tile - 1) / B.tile);
+    B.n_slices = (B.G + B.slice - 1) / B.slice;
+    B.entries_cap = W.entries_cap;
+    const uint64_t n_pmat = (uint64_t)B.n_parts * B.G;
+    if (P)
+        P->begin(kPhBinCount, s);
+    hipLaunchKernelGGL(k_bin_count<true>, dim3(B.G), dim3(kBinWG),
+                       (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
+                       W.parts, W.pmat, (unsigned long long *)(W.totals + 5));
+    if (P)
+        P->end(s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        if (P)
+            P->begin(kPhScan, s);
+        e = scan_u32_u32(W.pmat, W.pmat, n_pmat, W.n_entries + 2, W.partial32, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_part_bounds, dim3(1), dim3(256), 0, s, (const uint32_t *)W.pmat,
+                               B.G, B.n_parts, (const uint32_t *)(W.n_entries + 2), W.pbounds);
+            e = hipGetLastError();
+        }
+        if (P)
+            P->end(s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(W.pbounds_host, W.pbounds, (B.n_parts + 1) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) {
+        if (P)
+            P->begin(kPhBinPart, s);
+        hipLaunchKernelGGL(k_part_scatter, dim3(B.G), dim3(kBinWG), 0, s, c0, c1, F.k_h, B,
+                           (const uint32_t *)W.slots, (const uint8_t *)W.parts,
+                           (const uint32_t *)W.pmat, W.plist);
+        if (P)
+            P->end(s);
+        e = hipGetLastError();
+    }
+    // the partition sizes decide the passes' grids
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    for (uint32_t p = 0; p < B.n_parts && e == hipSuccess; p++) {
+        uint64_t lo = W.pbounds_host[p], hi = W.pbounds_host[p + 1];
+        if (hi > B.entries_cap)
+            hi = B.entries_cap;
+        if (hi <= lo)
+            continue;
+        const uint64_t n = hi - lo;
+        const BinPlan Q = part_pass(B, p, n, W.entries_cap);
+        const uint64_t *list = W.plist + lo;
+        const uint64_t n_fine = (uint64_t)Q.n_regions * Q.G;
+        const uint64_t n_coarse = (uint64_t)Q.n_buckets * Q.G;
+        if (P)
+            P->begin(kPhPartCount, s);
+        hipLaunchKernelGGL(k_list_count, dim3(Q.G), dim3(kBinWG),
+                           (size_t)Q.n_regions * sizeof(uint32_t), s, list, n, Q, W.matrix);
+        if (P)
+            P->end(s);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            break;
+        if (P)
+            P->begin(kPhScan, s);
+        hipLaunchKernelGGL(k_bucket_counts, dim3((unsigned)((n_coarse + 255) / 256)), dim3(256), 0,
+                           s, Q, (const uint32_t *)W.matrix, W.coarse);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+        if (e == hipSuccess)
+            e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
+        if (P)
+            P->end(s);
+        if (e != hipSuccess)
+            break;
+        if (P)
+            P->begin(kPhBinBucket, s);
+        hipLaunchKernelGGL(k_bin_bucket_list, dim3(Q.G), dim3(kBinWG), 0, s, list, n, Q,
+                           (const uint32_t *)W.coarse, W.bucketed);
+        if (P)
+            P->end(s);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            break;
+        if (P)
+            P->begin(kPhBinRegion, s);
+        hipLaunchKernelGGL(k_bin_region, dim3(Q.n_buckets * Q.n_slices), dim3(kBinWG), 0, s, Q,
+                           (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
+                           (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
+        if (P)
+            P->end(s);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            break;
+        if (P)
+            P->begin(kPhRegion, s);
+        hipLaunchKernelGGL(k_region, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
+                           (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
+                           (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
+        if (P)
+            P->end(s);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace
+
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
                                uint32_t tau, hipStream_t s, Profiler *P) {
+    if (plan.n_parts)
+        return launch_parts_chunk(F, R, c0, c1, plan, W, classify, tau, s, P);
     BinPlan B = plan;
     B.G = (uint32_t)((c1 - c0 + B.tile - 1) / B.tile);
     B.n_slices = (B.G + B.slice - 1) / B.slice;
@@ -410,8 +790,8 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
     if (P)
         P->begin(kPhBinCount, s);
-    hipLaunchKernelGGL(k_bin_count, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots,
-                       W.matrix, (unsigned long long *)(W.totals + 5));
+    hipLaunchKernelGGL(k_bin_count<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
+                       W.slots, nullptr, W.matrix, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();

@@ -22,6 +22,8 @@ struct kc_filter {
     hipStream_t last;      // stream of the last enqueued call
     uint64_t chunk;        // direct path: positions per first-seen chunk
     uint64_t bin_chunk;    // binned path: positions per chunk
+    uint64_t part_chunk;   // partitioned binned path: positions per chunk
+    uint32_t part_log;     // partitioned binned path: log2(regions per partition)
     KcPath path;
     kc::Profiler prof;     // optional per-kernel timing
 };

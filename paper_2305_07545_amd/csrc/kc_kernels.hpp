@@ -31,6 +31,12 @@ constexpr int kStage = 4096;                 // entries staged per batch in LDS:
 constexpr uint32_t kStageLog = 12;           // kStage == 1 << kStageLog
 constexpr uint32_t kSlice = 32;              // bin workgroups per level-2 workgroup
 constexpr int kTileGrid = 2048;              // workgroups of the persistent tile kernels
+// Partitioned binned path, for countBFs of more than kMaxRegions regions:
+// partition p holds regions [p * kMaxRegions, (p + 1) * kMaxRegions)
+constexpr uint32_t kPartLog = 14;            // kMaxRegions == 1 << kPartLog
+constexpr uint32_t kMaxParts = 256;          // partitions (4M regions: 64 GB at alpha = 8)
+constexpr uint64_t kPartChunk = 1ull << 30;  // positions per partitioned chunk
+constexpr uint32_t kMaxListTiles = 2048;     // list workgroups per partition pass
 constexpr int kSuper = 4;                    // tiles per iteration of the tile kernels
 
 struct BinPlan {
@@ -43,6 +49,9 @@ struct BinPlan {
     uint32_t n_slices;
     uint64_t tile;          // positions per bin workgroup (multiple of kBinWG)
     uint64_t entries_cap;   // capacity of each entry list
+    uint32_t n_parts;       // partitioned path: partitions (0: regions binned directly)
+    uint32_t part_log;      // partitioned path: log2(regions per partition) <= kPartLog
+    uint32_t region0;       // partition pass: global index of the pass's region 0
 };
 
 // Per-handle workspace (device memory owned by the handle).
@@ -69,9 +78,16 @@ struct Workspace {
     uint64_t *bucketed = nullptr; // entries_cap entries grouped by bucket
     uint64_t *entries = nullptr;  // entries_cap entries grouped by region
     uint64_t entries_cap = 0;
+    // partitioned binned path (per chunk)
+    uint8_t *parts = nullptr;     // slots_cap partition ids, beside the slot ids
+    uint64_t *plist = nullptr;    // slots_cap entries grouped by partition
+    uint32_t *pmat = nullptr;     // pmat_cap (partition, bin workgroup) counts -> offsets
+    uint64_t pmat_cap = 0;
+    uint32_t *pbounds = nullptr;  // kMaxParts + 1 partition starts in plist
+    uint32_t *pbounds_host = nullptr;  // pinned mirror
     // scalars
     uint64_t *totals = nullptr;   // 8 scan totals / saved counters
-    uint32_t *n_entries = nullptr;  // 2 entry totals
+    uint32_t *n_entries = nullptr;  // 4 entry totals
 };
 
 inline uint64_t tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
@@ -109,7 +125,7 @@ inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 enum Phase {
     kPhIngest = 0, kPhClaim, kPhIncrement, kPhClaimIncrement, kPhResolve, kPhScan, kPhScatter,
     kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhBinCount, kPhBinBucket, kPhRegion,
-    kPhTileCount, kPhBinRegion, kPhCount
+    kPhTileCount, kPhBinRegion, kPhBinPart, kPhPartCount, kPhCount
 };
 
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
@@ -125,7 +141,13 @@ hipError_t launch_ingest(const uint8_t *reads, uint64_t n_bases, const uint64_t 
                          uint64_t n_reads, const Workspace &W, hipStream_t s, Profiler *P);
 hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                bool zero_filter, const Workspace &W, hipStream_t s, Profiler *P);
-bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B);
+// Binned-path plan for chunks of chunk_positions; false when the countBF
+// has too many regions even for the partitioned path.  part_log sets the
+// partition size (regions) for countBFs of more than 2^part_log regions.
+bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B,
+              uint32_t part_log = kPartLog);
+// plan.n_parts > 0 takes the partitioned path, which waits on the host once
+// per chunk for the partition sizes (W.pbounds_host)
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
                                uint32_t tau, hipStream_t s, Profiler *P);

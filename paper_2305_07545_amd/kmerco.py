@@ -129,7 +129,7 @@ SIGNATURES = {
 
 PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
           "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
-          "region", "tile_count", "bin_region"]
+          "region", "tile_count", "bin_region", "bin_part", "part_count"]
 
 
 def load_library():

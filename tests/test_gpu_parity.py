@@ -255,11 +255,48 @@ def test_classify_thresholds(tau):
     check(rs, 53, 59, tau=tau, what=f"tau={tau} unfused", fused=False)
 
 
-def test_large_filter_uses_direct_path():
-    """A countBF beyond the binned path's region limit (33.6 M cells) is
-    filled by the direct path automatically."""
+def test_large_filter_takes_partitioned_path():
+    """A countBF of more than one partition of regions (16448 regions of 2048
+    cells at alpha = 8) is binned through partitions automatically."""
     rs = synth.random_reads(1050, 300, 50, 200, k=21, p_n=0.01)
     check(rs, 5801, 5807, what="large filter auto")
+    bf = P.CountBF(5801, 5807)
+    r, o = dev(rs)
+    bf.profile(True)
+    bf.insert(r, o, 21)
+    phases = bf.profile_read()
+    assert "bin_part" in phases and "part_count" in phases, phases
+
+
+@pytest.mark.parametrize("part_log,alpha,k_h", [(0, 8, 1), (2, 8, 2), (3, 5, 1), (1, 16, 3),
+                                                (4, 8, 1)])
+def test_partitioned_path_small_partitions(monkeypatch, part_log, alpha, k_h):
+    """The partitioned path on small countBFs, with partitions of 2^part_log
+    regions (so that many partitions, ragged last ones and empty ones occur)."""
+    monkeypatch.setenv("KMERCO_PATH", "binned")
+    monkeypatch.setenv("KMERCO_PART_LOG", str(part_log))
+    rs = synth.random_reads(1200 + part_log, 2500, 20, 300, k=25, p_n=0.005, tau=2)
+    check(rs, 401, 409, alpha=alpha, k_h=k_h, what=f"partitioned part_log={part_log}")
+    check(rs, 401, 409, alpha=alpha, k_h=k_h, what=f"partitioned unfused part_log={part_log}",
+          fused=False)
+
+
+@pytest.mark.parametrize("chunk", [1 << 14, 100_000])
+def test_partitioned_multi_chunk(monkeypatch, chunk):
+    monkeypatch.setenv("KMERCO_PATH", "binned")
+    monkeypatch.setenv("KMERCO_PART_LOG", "2")
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", str(chunk))
+    rs = synth.random_reads(1300, 3000, 20, 250, k=31, p_n=0.002, alphabet=b"ACGT")
+    check(rs, 211, 223, what=f"partitioned chunks of {chunk}")
+    low = synth.random_reads(1301, 1500, 30, 200, k=13, alphabet=b"AC")  # heavy collisions
+    check(low, 211, 223, alpha=4, what=f"partitioned low complexity chunks of {chunk}")
+
+
+def test_partitioned_bacterial_sample(monkeypatch):
+    monkeypatch.setenv("KMERCO_PART_LOG", "3")
+    rs = synth.config("bacterial", scale=0.05)
+    X, Y = oracle.dims(rs.n_items)
+    check(rs, X, Y, what="bacterial x0.05, partitions of 8 regions")
 
 
 def test_paths_agree_on_bacterial_sample(monkeypatch):
