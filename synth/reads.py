@@ -124,6 +124,28 @@ def _bernoulli_positions(rng, total: int, p: float) -> np.ndarray:
     return np.concatenate(out)
 
 
+def _gather_reads(genome, starts, rev, lengths, offsets, codes):
+    """codes[offsets[r]:offsets[r+1]] = genome[starts[r]:starts[r]+lengths[r]],
+    or its reverse complement where rev[r]."""
+    g = len(genome)
+    n = len(lengths)
+    if n == 0:
+        return
+    lmax = int(lengths.max())
+    # forward genome, then its reverse complement, then room for the last row;
+    # the reverse strand of genome[s:s+L] is (reverse complement)[g-s-L : g-s]
+    both = np.concatenate([genome, (3 - genome[::-1]).astype(np.uint8),
+                           np.zeros(lmax, dtype=np.uint8)])
+    rows = np.lib.stride_tricks.sliding_window_view(both, lmax)
+    src = np.where(rev, g + (g - starts - lengths), starts)
+    col = np.arange(lmax, dtype=np.int64)[None, :]
+    step = 262_144
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        block = rows[src[a:b]]
+        codes[int(offsets[a]):int(offsets[b])] = block[col < lengths[a:b, None]]
+
+
 def _sample_reads(rng, genome, lengths, p_sub=0.0, p_indel=0.0, p_n=0.0):
     """Sample reads of the given lengths; returns (codes uint8, offsets uint64).
 
@@ -142,18 +164,7 @@ def _sample_reads(rng, genome, lengths, p_sub=0.0, p_indel=0.0, p_n=0.0):
     margin = 64  # room for deletions
     starts = rng.integers(0, g - lengths - margin + 1)
     rev = rng.random(n) < 0.5
-    # gather in chunks of reads to bound memory
-    step = 200_000
-    for a in range(0, n, step):
-        b = min(n, a + step)
-        ln = lengths[a:b]
-        o0 = int(offsets[a])
-        cnt = int(offsets[b]) - o0
-        local = np.arange(cnt, dtype=np.int64) - np.repeat(offsets[a:b].astype(np.int64) - o0, ln)
-        rr = np.repeat(rev[a:b], ln)
-        gidx = np.repeat(starts[a:b], ln) + np.where(rr, np.repeat(ln, ln) - 1 - local, local)
-        c = genome[gidx]
-        codes[o0:o0 + cnt] = np.where(rr, 3 - c, c)
+    _gather_reads(genome, starts, rev, lengths, offsets, codes)
     if p_indel > 0.0:
         events = rng.binomial(lengths, p_indel)
         for r in np.nonzero(events)[0]:

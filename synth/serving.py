@@ -24,7 +24,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .reads import _ASCII, SIZING_FACTOR, _bernoulli_positions, _expected_distinct, _genome
+from .reads import (_ASCII, SIZING_FACTOR, _bernoulli_positions, _expected_distinct,
+                    _gather_reads, _genome)
 
 
 def sample_reads_fast(rng, genome: np.ndarray, lengths: np.ndarray, p_sub: float):
@@ -34,25 +35,13 @@ def sample_reads_fast(rng, genome: np.ndarray, lengths: np.ndarray, p_sub: float
     g = len(genome)
     lengths = np.asarray(lengths, dtype=np.int64)
     n = len(lengths)
-    lmax = int(lengths.max()) if n else 1
     offsets = np.zeros(n + 1, dtype=np.uint64)
     np.cumsum(lengths, out=offsets[1:])
     total = int(offsets[-1])
-    # forward genome, then its reverse complement, then room for the last row
-    both = np.concatenate([genome, (3 - genome[::-1]).astype(np.uint8),
-                           np.zeros(lmax, dtype=np.uint8)])
-    rows = np.lib.stride_tricks.sliding_window_view(both, lmax)
     starts = rng.integers(0, g - lengths + 1)
     rev = rng.random(n) < 0.5
-    # reverse strand of genome[s:s+L] is (reverse complement)[g-s-L : g-s]
-    src = np.where(rev, g + (g - starts - lengths), starts)
     codes = np.empty(total, dtype=np.uint8)
-    col = np.arange(lmax, dtype=np.int64)[None, :]
-    step = 262_144
-    for a in range(0, n, step):
-        b = min(n, a + step)
-        block = rows[src[a:b]]
-        codes[int(offsets[a]):int(offsets[b])] = block[col < lengths[a:b, None]]
+    _gather_reads(genome, starts, rev, lengths, offsets, codes)
     pos = _bernoulli_positions(rng, total, p_sub)
     codes[pos] = (codes[pos] + rng.integers(1, 4, size=len(pos), dtype=np.uint8)) % 4
     return _ASCII[codes], offsets
