@@ -30,6 +30,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# 32-bit integer VALU operations: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+ALU_PEAK_GOPS = 256 * 64 * 2.4
+
+# Algorithmic 32-bit integer operations per valid k-mer window of the hashing
+# kernel (k_h = 1), counted from the method's definitions: rolling update of
+# the forward and reverse-complement keys (2 x 8), the high word of H_1 for
+# both strands and the low word for the canonical one (3 MurmurHash3 x86_32
+# evaluations of an 8-byte key, 23 ops each), the canonical compare/select
+# (4), the slot map h mod X and h mod Y (12 each as a Barrett reduction of a
+# 64-bit value), h mod eta (1 for a power-of-two eta) and w = i*Y + j (3).
+OPS_PER_WINDOW = 16 + 3 * 23 + 4 + 2 * 12 + 1 + 3
+# each further hash function H_a: 2 MurmurHash3 evaluations + its slot map
+OPS_PER_EXTRA_HASH = 2 * 23 + 2 * 12 + 1 + 3
 
 
 def parse():
@@ -37,7 +50,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bacterial", choices=["tiny", "bacterial"])
+    ap.add_argument("--workload", default="bacterial", choices=["tiny", "bacterial", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-verify", action="store_true")
@@ -54,18 +67,23 @@ def sha(t) -> str:
 
 
 def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
-                      n_words: int) -> float:
-    """Bytes a launch of `phase` must move by its definition (logical
-    accesses, not cache lines): see the per-kernel table in the design notes."""
+                      n_words: int, n_chunks: int = 1, partitioned: bool = False) -> float:
+    """Bytes one step's launches of `phase` must move by their definition
+    (logical accesses, not cache lines), summed over the step's launches:
+    see the per-kernel table in the design notes."""
     entries = n_windows * k_h
-    if phase == "bin_count":         # packed input, one 4-byte slot id per (position, hash fn)
-        return n_bases * (0.5 + 4 * k_h)
-    if phase == "bin_bucket":        # slot ids in, one 8-byte entry per (window, hash fn) out
-        return n_bases * 4 * k_h + entries * 8
+    if phase == "bin_count":         # packed input, a 4-byte slot id (+ partition byte)
+        return n_bases * (0.5 + (5 if partitioned else 4) * k_h)
+    if phase == "bin_part":          # slot ids + partition bytes in, 8-byte entries out
+        return n_bases * 5 * k_h + entries * 8
+    if phase == "part_count":        # entries of the partition lists in
+        return entries * 8
+    if phase == "bin_bucket":        # slot ids (or list entries) in, entries out
+        return entries * 16 if partitioned else n_bases * 4 * k_h + entries * 8
     if phase == "bin_region":        # entries in and out
         return entries * 16
-    if phase == "region":            # entries in, countBF cells read + written, flags
-        return entries * 8 + n_words * 16 + n_distinct
+    if phase == "region":            # entries in, countBF cells read + written per chunk, flags
+        return entries * 8 + n_chunks * n_words * 16 + n_distinct
     if phase == "tile_count":        # flag byte + packed input per position
         return n_bases * 1.5
     if phase == "claim_increment":   # cell RMW + first-seen entry RMW per slot, packed input
@@ -87,11 +105,11 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
     return 0.0
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if one
-    exists for this kernel and workload and the kernel sources have not
-    changed since; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def traffic_for(phase: str, workload: str):
+    """HBM bytes per launch of a phase, from the committed rocprofv3 --pmc
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, calibrated on a
+    copy kernel), if the kernel sources have not changed since; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -100,7 +118,8 @@ def traffic_for(kernel: str, workload: str):
         return None
     if rec.get("source_sha256") != source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    ph = rec.get("phases", {}).get(phase)
+    return None if ph is None else ph.get("bytes_per_launch")
 
 
 def source_digest() -> str:
@@ -128,18 +147,50 @@ def cpu_baseline(rs, X, Y, n_sample_reads):
                       f"countBF {X}x{Y}, single-threaded C oracle, {secs:.1f} s"}
 
 
-def roofline_of(phases, n_bases, n_windows, n_distinct, k_h, n_words, workload):
-    """HBM roofline of the phase with the largest total time."""
+def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
+                n_chunks=1, partitioned=False):
+    """Roofline of the phase with the largest total time: the hashing kernel
+    against the integer-VALU peak (algorithmic ops per window), the others
+    against HBM (algorithmic bytes), per launch over the average launch."""
     if not phases:
         return None
     dom = max(phases, key=lambda k: phases[k][0])
     avg_s = phases[dom][0] / phases[dom][1] / 1e3
-    nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words)
+    per_step = phases[dom][1] / max(1, steps)
+    traffic = traffic_for(dom, workload)
+    if dom == "bin_count":
+        ops = n_windows * (OPS_PER_WINDOW + (k_h - 1) * OPS_PER_EXTRA_HASH) / per_step
+        achieved = ops / avg_s / 1e9
+        return {"bound": "alu", "achieved": round(achieved, 1), "peak": round(ALU_PEAK_GOPS, 1),
+                "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": traffic,
+                "kernel": dom, "algorithmic_ops_per_launch": ops,
+                "ops_per_window": OPS_PER_WINDOW + (k_h - 1) * OPS_PER_EXTRA_HASH,
+                "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": per_step}
+    nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
+                               partitioned) / per_step
     achieved = nbytes / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(dom, workload), "kernel": dom,
-            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": round(avg_s * 1e3, 4)}
+            "traffic": traffic, "kernel": dom,
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": round(avg_s * 1e3, 4),
+            "launches_per_step": per_step}
+
+
+def hbm_rooflines(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
+                  n_chunks=1, partitioned=False):
+    """The HBM roofline of every memory-bound phase (all but the hashing)."""
+    out = {}
+    for ph, (ms, launches) in phases.items():
+        b = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
+                              partitioned)
+        if ph == "bin_count" or b <= 0:
+            continue
+        per_step = launches / max(1, steps)
+        avg_s = ms / launches / 1e3
+        gbs = b / per_step / avg_s / 1e9
+        out[ph] = {"achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                   "traffic": traffic_for(ph, workload)}
+    return out
 
 
 def batched_leg(args, dev):
@@ -269,7 +320,8 @@ def _batched_leg(args, dev, sets, stream, t_gen):
         "steps": steps, "tile": batch.tile, "graph": True,
         "verified_vs_oracle_digests": {"batched": batch_ok, "plain": plain_ok},
         "phases": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()},
-        "roofline": roofline_of(phases, total, n_windows, n_distinct, 1, n_words, "batched"),
+        "roofline": roofline_of(phases, steps, total, n_windows, n_distinct, 1, n_words,
+                                "batched"),
         "input_generation_s": round(t_gen, 1),
     }
     for f in filters:
@@ -402,7 +454,7 @@ def main():
     reads = torch.from_numpy(rs.reads).to(dev)
     offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
     n_bases = rs.n_bases
-    cap = n_bases
+    cap = min(n_bases, 1 << 31)  # keys of room per output list (a shortfall raises)
     distinct = torch.empty(cap, dtype=torch.int64, device=dev)
     trust = torch.empty(cap, dtype=torch.int64, device=dev)
     err = torch.empty(cap, dtype=torch.int64, device=dev)
@@ -450,7 +502,12 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     value = n_windows * args.steps / elapsed
     per_phase = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()}
-    roofline = roofline_of(phases, n_bases, n_windows, n_distinct, k_h, X * Y, args.workload)
+    # the binned path's chunking (the partitioned path beyond 16384 regions)
+    partitioned = X * Y > 16384 * (16384 // (64 // alpha))
+    chunk = min(1 << 31, ((1 << 32) - 1) // k_h // 1024 * 1024) if partitioned else (1 << 28)
+    n_chunks = (n_bases + chunk - 1) // chunk
+    roofline = roofline_of(phases, args.steps, n_bases, n_windows, n_distinct, k_h, X * Y,
+                           args.workload, n_chunks, partitioned)
 
     out = {
         "metric": "k-mer insertions/s",
@@ -473,6 +530,8 @@ def main():
         "verified_vs_oracle_digests": verified,
         "phases": per_phase,
         "roofline": roofline,
+        "hbm_rooflines": hbm_rooflines(phases, args.steps, n_bases, n_windows, n_distinct, k_h,
+                                       X * Y, args.workload, n_chunks, partitioned),
     }
     bf.close()
     del reads, offs, distinct, trust, err

@@ -292,7 +292,10 @@ bool choose_plan(const kc_filter *f, uint64_t n_bases, kc::BinPlan &plan, uint64
     if (!kc::bin_plan(f->F, chunk, plan, f->part_log))
         return false;
     if (plan.n_parts) {
-        chunk = n_bases < f->part_chunk ? n_bases : f->part_chunk;
+        // entries of a chunk (positions x hash functions) index 32-bit offsets
+        const uint64_t most = ((1ull << 32) - 1) / f->layout.k_h / kc::kTile * kc::kTile;
+        const uint64_t pc = f->part_chunk < most ? f->part_chunk : most;
+        chunk = n_bases < pc ? n_bases : pc;
         return kc::bin_plan(f->F, chunk, plan, f->part_log);
     }
     return true;

@@ -656,8 +656,10 @@ BinPlan part_pass(const BinPlan &B, uint32_t p, uint64_t n, uint64_t entries_cap
         bshift++;
     Q.bucket_shift = bshift;
     Q.n_buckets = (Q.n_regions + (1u << bshift) - 1) >> bshift;
+    // about kListTiles workgroups: enough to fill the chip, and a pass
+    // matrix (regions x workgroups) that stays small to scan
     uint64_t tile = kBinTileMin;
-    while ((n + tile - 1) / tile > kMaxListTiles)
+    while ((n + tile - 1) / tile > kListTiles)
         tile *= 2;
     Q.tile = tile;
     Q.G = (uint32_t)((n + tile - 1) / tile);

@@ -35,8 +35,10 @@ constexpr int kTileGrid = 2048;              // workgroups of the persistent til
 // partition p holds regions [p * kMaxRegions, (p + 1) * kMaxRegions)
 constexpr uint32_t kPartLog = 14;            // kMaxRegions == 1 << kPartLog
 constexpr uint32_t kMaxParts = 256;          // partitions (4M regions: 64 GB at alpha = 8)
-constexpr uint64_t kPartChunk = 1ull << 30;  // positions per partitioned chunk
-constexpr uint32_t kMaxListTiles = 2048;     // list workgroups per partition pass
+constexpr uint64_t kPartChunk = 1ull << 31;  // positions per partitioned chunk (k_h = 1;
+                                             // entry offsets are 32-bit: chunk * k_h < 2^32)
+constexpr uint32_t kMaxListTiles = 2048;     // list workgroups per partition pass (at most)
+constexpr uint32_t kListTiles = 1024;        // list workgroups per pass aimed at
 constexpr int kSuper = 4;                    // tiles per iteration of the tile kernels
 
 struct BinPlan {

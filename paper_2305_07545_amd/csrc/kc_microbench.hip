@@ -1,7 +1,8 @@
-// Memory-system microbenchmarks that give the KmerCo kernels their roofline
-// denominators on gfx950: uniform-random 64-bit atomics / reads and 32-bit
-// atomicMin over a chosen footprint (L2-, Infinity-Cache- or HBM-sized), a
-// streaming copy, and LDS atomics.  Built as its own library
+// Microbenchmarks that give the KmerCo kernels their roofline denominators on
+// gfx950: uniform-random 64-bit atomics / reads and 32-bit atomicMin over a
+// chosen footprint (L2-, Infinity-Cache- or HBM-sized), a streaming copy, LDS
+// atomics, and the issue rate of the integer VALU instructions the hashing
+// uses (add, 32-bit multiply low / high, 64-bit multiply-add).  Built as its own library
 // (libkmerco_microbench.so); the KmerCo library does not use it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,7 +28,48 @@ enum Kind {
     kAdd64Ret = 4,      // random 8-byte atomicAdd, result used
     kCopy64 = 5,        // streaming copy, 8 bytes read + 8 written per op
     kLds = 6,           // random LDS add + min within 128 KiB per workgroup
+    kAluAdd = 7,        // v_add_u32 chains (ops = lane operations)
+    kAluMulLo = 8,      // v_mul_lo_u32 chains
+    kAluMulHi = 9,      // v_mul_hi_u32 chains
+    kAluMad64 = 10,     // v_mad_u64_u32 chains
 };
+
+// Eight independent dependency chains per thread, one instruction per link,
+// so that issue rate rather than latency bounds the loop.
+template <int K>
+__global__ void __launch_bounds__(256) k_alu(uint32_t iters, uint32_t c,
+                                             uint64_t *__restrict__ sink) {
+    uint32_t x[8];
+    uint64_t y[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        x[j] = threadIdx.x * 8u + (uint32_t)j + 1u;
+        y[j] = x[j];
+    }
+    for (uint32_t i = 0; i < iters; i++) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (K == kAluAdd)
+                asm volatile("v_add_u32 %0, %0, %1" : "+v"(x[j]) : "v"(c));
+            else if (K == kAluMulLo)
+                asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(x[j]) : "v"(c));
+            else if (K == kAluMulHi)
+                asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(x[j]) : "v"(c));
+            else {
+                uint64_t carry;
+                asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0"
+                             : "+v"(y[j]), "=s"(carry)
+                             : "v"((uint32_t)y[j]), "v"(c));
+            }
+        }
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+        acc += x[j] + y[j];
+    if (acc == 0x123456789ull)
+        *sink = acc;
+}
 
 __global__ void __launch_bounds__(256) k_random(int kind, uint64_t *__restrict__ buf, uint64_t n64,
                                                 uint64_t *__restrict__ dst, uint64_t ops,
@@ -88,6 +130,50 @@ __global__ void __launch_bounds__(256) k_lds(uint64_t ops_per_block, uint64_t se
         *sink = s[1][0];
 }
 
+
+int run_alu(int kind, uint64_t ops, double *ms) {
+    uint64_t *sink = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = 0;
+    const unsigned blocks = 256 * 8, threads = 256;
+    const uint64_t per_iter = (uint64_t)blocks * threads * 8;  // lane operations
+    const uint32_t iters = (uint32_t)((ops + per_iter - 1) / per_iter);
+    if (hipMalloc((void **)&sink, 8) != hipSuccess)
+        return -4;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        rc = -4;
+    for (int rep = 0; rep < 2 && rc == 0; rep++) {  // rep 0 warms up
+        (void)hipEventRecord(a, nullptr);
+        const uint32_t c = 0x9E3779B9u + (uint32_t)rep;
+        if (kind == kAluAdd)
+            hipLaunchKernelGGL(k_alu<kAluAdd>, dim3(blocks), dim3(threads), 0, nullptr, iters, c,
+                               sink);
+        else if (kind == kAluMulLo)
+            hipLaunchKernelGGL(k_alu<kAluMulLo>, dim3(blocks), dim3(threads), 0, nullptr, iters,
+                               c, sink);
+        else if (kind == kAluMulHi)
+            hipLaunchKernelGGL(k_alu<kAluMulHi>, dim3(blocks), dim3(threads), 0, nullptr, iters,
+                               c, sink);
+        else
+            hipLaunchKernelGGL(k_alu<kAluMad64>, dim3(blocks), dim3(threads), 0, nullptr, iters,
+                               c, sink);
+        (void)hipEventRecord(b, nullptr);
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+            rc = -4;
+    }
+    float t = 0.f;
+    if (rc == 0 && hipEventElapsedTime(&t, a, b) != hipSuccess)
+        rc = -4;
+    // report the time of exactly `ops` lane operations
+    *ms = t * (double)ops / ((double)iters * per_iter);
+    if (a)
+        (void)hipEventDestroy(a);
+    if (b)
+        (void)hipEventDestroy(b);
+    (void)hipFree(sink);
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -97,8 +183,10 @@ extern "C" {
 // multiple of 8, allocated and freed here); ops: operations to issue.
 // Returns 0 on success, -1 on bad arguments, -4 on a runtime error.
 int kcmb_run(int kind, uint64_t footprint_bytes, uint64_t ops, double *ms) {
-    if (!ms || kind < 0 || kind > kLds || ops == 0)
+    if (!ms || kind < 0 || kind > kAluMad64 || ops == 0)
         return -1;
+    if (kind >= kAluAdd)
+        return run_alu(kind, ops, ms);
     uint64_t n64 = footprint_bytes / 8;
     if (kind != kLds && n64 == 0)
         return -1;

@@ -15,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libkmerco_microbench.so")
 
-KINDS = {"read64": 0, "add64": 1, "cas64": 2, "min32": 3, "add64_ret": 4, "copy64": 5, "lds": 6}
+KINDS = {"read64": 0, "add64": 1, "cas64": 2, "min32": 3, "add64_ret": 4, "copy64": 5, "lds": 6,
+         "alu_add32": 7, "alu_mul_lo32": 8, "alu_mul_hi32": 9, "alu_mad64": 10}
 
 
 def load():
@@ -42,6 +43,14 @@ def rate(kind: str, footprint: int, ops: int) -> float:
 
 def main(argv):
     import torch  # noqa: F401 - initialises the HIP runtime the same way the library sees it
+    if argv and argv[0] == "--alu":
+        # integer VALU issue rates (lane operations per second)
+        out = {k: rate(k, 8, 1 << 34) for k in ("alu_add32", "alu_mul_lo32", "alu_mul_hi32",
+                                                  "alu_mad64")}
+        for k, v in out.items():
+            print(f"{k:14s} {v / 1e12:8.2f} T lane-ops/s", flush=True)
+        print(json.dumps(out))
+        return
     if argv and argv[0] == "--copy":
         # one streaming copy of a known size (calibrates traffic counters):
         # reads and writes argv[1] bytes

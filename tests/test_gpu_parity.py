@@ -334,3 +334,39 @@ def test_repeatable():
     b = gpu_run(rs, 89, 97, k_h=2)
     for x, y in zip(a[:4], b[:4]):
         assert np.array_equal(x, y)
+
+
+def test_large_full_size_digests():
+    """The large workload at full size: 8 Gbases of reads into an 8 GB
+    countBF (the partitioned binned path, several chunks), against the
+    oracle's digests."""
+    path = os.path.join(GOLDEN, "large_digests.json")
+    if not os.path.exists(path):
+        pytest.skip("no oracle digests for the large workload")
+    ref = json.load(open(path))
+    print("case large full size: generating reads", flush=True)
+    rs = synth.config("large")
+    assert rs.n_bases == ref["n_bases"]
+    X, Y = ref["X"], ref["Y"]
+    r, o = dev(rs)
+    del rs
+    room = ref["n_distinct"] + 1024
+    out = {n: torch.empty(room, dtype=torch.int64, device="cuda") for n in ("d", "t", "e")}
+    bf = P.CountBF(X, Y)
+    print(f"case large full size: insert+classify X={X} Y={Y}", flush=True)
+    _, _, n_trust, _, n_err = bf.insert_classify(r, o, ref["k"], ref["tau"], distinct=out["d"],
+                                                 trust=out["t"], err=out["e"])
+    bf.sync()
+    del r, o
+    nd, nt, ne = int(bf.n_distinct.item()), int(n_trust.item()), int(n_err.item())
+    assert int(bf.n_windows.item()) == ref["n_windows"]
+    assert (nd, nt, ne) == (ref["n_distinct"], ref["n_trust"], ref["n_err"])
+
+    def h(t):
+        return hashlib.sha256(t.cpu().numpy().view(np.uint64).tobytes()).hexdigest()
+
+    assert h(bf.words) == ref["words_sha256"]
+    assert h(out["d"][:nd]) == ref["distinct_sha256"]
+    assert h(out["t"][:nt]) == ref["trust_sha256"]
+    assert h(out["e"][:ne]) == ref["err_sha256"]
+    bf.close()
