@@ -36,6 +36,28 @@ __device__ __forceinline__ uint32_t wave_id() {
 }
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
+
+// coarse[b * G + g] = sum of the region counts s_hist[r] over the regions r
+// of bucket b (after the histogram is complete in LDS).  kBinWG threads: 8
+// per bucket, each summing every 8th region, then a shuffle reduction.
+__device__ __forceinline__ void write_bucket_sums(const uint32_t *s_hist, const BinPlan &B,
+                                                  uint32_t *__restrict__ coarse, uint32_t g) {
+    static_assert(kBinWG == 8 * kMaxBuckets, "8 threads per bucket");
+    const uint32_t b = threadIdx.x >> 3, sub = threadIdx.x & 7u;
+    uint32_t sum = 0;
+    if (b < B.n_buckets) {
+        const uint32_t r0 = b << B.bucket_shift;
+        const uint32_t r1 = r0 + (1u << B.bucket_shift) < B.n_regions
+                                ? r0 + (1u << B.bucket_shift) : B.n_regions;
+        for (uint32_t r = r0 + sub; r < r1; r += 8)
+            sum += s_hist[r];
+    }
+    sum += __shfl_xor(sum, 1, 64);
+    sum += __shfl_xor(sum, 2, 64);
+    sum += __shfl_xor(sum, 4, 64);
+    if (b < B.n_buckets && sub == 0)
+        coarse[(uint64_t)b * B.G + g] = sum;
+}
 constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
 static_assert(kStage == (1 << kStageLog), "stage size");
 static_assert(kRegionCounters == (1 << kLocalBits), "region size");
@@ -52,6 +74,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                                                       uint32_t *__restrict__ slots,
                                                       uint8_t *__restrict__ parts,
                                                       uint32_t *__restrict__ fine,
+                                                      uint32_t *__restrict__ coarse,
                                                       unsigned long long *__restrict__ n_valid) {
     extern __shared__ uint32_t s_hist[];  // n_regions region (n_parts partition) counts
     __shared__ uint32_t s_valid;
@@ -103,25 +126,10 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
         fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
+    if (!kParts)
+        write_bucket_sums(s_hist, B, coarse, blockIdx.x);
     if (threadIdx.x == 0)
         atomicAdd(n_valid, (unsigned long long)s_valid);
-}
-
-// Bucket counts: coarse[b][g] = sum of fine[r][g] over the regions r of b.
-__global__ void k_bucket_counts(BinPlan B, const uint32_t *__restrict__ fine,
-                                uint32_t *__restrict__ coarse) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (uint64_t)B.n_buckets * B.G)
-        return;
-    const uint32_t b = (uint32_t)(i / B.G);
-    const uint32_t g = (uint32_t)(i % B.G);
-    const uint32_t r0 = b << B.bucket_shift;
-    const uint32_t r1 = (r0 + (1u << B.bucket_shift)) < B.n_regions ? r0 + (1u << B.bucket_shift)
-                                                                     : B.n_regions;
-    uint32_t sum = 0;
-    for (uint32_t r = r0; r < r1; r++)
-        sum += fine[(uint64_t)r * B.G + g];
-    coarse[i] = sum;
 }
 
 // Level 1: slot ids of this workgroup's positions -> runs of the bucket list.
@@ -428,7 +436,8 @@ __global__ void __launch_bounds__(kBinWG) k_part_scatter(uint64_t c0, uint64_t c
 // single-level path.
 __global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restrict__ list,
                                                        uint64_t n, BinPlan B,
-                                                       uint32_t *__restrict__ fine) {
+                                                       uint32_t *__restrict__ fine,
+                                                       uint32_t *__restrict__ coarse) {
     extern __shared__ uint32_t s_hist[];
     for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
         s_hist[i] = 0;
@@ -451,6 +460,7 @@ __global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restric
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
         fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
+    write_bucket_sums(s_hist, B, coarse, blockIdx.x);
 }
 
 // Level 1 over one partition's list: entries of list workgroup g -> runs of
@@ -680,7 +690,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         P->begin(kPhBinCount, s);
     hipLaunchKernelGGL(k_bin_count<true>, dim3(B.G), dim3(kBinWG),
                        (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
-                       W.parts, W.pmat, (unsigned long long *)(W.totals + 5));
+                       W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -726,7 +736,8 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         if (P)
             P->begin(kPhPartCount, s);
         hipLaunchKernelGGL(k_list_count, dim3(Q.G), dim3(kBinWG),
-                           (size_t)Q.n_regions * sizeof(uint32_t), s, list, n, Q, W.matrix);
+                           (size_t)Q.n_regions * sizeof(uint32_t), s, list, n, Q, W.matrix,
+                           W.coarse);
         if (P)
             P->end(s);
         e = hipGetLastError();
@@ -734,11 +745,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
             break;
         if (P)
             P->begin(kPhScan, s);
-        hipLaunchKernelGGL(k_bucket_counts, dim3((unsigned)((n_coarse + 255) / 256)), dim3(256), 0,
-                           s, Q, (const uint32_t *)W.matrix, W.coarse);
-        e = hipGetLastError();
-        if (e == hipSuccess)
-            e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+        e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
         if (e == hipSuccess)
             e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
         if (P)
@@ -793,7 +800,7 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (P)
         P->begin(kPhBinCount, s);
     hipLaunchKernelGGL(k_bin_count<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
-                       W.slots, nullptr, W.matrix, (unsigned long long *)(W.totals + 5));
+                       W.slots, nullptr, W.matrix, W.coarse, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -801,11 +808,7 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhScan, s);
-    hipLaunchKernelGGL(k_bucket_counts, dim3((unsigned)((n_coarse + 255) / 256)), dim3(256), 0, s,
-                       B, (const uint32_t *)W.matrix, W.coarse);
-    e = hipGetLastError();
-    if (e == hipSuccess)
-        e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+    e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
     if (e == hipSuccess)
         e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
     if (P)

@@ -132,13 +132,15 @@ KC_HD bool base_valid(uint32_t b, uint32_t code) {
 
 // 2-bit reverse complement of a K-base key (K <= 32): complement every code
 // (x ^ 3 == ~x on 2 bits), reverse the order of the 32 2-bit groups, drop the
-// 32-K groups that came from the unused high end.
+// 32-K groups that came from the unused high end.  The group order is
+// reversed by a full bit reversal (one instruction per 32-bit half), which
+// also swaps the two bits inside every group; swapping them back restores
+// each code.
 KC_HD uint64_t revcomp_key(uint64_t x, uint32_t K) {
-    x = ~x;
-    x = ((x >> 2) & 0x3333333333333333ull) | ((x & 0x3333333333333333ull) << 2);
-    x = ((x >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((x & 0x0F0F0F0F0F0F0F0Full) << 4);
-    x = __builtin_bswap64(x);
-    return x >> (64u - 2u * K);
+    const uint32_t lo = ~(uint32_t)x, hi = ~(uint32_t)(x >> 32);
+    uint64_t r = ((uint64_t)__builtin_bitreverse32(lo) << 32) | __builtin_bitreverse32(hi);
+    r = ((r >> 1) & 0x5555555555555555ull) | ((r & 0x5555555555555555ull) << 1);
+    return r >> (64u - 2u * K);
 }
 
 // Forward key of the K-base window starting at p (first base most
