@@ -269,7 +269,7 @@ def _cfg_large(scale: float) -> ReadSet:
                    {"genome": g, "reads": n, "read_len": 250, "p_sub": 0.003})
 
 
-_CONFIGS = {
+_WORKLOADS = {
     "tiny": _cfg_tiny,
     "bacterial": _cfg_bacterial,
     "batched": _cfg_batched,
@@ -278,7 +278,7 @@ _CONFIGS = {
 
 
 def config_names():
-    return list(_CONFIGS)
+    return list(_WORKLOADS)
 
 
 def config(name: str, scale: float = 1.0):
@@ -287,7 +287,7 @@ def config(name: str, scale: float = 1.0):
     ``scale`` shrinks genome and read counts proportionally (tests use small
     scales); the seeds do not depend on it.
     """
-    return _CONFIGS[name](scale)
+    return _WORKLOADS[name](scale)
 
 
 # ---------------------------------------------------------------------------
