@@ -14,36 +14,49 @@ constexpr int kScanPer = 16;
 constexpr int kScanBlock = kScanThreads * kScanPer;  // elements per workgroup
 constexpr int kTopThreads = 1024;
 
+// Exclusive sum of one value per thread over the workgroup: wave scans by
+// shuffles, then the wave totals.  s_wave: kScanThreads / 64 entries.
 template <typename T>
-__device__ __forceinline__ T wg_exclusive_sum(T v, T *s_tmp, T &total) {
-    // s_tmp: kScanThreads entries.  Hillis-Steele over the workgroup.
-    const int tid = threadIdx.x;
-    s_tmp[tid] = v;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        T add = tid >= d ? s_tmp[tid - d] : (T)0;
-        __syncthreads();
-        s_tmp[tid] += add;
-        __syncthreads();
+__device__ __forceinline__ T wg_exclusive_sum(T v, T *s_wave, T &total) {
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
     }
-    total = s_tmp[kScanThreads - 1];
-    T incl = s_tmp[tid];
+    if (lane == 63)
+        s_wave[wave] = incl;
     __syncthreads();
-    return incl - v;
+    T before = 0;
+    total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kScanThreads / 64; w++) {
+        const T t = s_wave[w];
+        if (w < wave)
+            before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + incl - v;
 }
 
+// Sum of each workgroup's kScanBlock elements (coalesced: element i*256+tid).
 template <typename TIn, typename TOut>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const TIn *__restrict__ in, uint64_t n,
                                                              TOut *__restrict__ partial) {
-    __shared__ TOut s[kScanThreads];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+    __shared__ TOut s_wave[kScanThreads / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
     TOut sum = 0;
 #pragma unroll
-    for (int i = 0; i < kScanPer; i++)
-        if (base + i < n)
-            sum += (TOut)in[base + i];
+    for (int i = 0; i < kScanPer; i++) {
+        const uint64_t x = base + (uint64_t)i * kScanThreads;
+        if (x < n)
+            sum += (TOut)in[x];
+    }
     TOut total;
-    (void)wg_exclusive_sum<TOut>(sum, s, total);
+    (void)wg_exclusive_sum<TOut>(sum, s_wave, total);
     if (threadIdx.x == 0)
         partial[blockIdx.x] = total;
 }
@@ -78,26 +91,47 @@ __global__ void __launch_bounds__(kTopThreads) k_scan_top(TOut *__restrict__ par
         *total = s[kTopThreads - 1];
 }
 
+// LDS slot of element e of a block: one pad word after every kScanPer
+// elements, so that thread t's run (elements 16t .. 16t+15) and the
+// coalesced rows (elements i*256 + t) are both free of bank conflicts.
+__device__ __forceinline__ uint32_t pad_at(uint32_t e) { return e + e / kScanPer; }
+
+// Exclusive scan of each workgroup's elements, offset by its partial:
+// coalesced loads into LDS, a sequential scan of 16 consecutive elements per
+// thread, the workgroup scan of the thread sums, coalesced stores.
 template <typename TIn, typename TOut>
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(const TIn *__restrict__ in, uint64_t n,
                                                            const TOut *__restrict__ partial,
                                                            TOut *__restrict__ out) {
-    __shared__ TOut s[kScanThreads];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+    __shared__ TOut s_buf[kScanBlock + kScanBlock / kScanPer];
+    __shared__ TOut s_wave[kScanThreads / 64];
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock;
+#pragma unroll
+    for (int i = 0; i < kScanPer; i++) {
+        const uint32_t e = (uint32_t)i * kScanThreads + threadIdx.x;
+        s_buf[pad_at(e)] = b0 + e < n ? (TOut)in[b0 + e] : (TOut)0;
+    }
+    __syncthreads();
     TOut v[kScanPer];
     TOut sum = 0;
 #pragma unroll
     for (int i = 0; i < kScanPer; i++) {
-        v[i] = base + i < n ? (TOut)in[base + i] : (TOut)0;
+        v[i] = s_buf[pad_at(threadIdx.x * kScanPer + i)];
         sum += v[i];
     }
     TOut total;
-    TOut run = partial[blockIdx.x] + wg_exclusive_sum<TOut>(sum, s, total);
+    TOut run = partial[blockIdx.x] + wg_exclusive_sum<TOut>(sum, s_wave, total);
 #pragma unroll
     for (int i = 0; i < kScanPer; i++) {
-        if (base + i < n)
-            out[base + i] = run;
+        s_buf[pad_at(threadIdx.x * kScanPer + i)] = run;
         run += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanPer; i++) {
+        const uint32_t e = (uint32_t)i * kScanThreads + threadIdx.x;
+        if (b0 + e < n)
+            out[b0 + e] = s_buf[pad_at(e)];
     }
 }
 
