@@ -68,6 +68,40 @@ static_assert(kMaxParts <= 256, "partition ids are bytes");
 
 // kParts: the partitioned path; the slot id holds the region within its
 // partition, parts[] the partition, and the histogram counts partitions.
+// Slot ids of one valid window at chunk-relative position q (hash functions
+// 1..k_h), with the workgroup histogram update.
+template <bool kParts>
+__device__ __forceinline__ void bin_window(const FilterArgs &F, const BinPlan &B, uint64_t fwd,
+                                           uint32_t K, uint64_t q, uint64_t len,
+                                           uint32_t *__restrict__ slots,
+                                           uint8_t *__restrict__ parts, uint32_t *s_hist) {
+    const uint32_t shift = B.region_shift;
+    const uint64_t smask = (1ull << shift) - 1ull;
+    const Canon c = canonical_fast(fwd, K);
+    for (uint32_t a = 1; a <= F.k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
+        const uint32_t r = (uint32_t)(word >> shift);
+        const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
+        const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
+        const uint64_t at = (uint64_t)(a - 1) * len + q;
+        slots[at] = id;
+        if (kParts) {
+            parts[at] = (uint8_t)(r >> B.part_log);
+            atomicAdd(&s_hist[r >> B.part_log], 1u);
+        } else {
+            atomicAdd(&s_hist[r], 1u);
+        }
+    }
+}
+
+// kParts: the partitioned path; the slot id holds the region within its
+// partition, parts[] the partition, and the histogram counts partitions.
+// Each wavefront extracts windows 64 positions at a time and queues the
+// valid ones (key and position) in an LDS ring of its own; it hashes 64
+// queued windows at a time, so that no lane hashes an invalid window (the
+// last K-1 positions of every read, windows over 'N').
 template <bool kParts>
 __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                       uint64_t c1, BinPlan B,
@@ -76,7 +110,10 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                                                       uint32_t *__restrict__ fine,
                                                       uint32_t *__restrict__ coarse,
                                                       unsigned long long *__restrict__ n_valid) {
+    constexpr uint32_t kRing = 128;  // queued windows per wavefront (< 64 + 64)
     extern __shared__ uint32_t s_hist[];  // n_regions region (n_parts partition) counts
+    __shared__ uint64_t s_key[kBinWG / 64][kRing];
+    __shared__ uint32_t s_pos[kBinWG / 64][kRing];
     __shared__ uint32_t s_valid;
     const uint32_t n_keys = kParts ? B.n_parts : B.n_regions;
     for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
@@ -85,42 +122,46 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
         s_valid = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t shift = B.region_shift;
+    const uint32_t wv = wave_id();
     const uint64_t len = c1 - c0;
     const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
     const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
-    const uint64_t smask = (1ull << shift) - 1ull;
     uint32_t nv = 0;
-    for (uint64_t pb = g0 + 64u * wave_id(); pb < g1; pb += kBinWG) {
+    uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
+    for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
         WaveWords w;
         wave_load(R, pb, w);
         uint64_t fwd;
         const uint64_t p = pb + lane;
         const bool in = p < g1;
         const bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd) && in;
-        if (valid) {
-            nv++;
-            const Canon c = canonical_fast(fwd, R.k);
-            for (uint32_t a = 1; a <= F.k_h; a++) {
-                uint64_t word;
-                uint32_t l;
-                slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
-                const uint32_t r = (uint32_t)(word >> shift);
-                const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
-                const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
-                const uint64_t at = (uint64_t)(a - 1) * len + (p - c0);
-                slots[at] = id;
-                if (kParts) {
-                    parts[at] = (uint8_t)(r >> B.part_log);
-                    atomicAdd(&s_hist[r >> B.part_log], 1u);
-                } else {
-                    atomicAdd(&s_hist[r], 1u);
-                }
-            }
-        } else if (in) {
+        if (!valid && in)
             for (uint32_t a = 1; a <= F.k_h; a++)
                 slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
+        const uint64_t m = __ballot(valid);
+        if (valid) {
+            nv++;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t at = (head + queued + rank) & (kRing - 1u);
+            s_key[wv][at] = fwd;
+            s_pos[wv][at] = (uint32_t)(p - c0);
         }
+        queued += (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        if (queued >= 64u) {
+            const uint32_t at = (head + lane) & (kRing - 1u);
+            const uint64_t key = s_key[wv][at];
+            const uint32_t q = s_pos[wv][at];
+            __builtin_amdgcn_wave_barrier();
+            head = (head + 64u) & (kRing - 1u);
+            queued -= 64u;
+            bin_window<kParts>(F, B, key, R.k, q, len, slots, parts, s_hist);
+        }
+    }
+    if (lane < queued) {  // the last windows of the wavefront's positions
+        const uint32_t at = (head + lane) & (kRing - 1u);
+        bin_window<kParts>(F, B, s_key[wv][at], R.k, s_pos[wv][at], len, slots, parts, s_hist);
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
