@@ -73,50 +73,84 @@ __global__ void kb_zero_valid(unsigned long long *__restrict__ valid, uint32_t n
         valid[s] = 0;
 }
 
+__device__ __forceinline__ void kb_bin_window(const SetDesc &S, const FilterArgs &F, uint64_t fwd,
+                                              uint64_t q, uint32_t *__restrict__ slots,
+                                              uint32_t *s_hist) {
+    const uint32_t shift = S.region_shift;
+    const uint64_t smask = (1ull << shift) - 1ull;
+    const Canon c = canonical_fast(fwd, S.k);
+    for (uint32_t a = 1; a <= F.k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
+        const uint32_t r = (uint32_t)(word >> shift);
+        slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + q] =
+            (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
+        atomicAdd(&s_hist[r], 1u);
+    }
+}
+
+// Slot ids of an item's windows and its per-region counts.  As in the
+// single-set bin pass, each wavefront queues its valid windows in an LDS
+// ring and hashes 64 of them at a time.
 __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict__ sets,
                                                        const uint32_t *__restrict__ item_set,
                                                        ReadsArgs R, uint64_t tile,
                                                        uint32_t *__restrict__ slots,
                                                        uint32_t *__restrict__ matrix,
                                                        unsigned long long *__restrict__ valid) {
+    constexpr uint32_t kRing = 128;
     __shared__ uint32_t s_hist[kBatchMaxRegions];
+    __shared__ uint64_t s_key[kBinWG / 64][kRing];
+    __shared__ uint32_t s_pos[kBinWG / 64][kRing];
     __shared__ uint32_t s_valid;
     const Item it = item_of(sets, item_set, blockIdx.x, tile);
     const SetDesc &S = sets[it.s];
     const FilterArgs F = S.F;
-    const uint32_t shift = S.region_shift;
     for (uint32_t i = threadIdx.x; i < S.n_regions; i += kBinWG)
         s_hist[i] = 0;
     if (threadIdx.x == 0)
         s_valid = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t smask = (1ull << shift) - 1ull;
+    const uint32_t wv = wave_id();
     R.k = S.k;
     uint32_t nv = 0;
-    for (uint64_t pb = it.g0 + 64u * wave_id(); pb < it.g1; pb += kBinWG) {
+    uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
+    for (uint64_t pb = it.g0 + 64u * wv; pb < it.g1; pb += kBinWG) {
         WaveWords w;
         wave_load(R, pb, w);
         uint64_t fwd;
         const uint64_t p = pb + lane;
         const bool in = p < it.g1;
         const bool ok = wave_window(w, pb, lane, S.k, R.n_bases, fwd) && in;
-        if (ok) {
-            nv++;
-            const Canon c = canonical_fast(fwd, S.k);
-            for (uint32_t a = 1; a <= F.k_h; a++) {
-                uint64_t word;
-                uint32_t l;
-                slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
-                const uint32_t r = (uint32_t)(word >> shift);
-                slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + (p - S.base)] =
-                    (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
-                atomicAdd(&s_hist[r], 1u);
-            }
-        } else if (in) {
+        if (!ok && in)
             for (uint32_t a = 1; a <= F.k_h; a++)
                 slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + (p - S.base)] = kNoSlot;
+        const uint64_t m = __ballot(ok);
+        if (ok) {
+            nv++;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t at = (head + queued + rank) & (kRing - 1u);
+            s_key[wv][at] = fwd;
+            s_pos[wv][at] = (uint32_t)(p - S.base);
         }
+        queued += (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        if (queued >= 64u) {
+            const uint32_t at = (head + lane) & (kRing - 1u);
+            const uint64_t key = s_key[wv][at];
+            const uint32_t q = s_pos[wv][at];
+            __builtin_amdgcn_wave_barrier();
+            head = (head + 64u) & (kRing - 1u);
+            queued -= 64u;
+            kb_bin_window(S, F, key, q, slots, s_hist);
+        }
+    }
+    if (lane < queued) {
+        const uint32_t at = (head + lane) & (kRing - 1u);
+        kb_bin_window(S, F, s_key[wv][at], s_pos[wv][at], slots, s_hist);
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
@@ -127,7 +161,13 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
 }
 
 // Slot ids of an item -> its segments of the entry list, counting-sorted by
-// region in LDS per batch of kStage entries.
+// region in LDS per batch of kWriteStage entries.  The large batch keeps the
+// runs written per region long even for sets of 2048 regions (runs of the
+// smaller level-1 batches of the single-set path would be 2 entries there).
+constexpr int kWriteStage = 16384;  // 128 KiB of staged entries
+constexpr uint32_t kWriteStageLog = 14;
+static_assert(kWriteStage == (1 << kWriteStageLog), "stage size");
+
 __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict__ sets,
                                                        const uint32_t *__restrict__ item_set,
                                                        uint64_t tile,
@@ -135,14 +175,15 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
                                                        const uint32_t *__restrict__ offsets,
                                                        uint64_t *__restrict__ entries,
                                                        uint64_t cap) {
-    constexpr int kPer = kStage / kBinWG;
+    constexpr int kPer = kWriteStage / kBinWG;
     constexpr int kScanPer = kBatchMaxRegions / kBinWG;
-    __shared__ uint64_t s_stage[kStage];
+    __shared__ uint64_t s_stage[kWriteStage];
     __shared__ uint32_t s_cnt[kBatchMaxRegions];
-    __shared__ uint32_t s_start[kBatchMaxRegions];
+    __shared__ uint16_t s_start[kBatchMaxRegions];  // < kWriteStage
     __shared__ uint32_t s_fill[kBatchMaxRegions];
     __shared__ uint32_t s_cursor[kBatchMaxRegions];
     __shared__ uint32_t s_wave[kBinWG / 64];
+    __shared__ uint32_t s_total;
     const Item it = item_of(sets, item_set, blockIdx.x, tile);
     const SetDesc &S = sets[it.s];
     const uint32_t nr = S.n_regions;
@@ -156,20 +197,24 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
     uint32_t bl = 0;
     while ((1u << bl) < k_h)
         bl++;
-    const uint32_t batch_log = kStageLog - bl;
-    const uint64_t batch = 1ull << batch_log;
-    const uint64_t q_lo = it.g0 - S.base, q_hi = it.g1 - S.base;  // set-relative positions
+    const uint32_t batch_log = kWriteStageLog - bl;
+    const uint32_t batch = 1u << batch_log;
+    // set-relative positions and slot offsets fit 32 bits (sets hold at most
+    // 2^28 bases, k_h <= 8)
+    const uint32_t q_lo = (uint32_t)(it.g0 - S.base), q_hi = (uint32_t)(it.g1 - S.base);
+    const uint32_t nb = (uint32_t)S.n_bases;
+    const uint32_t *__restrict__ sl = slots + S.slot_base;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    for (uint64_t q0 = q_lo; q0 < q_hi; q0 += batch) {
-        const uint64_t nq = (q0 + batch < q_hi ? q0 + batch : q_hi) - q0;
+    for (uint32_t q0 = q_lo; q0 < q_hi; q0 += batch) {
+        const uint32_t nq = (q_hi - q0 < batch ? q_hi - q0 : batch);
         uint32_t id[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
-            const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
-            const uint64_t a = i >> batch_log;
-            const uint64_t q = q0 + (i & (batch - 1));
-            id[u] = (a < k_h && q - q0 < nq) ? slots[S.slot_base + a * S.n_bases + q] : kNoSlot;
+            const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
+            const uint32_t a = i >> batch_log;
+            const uint32_t qq = i & (batch - 1u);
+            id[u] = (a < k_h && qq < nq) ? sl[a * nb + q0 + qq] : kNoSlot;
         }
 #pragma unroll
         for (int u = 0; u < kPer; u++)
@@ -198,22 +243,24 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
                 run += s_wave[w];
 #pragma unroll
             for (int u = 0; u < kScanPer; u++) {
-                s_start[threadIdx.x * kScanPer + u] = run;
+                s_start[threadIdx.x * kScanPer + u] = (uint16_t)run;
                 run += v[u];
             }
+            if (threadIdx.x == kBinWG - 1)
+                s_total = run;  // staged entries of this batch (<= kWriteStage)
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot) {
-                const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
-                const uint64_t q = q0 + (i & (batch - 1));
+                const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
+                const uint32_t q = q0 + (i & (batch - 1u));
                 const uint32_t r = id[u] >> kLocalBits;
                 const uint32_t j = s_start[r] + atomicAdd(&s_fill[r], 1u);
-                s_stage[j] = (q << 32) | id[u];
+                s_stage[j] = ((uint64_t)q << 32) | id[u];
             }
         __syncthreads();
-        const uint32_t n_stage = s_start[kBatchMaxRegions - 1] + s_cnt[kBatchMaxRegions - 1];
+        const uint32_t n_stage = s_total;
         for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
             const uint64_t e = s_stage[j];
             const uint32_t r = (uint32_t)e >> kLocalBits;
