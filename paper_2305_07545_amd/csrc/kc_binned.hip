@@ -576,34 +576,75 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
     }
 }
 
+// Counter update of cell w of the region (pre = its value before the chunk).
+__device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &B, uint64_t wbase,
+                                            uint32_t w, uint64_t pre, const uint32_t *hits,
+                                            const uint32_t *first, uint8_t *__restrict__ flags,
+                                            uint64_t c0, int classify, uint32_t tau) {
+    uint64_t next = pre;
+    for (uint32_t l = 0; l < F.eta; l++) {
+        const uint32_t idx = (l << B.region_shift) | w;
+        const uint64_t h = hits[idx];
+        if (h == 0)
+            continue;
+        const uint32_t sh = F.alpha * l;
+        const uint64_t pf = (pre >> sh) & F.field_max;
+        const uint64_t room = F.field_max - pf;
+        const uint64_t nf = pf + (h < room ? h : room);
+        next = (next & ~(F.field_max << sh)) | (nf << sh);
+        if (pf == 0) {
+            uint8_t flag = 1;
+            if (classify && nf > (uint64_t)tau)
+                flag = 3;
+            flags[c0 + first[idx]] = flag;
+        }
+    }
+    if (next != pre)
+        F.words[wbase + w] = next;
+}
+
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
                                                       const uint64_t *__restrict__ entries,
                                                       uint8_t *__restrict__ flags, int classify,
                                                       uint32_t tau) {
+    constexpr int kUnroll = 8;
+    constexpr int kHold = 4;  // cells per thread held in registers (regions <= 4096 cells)
     __shared__ uint32_t hits[kRegionCounters];
     __shared__ uint32_t first[kRegionCounters];
     const uint32_t r = blockIdx.x;
     const uint32_t S = 1u << B.region_shift;
     const uint32_t n_ctr = S * F.eta;
+    const uint64_t e0 = offsets[(uint64_t)r * B.G];
+    uint64_t e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
+    if (e1 > B.entries_cap)
+        e1 = B.entries_cap;
+    const uint64_t wbase = (uint64_t)(B.region0 + r) << B.region_shift;
+    const uint64_t n_words = F.X * F.Y;
+    const uint32_t nw = wbase + S <= n_words ? S : (uint32_t)(n_words - wbase);
+    // the first entries and the region's cells are requested before the LDS
+    // clear, so that their latency overlaps it (this workgroup alone writes
+    // these cells)
+    uint64_t v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const uint64_t x = e0 + threadIdx.x + (uint64_t)u * kRegionWG;
+        v[u] = x < e1 ? entries[x] : ~0ull;
+    }
+    const bool hold = nw <= (uint32_t)kHold * kRegionWG;
+    uint64_t cell[kHold];
+#pragma unroll
+    for (int k = 0; k < kHold; k++) {
+        const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+        cell[k] = (hold && w < nw) ? F.words[wbase + w] : 0ull;
+    }
     for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
         hits[i] = 0;
         first[i] = kIdle;
     }
     __syncthreads();
-    const uint64_t e0 = offsets[(uint64_t)r * B.G];
-    uint64_t e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
-    if (e1 > B.entries_cap)
-        e1 = B.entries_cap;
-    constexpr int kUnroll = 8;
-    for (uint64_t e = e0 + threadIdx.x; e < e1; e += (uint64_t)kUnroll * kRegionWG) {
-        uint64_t v[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-            const uint64_t x = e + (uint64_t)u * kRegionWG;
-            v[u] = x < e1 ? entries[x] : ~0ull;
-        }
+    for (uint64_t e = e0 + threadIdx.x;;) {
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
             if (v[u] == ~0ull)
@@ -612,33 +653,27 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             atomicAdd(&hits[local], 1u);
             atomicMin(&first[local], (uint32_t)(v[u] >> 32));
         }
+        e += (uint64_t)kUnroll * kRegionWG;
+        if (e >= e1)
+            break;
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint64_t x = e + (uint64_t)u * kRegionWG;
+            v[u] = x < e1 ? entries[x] : ~0ull;
+        }
     }
     __syncthreads();
-    const uint64_t wbase = (uint64_t)(B.region0 + r) << B.region_shift;
-    const uint64_t n_words = F.X * F.Y;
-    const uint32_t nw = wbase + S <= n_words ? S : (uint32_t)(n_words - wbase);
-    for (uint32_t w = threadIdx.x; w < nw; w += kRegionWG) {
-        const uint64_t pre = F.words[wbase + w];
-        uint64_t next = pre;
-        for (uint32_t l = 0; l < F.eta; l++) {
-            const uint32_t idx = (l << B.region_shift) | w;
-            const uint64_t h = hits[idx];
-            if (h == 0)
-                continue;
-            const uint32_t sh = F.alpha * l;
-            const uint64_t pf = (pre >> sh) & F.field_max;
-            const uint64_t room = F.field_max - pf;
-            const uint64_t nf = pf + (h < room ? h : room);
-            next = (next & ~(F.field_max << sh)) | (nf << sh);
-            if (pf == 0) {
-                uint8_t flag = 1;
-                if (classify && nf > (uint64_t)tau)
-                    flag = 3;
-                flags[c0 + first[idx]] = flag;
-            }
+    if (hold) {
+#pragma unroll
+        for (int k = 0; k < kHold; k++) {
+            const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+            if (w < nw)
+                region_cell(F, B, wbase, w, cell[k], hits, first, flags, c0, classify, tau);
         }
-        if (next != pre)
-            F.words[wbase + w] = next;
+    } else {
+        for (uint32_t w = threadIdx.x; w < nw; w += kRegionWG)
+            region_cell(F, B, wbase, w, F.words[wbase + w], hits, first, flags, c0, classify,
+                        tau);
     }
 }
 
