@@ -138,28 +138,30 @@ kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positi
     kc::Workspace &W = *f->W;
     const uint64_t n_slots = chunk_positions * f->layout.k_h;
     const uint64_t n_pmat = (uint64_t)B.n_parts * B.G;
-    const uint64_t n_mat = kc::kMaxMatrix;  // a pass: regions x list workgroups
-    const uint64_t n_coarse = (uint64_t)kc::kMaxBuckets * kc::kMaxListTiles;
-    const uint64_t n_scan = n_pmat > n_mat ? n_pmat : n_mat;
-    if (W.plist && W.pbounds && n_slots <= W.slots_cap && n_slots <= W.entries_cap &&
-        n_pmat <= W.pmat_cap && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap &&
-        n_scan <= W.matrix_cap)
+    const uint64_t n_fine = (uint64_t)B.n_regions * B.list_g;
+    const uint64_t nbp = (1ull << B.part_log) >> B.bucket_shift;
+    const uint64_t n_coarse = (uint64_t)B.n_parts * nbp * B.list_g;
+    const uint64_t n_mat = n_fine > n_pmat ? n_fine : n_pmat;  // the scans share partial32
+    if (W.plist && W.pbounds && W.pdesc && n_slots <= W.slots_cap && n_slots <= W.entries_cap &&
+        n_pmat <= W.pmat_cap && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap)
         return KC_OK;
     wait_idle(f);
-    if (!W.pbounds && (!dev_alloc(&W.pbounds, kc::kMaxParts + 1) ||
-                       hipHostMalloc((void **)&W.pbounds_host, (kc::kMaxParts + 1) * sizeof(uint32_t),
-                                     hipHostMallocDefault) != hipSuccess))
+    if (!W.pbounds && !dev_alloc(&W.pbounds, kc::kMaxParts + 1))
         return KC_ENOMEM;
-    if (!W.matrix || n_scan > W.matrix_cap || n_coarse > W.coarse_cap) {
+    if (!W.pdesc && !dev_alloc(&W.pdesc, 3ull * kc::kMaxParts))
+        return KC_ENOMEM;
+    if (!W.matrix || n_mat > W.matrix_cap || n_coarse > W.coarse_cap) {
+        const uint64_t m = n_mat > W.matrix_cap ? n_mat : W.matrix_cap;
+        const uint64_t c = n_coarse > W.coarse_cap ? n_coarse : W.coarse_cap;
         dev_free(W.matrix);
         dev_free(W.coarse);
         dev_free(W.partial32);
         W.matrix_cap = W.coarse_cap = 0;
-        if (!dev_alloc(&W.matrix, n_scan) || !dev_alloc(&W.coarse, n_coarse) ||
-            !dev_alloc(&W.partial32, kc::scan_partials(n_scan)))
+        if (!dev_alloc(&W.matrix, m) || !dev_alloc(&W.coarse, c) ||
+            !dev_alloc(&W.partial32, kc::scan_partials(m > c ? m : c)))
             return KC_ENOMEM;
-        W.matrix_cap = n_scan;
-        W.coarse_cap = n_coarse;
+        W.matrix_cap = m;
+        W.coarse_cap = c;
     }
     if (!W.pmat || n_pmat > W.pmat_cap) {
         dev_free(W.pmat);
@@ -232,9 +234,7 @@ void free_workspace(kc::Workspace &W) {
     dev_free(W.plist);
     dev_free(W.pmat);
     dev_free(W.pbounds);
-    if (W.pbounds_host)
-        (void)hipHostFree(W.pbounds_host);
-    W.pbounds_host = nullptr;
+    dev_free(W.pdesc);
     W.slots_cap = W.entries_cap = W.matrix_cap = W.coarse_cap = W.pmat_cap = 0;
     dev_free(W.totals);
     dev_free(W.n_entries);

@@ -38,26 +38,31 @@ __device__ __forceinline__ uint32_t wave_id() {
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
 
 // coarse[b * G + g] = sum of the region counts s_hist[r] over the regions r
-// of bucket b (after the histogram is complete in LDS).  kBinWG threads: 8
-// per bucket, each summing every 8th region, then a shuffle reduction.
-__device__ __forceinline__ void write_bucket_sums(const uint32_t *s_hist, const BinPlan &B,
+// of bucket b (after the histogram is complete in LDS), for n_regions
+// regions in buckets of 2^bshift, for every one of the n_rows buckets
+// (buckets past the last region get 0: every row of a scanned matrix must be
+// written).  kBinWG threads: 8 per bucket, each summing every 8th region,
+// then a shuffle reduction.
+__device__ __forceinline__ void write_bucket_sums(const uint32_t *s_hist, uint32_t n_regions,
+                                                  uint32_t n_rows, uint32_t bshift, uint64_t G,
                                                   uint32_t *__restrict__ coarse, uint32_t g) {
     static_assert(kBinWG == 8 * kMaxBuckets, "8 threads per bucket");
+    const uint32_t n_buckets = n_rows;
     const uint32_t b = threadIdx.x >> 3, sub = threadIdx.x & 7u;
     uint32_t sum = 0;
-    if (b < B.n_buckets) {
-        const uint32_t r0 = b << B.bucket_shift;
-        const uint32_t r1 = r0 + (1u << B.bucket_shift) < B.n_regions
-                                ? r0 + (1u << B.bucket_shift) : B.n_regions;
-        for (uint32_t r = r0 + sub; r < r1; r += 8)
+    if (b < n_buckets) {
+        const uint32_t r0 = b << bshift;
+        const uint32_t r1 = r0 + (1u << bshift) < n_regions ? r0 + (1u << bshift) : n_regions;
+        for (uint32_t r = r0 + sub; r < r1; r += 8)  // empty when r0 >= n_regions
             sum += s_hist[r];
     }
     sum += __shfl_xor(sum, 1, 64);
     sum += __shfl_xor(sum, 2, 64);
     sum += __shfl_xor(sum, 4, 64);
-    if (b < B.n_buckets && sub == 0)
-        coarse[(uint64_t)b * B.G + g] = sum;
+    if (b < n_buckets && sub == 0)
+        coarse[(uint64_t)b * G + g] = sum;
 }
+
 constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
 static_assert(kStage == (1 << kStageLog), "stage size");
 static_assert(kRegionCounters == (1 << kLocalBits), "region size");
@@ -66,8 +71,6 @@ static_assert(kMaxParts <= 256, "partition ids are bytes");
 
 }  // namespace
 
-// kParts: the partitioned path; the slot id holds the region within its
-// partition, parts[] the partition, and the histogram counts partitions.
 // Slot ids of one valid window at chunk-relative position q (hash functions
 // 1..k_h), with the workgroup histogram update.
 template <bool kParts>
@@ -168,7 +171,8 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
         fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
     if (!kParts)
-        write_bucket_sums(s_hist, B, coarse, blockIdx.x);
+        write_bucket_sums(s_hist, B.n_regions, B.n_buckets, B.bucket_shift, B.G, coarse,
+                          blockIdx.x);
     if (threadIdx.x == 0)
         atomicAdd(n_valid, (unsigned long long)s_valid);
 }
@@ -285,6 +289,9 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
     const uint32_t r0 = b << B.bucket_shift;
     const uint32_t nr = (r0 + (1u << B.bucket_shift) <= B.n_regions) ? (1u << B.bucket_shift)
                                                                       : B.n_regions - r0;
+    // slot ids name the region within its partition (buckets never straddle
+    // partitions)
+    const uint32_t r0l = B.n_parts ? (r0 & ((1u << B.part_log) - 1u)) : r0;
     for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kBinWG) {
         s_cursor[i] = i < nr ? fine_off[(uint64_t)(r0 + i) * B.G + gs0] : 0u;
         s_cnt[i] = 0;
@@ -310,7 +317,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
             const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
             v[u] = x < e1 ? bucketed[x] : ~0ull;
             const uint32_t r = ((uint32_t)v[u] >> kLocalBits) & ((1u << kLocalBits) - 1u);
-            ri[u] = (v[u] != ~0ull && r - r0 < nr) ? r - r0 : 0xFFFFFFFFu;
+            ri[u] = (v[u] != ~0ull && r - r0l < nr) ? r - r0l : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int u = 0; u < kPer; u++)
@@ -347,7 +354,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
             s_start[kMaxRegionsPerBucket - 1] + s_cnt[kMaxRegionsPerBucket - 1];
         for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
             const uint64_t e = s_stage[j];
-            const uint32_t r = (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0;
+            const uint32_t r = (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
             const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
             if (dst < cap)
                 entries[dst] = e;
@@ -472,42 +479,82 @@ __global__ void __launch_bounds__(kBinWG) k_part_scatter(uint64_t c0, uint64_t c
     }
 }
 
-// Region counts of one partition's list, per list workgroup of B.tile
-// entries: fine[r][g] (region-major), as k_bin_count produces them for the
-// single-level path.
-__global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restrict__ list,
-                                                       uint64_t n, BinPlan B,
-                                                       uint32_t *__restrict__ fine,
+// The list slice of partition p handled by its list workgroup g: tiles of
+// pdesc[p].tile entries from pdesc[p].lo (the tile size comes from the
+// partition sizes on the device, so no host round trip is needed).
+struct ListTile {
+    uint64_t lo, n;  // first entry in the partition list, entries
+};
+
+__device__ __forceinline__ ListTile list_tile(const uint64_t *__restrict__ pdesc, uint32_t p,
+                                              uint32_t g) {
+    const uint64_t lo = pdesc[3 * p], n = pdesc[3 * p + 1], tile = pdesc[3 * p + 2];
+    const uint64_t a = (uint64_t)g * tile;
+    ListTile t;
+    t.lo = lo + (a < n ? a : n);
+    t.n = a < n ? (n - a < tile ? n - a : tile) : 0;
+    return t;
+}
+
+// pdesc[p] = (start, entries, list tile) of each partition's list.
+__global__ void k_pass_plan(const uint32_t *__restrict__ bounds, uint32_t n_parts, uint32_t list_g,
+                            uint64_t cap, uint64_t *__restrict__ pdesc) {
+    for (uint32_t p = threadIdx.x; p < n_parts; p += blockDim.x) {
+        const uint64_t lo = bounds[p];
+        uint64_t hi = bounds[p + 1];
+        if (hi > cap)
+            hi = cap;
+        const uint64_t n = hi > lo ? hi - lo : 0;
+        pdesc[3 * p] = lo;
+        pdesc[3 * p + 1] = n;
+        pdesc[3 * p + 2] = (n + list_g - 1) / list_g;
+    }
+}
+
+// Region counts per list workgroup of every partition's list:
+// fine[(partition region) x list_g + g] over all regions of the countBF
+// (region-major, the layout the single-level path uses), and the bucket sums
+// into coarse[(p * buckets per partition + b) x list_g + g].
+__global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restrict__ plist,
+                                                       const uint64_t *__restrict__ pdesc,
+                                                       BinPlan B, uint32_t *__restrict__ fine,
                                                        uint32_t *__restrict__ coarse) {
     extern __shared__ uint32_t s_hist[];
-    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
+    const uint32_t p = blockIdx.x / B.list_g, g = blockIdx.x % B.list_g;
+    const uint32_t per = 1u << B.part_log;
+    const uint32_t rp0 = p << B.part_log;
+    const uint32_t nrp = B.n_regions - rp0 < per ? B.n_regions - rp0 : per;
+    for (uint32_t i = threadIdx.x; i < nrp; i += kBinWG)
         s_hist[i] = 0;
     __syncthreads();
-    const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;
-    const uint64_t g1 = g0 + B.tile < n ? g0 + B.tile : n;
+    const ListTile t = list_tile(pdesc, p, g);
+    const uint64_t *__restrict__ list = plist + t.lo;
     constexpr int kUnroll = 8;
-    for (uint64_t e = g0 + threadIdx.x; e < g1; e += (uint64_t)kUnroll * kBinWG) {
+    for (uint64_t e = threadIdx.x; e < t.n; e += (uint64_t)kUnroll * kBinWG) {
         uint32_t v[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
             const uint64_t x = e + (uint64_t)u * kBinWG;
-            v[u] = x < g1 ? (uint32_t)list[x] : kNoSlot;
+            v[u] = x < t.n ? (uint32_t)list[x] : kNoSlot;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
             if (v[u] != kNoSlot)
-                atomicAdd(&s_hist[(v[u] >> kLocalBits) & (kMaxRegions - 1u)], 1u);
+                atomicAdd(&s_hist[(v[u] >> kLocalBits) & (per - 1u)], 1u);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < B.n_regions; i += kBinWG)
-        fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
-    write_bucket_sums(s_hist, B, coarse, blockIdx.x);
+    for (uint32_t i = threadIdx.x; i < nrp; i += kBinWG)
+        fine[(uint64_t)(rp0 + i) * B.list_g + g] = s_hist[i];
+    const uint32_t nbp = per >> B.bucket_shift;  // bucket rows per partition
+    write_bucket_sums(s_hist, nrp, nbp, B.bucket_shift, B.list_g,
+                      coarse + (uint64_t)p * nbp * B.list_g, g);
 }
 
-// Level 1 over one partition's list: entries of list workgroup g -> runs of
-// the bucket list, as k_bin_bucket does for slot ids.
-__global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__restrict__ list,
-                                                            uint64_t n, BinPlan B,
+// Level 1 over every partition's list: the entries of list workgroup g of
+// partition p -> runs of the partition's bucket segments.
+__global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__restrict__ plist,
+                                                            const uint64_t *__restrict__ pdesc,
+                                                            BinPlan B,
                                                             const uint32_t *__restrict__ coarse_off,
                                                             uint64_t *__restrict__ bucketed) {
     constexpr int kPer = kStage / kBinWG;
@@ -516,28 +563,31 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
     __shared__ uint32_t s_start[kMaxBuckets];
     __shared__ uint32_t s_fill[kMaxBuckets];
     __shared__ uint32_t s_cursor[kMaxBuckets];
+    const uint32_t p = blockIdx.x / B.list_g, g = blockIdx.x % B.list_g;
+    const uint32_t per = 1u << B.part_log;
+    const uint32_t nbp = per >> B.bucket_shift;
     const uint32_t bshift = B.bucket_shift + kLocalBits;
-    const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;
-    const uint64_t g1 = g0 + B.tile < n ? g0 + B.tile : n;
+    const ListTile t = list_tile(pdesc, p, g);
+    const uint64_t *__restrict__ list = plist + t.lo;
     const uint64_t cap = B.entries_cap;
     for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
-        s_cursor[i] = i < B.n_buckets ? coarse_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
+        s_cursor[i] = i < nbp ? coarse_off[((uint64_t)p * nbp + i) * B.list_g + g] : 0u;
         s_cnt[i] = 0;
         s_fill[i] = 0;
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint64_t q0 = g0; q0 < g1; q0 += kStage) {
+    for (uint64_t q0 = 0; q0 < t.n; q0 += kStage) {
         uint64_t v[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
             const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
-            v[u] = x < g1 ? list[x] : ~0ull;
+            v[u] = x < t.n ? list[x] : ~0ull;
         }
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (v[u] != ~0ull)
-                atomicAdd(&s_cnt[(uint32_t)v[u] >> bshift], 1u);
+                atomicAdd(&s_cnt[((uint32_t)v[u] >> bshift) & (kMaxBuckets - 1u)], 1u);
         __syncthreads();
         if (threadIdx.x < 64) {
             uint32_t c = s_cnt[lane];
@@ -553,7 +603,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (v[u] != ~0ull) {
-                const uint32_t b = (uint32_t)v[u] >> bshift;
+                const uint32_t b = ((uint32_t)v[u] >> bshift) & (kMaxBuckets - 1u);
                 const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
                 s_stage[j] = v[u];
             }
@@ -561,7 +611,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
         const uint32_t n_stage = s_start[kMaxBuckets - 1] + s_cnt[kMaxBuckets - 1];
         for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
             const uint64_t e = s_stage[j];
-            const uint32_t b = (uint32_t)e >> bshift;
+            const uint32_t b = ((uint32_t)e >> bshift) & (kMaxBuckets - 1u);
             const uint64_t dst = (uint64_t)s_cursor[b] + (j - s_start[b]);
             if (dst < cap)
                 bucketed[dst] = e;
@@ -703,6 +753,23 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_
         B.n_regions = (uint32_t)n_regions;
         B.n_parts = (uint32_t)np;
         B.part_log = part_log;
+        // 64 buckets per partition (fewer for tiny test partitions), so that
+        // global bucket b holds regions [b << bshift, (b + 1) << bshift)
+        B.bucket_shift = part_log >= 6 ? part_log - 6 : 0;
+        B.n_buckets = (uint32_t)((n_regions + (1ull << B.bucket_shift) - 1) >> B.bucket_shift);
+        // list workgroups per partition: about kListWGs in all, and region /
+        // bucket count matrices of bounded size
+        uint64_t lg = (kListWGs + np - 1) / np;
+        if (lg > kMaxListG)
+            lg = kMaxListG;
+        if (lg * n_regions > kMaxMatrix)
+            lg = kMaxMatrix / n_regions;
+        const uint64_t nbp = (1ull << part_log) >> B.bucket_shift;
+        if (lg * np * nbp > kMaxCoarse)
+            lg = kMaxCoarse / (np * nbp);
+        if (lg == 0)
+            return false;
+        B.list_g = (uint32_t)lg;
         uint64_t tile = kBinTileMin;
         while ((chunk_positions + tile - 1) / tile * np > kMaxMatrix)
             tile *= 2;
@@ -730,30 +797,10 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_
 
 namespace {
 
-// The plan of one partition's pass over its n entries of the list.
-BinPlan part_pass(const BinPlan &B, uint32_t p, uint64_t n, uint64_t entries_cap) {
-    BinPlan Q = B;
-    Q.n_parts = 0;
-    Q.region0 = p << B.part_log;
-    const uint32_t per = 1u << B.part_log;
-    Q.n_regions = B.n_regions - Q.region0 < per ? B.n_regions - Q.region0 : per;
-    uint32_t bshift = 0;
-    while (((Q.n_regions + (1u << bshift) - 1) >> bshift) > kMaxBuckets)
-        bshift++;
-    Q.bucket_shift = bshift;
-    Q.n_buckets = (Q.n_regions + (1u << bshift) - 1) >> bshift;
-    // about kListTiles workgroups: enough to fill the chip, and a pass
-    // matrix (regions x workgroups) that stays small to scan
-    uint64_t tile = kBinTileMin;
-    while ((n + tile - 1) / tile > kListTiles)
-        tile *= 2;
-    Q.tile = tile;
-    Q.G = (uint32_t)((n + tile - 1) / tile);
-    Q.n_slices = (Q.G + Q.slice - 1) / Q.slice;
-    Q.entries_cap = entries_cap;
-    return Q;
-}
-
+// Partitioned chunk: hash + partition counts, partition lists, then the
+// per-partition binning for all partitions at once (list workgroups size
+// their slices from the partition sizes on the device), level 2 and the
+// region pass over every region of the countBF.
 hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                               const BinPlan &plan, const Workspace &W, bool classify,
                               uint32_t tau, hipStream_t s, Profiler *P) {
@@ -782,9 +829,6 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         if (P)
             P->end(s);
     }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(W.pbounds_host, W.pbounds, (B.n_parts + 1) * sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinPart, s);
@@ -795,30 +839,34 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
             P->end(s);
         e = hipGetLastError();
     }
-    // the partition sizes decide the passes' grids
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
-    for (uint32_t p = 0; p < B.n_parts && e == hipSuccess; p++) {
-        uint64_t lo = W.pbounds_host[p], hi = W.pbounds_host[p + 1];
-        if (hi > B.entries_cap)
-            hi = B.entries_cap;
-        if (hi <= lo)
-            continue;
-        const uint64_t n = hi - lo;
-        const BinPlan Q = part_pass(B, p, n, W.entries_cap);
-        const uint64_t *list = W.plist + lo;
-        const uint64_t n_fine = (uint64_t)Q.n_regions * Q.G;
-        const uint64_t n_coarse = (uint64_t)Q.n_buckets * Q.G;
-        if (P)
-            P->begin(kPhPartCount, s);
-        hipLaunchKernelGGL(k_list_count, dim3(Q.G), dim3(kBinWG),
-                           (size_t)Q.n_regions * sizeof(uint32_t), s, list, n, Q, W.matrix,
-                           W.coarse);
-        if (P)
-            P->end(s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pass_plan, dim3(1), dim3(256), 0, s, (const uint32_t *)W.pbounds,
+                           B.n_parts, B.list_g, W.entries_cap, W.pdesc);
         e = hipGetLastError();
-        if (e != hipSuccess)
-            break;
+    }
+    if (e != hipSuccess)
+        return e;
+    // the plan of the list passes, level 2 and the region pass: every region
+    // of the countBF, list_g workgroup columns
+    BinPlan Q = B;
+    Q.G = B.list_g;
+    Q.n_slices = (Q.G + Q.slice - 1) / Q.slice;
+    Q.region0 = 0;
+    const uint32_t per = 1u << B.part_log;
+    const uint64_t nbp = per >> B.bucket_shift;
+    const uint64_t n_fine = (uint64_t)B.n_regions * Q.G;
+    const uint64_t n_coarse = (uint64_t)B.n_parts * nbp * Q.G;
+    const uint32_t n_list = B.n_parts * B.list_g;
+    const uint32_t hist = B.n_regions < per ? B.n_regions : per;
+    if (P)
+        P->begin(kPhPartCount, s);
+    hipLaunchKernelGGL(k_list_count, dim3(n_list), dim3(kBinWG), (size_t)hist * sizeof(uint32_t),
+                       s, (const uint64_t *)W.plist, (const uint64_t *)W.pdesc, Q, W.matrix,
+                       W.coarse);
+    if (P)
+        P->end(s);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
         if (P)
             P->begin(kPhScan, s);
         e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
@@ -826,17 +874,18 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
             e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
         if (P)
             P->end(s);
-        if (e != hipSuccess)
-            break;
+    }
+    if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinBucket, s);
-        hipLaunchKernelGGL(k_bin_bucket_list, dim3(Q.G), dim3(kBinWG), 0, s, list, n, Q,
+        hipLaunchKernelGGL(k_bin_bucket_list, dim3(n_list), dim3(kBinWG), 0, s,
+                           (const uint64_t *)W.plist, (const uint64_t *)W.pdesc, Q,
                            (const uint32_t *)W.coarse, W.bucketed);
         if (P)
             P->end(s);
         e = hipGetLastError();
-        if (e != hipSuccess)
-            break;
+    }
+    if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinRegion, s);
         hipLaunchKernelGGL(k_bin_region, dim3(Q.n_buckets * Q.n_slices), dim3(kBinWG), 0, s, Q,
@@ -845,8 +894,8 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         if (P)
             P->end(s);
         e = hipGetLastError();
-        if (e != hipSuccess)
-            break;
+    }
+    if (e == hipSuccess) {
         if (P)
             P->begin(kPhRegion, s);
         hipLaunchKernelGGL(k_region, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,

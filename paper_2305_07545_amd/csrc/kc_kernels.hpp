@@ -37,8 +37,9 @@ constexpr uint32_t kPartLog = 14;            // kMaxRegions == 1 << kPartLog
 constexpr uint32_t kMaxParts = 256;          // partitions (4M regions: 64 GB at alpha = 8)
 constexpr uint64_t kPartChunk = 1ull << 31;  // positions per partitioned chunk (k_h = 1;
                                              // entry offsets are 32-bit: chunk * k_h < 2^32)
-constexpr uint32_t kMaxListTiles = 2048;     // list workgroups per partition pass (at most)
-constexpr uint32_t kListTiles = 1024;        // list workgroups per pass aimed at
+constexpr uint32_t kListWGs = 4096;          // list workgroups over all partitions, about
+constexpr uint32_t kMaxListG = 512;          // list workgroups per partition (at most)
+constexpr uint64_t kMaxCoarse = 1ull << 19;  // (partition bucket, list workgroup) counts
 constexpr int kSuper = 4;                    // tiles per iteration of the tile kernels
 
 struct BinPlan {
@@ -53,7 +54,8 @@ struct BinPlan {
     uint64_t entries_cap;   // capacity of each entry list
     uint32_t n_parts;       // partitioned path: partitions (0: regions binned directly)
     uint32_t part_log;      // partitioned path: log2(regions per partition) <= kPartLog
-    uint32_t region0;       // partition pass: global index of the pass's region 0
+    uint32_t region0;       // global index of region 0 of the launch (0 but in tests)
+    uint32_t list_g;        // partitioned path: list workgroups per partition
 };
 
 // Per-handle workspace (device memory owned by the handle).
@@ -86,7 +88,7 @@ struct Workspace {
     uint32_t *pmat = nullptr;     // pmat_cap (partition, bin workgroup) counts -> offsets
     uint64_t pmat_cap = 0;
     uint32_t *pbounds = nullptr;  // kMaxParts + 1 partition starts in plist
-    uint32_t *pbounds_host = nullptr;  // pinned mirror
+    uint64_t *pdesc = nullptr;    // kMaxParts x (list start, entries, list tile)
     // scalars
     uint64_t *totals = nullptr;   // 8 scan totals / saved counters
     uint32_t *n_entries = nullptr;  // 4 entry totals
@@ -148,8 +150,7 @@ hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
 // partition size (regions) for countBFs of more than 2^part_log regions.
 bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B,
               uint32_t part_log = kPartLog);
-// plan.n_parts > 0 takes the partitioned path, which waits on the host once
-// per chunk for the partition sizes (W.pbounds_host)
+// plan.n_parts > 0 takes the partitioned path
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
                                uint32_t tau, hipStream_t s, Profiler *P);
