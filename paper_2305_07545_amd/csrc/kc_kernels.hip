@@ -176,61 +176,40 @@ __global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *
                                                     uint32_t *__restrict__ tile_d,
                                                     uint32_t *__restrict__ tile_t,
                                                     uint32_t *__restrict__ tile_v) {
-    static_assert(kTile == 4 * kWG, "one flag word per thread and tile");
-    __shared__ uint32_t s_cnt[3 * kSuper];
+    // one wavefront per tile: 16 flag bytes per lane, counts reduced by
+    // shuffles, no LDS and no barriers
+    static_assert(kTile == 64 * 16, "16 flag bytes per lane and tile");
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t *f32 = reinterpret_cast<const uint32_t *>(flags);
-    const uint64_t n_super = (n_tiles + kSuper - 1) / kSuper;
-    for (uint64_t st = blockIdx.x; st < n_super; st += gridDim.x) {
-        if (threadIdx.x < 3 * kSuper)
-            s_cnt[threadIdx.x] = 0;
-        __syncthreads();
-        uint32_t x[kSuper];
-#pragma unroll
-        for (int u = 0; u < kSuper; u++) {
-            const uint64_t tile = st * kSuper + u;
-            x[u] = tile < n_tiles ? f32[tile * kWG + threadIdx.x] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kSuper; u++) {
-            const uint64_t tile = st * kSuper + u;
-            uint32_t nd = (uint32_t)__popc(x[u] & 0x01010101u);
-            uint32_t nt = (uint32_t)__popc(x[u] & 0x02020202u);
-            uint32_t nv = 0;
-            if (count_valid && tile < n_tiles) {
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kWG / 64);
+    const uint4 *f128 = reinterpret_cast<const uint4 *>(flags);
+    for (uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave; tile < n_tiles;
+         tile += n_waves) {
+        const uint4 x = f128[tile * 64 + lane];
+        uint32_t nd = (uint32_t)(__popc(x.x & 0x01010101u) + __popc(x.y & 0x01010101u) +
+                                 __popc(x.z & 0x01010101u) + __popc(x.w & 0x01010101u));
+        uint32_t nt = (uint32_t)(__popc(x.x & 0x02020202u) + __popc(x.y & 0x02020202u) +
+                                 __popc(x.z & 0x02020202u) + __popc(x.w & 0x02020202u));
+        uint32_t nv = 0;  // the same on every lane
+        if (count_valid) {
 #pragma unroll 1
-                for (int j = 0; j < kTile / kWG; j++) {
-                    const uint64_t pb = tile * kTile + (uint64_t)j * kWG + 64u * wave;
-                    WaveWords w;
-                    wave_load(R, pb, w);
-                    uint64_t fwd;
-                    nv += (uint32_t)__popcll(
-                        __ballot(wave_window(w, pb, lane, R.k, R.n_bases, fwd)));
-                }
-                if (lane != 0)
-                    nv = 0;
-            }
-            for (uint32_t d = 32; d >= 1; d >>= 1) {
-                nd += __shfl_down(nd, d, 64);
-                nt += __shfl_down(nt, d, 64);
-            }
-            if (lane == 0) {
-                atomicAdd(&s_cnt[3 * u], nd);
-                atomicAdd(&s_cnt[3 * u + 1], nt);
-                atomicAdd(&s_cnt[3 * u + 2], nv);
+            for (int j = 0; j < kTile / 64; j++) {
+                const uint64_t pb = tile * kTile + 64u * (uint64_t)j;
+                WaveWords w;
+                wave_load(R, pb, w);
+                uint64_t fwd;
+                nv += (uint32_t)__popcll(__ballot(wave_window(w, pb, lane, R.k, R.n_bases, fwd)));
             }
         }
-        __syncthreads();
-        if (threadIdx.x < kSuper) {
-            const uint64_t tile = st * kSuper + threadIdx.x;
-            if (tile < n_tiles) {
-                tile_d[tile] = s_cnt[3 * threadIdx.x];
-                tile_t[tile] = s_cnt[3 * threadIdx.x + 1];
-                tile_v[tile] = s_cnt[3 * threadIdx.x + 2];
-            }
+        for (uint32_t d = 32; d >= 1; d >>= 1) {
+            nd += __shfl_down(nd, d, 64);
+            nt += __shfl_down(nt, d, 64);
         }
-        __syncthreads();
+        if (lane == 0) {
+            tile_d[tile] = nd;
+            tile_t[tile] = nt;
+            tile_v[tile] = nv;
+        }
     }
 }
 
