@@ -213,10 +213,21 @@ __global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *
     }
 }
 
-// Ordered output.  Per super-tile (kSuper tiles), the flagged positions are
-// first gathered into a dense list in position order (so that hashing is done
-// only for them), then each listed window's canonical key goes to the
+// Ordered output, one wavefront per tile.  The tile's flagged positions are
+// first gathered into a wavefront-private list in position order (so that
+// only they are hashed), then each listed window's canonical key goes to the
 // distinct list and, when split, to the trustworthy or erroneous list.
+__device__ __forceinline__ uint32_t wave_exclusive(uint32_t v, uint32_t lane, uint32_t &total) {
+    uint32_t incl = v;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
 __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__restrict__ flags,
                                                  uint64_t n_tiles,
                                                  const uint64_t *__restrict__ off_d,
@@ -226,54 +237,55 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
                                                  uint64_t *__restrict__ trust,
                                                  uint64_t *__restrict__ err, uint64_t cap_te,
                                                  int split) {
-    constexpr int kSuperPos = kSuper * kTile;  // positions per super-tile
-    constexpr int kWords = kSuperPos / 4 / kWG; // flag words per thread
-    static_assert(kSuperPos <= 32768, "list entries are 15-bit");
-    __shared__ uint32_t s_wave[2][kWG / 64];
-    __shared__ uint16_t s_pos[kSuperPos];  // super-tile position of the i-th flagged window
-    __shared__ uint16_t s_tb[kSuperPos];   // trustworthy windows before it; bit 15: it is one
-    const uint32_t *f32 = reinterpret_cast<const uint32_t *>(flags);
+    static_assert(kTile == 64 * 16, "16 flag bytes per lane and tile");
+    static_assert(kTile <= 32768, "list entries are 15-bit");
+    __shared__ uint16_t s_pos[kWG / 64][kTile];  // tile position of the i-th flagged window
+    __shared__ uint16_t s_tb[kWG / 64][kTile];   // trustworthy windows before it; bit 15: it is one
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kWG / 64);
+    const uint4 *f128 = reinterpret_cast<const uint4 *>(flags);
     const uint64_t base = split ? *call_base : 0;
-    const uint64_t n_super = (n_tiles + kSuper - 1) / kSuper;
-    const uint64_t n_words = n_tiles * kWG;
-    for (uint64_t st = blockIdx.x; st < n_super; st += gridDim.x) {
-        const uint64_t w0 = st * (kSuperPos / 4) + (uint64_t)threadIdx.x * kWords;
-        uint32_t x[kWords];
+    uint16_t *lpos = s_pos[wave];
+    uint16_t *ltb = s_tb[wave];
+    for (uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave; tile < n_tiles;
+         tile += n_waves) {
+        const uint4 x4 = f128[tile * 64 + lane];
+        const uint32_t x[4] = {x4.x, x4.y, x4.z, x4.w};
         uint32_t cd = 0, ct = 0;
 #pragma unroll
-        for (int u = 0; u < kWords; u++) {
-            x[u] = w0 + u < n_words ? f32[w0 + u] : 0u;
+        for (int u = 0; u < 4; u++) {
             cd += (uint32_t)__popc(x[u] & 0x01010101u);
             ct += (uint32_t)__popc(x[u] & 0x02020202u);
         }
         uint32_t tot_d, tot_t;
-        uint32_t rd = wg_exclusive_u32(cd, s_wave[0], tot_d);
-        uint32_t rt = wg_exclusive_u32(ct, s_wave[1], tot_t);
+        uint32_t rd = wave_exclusive(cd, lane, tot_d);
+        uint32_t rt = wave_exclusive(ct, lane, tot_t);
 #pragma unroll
-        for (int u = 0; u < kWords; u++) {
+        for (int u = 0; u < 4; u++) {
 #pragma unroll
             for (uint32_t sub = 0; sub < 4; sub++) {
                 const uint32_t fb = (x[u] >> (8u * sub)) & 0xFFu;
                 if (fb) {
-                    s_pos[rd] = (uint16_t)(4u * (threadIdx.x * kWords + u) + sub);
-                    s_tb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
+                    lpos[rd] = (uint16_t)(16u * lane + 4u * (uint32_t)u + sub);
+                    ltb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
                     rd++;
                     rt += fb == 3;
                 }
             }
         }
-        __syncthreads();
-        const uint64_t pos0 = st * kSuperPos;
-        const uint64_t od = off_d[st * kSuper];
-        const uint64_t ot = split ? off_t[st * kSuper] : 0;
-        for (uint32_t i = threadIdx.x; i < tot_d; i += kWG) {
-            const uint64_t p = pos0 + s_pos[i];
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t pos0 = tile * kTile;
+        const uint64_t od = off_d[tile];
+        const uint64_t ot = split ? off_t[tile] : 0;
+        for (uint32_t i = lane; i < tot_d; i += 64) {
+            const uint64_t p = pos0 + lpos[i];
             const uint64_t key = canonical_fast(window_key(R.codes, p, R.k), R.k).key;
             const uint64_t d = od + i;
             if (d < cap_d)
                 distinct[d] = key;
             if (split) {
-                const uint32_t tb = s_tb[i];
+                const uint32_t tb = ltb[i];
                 const uint64_t ti = ot + (tb & 0x7FFFu);  // trustworthy keys before this one
                 if (tb & 0x8000u) {
                     if (ti < cap_te)
@@ -285,7 +297,7 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
                 }
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // the list is rewritten by the next tile
     }
 }
 
