@@ -354,78 +354,83 @@ __global__ void __launch_bounds__(kRegionWG) kb_region(const SetDesc *__restrict
     }
 }
 
-// Per super-tile of every set: the set's ordered outputs (as k_compact).
+// Per tile of every set, one wavefront per tile: the set's ordered outputs
+// (as k_compact).  Sets start at multiples of 4096 positions, so a tile
+// belongs to one set.
 __global__ void __launch_bounds__(kWG) kb_compact(const SetDesc *__restrict__ sets,
                                                   const uint32_t *__restrict__ tile_set,
                                                   ReadsArgs R, const uint8_t *__restrict__ flags,
                                                   uint64_t n_tiles,
                                                   const uint64_t *__restrict__ off_d,
                                                   const uint64_t *__restrict__ off_t) {
-    constexpr int kSuperPos = kSuper * kTile;
-    constexpr int kWords = kSuperPos / 4 / kWG;
-    __shared__ uint32_t s_wave[2][kWG / 64];
-    __shared__ uint16_t s_pos[kSuperPos];
-    __shared__ uint16_t s_tb[kSuperPos];
-    const uint32_t *f32 = reinterpret_cast<const uint32_t *>(flags);
-    const uint64_t n_super = (n_tiles + kSuper - 1) / kSuper;
-    const uint64_t n_words = n_tiles * kWG;
-    for (uint64_t st = blockIdx.x; st < n_super; st += gridDim.x) {
-        const uint32_t sidx = tile_set[st * kSuper];
-        const uint64_t w0 = st * (kSuperPos / 4) + (uint64_t)threadIdx.x * kWords;
-        uint32_t x[kWords];
+    static_assert(kTile == 64 * 16, "16 flag bytes per lane and tile");
+    __shared__ uint16_t s_pos[kWG / 64][kTile];
+    __shared__ uint16_t s_tb[kWG / 64][kTile];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kWG / 64);
+    const uint4 *f128 = reinterpret_cast<const uint4 *>(flags);
+    uint16_t *lpos = s_pos[wave];
+    uint16_t *ltb = s_tb[wave];
+    for (uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave; tile < n_tiles;
+         tile += n_waves) {
+        const uint32_t sidx = tile_set[tile];
+        if (sidx == kNoSet)
+            continue;
+        const uint4 x4 = f128[tile * 64 + lane];
+        const uint32_t x[4] = {x4.x, x4.y, x4.z, x4.w};
         uint32_t cd = 0, ct = 0;
 #pragma unroll
-        for (int u = 0; u < kWords; u++) {
-            x[u] = (sidx != kNoSet && w0 + u < n_words) ? f32[w0 + u] : 0u;
+        for (int u = 0; u < 4; u++) {
             cd += (uint32_t)__popc(x[u] & 0x01010101u);
             ct += (uint32_t)__popc(x[u] & 0x02020202u);
         }
         uint32_t tot_d, tot_t;
-        uint32_t rd = wg_exclusive_u32(cd, s_wave[0], tot_d);
-        uint32_t rt = wg_exclusive_u32(ct, s_wave[1], tot_t);
+        uint32_t rd = wave_exclusive(cd, lane, tot_d);
+        uint32_t rt = wave_exclusive(ct, lane, tot_t);
+        if (tot_d == 0)
+            continue;
 #pragma unroll
-        for (int u = 0; u < kWords; u++) {
+        for (int u = 0; u < 4; u++) {
 #pragma unroll
             for (uint32_t sub = 0; sub < 4; sub++) {
                 const uint32_t fb = (x[u] >> (8u * sub)) & 0xFFu;
                 if (fb) {
-                    s_pos[rd] = (uint16_t)(4u * (threadIdx.x * kWords + u) + sub);
-                    s_tb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
+                    lpos[rd] = (uint16_t)(16u * lane + 4u * (uint32_t)u + sub);
+                    ltb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
                     rd++;
                     rt += fb == 3;
                 }
             }
         }
-        __syncthreads();
-        if (sidx != kNoSet && tot_d > 0) {
-            const SetDesc &S = sets[sidx];
-            const uint64_t first_tile = S.base / kTile;
-            const uint64_t pos0 = st * kSuperPos;
-            // this set's distinct / trustworthy keys before the super-tile
-            const uint64_t dd = off_d[st * kSuper] - off_d[first_tile];
-            const uint64_t tt = off_t[st * kSuper] - off_t[first_tile];
-            const uint64_t od = *S.n_distinct + dd;
-            for (uint32_t i = threadIdx.x; i < tot_d; i += kWG) {
-                const uint64_t p = pos0 + s_pos[i];
-                const uint64_t key = canonical_fast(window_key(R.codes, p, S.k), S.k).key;
-                const uint64_t d = od + i;
-                if (d < S.cap_d)
-                    S.distinct[d] = key;
-                if (S.fused) {
-                    const uint32_t tb = s_tb[i];
-                    const uint64_t ti = tt + (tb & 0x7FFFu);
-                    if (tb & 0x8000u) {
-                        if (ti < S.cap_te)
-                            S.trust[ti] = key;
-                    } else {
-                        const uint64_t ei = dd + i - ti;
-                        if (ei < S.cap_te)
-                            S.err[ei] = key;
-                    }
+        __builtin_amdgcn_wave_barrier();
+        const SetDesc &S = sets[sidx];
+        const uint64_t first_tile = S.base / kTile;
+        const uint64_t pos0 = tile * kTile;
+        // this set's distinct / trustworthy keys before the tile
+        const uint64_t dd = off_d[tile] - off_d[first_tile];
+        const uint64_t tt = off_t[tile] - off_t[first_tile];
+        const uint64_t od = *S.n_distinct + dd;
+        for (uint32_t i = lane; i < tot_d; i += 64) {
+            const uint64_t p = pos0 + lpos[i];
+            const uint64_t key = canonical_fast(window_key(R.codes, p, S.k), S.k).key;
+            const uint64_t d = od + i;
+            if (d < S.cap_d)
+                S.distinct[d] = key;
+            if (S.fused) {
+                const uint32_t tb = ltb[i];
+                const uint64_t ti = tt + (tb & 0x7FFFu);
+                if (tb & 0x8000u) {
+                    if (ti < S.cap_te)
+                        S.trust[ti] = key;
+                } else {
+                    const uint64_t ei = dd + i - ti;
+                    if (ei < S.cap_te)
+                        S.err[ei] = key;
                 }
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // the list is rewritten by the next tile
     }
 }
 

@@ -217,17 +217,6 @@ __global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *
 // first gathered into a wavefront-private list in position order (so that
 // only they are hashed), then each listed window's canonical key goes to the
 // distinct list and, when split, to the trustworthy or erroneous list.
-__device__ __forceinline__ uint32_t wave_exclusive(uint32_t v, uint32_t lane, uint32_t &total) {
-    uint32_t incl = v;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d)
-            incl += o;
-    }
-    total = __shfl(incl, 63, 64);
-    return incl - v;
-}
-
 __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__restrict__ flags,
                                                  uint64_t n_tiles,
                                                  const uint64_t *__restrict__ off_d,

@@ -122,6 +122,19 @@ __device__ __forceinline__ uint32_t wg_exclusive_u32(uint32_t v, uint32_t *s_wav
     __syncthreads();
     return before + incl - v;
 }
+// Exclusive sum over one wavefront (lane = threadIdx.x & 63); `total`
+// receives the wavefront's sum on every lane.
+__device__ __forceinline__ uint32_t wave_exclusive(uint32_t v, uint32_t lane, uint32_t &total) {
+    uint32_t incl = v;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
 inline uint64_t mask_words(uint64_t n) { return tiles(n) * (kTile / 32) + 2; }
 inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 
