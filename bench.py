@@ -67,7 +67,8 @@ def sha(t) -> str:
 
 
 def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
-                      n_words: int, n_chunks: int = 1, partitioned: bool = False) -> float:
+                      n_words: int, n_chunks: int = 1, partitioned: bool = False,
+                      binned: bool = True) -> float:
     """Bytes one step's launches of `phase` must move by their definition
     (logical accesses, not cache lines), summed over the step's launches:
     see the per-kernel table in the design notes."""
@@ -84,8 +85,8 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return entries * 16
     if phase == "region":            # entries in, countBF cells read + written per chunk, flags
         return entries * 8 + n_chunks * n_words * 16 + n_distinct
-    if phase == "tile_count":        # flag byte + packed input per position
-        return n_bases * 1.5
+    if phase == "tile_count":        # flag byte per position (+ packed input when the
+        return n_bases * (1.0 if binned else 1.5)  # insert passes did not count windows)
     if phase == "claim_increment":   # cell RMW + first-seen entry RMW per slot, packed input
         return n_windows * k_h * (16 + 8) + n_bases * 0.5
     if phase == "claim":             # cell read + entry RMW per slot
