@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--forms", default="batched,serving",
                     help="comma list of extra forms to measure: batched, serving, or none")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--serving-lanes", type=int, default=2)
     ap.add_argument("--form-steps", type=int, default=5)
     return ap.parse_args()
 
@@ -367,7 +368,8 @@ def serving_leg(args, dev):
     budget = 200 * 10**9
     server = P.Server(memory_budget=budget,
                       lane_bases=max(w.request_bases(i) for i in range(n)),
-                      lane_reads=max(q.n_reads for q in w.requests), lane_requests=64, lanes=2)
+                      lane_reads=max(q.n_reads for q in w.requests), lane_requests=64,
+                      lanes=args.serving_lanes)
     caps = [int(math.ceil(1.2 * d)) + 4096 for d in w.expected_distinct]
     dims = [P.dims(x) for x in w.n_items]
     sessions = [server.open(X, Y, w.ks[g], caps[g]) for g, (X, Y) in enumerate(dims)]
@@ -391,7 +393,8 @@ def serving_leg(args, dev):
     # capacity: the same requests all submitted at once to fresh sessions
     sat = P.Server(memory_budget=budget,
                    lane_bases=max(w.request_bases(i) for i in range(n)),
-                   lane_reads=max(q.n_reads for q in w.requests), lane_requests=64, lanes=2)
+                   lane_reads=max(q.n_reads for q in w.requests), lane_requests=64,
+                   lanes=args.serving_lanes)
     server = sat  # submit() now targets the fresh server and its sessions
     sessions[:] = [sat.open(X, Y, w.ks[g], caps[g]) for g, (X, Y) in enumerate(dims)]
     res_sat = serve.replay(sat, [0.0] * n, submit)
@@ -419,7 +422,7 @@ def serving_leg(args, dev):
         "memory_budget_bytes": budget, "session_bytes": st["session_bytes"],
         "staging_bytes": st["staging_bytes"], "batches": st["batches"],
         "batched_requests": st["batched_requests"], "plain_requests": st["plain_requests"],
-        "max_batch": st["max_batch"],
+        "max_batch": st["max_batch"], "lanes": args.serving_lanes,
         "saturated": {"value": windows / sat_span, "unit": "insertions/s",
                       "makespan_s": sat_span, "latency": serve.latency_summary(res_sat),
                       "batches": sat_st["batches"], "max_batch": sat_st["max_batch"],
