@@ -266,15 +266,17 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
 
 // Level 2: the entries of bucket b written by bin workgroups [s*slice,
 // (s+1)*slice) -> their regions' segments for those workgroups.  Batches of
-// kStage entries are counting-sorted by region in LDS and written as runs.
+// kStage2 entries are counting-sorted by region in LDS and written as runs
+// (twice the level-1 batch: runs of 2 x 4096 / regions per bucket entries).
+constexpr int kStage2 = 2 * kStage;
 __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
                                                        const uint32_t *__restrict__ coarse_off,
                                                        const uint32_t *__restrict__ n_entries,
                                                        const uint32_t *__restrict__ fine_off,
                                                        const uint64_t *__restrict__ bucketed,
                                                        uint64_t *__restrict__ entries) {
-    constexpr int kPer = kStage / kBinWG;
-    __shared__ uint64_t s_stage[kStage];
+    constexpr int kPer = kStage2 / kBinWG;
+    __shared__ uint64_t s_stage[kStage2];
     __shared__ uint32_t s_cursor[kMaxRegionsPerBucket];
     __shared__ uint32_t s_cnt[kMaxRegionsPerBucket];
     __shared__ uint32_t s_start[kMaxRegionsPerBucket];
@@ -309,7 +311,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
         e1 = cap;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    for (uint64_t q0 = e0; q0 < e1; q0 += kStage) {
+    for (uint64_t q0 = e0; q0 < e1; q0 += kStage2) {
         uint64_t v[kPer];
         uint32_t ri[kPer];
 #pragma unroll
