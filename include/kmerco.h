@@ -79,10 +79,9 @@ uint32_t kc_eta(uint32_t alpha);
 /* Create a countBF over caller-owned device memory `words_dev` (X*Y uint64,
  * 8-byte aligned).  zero != 0: the library clears the words (async on
  * `stream`) and the filter starts empty; zero == 0: the words are taken as
- * they are (resuming an existing countBF).  The handle owns a first-seen
- * workspace of 4 bytes per counter (X*Y*eta*4 bytes of device memory),
- * allocated here.  Returns KC_EINVAL for a bad layout, KC_ENOMEM when the
- * workspace cannot be allocated. */
+ * they are (resuming an existing countBF).  The handle's scratch is
+ * allocated on first use (see kc_reserve).  Returns KC_EINVAL for a bad
+ * layout, KC_ENOMEM when the handle cannot be allocated. */
 kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void *stream,
                     kc_filter **out);
 
@@ -90,9 +89,15 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
  * the handle's outstanding work first.  NULL is ignored. */
 void kc_destroy(kc_filter *f);
 
-/* Pre-size the per-call workspace for inserts of up to `max_bases` bases
- * (about max_bases/2 bytes + 256 B per 1024 bases) so that later kc_insert
- * calls of that size allocate nothing.  Synchronous. */
+/* Pre-size the handle's scratch for inserts of up to `max_bases` bases so
+ * that later kc_insert calls of that size allocate nothing.  Synchronous.
+ * Sizes, k_h = 1: countBFs of up to 16384 regions (256 MB at alpha = 8) take
+ * the binned path, about 22 bytes per base (packed codes and bitmaps, a flag
+ * byte, slot ids, two entry lists); larger countBFs take the partitioned
+ * path, about 31 bytes per base of a chunk of up to 2^31 bases; the direct
+ * path (forced, or beyond 256 partitions) takes 4 bytes per counter plus
+ * about 2 bytes per base.  Scratch grows, and is never shrunk, by calls
+ * larger than the reservation. */
 kc_status kc_reserve(kc_filter *f, uint64_t max_bases);
 
 /* Insertion phase (Algorithm 1 with Query-I / Algorithm 4 before the
