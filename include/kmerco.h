@@ -367,8 +367,12 @@ kc_status kc_server_submit(kc_server *s, const kc_request *req, uint64_t *ticket
 kc_status kc_server_pump(kc_server *s, uint32_t *n_done);
 /* Pump until the ticket's request is done (ticket 0: until all are). */
 kc_status kc_server_wait(kc_server *s, uint64_t ticket);
-/* The ticket's result so far (done == 0 while queued or running). */
+/* The ticket's result so far (done == 0 while queued or running).  Results
+ * are kept until kc_server_release or kc_server_destroy. */
 kc_status kc_server_result(const kc_server *s, uint64_t ticket, kc_result *out);
+/* Forget a done request's result; its ticket becomes unknown.  KC_ESTATE
+ * while the request is not done, KC_EINVAL for an unknown ticket. */
+kc_status kc_server_release(kc_server *s, uint64_t ticket);
 /* Copy n keys of a session's distinct list, from index first, to host
  * memory (waits for the session's issued work).  KC_ERANGE past the end. */
 kc_status kc_server_read_distinct(kc_server *s, uint32_t session, uint64_t first, uint64_t n,

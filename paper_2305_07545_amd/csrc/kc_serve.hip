@@ -670,6 +670,18 @@ kc_status kc_server_result(const kc_server *s, uint64_t ticket, kc_result *out) 
     return KC_OK;
 }
 
+kc_status kc_server_release(kc_server *s, uint64_t ticket) {
+    if (!s)
+        return KC_EINVAL;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return KC_EINVAL;
+    if (!it->second.res.done)
+        return KC_ESTATE;
+    s->reqs.erase(it);
+    return KC_OK;
+}
+
 kc_status kc_server_read_distinct(kc_server *s, uint32_t session, uint64_t first, uint64_t n,
                                   uint64_t *dst_host) {
     if (!s || session >= s->sessions.size() || (n > 0 && !dst_host))

@@ -121,6 +121,7 @@ SIGNATURES = {
     "kc_server_pump": (_i, [_vp, ctypes.POINTER(_u32)]),
     "kc_server_wait": (_i, [_vp, _u64]),
     "kc_server_result": (_i, [_vp, _u64, ctypes.POINTER(kc_result)]),
+    "kc_server_release": (_i, [_vp, _u64]),
     "kc_server_read_distinct": (_i, [_vp, _u32, _u64, _u64, _vp]),
     "kc_server_read_words": (_i, [_vp, _u32, _vp]),
     "kc_server_stats_get": (_i, [_vp, ctypes.POINTER(kc_server_stats)]),
@@ -567,6 +568,11 @@ class Server:
         if r.done:
             self._keep.pop(int(ticket), None)
         return {f: getattr(r, f) for f, _ in kc_result._fields_}
+
+    def release(self, ticket: int):
+        """Forget a done request's result (kc_server_release)."""
+        _check(self.lib.kc_server_release(self._h, int(ticket)), "kc_server_release")
+        self._keep.pop(int(ticket), None)
 
     def read_distinct(self, session: int, first: int, n: int):
         import numpy as np

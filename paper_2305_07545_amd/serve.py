@@ -42,6 +42,7 @@ def replay(server, arrivals, submit, on_submitted=None, idle_sleep_s: float = 50
                 r = server.result(tickets[j])
                 if r["done"]:
                     results[j] = r
+                    server.release(tickets[j])
                 else:
                     still.append(j)
             progressed = len(still) < len(pending)

@@ -199,6 +199,11 @@ def test_request_errors(workload):
     server.wait(tk)
     r = server.result(tk)
     assert r["done"] and r["status"] == P.kmerco.KC_ERANGE and r["n_new"] > 64
+    server.release(tk)
+    with pytest.raises(P.KmercoError):
+        server.result(tk)  # released
+    with pytest.raises(P.KmercoError):
+        server.release(tk)
     bad = offs.copy()
     bad[5], bad[6] = bad[6], bad[5]
     with pytest.raises(P.KmercoError):
