@@ -475,6 +475,7 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     F.eta = 64u / layout->alpha;
     F.mEta = UINT64_MAX / F.eta;
     F.eta_pow2 = (F.eta & (F.eta - 1)) == 0;
+    F.small_dims = layout->X <= kc::kSmallDivisor && layout->Y <= kc::kSmallDivisor;
     F.k_h = layout->k_h;
     F.field_max = (layout->alpha >= 64) ? ~0ull : ((1ull << layout->alpha) - 1ull);
     hipStream_t s = (hipStream_t)stream;

@@ -29,6 +29,7 @@ struct FilterArgs {
     uint32_t alpha;
     uint32_t k_h;
     uint32_t eta_pow2;    // eta is a power of two (then l = h & (eta-1))
+    uint32_t small_dims;  // X, Y <= kSmallDivisor (then mod_small applies)
     uint64_t field_max;   // 2^alpha - 1
 };
 
@@ -108,12 +109,41 @@ KC_HD uint64_t mod_by(uint64_t h, uint64_t d, uint64_t m) {
     return r >= d ? r - d : r;
 }
 
+// The same remainder for divisors d <= kSmallDivisor, in 32-bit arithmetic.
+// Dropping the low partial product h_lo*m_lo from the 128-bit product h*m
+// lowers the quotient estimate by at most one more, so q is floor(h/d),
+// one or two less, and r = h - q*d lies in [0, 3d).  3d < 2^32, so r is
+// exact from the low words alone (r = h_lo - q_lo*d mod 2^32), and only the
+// low word of q is needed: the low word of h_hi*m_hi plus bits 32..63 of
+// the middle products' sum (its carry out of bit 63 only changes q's high
+// word).  Two conditional subtractions finish; min(r, r - d) is one, since
+// r - d wraps above r exactly when r < d.
+constexpr uint64_t kSmallDivisor = 0x55555555ull;  // floor((2^32 - 1) / 3)
+
+KC_HD uint32_t mod_small(uint64_t h, uint32_t d, uint64_t m) {
+    const uint32_t hl = (uint32_t)h, hh = (uint32_t)(h >> 32);
+    const uint32_t ml = (uint32_t)m, mh = (uint32_t)(m >> 32);
+    const uint64_t mid = (uint64_t)hh * ml + (uint64_t)hl * mh;
+    const uint32_t q = hh * mh + (uint32_t)(mid >> 32);
+    uint32_t r = hl - q * d;
+    uint32_t t = r - d;
+    r = t < r ? t : r;
+    t = r - d;
+    return t < r ? t : r;
+}
+
 // Counter index (word * eta + l) of hash value h.
 KC_HD void slot_of(const FilterArgs &F, uint64_t h, uint64_t &word,
                                         uint32_t &l) {
+    l = F.eta_pow2 ? (uint32_t)(h & (uint64_t)(F.eta - 1)) : (uint32_t)mod_by(h, F.eta, F.mEta);
+    if (F.small_dims) {
+        const uint32_t i = mod_small(h, (uint32_t)F.X, F.mX);
+        const uint32_t j = mod_small(h, (uint32_t)F.Y, F.mY);
+        word = (uint64_t)i * (uint32_t)F.Y + j;
+        return;
+    }
     uint64_t i = mod_by(h, F.X, F.mX);
     uint64_t j = mod_by(h, F.Y, F.mY);
-    l = F.eta_pow2 ? (uint32_t)(h & (uint64_t)(F.eta - 1)) : (uint32_t)mod_by(h, F.eta, F.mEta);
     word = i * F.Y + j;
 }
 

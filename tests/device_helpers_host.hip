@@ -8,6 +8,29 @@ extern "C" {
 
 uint64_t kch_mod_by(uint64_t h, uint64_t d) { return kc::mod_by(h, d, UINT64_MAX / d); }
 
+uint64_t kch_mod_small(uint64_t h, uint32_t d) {
+    return kc::mod_small(h, d, UINT64_MAX / d);
+}
+
+// Counts the h (n pseudo-random values, half of them within 2 of a multiple
+// of d) where mod_small differs from h % d.  The generator is splitmix64.
+uint64_t kch_mod_small_mismatches(uint32_t d, uint64_t n, uint64_t seed) {
+    const uint64_t m = UINT64_MAX / d;
+    uint64_t x = seed, bad = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        x += 0x9e3779b97f4a7c15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        uint64_t h = z;
+        if (i & 1)
+            h = (z % (UINT64_MAX / d)) * d + (i >> 1) % 5 - 2;
+        bad += kc::mod_small(h, d, m) != h % d;
+    }
+    return bad;
+}
+
 uint64_t kch_revcomp(uint64_t x, uint32_t K) { return kc::revcomp_key(x, K); }
 
 uint64_t kch_window_key(const uint32_t *codes, uint64_t p, uint32_t K) {
@@ -42,6 +65,7 @@ void kch_slot(uint64_t X, uint64_t Y, uint32_t alpha, uint64_t h, uint64_t *word
     F.eta = 64u / alpha;
     F.mEta = UINT64_MAX / F.eta;
     F.eta_pow2 = (F.eta & (F.eta - 1)) == 0;
+    F.small_dims = X <= kc::kSmallDivisor && Y <= kc::kSmallDivisor;
     kc::slot_of(F, h, *word, *l);
 }
 

@@ -26,6 +26,9 @@ def H(tmp_path_factory):
     u64, u32 = ctypes.c_uint64, ctypes.c_uint32
     p32 = ctypes.POINTER(ctypes.c_uint32)
     L.kch_mod_by.argtypes = [u64, u64]; L.kch_mod_by.restype = u64
+    L.kch_mod_small.argtypes = [u64, u32]; L.kch_mod_small.restype = u64
+    L.kch_mod_small_mismatches.argtypes = [u32, u64, u64]
+    L.kch_mod_small_mismatches.restype = u64
     L.kch_revcomp.argtypes = [u64, u32]; L.kch_revcomp.restype = u64
     L.kch_window_key.argtypes = [p32, u64, u32]; L.kch_window_key.restype = u64
     L.kch_window_valid.argtypes = [p32, p32, p32, u64, u32, u64]; L.kch_window_valid.restype = ctypes.c_int
@@ -54,10 +57,30 @@ def test_mod_by_exact(H):
             assert H.kch_mod_by(h, d) == h % d, (h, d)
 
 
+SMALL_MAX = (2**32 - 1) // 3
+
+
+def test_mod_small_exact(H):
+    """The 32-bit reduction for divisors up to (2^32-1)/3: exact remainders on
+    edge values, near multiples of d and a million pseudo-random values per
+    divisor."""
+    rng = np.random.default_rng(4)
+    ds = [1, 2, 3, 5, 8, 239, 2621, 2657, 31627, 65536, 2**20 + 7, 2**30, 2**30 + 3,
+          SMALL_MAX - 1, SMALL_MAX] + [int(x) for x in rng.integers(1, SMALL_MAX, 12)]
+    for d in ds:
+        edge = [0, 1, d - 1, d, d + 1, 2**32 - 1, 2**32, 2**63, 2**64 - 1, 2**64 - 2,
+                (2**64 - 1) // d * d, (2**64 - 1) // d * d - 1]
+        for h in edge:
+            h %= 2**64
+            assert H.kch_mod_small(h, d) == h % d, (h, d)
+        assert H.kch_mod_small_mismatches(d, 1 << 20, 17 + d) == 0, d
+
+
 def test_slot_map(H):
     rng = np.random.default_rng(2)
     for X, Y, alpha in [(239, 257, 8), (3, 5, 5), (2621, 2657, 7), (31627, 31657, 12),
-                        (1, 1, 32), (13, 17, 3)]:
+                        (1, 1, 32), (13, 17, 3), (SMALL_MAX, SMALL_MAX - 2, 8),
+                        (SMALL_MAX + 1, 7, 8), (5, 2**33 + 1, 16)]:
         eta = 64 // alpha
         for h in [0, 2**64 - 1] + [int(x) * 3 for x in rng.integers(0, 2**62, 200, dtype=np.int64)]:
             w = ctypes.c_uint64()
