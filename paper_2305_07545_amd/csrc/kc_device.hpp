@@ -174,14 +174,17 @@ KC_HD uint64_t revcomp_key(uint64_t x, uint32_t K) {
 }
 
 // Forward key of the K-base window starting at p (first base most
-// significant).  Needs codes[p/16 + 2] to exist.
+// significant).  Needs codes[p/16 + 2] to exist.  The 64 bits from base
+// p % 16 of codes[p/16] on are the high word of (w0:w1) << s and the low word
+// of (w1:w2) >> (32 - s), s = 2 (p % 16); both shifts stay below 64.
 KC_HD uint64_t window_key(const uint32_t *__restrict__ codes, uint64_t p,
                                                uint32_t K) {
-    uint64_t m = p >> 4;
-    uint32_t s = 2u * (uint32_t)(p & 15u);
-    uint64_t hi = ((uint64_t)codes[m] << 32) | codes[m + 1];
-    uint64_t top = s ? ((hi << s) | ((uint64_t)codes[m + 2] >> (32u - s))) : hi;
-    return top >> (64u - 2u * K);
+    const uint64_t m = p >> 4;
+    const uint32_t s = 2u * (uint32_t)(p & 15u);
+    const uint32_t w0 = codes[m], w1 = codes[m + 1], w2 = codes[m + 2];
+    const uint32_t top_hi = (uint32_t)(((((uint64_t)w0 << 32) | w1) << s) >> 32);
+    const uint32_t top_lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32u - s));
+    return (((uint64_t)top_hi << 32) | top_lo) >> (64u - 2u * K);
 }
 
 // Window validity (see the layout note above).  Needs inv/rs[p/32 + 1].
@@ -300,9 +303,10 @@ KC_HD bool wave_window(const WaveWords &w, uint64_t pb, uint32_t lane, uint32_t 
     const uint32_t w1 = pick4(w.c[1], w.c[2], w.c[3], w.c[4], mo);
     const uint32_t w2 = pick4(w.c[2], w.c[3], w.c[4], w.c[5], mo);
     const uint32_t s = 2u * (lane & 15u);
-    // 64 bits starting at base (lane & 15) of w0: (w0:w1:w2) << s
-    const uint32_t top_hi = s ? funnel32(w0, w1, 32u - s) : w0;
-    const uint32_t top_lo = s ? funnel32(w1, w2, 32u - s) : w1;
+    // 64 bits starting at base (lane & 15) of w0: (w0:w1:w2) << s, as in
+    // window_key
+    const uint32_t top_hi = (uint32_t)(((((uint64_t)w0 << 32) | w1) << s) >> 32);
+    const uint32_t top_lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32u - s));
     fwd = (((uint64_t)top_hi << 32) | top_lo) >> (64u - 2u * K);
     // 32 mask bits starting at the window's first base
     const bool upper = (lane & 32u) != 0;
