@@ -156,6 +156,29 @@ KC_HD bool base_valid(uint32_t b, uint32_t code) {
     return b == ((0x54474341u >> (8u * code)) & 0xFFu);
 }
 
+// Four bases at once: x holds 4 bytes (base i in bits 8i..8i+7).  Returns
+// their codes packed in 8 bits (base 0 in bits 7..6, an invalid base as 0)
+// and sets bit i of valid4 when base i is A, C, G or T.  Per byte: the code
+// as base_code; the expected letter of that code picked from "ACGT" (one
+// byte permute on the device); an exact zero-byte test of x ^ expected; the
+// byte flags and the 2-bit codes gathered by multiplications whose partial
+// products land on distinct bits (no carries).
+KC_HD uint32_t codes4(uint32_t x, uint32_t &valid4) {
+    const uint32_t c4 = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t e = __builtin_amdgcn_perm(0u, 0x54474341u, c4);
+#else
+    uint32_t e = 0;
+    for (int i = 0; i < 4; i++)
+        e |= ((0x54474341u >> (8 * ((c4 >> (8 * i)) & 3u))) & 0xFFu) << (8 * i);
+#endif
+    const uint32_t d = x ^ e;
+    const uint32_t z = ~(((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d | 0x7F7F7F7Fu);  // 0x80: equal
+    valid4 = (((z >> 7) * 0x00204081u) >> 21) & 0xFu;
+    const uint32_t c = c4 & ((z >> 6) | (z >> 7));
+    return (c * 0x40100401u) >> 24;
+}
+
 // ----------------------------------------------------------------------------
 // Window extraction from the packed layout
 // ----------------------------------------------------------------------------

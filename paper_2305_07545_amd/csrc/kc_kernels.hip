@@ -50,10 +50,19 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
 // ---------------------------------------------------------------------------
 __global__ void k_ingest(const uint8_t *__restrict__ reads, uint64_t n_bases,
                          uint32_t *__restrict__ codes, uint32_t *__restrict__ inv,
-                         uint64_t n_mask_words, int aligned16) {
+                         uint32_t *__restrict__ rs, uint8_t *__restrict__ flags,
+                         uint64_t n_mask_words, uint64_t n_flag_words, int aligned16) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_mask_words)
         return;
+    // clear this word's read-start bits (set afterwards by k_read_starts) and
+    // its 32 flag bytes
+    rs[i] = 0;
+    if (i < n_flag_words) {
+        uint4 *f = reinterpret_cast<uint4 *>(flags + 32u * i);
+        f[0] = make_uint4(0u, 0u, 0u, 0u);
+        f[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
     uint64_t p0 = i * 32u;
     uint32_t bytes[8];
     if (aligned16 && p0 + 32u <= n_bases) {
@@ -72,22 +81,20 @@ __global__ void k_ingest(const uint8_t *__restrict__ reads, uint64_t n_bases,
             bytes[w] = x;
         }
     }
-    uint32_t c_hi = 0, c_lo = 0, bad = 0;
+    uint32_t c_hi = 0, c_lo = 0, good = 0;
 #pragma unroll
-    for (int q = 0; q < 32; q++) {
-        uint32_t b = (bytes[q >> 2] >> (8 * (q & 3))) & 0xFFu;
-        uint32_t c = base_code(b);
-        uint32_t ok = base_valid(b, c);
-        c = ok ? c : 0u;
-        bad |= (ok ? 0u : 1u) << q;
-        if (q < 16)
-            c_hi |= c << (30 - 2 * q);
+    for (int w = 0; w < 8; w++) {
+        uint32_t v4;
+        const uint32_t c8 = codes4(bytes[w], v4);
+        good |= v4 << (4 * w);
+        if (w < 4)
+            c_hi |= c8 << (24 - 8 * w);
         else
-            c_lo |= c << (30 - 2 * (q - 16));
+            c_lo |= c8 << (24 - 8 * (w - 4));
     }
     codes[2 * i] = c_hi;
     codes[2 * i + 1] = c_lo;
-    inv[i] = bad;
+    inv[i] = ~good;
 }
 
 __global__ void k_read_starts(const uint64_t *__restrict__ offsets, uint64_t n_reads,
@@ -495,15 +502,13 @@ hipError_t launch_ingest(const uint8_t *reads, uint64_t n_bases, const uint64_t 
     uint64_t n_mask = mask_words(n_bases);
     if (P)
         P->begin(kPhIngest, s);
-    hipError_t e = fill_u32(W.rs, n_mask, 0u, s);
-    if (e == hipSuccess)  // flag bytes of every tile of the call
-        e = fill_u32((uint32_t *)W.flags8, tiles(n_bases) * (kTile / 4), 0u, s);
-    if (e == hipSuccess) {
-        int aligned = ((uintptr_t)reads & 15u) == 0;
-        hipLaunchKernelGGL(k_ingest, dim3(grid_for(n_mask, 256)), dim3(256), 0, s, reads,
-                           n_bases, W.codes, W.inv, n_mask, aligned);
-        e = hipGetLastError();
-    }
+    // k_ingest also clears the read-start words and the flag bytes of every
+    // tile of the call (n_mask * 32 positions cover them)
+    int aligned = ((uintptr_t)reads & 15u) == 0;
+    hipLaunchKernelGGL(k_ingest, dim3(grid_for(n_mask, 256)), dim3(256), 0, s, reads, n_bases,
+                       W.codes, W.inv, W.rs, W.flags8, n_mask, tiles(n_bases) * (kTile / 32),
+                       aligned);
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess && n_reads > 0) {
         hipLaunchKernelGGL(k_read_starts, dim3(grid_for(n_reads, 256)), dim3(256), 0, s, offsets,
                            n_reads, n_bases, W.rs);

@@ -31,6 +31,8 @@ uint64_t kch_mod_small_mismatches(uint32_t d, uint64_t n, uint64_t seed) {
     return bad;
 }
 
+uint32_t kch_codes4(uint32_t x, uint32_t *valid4) { return kc::codes4(x, *valid4); }
+
 uint64_t kch_revcomp(uint64_t x, uint32_t K) { return kc::revcomp_key(x, K); }
 
 uint64_t kch_window_key(const uint32_t *codes, uint64_t p, uint32_t K) {

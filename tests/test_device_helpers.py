@@ -29,6 +29,7 @@ def H(tmp_path_factory):
     L.kch_mod_small.argtypes = [u64, u32]; L.kch_mod_small.restype = u64
     L.kch_mod_small_mismatches.argtypes = [u32, u64, u64]
     L.kch_mod_small_mismatches.restype = u64
+    L.kch_codes4.argtypes = [u32, ctypes.POINTER(u32)]; L.kch_codes4.restype = u32
     L.kch_revcomp.argtypes = [u64, u32]; L.kch_revcomp.restype = u64
     L.kch_window_key.argtypes = [p32, u64, u32]; L.kch_window_key.restype = u64
     L.kch_window_valid.argtypes = [p32, p32, p32, u64, u32, u64]; L.kch_window_valid.restype = ctypes.c_int
@@ -87,6 +88,35 @@ def test_slot_map(H):
             l = ctypes.c_uint32()
             H.kch_slot(X, Y, alpha, h, ctypes.byref(w), ctypes.byref(l))
             assert (w.value, l.value) == ((h % X) * Y + (h % Y), h % eta)
+
+
+def test_codes4_every_byte_in_every_lane(H):
+    """The 4-bases-at-a-time conversion: every byte value in each of the 4
+    lanes, beside random neighbours, against the one-base definition."""
+    rng = np.random.default_rng(6)
+    v = ctypes.c_uint32()
+    c = ctypes.c_uint32()
+    for lane in range(4):
+        for b in range(256):
+            others = [int(x) for x in rng.integers(0, 256, 3)]
+            others.insert(lane, b)
+            x = sum(o << (8 * i) for i, o in enumerate(others))
+            got = H.kch_codes4(x, ctypes.byref(v))
+            want_c, want_v = 0, 0
+            for i, o in enumerate(others):
+                ok = H.kch_base(o, ctypes.byref(c))
+                want_v |= ok << i
+                want_c |= (c.value if ok else 0) << (6 - 2 * i)
+            assert (got, v.value) == (want_c, want_v), (hex(x), lane, b)
+    for x in [0, 0xFFFFFFFF, 0x54474341, 0x41414141, 0x54545454, 0x4E4E4E4E, 0x80C1C3C7]:
+        got = H.kch_codes4(x, ctypes.byref(v))
+        want_c, want_v = 0, 0
+        for i in range(4):
+            o = (x >> (8 * i)) & 0xFF
+            ok = H.kch_base(o, ctypes.byref(c))
+            want_v |= ok << i
+            want_c |= (c.value if ok else 0) << (6 - 2 * i)
+        assert (got, v.value) == (want_c, want_v), hex(x)
 
 
 def test_base_codes(H):
