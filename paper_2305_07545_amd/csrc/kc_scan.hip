@@ -1,6 +1,6 @@
-// Multi-workgroup exclusive prefix sums (reduce -> scan of block sums ->
-// rescan with block offsets) used for the ordered outputs and the bin
-// offsets.
+// Multi-workgroup exclusive prefix sums (block sums, then a rescan of each
+// block with the sum of the blocks before it) used for the ordered outputs
+// and the bin offsets.
 #include <hip/hip_runtime.h>
 
 #include "kc_kernels.hpp"
@@ -12,7 +12,6 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;
 constexpr int kScanBlock = kScanThreads * kScanPer;  // elements per workgroup
-constexpr int kTopThreads = 1024;
 
 // Exclusive sum of one value per thread over the workgroup: wave scans by
 // shuffles, then the wave totals.  s_wave: kScanThreads / 64 entries.
@@ -61,50 +60,31 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const TIn *__restr
         partial[blockIdx.x] = total;
 }
 
-// One workgroup: partial[b] <- base + sum(partial[0..b)), *total <- sum.
-template <typename TOut>
-__global__ void __launch_bounds__(kTopThreads) k_scan_top(TOut *__restrict__ partial, uint64_t nb,
-                                                         const TOut *__restrict__ base,
-                                                         TOut *__restrict__ total) {
-    __shared__ TOut s[kTopThreads];
-    const uint64_t per = (nb + kTopThreads - 1) / kTopThreads;
-    const uint64_t lo = per * threadIdx.x;
-    const uint64_t hi = lo + per < nb ? lo + per : nb;
-    TOut sum = 0;
-    for (uint64_t i = lo; i < hi; i++)
-        sum += partial[i];
-    s[threadIdx.x] = sum;
-    __syncthreads();
-    for (int d = 1; d < kTopThreads; d <<= 1) {
-        TOut add = threadIdx.x >= (unsigned)d ? s[threadIdx.x - d] : (TOut)0;
-        __syncthreads();
-        s[threadIdx.x] += add;
-        __syncthreads();
-    }
-    TOut run = (base ? *base : (TOut)0) + s[threadIdx.x] - sum;
-    for (uint64_t i = lo; i < hi; i++) {
-        TOut v = partial[i];
-        partial[i] = run;
-        run += v;
-    }
-    if (threadIdx.x == kTopThreads - 1 && total)
-        *total = s[kTopThreads - 1];
-}
-
 // LDS slot of element e of a block: one pad word after every kScanPer
 // elements, so that thread t's run (elements 16t .. 16t+15) and the
 // coalesced rows (elements i*256 + t) are both free of bank conflicts.
 __device__ __forceinline__ uint32_t pad_at(uint32_t e) { return e + e / kScanPer; }
 
-// Exclusive scan of each workgroup's elements, offset by its partial:
-// coalesced loads into LDS, a sequential scan of 16 consecutive elements per
-// thread, the workgroup scan of the thread sums, coalesced stores.
+// Exclusive scan of each workgroup's elements, offset by base and the sums
+// of the workgroups before it (each workgroup adds up those block sums
+// itself: a few KB from L2, one launch fewer than a separate scan of the
+// sums): coalesced loads into LDS, a sequential scan of 16 consecutive
+// elements per thread, the workgroup scan of the thread sums, coalesced
+// stores.  The last workgroup writes the grand total (without base).
 template <typename TIn, typename TOut>
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(const TIn *__restrict__ in, uint64_t n,
                                                            const TOut *__restrict__ partial,
-                                                           TOut *__restrict__ out) {
+                                                           const TOut *__restrict__ base,
+                                                           TOut *__restrict__ out,
+                                                           TOut *__restrict__ total_out) {
     __shared__ TOut s_buf[kScanBlock + kScanBlock / kScanPer];
     __shared__ TOut s_wave[kScanThreads / 64];
+    TOut before = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads)
+        before += partial[i];
+    TOut pre;
+    (void)wg_exclusive_sum<TOut>(before, s_wave, pre);
+    const TOut offset = (base ? *base : (TOut)0) + pre;
     const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock;
 #pragma unroll
     for (int i = 0; i < kScanPer; i++) {
@@ -120,12 +100,14 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(const TIn *__restric
         sum += v[i];
     }
     TOut total;
-    TOut run = partial[blockIdx.x] + wg_exclusive_sum<TOut>(sum, s_wave, total);
+    TOut run = offset + wg_exclusive_sum<TOut>(sum, s_wave, total);
 #pragma unroll
     for (int i = 0; i < kScanPer; i++) {
         s_buf[pad_at(threadIdx.x * kScanPer + i)] = run;
         run += v[i];
     }
+    if (total_out && threadIdx.x == 0 && blockIdx.x + 1 == gridDim.x)
+        *total_out = pre + total;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kScanPer; i++) {
@@ -146,12 +128,8 @@ hipError_t scan_impl(const TIn *in, TOut *out, uint64_t n, const TOut *base, TOu
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_scan_top<TOut>), dim3(1), dim3(kTopThreads), 0, s, partial, nb, base,
-                       total);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
     hipLaunchKernelGGL((k_scan_down<TIn, TOut>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
-                       n, (const TOut *)partial, out);
+                       n, (const TOut *)partial, base, out, total);
     return hipGetLastError();
 }
 
