@@ -203,6 +203,9 @@ typedef enum {
 } kc_phase;
 
 kc_status kc_profile(kc_filter *f, int enable);
+/* Time only the phases whose bit (1u << kc_phase) is set in mask; 0 turns
+ * timing off.  Fewer events per call: two per timed kernel launch. */
+kc_status kc_profile_phases(kc_filter *f, uint32_t mask);
 kc_status kc_profile_read(kc_filter *f, double *ms, uint64_t *launches, uint32_t n_phases);
 const char *kc_phase_name(uint32_t phase);
 

@@ -658,6 +658,16 @@ kc_status kc_profile(kc_filter *f, int enable) {
         return KC_EINVAL;
     f->prof.collect(nullptr, nullptr, 0);
     f->prof.on = enable != 0;
+    f->prof.mask = ~0u;
+    return KC_OK;
+}
+
+kc_status kc_profile_phases(kc_filter *f, uint32_t mask) {
+    if (!f)
+        return KC_EINVAL;
+    f->prof.collect(nullptr, nullptr, 0);
+    f->prof.on = mask != 0;
+    f->prof.mask = mask;
     return KC_OK;
 }
 

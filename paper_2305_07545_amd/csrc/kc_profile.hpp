@@ -1,4 +1,6 @@
 // Optional per-kernel timing with HIP events recorded on the launch stream.
+// The events only time the work between them: they are created without the
+// system-scope fence, so waiting for one does not order memory for the host.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,10 +13,12 @@ namespace kc {
 class Profiler {
   public:
     bool on = false;
+    uint32_t mask = ~0u;  // phases timed while on (bit per phase)
 
-    // Record a start event for `phase` on stream s (no-op when off).
+    // Record a start event for `phase` on stream s (no-op when off or when
+    // the phase is masked out).
     void begin(int phase, hipStream_t s) {
-        if (!on)
+        if (!on || phase < 0 || phase >= 32 || !((mask >> phase) & 1u))
             return;
         Rec r;
         r.phase = phase;
@@ -80,8 +84,10 @@ class Profiler {
             pool_.pop_back();
             return e;
         }
+        // timing only: no system-scope fence (and its L2 writeback and
+        // invalidate) when an event is recorded
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess)
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
             return nullptr;
         return e;
     }

@@ -103,6 +103,7 @@ SIGNATURES = {
     "kc_get_layout": (_i, [_vp, ctypes.POINTER(kc_layout)]),
     "kc_reset": (_i, [_vp, _vp]),
     "kc_profile": (_i, [_vp, _i]),
+    "kc_profile_phases": (_i, [_vp, _u32]),
     "kc_profile_read": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64), _u32]),
     "kc_phase_name": (ctypes.c_char_p, [_u32]),
     "kc_batch_create": (_i, [ctypes.POINTER(_vp)]),
@@ -327,8 +328,16 @@ class CountBF:
         with torch.cuda.device(self.device):
             _check(self.lib.kc_reset(self._h, _stream_ptr(stream)), "kc_reset")
 
-    def profile(self, enable: bool = True):
-        _check(self.lib.kc_profile(self._h, int(enable)), "kc_profile")
+    def profile(self, enable: bool = True, phases=None):
+        """Time every phase (or only the named ones) of the following calls."""
+        if phases is None:
+            _check(self.lib.kc_profile(self._h, int(enable)), "kc_profile")
+        else:
+            mask = 0
+            for ph in phases:
+                mask |= 1 << PHASES.index(ph)
+            _check(self.lib.kc_profile_phases(self._h, mask if enable else 0),
+                   "kc_profile_phases")
 
     def profile_read(self):
         """{phase: (total ms, launches)} of the kernels recorded since the
