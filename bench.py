@@ -56,8 +56,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bacterial", choices=["tiny", "bacterial", "large"])
+    ap.add_argument("--alpha", type=int, default=8, help="counter length (bits)")
+    ap.add_argument("--k-h", type=int, default=1, help="hash functions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
+    ap.add_argument("--cpu-sample-sets", type=int, default=64,
+                    help="sets of the 256-set workload in the parallel oracle baseline")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--forms", default="batched,serving",
                     help="comma list of extra forms to measure: batched, serving, or none")
@@ -157,8 +161,30 @@ def cpu_baseline(rs, X, Y, n_sample_reads):
                       f"countBF {X}x{Y}, single-threaded C oracle, {secs:.1f} s"}
 
 
+def set_baseline(n_sets: int):
+    """The oracle on the first sets of the 256-set workload, one process per
+    set on the host's cores (the sets are independent), started as a child
+    program that never touches the GPU."""
+    import subprocess
+    r = subprocess.run([sys.executable, "-m", "oracle.set_baseline", "--sets", str(n_sets),
+                        "--workers", "16"], cwd=ROOT, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def ops_per_window(k_h: int, alpha: int) -> int:
+    """Algorithmic integer ops per valid window: l = h mod eta is one AND
+    when eta = 64 / alpha is a power of two, else a Barrett reduction
+    (12 ops, like h mod X), once per hash function."""
+    eta = 64 // alpha
+    l_extra = 0 if eta & (eta - 1) == 0 else 11
+    return OPS_PER_WINDOW + l_extra + (k_h - 1) * (OPS_PER_EXTRA_HASH + l_extra)
+
+
 def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                n_chunks=1, partitioned=False):
+                n_chunks=1, partitioned=False, alpha=8):
     """Roofline of the phase with the largest total time: the hashing kernel
     against the integer-VALU peak (algorithmic ops per window), the others
     against HBM (algorithmic bytes), per launch over the average launch."""
@@ -169,12 +195,12 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
     per_step = phases[dom][1] / max(1, steps)
     traffic = traffic_for(dom, workload)
     if dom == "bin_count":
-        ops = n_windows * (OPS_PER_WINDOW + (k_h - 1) * OPS_PER_EXTRA_HASH) / per_step
+        ops = n_windows * ops_per_window(k_h, alpha) / per_step
         achieved = ops / avg_s / 1e9
         return {"bound": "alu", "achieved": round(achieved, 1), "peak": round(ALU_PEAK_GOPS, 1),
                 "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": traffic,
                 "kernel": dom, "algorithmic_ops_per_launch": ops,
-                "ops_per_window": OPS_PER_WINDOW + (k_h - 1) * OPS_PER_EXTRA_HASH,
+                "ops_per_window": ops_per_window(k_h, alpha),
                 "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": per_step}
     nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
                                partitioned) / per_step
@@ -462,7 +488,7 @@ def main():
 
     rs = synth.config(args.workload)
     X, Y = P.dims(rs.n_items)
-    k_h, alpha = 1, 8
+    k_h, alpha = args.k_h, args.alpha
     reads = torch.from_numpy(rs.reads).to(dev)
     offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
     n_bases = rs.n_bases
@@ -509,7 +535,7 @@ def main():
 
     n_distinct, n_windows, n_trust, n_err = (int(x) for x in counters.cpu().tolist())
     verified = None
-    if not args.no_verify:
+    if not args.no_verify and (alpha, k_h) == (8, 1):  # the digests' layout
         ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_digests.json")
         if os.path.exists(ref_path):
             ref = json.load(open(ref_path))
@@ -525,11 +551,13 @@ def main():
     per_phase = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()}
     per_phase[dom]["timed_avg_ms"] = timed[dom][0] / timed[dom][1]
     # the binned path's chunking (the partitioned path beyond 16384 regions)
-    partitioned = X * Y > 16384 * (16384 // (64 // alpha))
+    eta = 64 // alpha
+    region_cells = 1 << ((16384 // eta).bit_length() - 1)  # power of two, eta counters each
+    partitioned = X * Y > 16384 * region_cells
     chunk = min(1 << 31, ((1 << 32) - 1) // k_h // 1024 * 1024) if partitioned else (1 << 28)
     n_chunks = (n_bases + chunk - 1) // chunk
     roofline = roofline_of(timed, args.steps, n_bases, n_windows, n_distinct, k_h, X * Y,
-                           args.workload, n_chunks, partitioned)
+                           args.workload, n_chunks, partitioned, alpha)
 
     out = {
         "metric": "k-mer insertions/s",
@@ -562,6 +590,8 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if "batched" in forms:
         out["batched"] = batched_leg(args, dev)
+        if not args.no_cpu_baseline:
+            out["batched"]["cpu_baseline"] = set_baseline(args.cpu_sample_sets)
     if "serving" in forms:
         out["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:

@@ -232,13 +232,15 @@ def _cfg_bacterial(scale: float) -> ReadSet:
                     "p_indel": 0.0005, "p_n": 0.001})
 
 
-def _cfg_batched(scale: float, n_sets: int = 256) -> list[ReadSet]:
+def _cfg_batched(scale: float, n_sets: int = 256, first: int | None = None) -> list[ReadSet]:
     """256 independent sets: read counts lognormal (median 20k, clipped to
     1k..500k), read lengths U[50, 300], k in {21, 25, 31}, substitution rate
-    U[0.1%, 2%], each from its own uniform genome at about 20x coverage."""
+    U[0.1%, 2%], each from its own uniform genome at about 20x coverage.
+    ``first`` builds only the first sets (the same ones: each set draws from
+    its own seed)."""
     seeds = np.random.SeedSequence(1003).spawn(n_sets)
     out = []
-    for s, ss in enumerate(seeds):
+    for s, ss in enumerate(seeds[:first]):
         rng = np.random.default_rng(ss)
         n = int(np.clip(round(rng.lognormal(math.log(20_000), 1.0)), 1_000, 500_000))
         n = max(1, int(n * scale))
