@@ -68,6 +68,39 @@ const char *kc_strerror(int status);
 /* Library ABI version (incremented on incompatible changes). */
 int kc_version(void);
 
+/* ------------------------------------------------------------------------
+ * Input front end (host only).  The paper inserts the k-mers of sequencing
+ * data sets read from files (Sec. 4.1); kc_parse_fastx turns FASTA or FASTQ text
+ * in host memory into the read layout the insert calls take.
+ *
+ * text[0..len): FASTA ('>' header lines, the sequence lines up to the next
+ * header; ';' lines are comments) or FASTQ ('@' header, sequence lines, a
+ * '+' line, quality lines of the same total length), the format taken from
+ * the first line that is neither blank nor a comment; blank lines are
+ * skipped.  Each record's sequence
+ * lines are concatenated, line ends ("
+", "
+") removed and bytes kept
+ * as they are (so 'N' and lower case stay invalid bases), into
+ * seq[0..*n_bases), and offsets[0..*n_reads] receives the CSR offsets
+ * (offsets[0] = 0): one read per record, records with no bases included.
+ * flags: KC_FASTX_ONE_SEQUENCE makes all records one read, so windows span
+ * record boundaries: the paper counts L - K + 1 windows per data set (its
+ * 28-mer and 55-mer totals differ by 27 for every data set, Sec. 4.2).
+ * All buffers are the caller's host memory.  *n_bases and *n_reads are
+ * always set to the sizes needed; KC_ERANGE when seq_cap < *n_bases or
+ * off_cap < *n_reads + 1, with nothing written past either capacity (call
+ * with capacities 0 to size the buffers, then again).  KC_EINVAL: null
+ * pointers (text with len > 0, outputs with non-zero capacities, the
+ * counts), unknown flags, a first line starting with neither '>' nor '@', a
+ * FASTQ record not starting with '@', without its '+' line, or whose
+ * quality lines do not add up to its sequence length.
+ * ---------------------------------------------------------------------- */
+#define KC_FASTX_ONE_SEQUENCE 1u
+kc_status kc_parse_fastx(const char *text, uint64_t len, uint32_t flags, uint8_t *seq,
+                         uint64_t seq_cap, uint64_t *offsets, uint64_t off_cap,
+                         uint64_t *n_bases, uint64_t *n_reads);
+
 /* Eq. (1), host only, pure: m = -n ln(fpp) / (ln 2)^2, v = sqrt(m / 128),
  * X = smallest prime > v, Y = third prime after X.
  * n_items > 0, 0 < fpp < 1, else KC_EINVAL. */

@@ -14,6 +14,8 @@ from .kmerco import (  # noqa: F401
     eta,
     load_library,
     pack_read_sets,
+    parse_fastx,
+    read_fastx,
     run_kmerco,
     strerror,
 )

@@ -90,6 +90,8 @@ SIGNATURES = {
     "kc_strerror": (ctypes.c_char_p, [_i]),
     "kc_version": (_i, []),
     "kc_dims": (_i, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "kc_parse_fastx": (_i, [_vp, _u64, _u32, _vp, _u64, _vp, _u64, ctypes.POINTER(_u64),
+                            ctypes.POINTER(_u64)]),
     "kc_eta": (_u32, [_u32]),
     "kc_create": (_i, [ctypes.POINTER(kc_layout), _vp, _i, _vp, ctypes.POINTER(_vp)]),
     "kc_destroy": (None, [_vp]),
@@ -166,6 +168,45 @@ def dims(n_items: float, fpp: float = 0.001):
     _check(load_library().kc_dims(float(n_items), float(fpp), ctypes.byref(X), ctypes.byref(Y)),
            "kc_dims")
     return int(X.value), int(Y.value)
+
+
+KC_FASTX_ONE_SEQUENCE = 1
+
+
+def parse_fastx(data, one_sequence: bool = False):
+    """FASTA or FASTQ text (bytes-like or a uint8 numpy array, host memory)
+    -> (reads uint8, offsets uint64) for the insert calls, by
+    kc_parse_fastx: one read per record, or one read for the whole text
+    with ``one_sequence``."""
+    import numpy as np
+    lib = load_library()
+    buf = data if isinstance(data, np.ndarray) else np.frombuffer(data, dtype=np.uint8)
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    flags = KC_FASTX_ONE_SEQUENCE if one_sequence else 0
+    nb, nr = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    text = buf.ctypes.data if buf.size else None
+    st = lib.kc_parse_fastx(text, buf.size, flags, None, 0, None, 0, ctypes.byref(nb),
+                            ctypes.byref(nr))
+    if st not in (KC_OK, KC_ERANGE):
+        _check(st, "kc_parse_fastx")
+    seq = np.empty(nb.value, dtype=np.uint8)
+    offs = np.empty(nr.value + 1, dtype=np.uint64)
+    _check(lib.kc_parse_fastx(text, buf.size, flags, seq.ctypes.data if seq.size else None,
+                              seq.size, offs.ctypes.data, offs.size, ctypes.byref(nb),
+                              ctypes.byref(nr)), "kc_parse_fastx")
+    return seq, offs
+
+
+def read_fastx(path: str, one_sequence: bool = False):
+    """parse_fastx of a file, memory-mapped."""
+    import mmap
+
+    import numpy as np
+    with open(path, "rb") as f:
+        if os.fstat(f.fileno()).st_size == 0:
+            return parse_fastx(b"", one_sequence)
+        with mmap.mmap(f.fileno(), 0, access=mmap.ACCESS_READ) as m:
+            return parse_fastx(np.frombuffer(m, dtype=np.uint8), one_sequence)
 
 
 def eta(alpha: int) -> int:
