@@ -1,0 +1,29 @@
+"""The evaluation on the GPU path: at every countBF size the reported
+k-mers exist, are unique, the trustworthy / erroneous lists partition them,
+no reported k-mer above tau is called erroneous (counters never under-count),
+and a countBF much larger than the sizing count misses under 1%."""
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2305_07545_amd")
+from paper_2305_07545_amd import evaluate as E  # noqa: E402
+
+
+def test_evaluation_properties():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rs = synth.config("tiny", scale=0.2)
+    print("case evaluate tiny x0.2 sizes 0.02, 1, 50", flush=True)
+    res = E.evaluate(rs, [0.02, 1.0, 50.0], steps=1)
+    for r in res:
+        assert r["distinct_unique"] and r["distinct_all_exist"] and r["split_is_partition"], r
+        assert r["trustworthy_missed_among_reported"] == 0, r
+        assert r["n_windows"] == r["exact_windows"]
+    assert res[0]["distinct_recall"] < res[1]["distinct_recall"] <= res[2]["distinct_recall"]
+    # Eq. (1) gives about 1.8 n counters at alpha = 8, so even 50x the
+    # sizing count leaves a k-mer a ~0.5% chance of a colliding first slot
+    assert res[2]["distinct_recall"] > 0.99 and res[2]["trustworthy_precision"] > 0.99
