@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bacterial", choices=["tiny", "bacterial", "large"])
     ap.add_argument("--alpha", type=int, default=8, help="counter length (bits)")
+    ap.add_argument("--size", type=float, default=1.0,
+                    help="countBF sized for this multiple of the workload's sizing count")
     ap.add_argument("--k-h", type=int, default=1, help="hash functions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
@@ -487,7 +489,7 @@ def main():
     torch.cuda.set_device(dev)
 
     rs = synth.config(args.workload)
-    X, Y = P.dims(rs.n_items)
+    X, Y = P.dims(rs.n_items * args.size)
     k_h, alpha = args.k_h, args.alpha
     reads = torch.from_numpy(rs.reads).to(dev)
     offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
@@ -535,7 +537,7 @@ def main():
 
     n_distinct, n_windows, n_trust, n_err = (int(x) for x in counters.cpu().tolist())
     verified = None
-    if not args.no_verify and (alpha, k_h) == (8, 1):  # the digests' layout
+    if not args.no_verify and (alpha, k_h, args.size) == (8, 1, 1.0):  # the digests' layout
         ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_digests.json")
         if os.path.exists(ref_path):
             ref = json.load(open(ref_path))

@@ -704,8 +704,12 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                                                       uint32_t tau) {
     constexpr int kUnroll = 8;
     constexpr int kHold = 4;  // cells per thread held in registers (regions <= 4096 cells)
+    constexpr uint32_t kSparseCells = 2048;  // cells of a region the sparse path stages
+    constexpr uint32_t kDone = 0xFFFFFFFEu;  // first[] of a counter already updated
+    static_assert(kSparseCells <= (uint32_t)kHold * kRegionWG, "sparse cells are held");
     __shared__ uint32_t hits[kRegionCounters];
     __shared__ uint32_t first[kRegionCounters];
+    __shared__ unsigned long long s_cell[kSparseCells];
     const uint32_t r = blockIdx.x;
     const uint32_t S = 1u << B.region_shift;
     const uint32_t n_ctr = S * F.eta;
@@ -731,6 +735,65 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     for (int k = 0; k < kHold; k++) {
         const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
         cell[k] = (hold && w < nw) ? F.words[wbase + w] : 0ull;
+    }
+    if (e1 - e0 <= (uint64_t)kUnroll * kRegionWG && nw <= kSparseCells) {
+        // Sparse region: every entry is in the register batch.  Only the
+        // counters the entries touch are cleared, and counters are updated
+        // per entry, not by a pass over all of them: the entry whose t is
+        // the counter's minimum applies min(2^alpha - 1, old + hits) to the
+        // staged cell (a 64-bit LDS add of the field's increase, which
+        // cannot carry into the next field) and flags its occurrence when
+        // the counter was zero.  atomicCAS(first, t, kDone) succeeds for
+        // exactly one entry holding the minimum (with k_h > 1 one window
+        // can put two entries on one counter).
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            if (v[u] != ~0ull) {
+                const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+                hits[local] = 0;
+                first[local] = kIdle;
+            }
+#pragma unroll
+        for (int k = 0; k < kHold; k++) {
+            const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+            if (w < nw)
+                s_cell[w] = cell[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            if (v[u] != ~0ull) {
+                const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+                atomicAdd(&hits[local], 1u);
+                atomicMin(&first[local], (uint32_t)(v[u] >> 32));
+            }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            if (v[u] != ~0ull) {
+                const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+                const uint32_t t = (uint32_t)(v[u] >> 32);
+                if (atomicCAS(&first[local], t, kDone) != t)
+                    continue;
+                const uint32_t w = local & (S - 1u);
+                const uint32_t sh = F.alpha * (local >> B.region_shift);
+                const uint64_t pf = (s_cell[w] >> sh) & F.field_max;
+                const uint64_t h = hits[local];
+                const uint64_t room = F.field_max - pf;
+                const uint64_t nf = pf + (h < room ? h : room);
+                if (nf != pf)
+                    atomicAdd(&s_cell[w], (unsigned long long)((nf - pf) << sh));
+                if (pf == 0)
+                    flags[c0 + t] = (classify && nf > (uint64_t)tau) ? 3 : 1;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kHold; k++) {
+            const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+            if (w < nw && s_cell[w] != cell[k])
+                F.words[wbase + w] = s_cell[w];
+        }
+        return;
     }
     for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
         hits[i] = 0;

@@ -153,6 +153,20 @@ def test_low_complexity_saturation(path):
     check(homo, 7, 11, what="homopolymers")
 
 
+@pytest.mark.parametrize("k_h", [1, 2])
+def test_sparse_and_dense_regions_in_one_call(k_h):
+    """A countBF of ~500 regions fed mostly random reads (a few hundred
+    entries per region: the sparse per-entry update), plus a homopolymer and
+    a periodic read whose k-mers pile thousands of entries onto single
+    counters (saturating them) and push their regions past the sparse
+    bound (the dense per-counter update)."""
+    rnd = synth.random_reads(707 + k_h, 300, 50, 300, k=21, tau=3, p_n=0.01)
+    extra = synth.reads_from_strings(["A" * 20000, "ACGT" * 3000, "GATTACA" * 900], k=21, tau=3)
+    rs = synth.concat_reads([rnd, extra], name="sparse+dense")
+    check(rs, 1009, 1013, k_h=k_h, what=f"sparse+dense kh={k_h}")
+    check(rs, 1009, 1013, k_h=k_h, what=f"sparse+dense kh={k_h} unfused", fused=False)
+
+
 def test_multi_chunk(monkeypatch, path):
     """First-seen resolved in many chunks (chunk size forced small); the
     split of a multi-chunk call is classified after the insert."""
