@@ -103,11 +103,12 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     wait_idle(f);
     if (!W.matrix || n_mat > W.matrix_cap || n_coarse > W.coarse_cap) {
         dev_free(W.matrix);
+        dev_free(W.matrix_t);
         dev_free(W.coarse);
         dev_free(W.partial32);
         W.matrix_cap = W.coarse_cap = 0;
-        if (!dev_alloc(&W.matrix, n_mat) || !dev_alloc(&W.coarse, n_coarse) ||
-            !dev_alloc(&W.partial32, kc::scan_partials(n_mat)))
+        if (!dev_alloc(&W.matrix, n_mat) || !dev_alloc(&W.matrix_t, n_mat) ||
+            !dev_alloc(&W.coarse, n_coarse) || !dev_alloc(&W.partial32, kc::scan_partials(n_mat)))
             return KC_ENOMEM;
         W.matrix_cap = n_mat;
         W.coarse_cap = n_coarse;
@@ -154,10 +155,11 @@ kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positi
         const uint64_t m = n_mat > W.matrix_cap ? n_mat : W.matrix_cap;
         const uint64_t c = n_coarse > W.coarse_cap ? n_coarse : W.coarse_cap;
         dev_free(W.matrix);
+        dev_free(W.matrix_t);
         dev_free(W.coarse);
         dev_free(W.partial32);
         W.matrix_cap = W.coarse_cap = 0;
-        if (!dev_alloc(&W.matrix, m) || !dev_alloc(&W.coarse, c) ||
+        if (!dev_alloc(&W.matrix, m) || !dev_alloc(&W.matrix_t, m) || !dev_alloc(&W.coarse, c) ||
             !dev_alloc(&W.partial32, kc::scan_partials(m > c ? m : c)))
             return KC_ENOMEM;
         W.matrix_cap = m;
@@ -225,6 +227,7 @@ void free_workspace(kc::Workspace &W) {
     dev_free(W.tmask);
     dev_free(W.partial64);
     dev_free(W.matrix);
+    dev_free(W.matrix_t);
     dev_free(W.coarse);
     dev_free(W.partial32);
     dev_free(W.slots);

@@ -168,8 +168,12 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
+    // binned path: the workgroup's region counts as one contiguous row
+    // (transposed to region-major afterwards); partitioned path: partition
+    // counts, few per workgroup, written partition-major directly
     for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
-        fine[(uint64_t)i * B.G + blockIdx.x] = s_hist[i];
+        fine[kParts ? (uint64_t)i * B.G + blockIdx.x : (uint64_t)blockIdx.x * n_keys + i] =
+            s_hist[i];
     if (!kParts)
         write_bucket_sums(s_hist, B.n_regions, B.n_buckets, B.bucket_shift, B.G, coarse,
                           blockIdx.x);
@@ -1039,7 +1043,8 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (P)
         P->begin(kPhBinCount, s);
     hipLaunchKernelGGL(k_bin_count<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
-                       W.slots, nullptr, W.matrix, W.coarse, (unsigned long long *)(W.totals + 5));
+                       W.slots, nullptr, W.matrix_t, W.coarse,
+                       (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -1047,7 +1052,9 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhScan, s);
-    e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+    e = transpose_u32(W.matrix_t, W.matrix, B.G, B.n_regions, s);
+    if (e == hipSuccess)
+        e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
     if (e == hipSuccess)
         e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
     if (P)

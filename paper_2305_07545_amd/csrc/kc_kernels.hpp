@@ -74,6 +74,8 @@ struct Workspace {
     uint64_t tile_cap = 0;
     // binned path (per chunk)
     uint32_t *matrix = nullptr;   // matrix_cap region counts, scanned in place to offsets
+    uint32_t *matrix_t = nullptr; // matrix_cap counts as the bin workgroups write them
+                                  // (workgroup-major), transposed into matrix
     uint32_t *coarse = nullptr;   // coarse_cap bucket counts, scanned in place to offsets
     uint32_t *partial32 = nullptr;
     uint64_t matrix_cap = 0, coarse_cap = 0;
@@ -146,6 +148,10 @@ enum Phase {
 };
 
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// out[c * rows + r] = in[r * cols + c]: a rows x cols matrix, row-major, to
+// its transpose (rows / 64 <= 65535)
+hipError_t transpose_u32(const uint32_t *in, uint32_t *out, uint64_t rows, uint64_t cols,
+                         hipStream_t s);
 hipError_t fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
 uint64_t scan_partials(uint64_t n);

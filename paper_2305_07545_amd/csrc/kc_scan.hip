@@ -133,7 +133,40 @@ hipError_t scan_impl(const TIn *in, TOut *out, uint64_t n, const TOut *base, TOu
     return hipGetLastError();
 }
 
+// 64 x 64 tiles through LDS (one pad word per row: no bank conflicts on the
+// column reads); reads and writes are 256-byte rows.
+__global__ void __launch_bounds__(256) k_transpose_u32(const uint32_t *__restrict__ in,
+                                                       uint32_t *__restrict__ out, uint64_t rows,
+                                                       uint64_t cols) {
+    __shared__ uint32_t t[64][65];
+    const uint64_t c0 = (uint64_t)blockIdx.x * 64, r0 = (uint64_t)blockIdx.y * 64;
+    const uint32_t tx = threadIdx.x & 63u, ty = threadIdx.x >> 6;
+    for (uint32_t j = ty; j < 64; j += 4) {
+        const uint64_t r = r0 + j, c = c0 + tx;
+        if (r < rows && c < cols)
+            t[j][tx] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (uint32_t j = ty; j < 64; j += 4) {
+        const uint64_t c = c0 + j, r = r0 + tx;
+        if (c < cols && r < rows)
+            out[c * rows + r] = t[tx][j];
+    }
+}
+
 }  // namespace
+
+hipError_t transpose_u32(const uint32_t *in, uint32_t *out, uint64_t rows, uint64_t cols,
+                         hipStream_t s) {
+    if (rows == 0 || cols == 0)
+        return hipSuccess;
+    const uint64_t gx = (cols + 63) / 64, gy = (rows + 63) / 64;
+    if (gx > 0x7FFFFFFFull || gy > 65535)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_transpose_u32, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, in,
+                       out, rows, cols);
+    return hipGetLastError();
+}
 
 uint64_t scan_partials(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
