@@ -142,7 +142,12 @@ kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positi
     const uint64_t n_fine = (uint64_t)B.n_regions * B.list_g;
     const uint64_t nbp = (1ull << B.part_log) >> B.bucket_shift;
     const uint64_t n_coarse = (uint64_t)B.n_parts * nbp * B.list_g;
-    const uint64_t n_mat = n_fine > n_pmat ? n_fine : n_pmat;  // the scans share partial32
+    // the scans share partial32; the list workgroups' rows (matrix_t) are
+    // 2^part_log counts long in every partition
+    const uint64_t n_rows = (uint64_t)B.n_parts * B.list_g << B.part_log;
+    uint64_t n_mat = n_fine > n_pmat ? n_fine : n_pmat;
+    if (n_rows > n_mat)
+        n_mat = n_rows;
     if (W.plist && W.pbounds && W.pdesc && n_slots <= W.slots_cap && n_slots <= W.entries_cap &&
         n_pmat <= W.pmat_cap && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap)
         return KC_OK;

@@ -558,10 +558,11 @@ __global__ void k_pass_plan(const uint32_t *__restrict__ bounds, uint32_t n_part
     }
 }
 
-// Region counts per list workgroup of every partition's list:
-// fine[(partition region) x list_g + g] over all regions of the countBF
-// (region-major, the layout the single-level path uses), and the bucket sums
-// into coarse[(p * buckets per partition + b) x list_g + g].
+// Region counts per list workgroup of every partition's list, one
+// contiguous row per workgroup: fine_t[((p * list_g) + g) * 2^part_log + i]
+// (transposed afterwards, partition by partition, to the region-major layout
+// the single-level path uses), and the bucket sums into
+// coarse[(p * buckets per partition + b) x list_g + g].
 __global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restrict__ plist,
                                                        const uint64_t *__restrict__ pdesc,
                                                        BinPlan B, uint32_t *__restrict__ fine,
@@ -591,7 +592,7 @@ __global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restric
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nrp; i += kBinWG)
-        fine[(uint64_t)(rp0 + i) * B.list_g + g] = s_hist[i];
+        fine[((uint64_t)p * B.list_g + g) * per + i] = s_hist[i];
     const uint32_t nbp = per >> B.bucket_shift;  // bucket rows per partition
     write_bucket_sums(s_hist, nrp, nbp, B.bucket_shift, B.list_g,
                       coarse + (uint64_t)p * nbp * B.list_g, g);
@@ -977,7 +978,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (P)
         P->begin(kPhPartCount, s);
     hipLaunchKernelGGL(k_list_count, dim3(n_list), dim3(kBinWG), (size_t)hist * sizeof(uint32_t),
-                       s, (const uint64_t *)W.plist, (const uint64_t *)W.pdesc, Q, W.matrix,
+                       s, (const uint64_t *)W.plist, (const uint64_t *)W.pdesc, Q, W.matrix_t,
                        W.coarse);
     if (P)
         P->end(s);
@@ -985,7 +986,9 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhScan, s);
-        e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
+        e = transpose_u32_blocks(W.matrix_t, W.matrix, B.list_g, per, B.n_regions, s);
+        if (e == hipSuccess)
+            e = scan_u32_u32(W.matrix, W.matrix, n_fine, W.n_entries, W.partial32, s);
         if (e == hipSuccess)
             e = scan_u32_u32(W.coarse, W.coarse, n_coarse, W.n_entries + 1, W.partial32, s);
         if (P)

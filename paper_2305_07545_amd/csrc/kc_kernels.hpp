@@ -152,6 +152,11 @@ hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 // its transpose (rows / 64 <= 65535)
 hipError_t transpose_u32(const uint32_t *in, uint32_t *out, uint64_t rows, uint64_t cols,
                          hipStream_t s);
+// The same for consecutive rows x cols blocks of a rows x total_cols matrix
+// stored block by block (block z: columns z*cols .. , the last one cut at
+// total_cols); out is the total_cols x rows transpose.
+hipError_t transpose_u32_blocks(const uint32_t *in, uint32_t *out, uint64_t rows, uint64_t cols,
+                                uint64_t total_cols, hipStream_t s);
 hipError_t fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
 uint64_t scan_partials(uint64_t n);

@@ -134,23 +134,29 @@ hipError_t scan_impl(const TIn *in, TOut *out, uint64_t n, const TOut *base, TOu
 }
 
 // 64 x 64 tiles through LDS (one pad word per row: no bank conflicts on the
-// column reads); reads and writes are 256-byte rows.
+// column reads); reads and writes are 256-byte rows.  Batch z transposes the
+// rows x cols block at in + z*rows*cols into out + z*cols*rows, its columns
+// cut at total_cols - z*cols (the last block may be narrower).
 __global__ void __launch_bounds__(256) k_transpose_u32(const uint32_t *__restrict__ in,
                                                        uint32_t *__restrict__ out, uint64_t rows,
-                                                       uint64_t cols) {
+                                                       uint64_t cols, uint64_t total_cols) {
     __shared__ uint32_t t[64][65];
+    const uint64_t z0 = (uint64_t)blockIdx.z * cols;
+    const uint64_t cz = total_cols - z0 < cols ? total_cols - z0 : cols;
+    const uint32_t *__restrict__ src = in + (uint64_t)blockIdx.z * rows * cols;
+    uint32_t *__restrict__ dst = out + z0 * rows;
     const uint64_t c0 = (uint64_t)blockIdx.x * 64, r0 = (uint64_t)blockIdx.y * 64;
     const uint32_t tx = threadIdx.x & 63u, ty = threadIdx.x >> 6;
     for (uint32_t j = ty; j < 64; j += 4) {
         const uint64_t r = r0 + j, c = c0 + tx;
-        if (r < rows && c < cols)
-            t[j][tx] = in[r * cols + c];
+        if (r < rows && c < cz)
+            t[j][tx] = src[r * cols + c];
     }
     __syncthreads();
     for (uint32_t j = ty; j < 64; j += 4) {
         const uint64_t c = c0 + j, r = r0 + tx;
-        if (c < cols && r < rows)
-            out[c * rows + r] = t[tx][j];
+        if (c < cz && r < rows)
+            dst[c * rows + r] = t[tx][j];
     }
 }
 
@@ -158,13 +164,19 @@ __global__ void __launch_bounds__(256) k_transpose_u32(const uint32_t *__restric
 
 hipError_t transpose_u32(const uint32_t *in, uint32_t *out, uint64_t rows, uint64_t cols,
                          hipStream_t s) {
-    if (rows == 0 || cols == 0)
+    return transpose_u32_blocks(in, out, rows, cols, cols, s);
+}
+
+hipError_t transpose_u32_blocks(const uint32_t *in, uint32_t *out, uint64_t rows, uint64_t cols,
+                                uint64_t total_cols, hipStream_t s) {
+    if (rows == 0 || cols == 0 || total_cols == 0)
         return hipSuccess;
     const uint64_t gx = (cols + 63) / 64, gy = (rows + 63) / 64;
-    if (gx > 0x7FFFFFFFull || gy > 65535)
+    const uint64_t gz = (total_cols + cols - 1) / cols;
+    if (gx > 0x7FFFFFFFull || gy > 65535 || gz > 65535)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_transpose_u32, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, in,
-                       out, rows, cols);
+    hipLaunchKernelGGL(k_transpose_u32, dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(256),
+                       0, s, in, out, rows, cols, total_cols);
     return hipGetLastError();
 }
 
