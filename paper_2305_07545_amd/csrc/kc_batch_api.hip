@@ -44,6 +44,7 @@ void free_batch_buffers(kc_batch *b) {
     dev_free(B.tile_set);
     dev_free(B.slots);
     dev_free(B.matrix);
+    dev_free(B.matrix_t);
     dev_free(B.partial32);
     dev_free(B.n_entries);
     dev_free(B.entries);
@@ -132,6 +133,8 @@ kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64
             b->h_tiles[t] = s;
         item += d.G;
         reg += d.n_regions;
+        P.max_G = d.G > P.max_G ? d.G : P.max_G;
+        P.max_regions = d.n_regions > P.max_regions ? d.n_regions : P.max_regions;
         mat += (uint64_t)d.n_regions * d.G;
         slot += q.n_bases * f->F.k_h;
     }
@@ -170,10 +173,12 @@ kc_status ensure_batch(kc_batch *b, const kc::BatchPlan &P, hipStream_t s) {
         return st;
     if (!B.matrix || P.n_matrix > b->cap_matrix) {
         dev_free(B.matrix);
+        dev_free(B.matrix_t);
         dev_free(B.partial32);
         b->cap_matrix = 0;
         uint64_t n = P.n_matrix + P.n_matrix / 8 + 16;
-        if (!dev_alloc(&B.matrix, n) || !dev_alloc(&B.partial32, kc::scan_partials(n)))
+        if (!dev_alloc(&B.matrix, n) || !dev_alloc(&B.matrix_t, n) ||
+            !dev_alloc(&B.partial32, kc::scan_partials(n)))
             return KC_ENOMEM;
         b->cap_matrix = n;
     }

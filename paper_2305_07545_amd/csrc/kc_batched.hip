@@ -154,10 +154,40 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
+    // the item's counts as one contiguous row of the set's block (kb_transpose
+    // makes the block region-major)
     for (uint32_t r = threadIdx.x; r < S.n_regions; r += kBinWG)
-        matrix[S.mat_base + (uint64_t)r * S.G + it.j] = s_hist[r];
+        matrix[S.mat_base + (uint64_t)it.j * S.n_regions + r] = s_hist[r];
     if (threadIdx.x == 0)
         atomicAdd(&valid[it.s], (unsigned long long)s_valid);
+}
+
+// Each set's G x n_regions block of item rows -> its n_regions x G
+// region-major block (blockIdx.z = set; 64 x 64 LDS tiles, tiles outside
+// the set's block return at once).
+__global__ void __launch_bounds__(256) kb_transpose(const SetDesc *__restrict__ sets,
+                                                    const uint32_t *__restrict__ in,
+                                                    uint32_t *__restrict__ out) {
+    __shared__ uint32_t t[64][65];
+    const SetDesc &S = sets[blockIdx.z];
+    const uint32_t rows = S.G, cols = S.n_regions;
+    const uint32_t c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    if (c0 >= cols || r0 >= rows)
+        return;
+    const uint32_t *__restrict__ src = in + S.mat_base;
+    uint32_t *__restrict__ dst = out + S.mat_base;
+    const uint32_t tx = threadIdx.x & 63u, ty = threadIdx.x >> 6;
+    for (uint32_t j = ty; j < 64; j += 4) {
+        const uint32_t r = r0 + j, c = c0 + tx;
+        if (r < rows && c < cols)
+            t[j][tx] = src[(uint64_t)r * cols + c];
+    }
+    __syncthreads();
+    for (uint32_t j = ty; j < 64; j += 4) {
+        const uint32_t c = c0 + j, r = r0 + tx;
+        if (c < cols && r < rows)
+            dst[(uint64_t)c * rows + r] = t[tx][j];
+    }
 }
 
 // Slot ids of an item -> its segments of the entry list, counting-sorted by
@@ -482,12 +512,22 @@ hipError_t launch_batch_bins(const BatchPlan &bp, const BatchBuffers &Bf, const 
     if (P)
         P->begin(kPhBinCount, s);
     hipLaunchKernelGGL(kb_bin_count, dim3(bp.n_items), dim3(kBinWG), 0, s, Bf.sets, Bf.item_set, R,
-                       bp.tile, Bf.slots, Bf.matrix, Bf.valid);
+                       bp.tile, Bf.slots, Bf.matrix_t, Bf.valid);
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
     if (P)
         P->begin(kPhScan, s);
+    if (e == hipSuccess && bp.n_sets) {
+        const uint32_t gx = (bp.max_regions + 63) / 64, gy = (bp.max_G + 63) / 64;
+        if (gy > 65535 || bp.n_sets > 65535) {
+            e = hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL(kb_transpose, dim3(gx, gy, bp.n_sets), dim3(256), 0, s, Bf.sets,
+                               (const uint32_t *)Bf.matrix_t, Bf.matrix);
+            e = hipGetLastError();
+        }
+    }
     if (e == hipSuccess)
         e = scan_u32_u32(Bf.matrix, Bf.matrix, bp.n_matrix, Bf.n_entries, Bf.partial32, s);
     if (P)

@@ -19,7 +19,7 @@ struct SetDesc {
     uint64_t base;            // first position (multiple of kSetAlign)
     uint64_t n_bases;
     uint64_t slot_base;       // first slot id of the set (slot ids are per set, per hash fn)
-    uint64_t mat_base;        // first count of the set's region-major block
+    uint64_t mat_base;        // first count of the set's block (n_regions x G)
     uint32_t k, tau;
     uint32_t region_shift, n_regions;
     uint32_t region_base;     // global index of the set's first region
@@ -41,6 +41,8 @@ struct BatchPlan {
     uint64_t tile;            // positions per work item (multiple of kBinWG)
     uint64_t n_matrix;        // total counts of all sets' blocks
     uint32_t n_regions;       // total regions of all sets
+    uint32_t max_G;           // most work items of one set
+    uint32_t max_regions;     // most regions of one set
     uint64_t n_tiles;         // 1024-position tiles of the whole buffer
     uint64_t n_slots;
     uint64_t entries_cap;
@@ -52,7 +54,8 @@ struct BatchBuffers {
     uint32_t *region_set = nullptr;   // set of each region
     uint32_t *tile_set = nullptr;     // set of each tile (kNoSet for padding)
     uint32_t *slots = nullptr;
-    uint32_t *matrix = nullptr;
+    uint32_t *matrix = nullptr;       // per set: region-major counts, scanned to offsets
+    uint32_t *matrix_t = nullptr;     // per set: the work items' counts, one row per item
     uint32_t *partial32 = nullptr;
     uint32_t *n_entries = nullptr;
     uint64_t *entries = nullptr;
