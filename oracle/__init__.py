@@ -18,6 +18,8 @@ Parity status of each function (how it is pinned, see ``tests/test_oracle_*``):
               symmetry; incremental == concatenated
   query       exact counts when collision-free; >= exact count always
   classify    partition of the distinct list; one-sided error vs exact counts
+  *_wide      K = 33..64 (128-bit keys): the same pins with brute force on
+              Python strings and scikit-learn's MurmurHash3 of the 16-byte key
 """
 from __future__ import annotations
 
@@ -89,6 +91,16 @@ def lib():
         L.kco_occurrences.argtypes = [lp, u8p, u64p, ctypes.c_uint64, ctypes.c_uint32,
                                       u64p, u64p, ctypes.c_uint64, u64p]
         L.kco_occurrences.restype = ctypes.c_int
+        L.kco_hash_wide.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
+        L.kco_hash_wide.restype = ctypes.c_uint64
+        L.kco_query_wide.argtypes = [lp, u64p, ctypes.c_uint64, ctypes.c_uint64]
+        L.kco_query_wide.restype = ctypes.c_uint64
+        L.kco_insert_wide.argtypes = L.kco_insert.argtypes
+        L.kco_insert_wide.restype = ctypes.c_int
+        L.kco_classify_wide.argtypes = L.kco_classify.argtypes
+        L.kco_classify_wide.restype = ctypes.c_int
+        L.kco_occurrences_wide.argtypes = L.kco_occurrences.argtypes
+        L.kco_occurrences_wide.restype = ctypes.c_int
         L.kco_dims.argtypes = [ctypes.c_double, ctypes.c_double, u64p, u64p]
         L.kco_dims.restype = ctypes.c_int
         L.kco_is_prime.argtypes = [ctypes.c_uint64]
@@ -120,8 +132,17 @@ def mm3_32(data: bytes, seed: int) -> int:
     return int(lib().kco_mm3_32(_p(buf, ctypes.c_uint8), len(data), seed))
 
 
-def hash_a(key: int, a: int) -> int:
+def hash_a(key: int, a: int, k: int = 32) -> int:
+    """H_a of a 2-bit key; keys of k > 32 bases (reading R10) as 16 bytes."""
+    if k > 32:
+        return int(lib().kco_hash_wide(key & ((1 << 64) - 1), key >> 64, a))
     return int(lib().kco_hash(key, a))
+
+
+def pairs_to_ints(a) -> list:
+    """(n, 2) uint64 (low, high) key pairs -> Python ints."""
+    a = np.asarray(a, dtype=np.uint64).reshape(-1, 2)
+    return [int(lo) | (int(hi) << 64) for lo, hi in a]
 
 
 def revcomp(s: bytes) -> bytes:
@@ -185,21 +206,24 @@ class CountBF:
         return eta(self.layout.alpha)
 
     def insert(self, reads, offsets, k: int):
-        """Algorithm 1 over one read batch; returns (distinct keys, n_windows)."""
+        """Algorithm 1 over one read batch; returns (distinct keys, n_windows).
+        Keys of k > 32 bases come as an (n, 2) array of (low, high) words."""
         reads, rp = _u8(reads)
         offsets, op = _u64(offsets)
         n_reads = len(offsets) - 1
         cap = max(1, int(offsets[-1]) if n_reads > 0 else 1)
-        out = np.zeros(cap, dtype=np.uint64)
+        w = 2 if k > 32 else 1
+        out = np.zeros(cap * w, dtype=np.uint64)
         nd = ctypes.c_uint64(0)
         nw = ctypes.c_uint64(0)
-        rc = lib().kco_insert(ctypes.byref(self.layout), _p(self.words, ctypes.c_uint64), rp, op,
-                              n_reads, k, _p(out, ctypes.c_uint64), cap,
-                              ctypes.byref(nd), ctypes.byref(nw))
+        fn = lib().kco_insert_wide if k > 32 else lib().kco_insert
+        rc = fn(ctypes.byref(self.layout), _p(self.words, ctypes.c_uint64), rp, op,
+                n_reads, k, _p(out, ctypes.c_uint64), cap, ctypes.byref(nd), ctypes.byref(nw))
         if rc != OK:
             raise ValueError(f"kco_insert failed ({rc})")
         self.k = k
-        return out[:nd.value].copy(), int(nw.value)
+        d = out[:nd.value * w].copy()
+        return (d.reshape(-1, 2) if w == 2 else d), int(nw.value)
 
     def query(self, keys):
         keys, kp = _u64(keys)
@@ -211,18 +235,23 @@ class CountBF:
         return out[:len(keys)]
 
     def classify(self, distinct, tau: int):
+        """Algorithm 2; (n, 2) key pairs (k > 32) give (n, 2) outputs."""
+        wide = np.ndim(distinct) == 2
         distinct, dp = _u64(distinct)
-        n = len(distinct)
-        trust = np.zeros(max(1, n), dtype=np.uint64)
-        err = np.zeros(max(1, n), dtype=np.uint64)
+        w = 2 if wide else 1
+        n = distinct.size // w
+        trust = np.zeros(max(1, n) * w, dtype=np.uint64)
+        err = np.zeros(max(1, n) * w, dtype=np.uint64)
         nt = ctypes.c_uint64(0)
         ne = ctypes.c_uint64(0)
-        rc = lib().kco_classify(ctypes.byref(self.layout), _p(self.words, ctypes.c_uint64), dp, n,
-                                tau, _p(trust, ctypes.c_uint64), ctypes.byref(nt),
-                                _p(err, ctypes.c_uint64), ctypes.byref(ne))
+        fn = lib().kco_classify_wide if wide else lib().kco_classify
+        rc = fn(ctypes.byref(self.layout), _p(self.words, ctypes.c_uint64), dp, n, tau,
+                _p(trust, ctypes.c_uint64), ctypes.byref(nt), _p(err, ctypes.c_uint64),
+                ctypes.byref(ne))
         if rc != OK:
             raise ValueError(f"kco_classify failed ({rc})")
-        return trust[:nt.value].copy(), err[:ne.value].copy()
+        t, e = trust[:nt.value * w].copy(), err[:ne.value * w].copy()
+        return (t.reshape(-1, 2), e.reshape(-1, 2)) if wide else (t, e)
 
     def counters(self):
         """Unpacked counters, shape (X*Y, eta), counter l of word w at [w, l]."""
@@ -244,12 +273,16 @@ def occurrences(reads, offsets, k: int, X: int, Y: int, alpha: int = 8, k_h: int
     slots = np.zeros(cap * k_h, dtype=np.uint64)
     n = ctypes.c_uint64(0)
     L = Layout(X, Y, alpha, k_h)
-    rc = lib().kco_occurrences(ctypes.byref(L), rp, op, n_reads, k, _p(kmers, ctypes.c_uint64),
-                               _p(slots, ctypes.c_uint64), cap, ctypes.byref(n))
+    if k > 32:
+        kmers = np.zeros(cap * 2, dtype=np.uint64)
+    fn = lib().kco_occurrences_wide if k > 32 else lib().kco_occurrences
+    rc = fn(ctypes.byref(L), rp, op, n_reads, k, _p(kmers, ctypes.c_uint64),
+            _p(slots, ctypes.c_uint64), cap, ctypes.byref(n))
     if rc != OK:
         raise ValueError(f"kco_occurrences failed ({rc})")
     m = int(n.value)
-    return kmers[:m].copy(), slots[:m * k_h].reshape(m, k_h).copy()
+    km = kmers[:m * 2].reshape(m, 2).copy() if k > 32 else kmers[:m].copy()
+    return km, slots[:m * k_h].reshape(m, k_h).copy()
 
 
 def run_kmerco(reads, offsets, k: int, tau: int, X: int, Y: int, alpha: int = 8, k_h: int = 1):

@@ -34,7 +34,11 @@
  *       occupies bits [alpha*l, alpha*l + alpha) (the paper's first extract
  *       mask 0x00000000000000FF);
  *   R8  eta = floor(64 / alpha) counters per 64-bit cell (supplement table);
- *   R9  trustworthy iff frequency > tau, erroneous otherwise (Sec. 3).
+ *   R9  trustworthy iff frequency > tau, erroneous otherwise (Sec. 3);
+ *   R10 K-mers of 33..64 bases (the paper's 55-mers, Sec. 4): the 2-bit key
+ *       is a 128-bit integer (first base most significant), hashed as its 16
+ *       little-endian bytes (R1 with a 16-byte key), and stored as two
+ *       uint64 words, low word first.
  */
 #include <math.h>
 #include <stddef.h>
@@ -364,6 +368,194 @@ int kco_occurrences(const kco_layout *L, const uint8_t *reads, const uint64_t *o
                     uint64_t word;
                     uint32_t l;
                     kco_slot(L, kco_hash(kmer, a), &word, &l);
+                    slot_ids[n * L->k_h + (a - 1)] = word * eta + l;
+                }
+            }
+            n++;
+        }
+    }
+    *n_out = n;
+    return n > cap ? KCO_ERANGE : KCO_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * K-mers of 33..64 bases (reading R10).  The same steps as above -- window
+ * visiting order, reverse complement, canonical strand by H_1, Query-I
+ * before the insert, Algorithm 3's saturating increments, Algorithm 2's
+ * split -- on 128-bit keys.
+ * ---------------------------------------------------------------------- */
+typedef unsigned __int128 kco_u128;
+
+/* H_a of a 128-bit key given as (low, high) words: MM3 over its 16
+ * little-endian bytes, low word first. */
+uint64_t kco_hash_wide(uint64_t lo, uint64_t hi, uint32_t a)
+{
+    uint8_t bytes[16];
+    for (int i = 0; i < 8; i++) {
+        bytes[i] = (uint8_t)(lo >> (8 * i));
+        bytes[8 + i] = (uint8_t)(hi >> (8 * i));
+    }
+    uint64_t h_hi = kco_mm3_32(bytes, 16, 2u * a - 2u);
+    uint64_t h_lo = kco_mm3_32(bytes, 16, 2u * a - 1u);
+    return (h_hi << 32) | h_lo;
+}
+
+static uint64_t hash_u128(kco_u128 key, uint32_t a)
+{
+    return kco_hash_wide((uint64_t)key, (uint64_t)(key >> 64), a);
+}
+
+/* 2-bit key of a K-character string (K <= 64), first base most significant. */
+static int encode_wide(const uint8_t *s, uint32_t K, kco_u128 *key)
+{
+    kco_u128 v = 0;
+    for (uint32_t i = 0; i < K; i++) {
+        int c = base_code(s[i]);
+        if (c < 0)
+            return -1;
+        v = v * 4u + (kco_u128)c;
+    }
+    *key = v;
+    return 0;
+}
+
+/* Algorithm 3 for a 128-bit key. */
+static void icountbf_wide(const kco_layout *L, uint64_t *C, kco_u128 kmer)
+{
+    uint64_t maxv = (L->alpha >= 64) ? ~(uint64_t)0 : (((uint64_t)1 << L->alpha) - 1u);
+    for (uint32_t a = 1; a <= L->k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        kco_slot(L, hash_u128(kmer, a), &word, &l);
+        uint64_t value = read_counter(L, C, word, l);
+        if (value == maxv)
+            continue;
+        value = value + 1u;
+        uint64_t reset = ~extract_mask(L->alpha, l);
+        C[word] = (C[word] & reset) | (value << (L->alpha * l));
+    }
+}
+
+/* Algorithm 5 for a 128-bit key: 0 if any counter is 0, else the minimum. */
+static uint64_t query_u128(const kco_layout *L, const uint64_t *C, kco_u128 kmer)
+{
+    uint64_t best = 0;
+    for (uint32_t a = 1; a <= L->k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        kco_slot(L, hash_u128(kmer, a), &word, &l);
+        uint64_t value = read_counter(L, C, word, l);
+        if (value == 0)
+            return 0;
+        if (a == 1 || value < best)
+            best = value;
+    }
+    return best;
+}
+
+uint64_t kco_query_wide(const kco_layout *L, const uint64_t *C, uint64_t lo, uint64_t hi)
+{
+    return query_u128(L, C, ((kco_u128)hi << 64) | lo);
+}
+
+/* Sec. 2.3 / Algorithm 4 for 128-bit keys (reading R4). */
+static kco_u128 canonical_wide(kco_u128 fwd, kco_u128 rc)
+{
+    return hash_u128(fwd, 1) < hash_u128(rc, 1) ? fwd : rc;
+}
+
+/* Algorithm 1 for K = 33..64; distinct receives (low, high) pairs. */
+int kco_insert_wide(const kco_layout *L, uint64_t *words, const uint8_t *reads,
+                    const uint64_t *offsets, uint64_t n_reads, uint32_t K,
+                    uint64_t *distinct, uint64_t distinct_cap, uint64_t *n_distinct,
+                    uint64_t *n_windows)
+{
+    if (check_layout(L) != KCO_OK || K < 33 || K > 64)
+        return KCO_EINVAL;
+    uint8_t read[64], read_rc[64];
+    uint64_t nd = 0, nw = 0;
+    int overflow = 0;
+    for (uint64_t r = 0; r < n_reads; r++) {
+        uint64_t start = offsets[r], end = offsets[r + 1];
+        if (end < start)
+            return KCO_EINVAL;
+        if (end - start < K)
+            continue;
+        for (uint64_t p = start; p + K <= end; p++) {
+            memcpy(read, reads + p, K);
+            kco_revcomp(read, K, read_rc);
+            kco_u128 fwd, rc = 0;
+            if (encode_wide(read, K, &fwd) != 0)
+                continue;
+            encode_wide(read_rc, K, &rc);
+            kco_u128 kmer = canonical_wide(fwd, rc);
+            if (query_u128(L, words, kmer) == 0) {
+                if (nd < distinct_cap) {
+                    distinct[2 * nd] = (uint64_t)kmer;
+                    distinct[2 * nd + 1] = (uint64_t)(kmer >> 64);
+                } else {
+                    overflow = 1;
+                }
+                nd++;
+            }
+            icountbf_wide(L, words, kmer);
+            nw++;
+        }
+    }
+    *n_distinct = nd;
+    *n_windows = nw;
+    return overflow ? KCO_ERANGE : KCO_OK;
+}
+
+/* Algorithm 2 for (low, high) key pairs. */
+int kco_classify_wide(const kco_layout *L, const uint64_t *words, const uint64_t *distinct,
+                      uint64_t n, uint64_t tau, uint64_t *trust, uint64_t *n_trust,
+                      uint64_t *err, uint64_t *n_err)
+{
+    if (check_layout(L) != KCO_OK)
+        return KCO_EINVAL;
+    uint64_t nt = 0, ne = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        kco_u128 kmer = ((kco_u128)distinct[2 * i + 1] << 64) | distinct[2 * i];
+        uint64_t *out = query_u128(L, words, kmer) > tau ? trust + 2 * nt++ : err + 2 * ne++;
+        out[0] = distinct[2 * i];
+        out[1] = distinct[2 * i + 1];
+    }
+    *n_trust = nt;
+    *n_err = ne;
+    return KCO_OK;
+}
+
+/* Test helper for K = 33..64: canonical keys as (low, high) pairs and the
+ * k_h slot ids of every valid window. */
+int kco_occurrences_wide(const kco_layout *L, const uint8_t *reads, const uint64_t *offsets,
+                         uint64_t n_reads, uint32_t K, uint64_t *kmers, uint64_t *slot_ids,
+                         uint64_t cap, uint64_t *n_out)
+{
+    if (check_layout(L) != KCO_OK || K < 33 || K > 64)
+        return KCO_EINVAL;
+    uint8_t read[64], read_rc[64];
+    uint64_t n = 0;
+    uint32_t eta = kco_eta(L->alpha);
+    for (uint64_t r = 0; r < n_reads; r++) {
+        uint64_t start = offsets[r], end = offsets[r + 1];
+        if (end - start < K)
+            continue;
+        for (uint64_t p = start; p + K <= end; p++) {
+            memcpy(read, reads + p, K);
+            kco_revcomp(read, K, read_rc);
+            kco_u128 fwd, rc = 0;
+            if (encode_wide(read, K, &fwd) != 0)
+                continue;
+            encode_wide(read_rc, K, &rc);
+            kco_u128 kmer = canonical_wide(fwd, rc);
+            if (n < cap) {
+                kmers[2 * n] = (uint64_t)kmer;
+                kmers[2 * n + 1] = (uint64_t)(kmer >> 64);
+                for (uint32_t a = 1; a <= L->k_h; a++) {
+                    uint64_t word;
+                    uint32_t l;
+                    kco_slot(L, hash_u128(kmer, a), &word, &l);
                     slot_ids[n * L->k_h + (a - 1)] = word * eta + l;
                 }
             }

@@ -21,9 +21,10 @@ def key_of(s: str) -> int:
     return int(s.translate(_DIGIT), 4)
 
 
-def h64(key: int, a: int = 1) -> int:
-    """H_a: two 32-bit MurmurHash3_x86_32 values of the 8-byte little-endian key."""
-    b = key.to_bytes(8, "little")
+def h64(key: int, a: int = 1, nbytes: int = 8) -> int:
+    """H_a: two 32-bit MurmurHash3_x86_32 values of the little-endian key
+    (8 bytes for K <= 32; 16 bytes for K = 33..64)."""
+    b = key.to_bytes(nbytes, "little")
     hi = murmurhash3_32(b, seed=2 * a - 2, positive=True)
     lo = murmurhash3_32(b, seed=2 * a - 1, positive=True)
     return (hi << 32) | lo
@@ -33,7 +34,8 @@ def canonical_str(window: str) -> int:
     """Sec. 2.3: the strand whose hash is smaller (ties: reverse complement)."""
     f = key_of(window)
     r = key_of(revcomp_str(window))
-    return f if h64(f) < h64(r) else r
+    nb = 16 if len(window) > 32 else 8
+    return f if h64(f, 1, nb) < h64(r, 1, nb) else r
 
 
 def windows(reads: list[str], k: int):
