@@ -14,13 +14,18 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls marked "async" only enqueue work on that stream; results are
  *    valid once the stream has reached them.
- *  - k-mers are 2-bit keys in a uint64: A=0, C=1, G=2, T=3, first base most
- *    significant, K <= 32.  Reads are ASCII bytes; any byte other than
+ *  - k-mers are 2-bit keys: A=0, C=1, G=2, T=3, first base most significant.
+ *    For K <= 32 a key is one uint64.  For K = 33..64 (the paper's 55-mers,
+ *    Sec. 4) it is a 128-bit integer stored as two uint64 words, low word
+ *    first, in every key array (capacities still count keys); such keys are
+ *    taken by the binned insertion paths, kc_classify and kc_query (not the
+ *    direct path, the batched form or the server: KC_EINVAL).
+ *    Reads are ASCII bytes; any byte other than
  *    'A','C','G','T' (upper case) is an invalid base and every window that
  *    contains one is skipped.  Windows never span two reads.
  *  - Hash functions: H_a(x) = (MM3(x, 2a-2) << 32) | MM3(x, 2a-1), with MM3
- *    = MurmurHash3_x86_32 over the 8-byte little-endian key (the paper names
- *    the murmur hash, Sec. 3).  Canonical k-mer = the strand with the smaller
+ *    = MurmurHash3_x86_32 over the 8-byte little-endian key (16 bytes, low
+ *    word first, for K > 32; the paper names the murmur hash, Sec. 3).  Canonical k-mer = the strand with the smaller
  *    H_1 (Sec. 2.3 equation; a tie keeps the reverse complement).
  *  - Slot of a k-mer for hash function a (Algorithm 3): h = H_a(canonical),
  *    cell (i, j) = (h mod X, h mod Y) stored row-major at word i*Y + j,
@@ -142,8 +147,9 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases);
  *              offsets must be non-decreasing and offsets[n_reads] must equal
  *              n_bases (not checked on the device; offsets outside the read
  *              buffer only change results, never the memory touched).
- * k            k-mer length, 1..32; every insert into one filter must use the
- *              same k (else KC_ESTATE).
+ * k            k-mer length, 1..64 (33..64: two-word keys, binned paths only);
+ *              every insert into one filter must use the same k (else
+ *              KC_ESTATE).
  * distinct_dev receives this call's distinct k-mers (canonical keys) in
  *              first-seen order (reads in input order, windows by start
  *              position), appended at index *n_distinct_dev.
@@ -183,14 +189,16 @@ kc_status kc_insert_classify(kc_filter *f, const uint8_t *reads_dev, const uint6
  * and its device count); n = min(*n_keys_dev, keys_cap) keys are used.
  * trust_dev, err_dev: outputs with room for n keys each; the order of
  * keys_dev is kept in both.  *n_trust_dev, *n_err_dev are overwritten with
- * the counts.  frequency > tau -> trustworthy, else erroneous. */
+ * the counts.  frequency > tau -> trustworthy, else erroneous.  Keys take
+ * two words each when the filter's inserts used k > 32. */
 kc_status kc_classify(kc_filter *f, const uint64_t *keys_dev, const uint64_t *n_keys_dev,
                       uint64_t keys_cap, uint32_t tau, uint64_t *trust_dev,
                       uint64_t *n_trust_dev, uint64_t *err_dev, uint64_t *n_err_dev,
                       void *stream);
 
 /* Query-II (Algorithm 5) for n canonical keys, async: freq_dev[i] = 0 if any
- * of the key's k_h counters is 0, else their minimum. */
+ * of the key's k_h counters is 0, else their minimum.  Keys take two words
+ * each (2n words) when the filter's inserts used k > 32. */
 kc_status kc_query(kc_filter *f, const uint64_t *keys_dev, uint64_t n, uint32_t *freq_dev,
                    void *stream);
 

@@ -226,6 +226,11 @@ class CountBF:
         return (d.reshape(-1, 2) if w == 2 else d), int(nw.value)
 
     def query(self, keys):
+        if np.ndim(keys) == 2:  # (low, high) pairs of k > 32 keys
+            L = lib()
+            w = _p(self.words, ctypes.c_uint64)
+            return np.array([L.kco_query_wide(ctypes.byref(self.layout), w, int(lo), int(hi))
+                             for lo, hi in np.asarray(keys, dtype=np.uint64)], dtype=np.uint64)
         keys, kp = _u64(keys)
         out = np.zeros(max(1, len(keys)), dtype=np.uint64)
         rc = lib().kco_query_many(ctypes.byref(self.layout), _p(self.words, ctypes.c_uint64),

@@ -371,6 +371,8 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     const bool binned = choose_plan(f, n_bases, plan, bchunk);
     if (f->path == KcPath::Binned && !binned)
         return KC_EINVAL;  // forced binned path but the filter does not fit it
+    if (k > 32 && !binned)
+        return KC_EINVAL;  // k-mers of 33..64 bases take the binned paths only
     if (binned) {
         if ((st = ensure_plan(f, plan, bchunk)) != KC_OK)
             return st;
@@ -407,7 +409,7 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         // base saved by the distinct output step
         e = kc::launch_classify(f->F, distinct, n_distinct, f->W->totals + 3, n_bases, cap_d, tau,
                                 trust, n_trust, err, n_err, cap_te, f->status, *f->W, s,
-                                &f->prof);
+                                &f->prof, k > 32);
         if (e != hipSuccess)
             return KC_EDEVICE;
     }
@@ -545,7 +547,7 @@ kc_status kc_insert(kc_filter *f, const uint8_t *reads_dev, const uint64_t *offs
                     uint64_t n_reads, uint64_t n_bases, uint32_t k, uint64_t *distinct_dev,
                     uint64_t distinct_cap, uint64_t *n_distinct_dev, uint64_t *n_windows_dev,
                     void *stream) {
-    if (!f || k < 1 || k > 32 || !n_distinct_dev)
+    if (!f || k < 1 || k > 64 || !n_distinct_dev)
         return KC_EINVAL;
     if (n_bases > 0 && (!reads_dev || !offsets_dev))
         return KC_EINVAL;
@@ -567,7 +569,7 @@ kc_status kc_insert_classify(kc_filter *f, const uint8_t *reads_dev, const uint6
                              uint64_t *n_distinct_dev, uint64_t *n_windows_dev,
                              uint64_t *trust_dev, uint64_t *n_trust_dev, uint64_t *err_dev,
                              uint64_t *n_err_dev, uint64_t class_cap, void *stream) {
-    if (!f || k < 1 || k > 32 || !n_distinct_dev || !n_trust_dev || !n_err_dev)
+    if (!f || k < 1 || k > 64 || !n_distinct_dev || !n_trust_dev || !n_err_dev)
         return KC_EINVAL;
     if (n_bases > 0 && (!reads_dev || !offsets_dev))
         return KC_EINVAL;
@@ -605,7 +607,7 @@ kc_status kc_classify(kc_filter *f, const uint64_t *keys_dev, const uint64_t *n_
         return st;
     hipError_t e = kc::launch_classify(f->F, keys_dev, n_keys_dev, nullptr, keys_cap, keys_cap,
                                        tau, trust_dev, n_trust_dev, err_dev, n_err_dev, keys_cap,
-                                       nullptr, *f->W, s, &f->prof);
+                                       nullptr, *f->W, s, &f->prof, f->k > 32);
     return e == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
@@ -618,8 +620,9 @@ kc_status kc_query(kc_filter *f, const uint64_t *keys_dev, uint64_t n, uint32_t 
         return KC_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     f->last = s;
-    return kc::launch_query(f->F, keys_dev, n, freq_dev, s, &f->prof) == hipSuccess ? KC_OK
-                                                                                    : KC_EDEVICE;
+    return kc::launch_query(f->F, keys_dev, n, freq_dev, s, &f->prof, f->k > 32) == hipSuccess
+               ? KC_OK
+               : KC_EDEVICE;
 }
 
 kc_status kc_sync(kc_filter *f) {

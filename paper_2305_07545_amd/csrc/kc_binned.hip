@@ -181,6 +181,110 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
         atomicAdd(n_valid, (unsigned long long)s_valid);
 }
 
+// The same for k-mers of 33..64 bases (128-bit keys).
+template <bool kParts>
+__device__ __forceinline__ void bin_window_wide(const FilterArgs &F, const BinPlan &B,
+                                                Key128 fwd, uint32_t K, uint64_t q, uint64_t len,
+                                                uint32_t *__restrict__ slots,
+                                                uint8_t *__restrict__ parts, uint32_t *s_hist) {
+    const uint32_t shift = B.region_shift;
+    const uint64_t smask = (1ull << shift) - 1ull;
+    const CanonWide c = canonical_wide(fwd, K);
+    for (uint32_t a = 1; a <= F.k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        slot_of(F, a == 1 ? c.h1 : hash_a_wide(c.b, a), word, l);
+        const uint32_t r = (uint32_t)(word >> shift);
+        const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
+        const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
+        const uint64_t at = (uint64_t)(a - 1) * len + q;
+        slots[at] = id;
+        if (kParts) {
+            parts[at] = (uint8_t)(r >> B.part_log);
+            atomicAdd(&s_hist[r >> B.part_log], 1u);
+        } else {
+            atomicAdd(&s_hist[r], 1u);
+        }
+    }
+}
+
+// k_bin_count for k-mers of 33..64 bases: each lane reads its own window
+// (five code words, 64-bit validity masks) and the ring holds 128-bit keys;
+// everything else is k_bin_count's.
+template <bool kParts>
+__global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsArgs R, uint64_t c0,
+                                                           uint64_t c1, BinPlan B,
+                                                           uint32_t *__restrict__ slots,
+                                                           uint8_t *__restrict__ parts,
+                                                           uint32_t *__restrict__ fine,
+                                                           uint32_t *__restrict__ coarse,
+                                                           unsigned long long *__restrict__ n_valid) {
+    constexpr uint32_t kRing = 128;
+    extern __shared__ uint32_t s_hist[];
+    __shared__ uint64_t s_klo[kBinWG / 64][kRing];
+    __shared__ uint64_t s_khi[kBinWG / 64][kRing];
+    __shared__ uint32_t s_pos[kBinWG / 64][kRing];
+    __shared__ uint32_t s_valid;
+    const uint32_t n_keys = kParts ? B.n_parts : B.n_regions;
+    for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
+        s_hist[i] = 0;
+    if (threadIdx.x == 0)
+        s_valid = 0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = wave_id();
+    const uint64_t len = c1 - c0;
+    const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
+    const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
+    uint32_t nv = 0;
+    uint32_t head = 0, queued = 0;
+    for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
+        const uint64_t p = pb + lane;
+        const bool in = p < g1;
+        const bool valid = in && window_valid_wide(R, p);
+        if (!valid && in)
+            for (uint32_t a = 1; a <= F.k_h; a++)
+                slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
+        const uint64_t m = __ballot(valid);
+        if (valid) {
+            const Key128 fwd = window_key_wide(R.codes, p, R.k);
+            nv++;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t at = (head + queued + rank) & (kRing - 1u);
+            s_klo[wv][at] = fwd.lo;
+            s_khi[wv][at] = fwd.hi;
+            s_pos[wv][at] = (uint32_t)(p - c0);
+        }
+        queued += (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        if (queued >= 64u) {
+            const uint32_t at = (head + lane) & (kRing - 1u);
+            const Key128 key{s_klo[wv][at], s_khi[wv][at]};
+            const uint32_t q = s_pos[wv][at];
+            __builtin_amdgcn_wave_barrier();
+            head = (head + 64u) & (kRing - 1u);
+            queued -= 64u;
+            bin_window_wide<kParts>(F, B, key, R.k, q, len, slots, parts, s_hist);
+        }
+    }
+    if (lane < queued) {
+        const uint32_t at = (head + lane) & (kRing - 1u);
+        bin_window_wide<kParts>(F, B, Key128{s_klo[wv][at], s_khi[wv][at]}, R.k, s_pos[wv][at],
+                                len, slots, parts, s_hist);
+    }
+    atomicAdd(&s_valid, nv);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
+        fine[kParts ? (uint64_t)i * B.G + blockIdx.x : (uint64_t)blockIdx.x * n_keys + i] =
+            s_hist[i];
+    if (!kParts)
+        write_bucket_sums(s_hist, B.n_regions, B.n_buckets, B.bucket_shift, B.G, coarse,
+                          blockIdx.x);
+    if (threadIdx.x == 0)
+        atomicAdd(n_valid, (unsigned long long)s_valid);
+}
+
 // Level 1: slot ids of this workgroup's positions -> runs of the bucket list.
 // A batch holds kStage1 entries: the thread's kPer entries stay in registers
 // between counting, staging and writing.  The pass runs one workgroup per
@@ -928,9 +1032,14 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     const uint64_t n_pmat = (uint64_t)B.n_parts * B.G;
     if (P)
         P->begin(kPhBinCount, s);
-    hipLaunchKernelGGL(k_bin_count<true>, dim3(B.G), dim3(kBinWG),
-                       (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
-                       W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
+    if (R.k > 32)
+        hipLaunchKernelGGL(k_bin_count_wide<true>, dim3(B.G), dim3(kBinWG),
+                           (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
+                           W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
+    else
+        hipLaunchKernelGGL(k_bin_count<true>, dim3(B.G), dim3(kBinWG),
+                           (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
+                           W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -1045,9 +1154,14 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
     if (P)
         P->begin(kPhBinCount, s);
-    hipLaunchKernelGGL(k_bin_count<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
-                       W.slots, nullptr, W.matrix_t, W.coarse,
-                       (unsigned long long *)(W.totals + 5));
+    if (R.k > 32)
+        hipLaunchKernelGGL(k_bin_count_wide<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1,
+                           B, W.slots, nullptr, W.matrix_t, W.coarse,
+                           (unsigned long long *)(W.totals + 5));
+    else
+        hipLaunchKernelGGL(k_bin_count<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
+                           W.slots, nullptr, W.matrix_t, W.coarse,
+                           (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();

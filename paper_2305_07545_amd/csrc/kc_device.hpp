@@ -340,6 +340,131 @@ KC_HD bool wave_window(const WaveWords &w, uint64_t pb, uint32_t lane, uint32_t 
     return (pb + lane + K <= n_bases) && ((iv & kmask) | (st & kmask & ~1u)) == 0;
 }
 
+// ----------------------------------------------------------------------------
+// K-mers of 33..64 bases: the 2-bit key is a 128-bit integer (first base most
+// significant), held as (lo, hi) and hashed as its 16 little-endian bytes,
+// low word first.
+// ----------------------------------------------------------------------------
+struct Key128 {
+    uint64_t lo, hi;
+};
+
+// The 32 2-bit groups of x in reverse order (a full bit reversal, then the
+// two bits of every group swapped back).
+KC_HD uint64_t reverse_groups(uint64_t x) {
+    uint64_t r = ((uint64_t)__builtin_bitreverse32((uint32_t)x) << 32) |
+                 __builtin_bitreverse32((uint32_t)(x >> 32));
+    return ((r >> 1) & 0x5555555555555555ull) | ((r & 0x5555555555555555ull) << 1);
+}
+
+// (hi:lo) >> sh for 0 <= sh < 64
+KC_HD Key128 shr128(uint64_t hi, uint64_t lo, uint32_t sh) {
+    Key128 k;
+    k.hi = hi >> sh;
+    k.lo = sh ? ((lo >> sh) | (hi << (64u - sh))) : lo;
+    return k;
+}
+
+// Reverse complement of a K-base key, 33 <= K <= 64: complement all 128 bits,
+// reverse the 64 groups, keep the K groups that came from the key.
+KC_HD Key128 revcomp_wide(Key128 x, uint32_t K) {
+    return shr128(reverse_groups(~x.lo), reverse_groups(~x.hi), 128u - 2u * K);
+}
+
+// Forward key of the K-base window at p (33 <= K <= 64): the 128 bits from
+// base p % 16 of codes[p/16] on, built from word pairs as in window_key, then
+// right-aligned.  Needs codes[p/16 + 4] to exist.
+KC_HD Key128 window_key_wide(const uint32_t *__restrict__ codes, uint64_t p, uint32_t K) {
+    const uint64_t m = p >> 4;
+    const uint32_t s = 2u * (uint32_t)(p & 15u);
+    const uint32_t w0 = codes[m], w1 = codes[m + 1], w2 = codes[m + 2], w3 = codes[m + 3],
+                   w4 = codes[m + 4];
+    const uint64_t t0 = ((((((uint64_t)w0 << 32) | w1) << s) >> 32) << 32) |
+                        (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32u - s));
+    const uint64_t t1 = ((((((uint64_t)w2 << 32) | w3) << s) >> 32) << 32) |
+                        (uint32_t)((((uint64_t)w3 << 32) | w4) >> (32u - s));
+    return shr128(t0, t1, 128u - 2u * K);
+}
+
+// 64 mask bits from position p on (words b, b+1, b+2 of a bitmap)
+KC_HD uint64_t mask64_at(const uint32_t *__restrict__ m, uint64_t p) {
+    const uint64_t b = p >> 5;
+    const uint32_t o = (uint32_t)(p & 31u);
+    const uint64_t x = ((uint64_t)m[b + 1] << 32) | m[b];
+    return o ? ((x >> o) | ((uint64_t)m[b + 2] << (64u - o))) : x;
+}
+
+// Validity of the K-base window at p for K <= 64 (the rule of window_valid).
+// Needs inv/rs[p/32 + 2] to exist.
+KC_HD bool window_valid_wide(const ReadsArgs &R, uint64_t p) {
+    if (p + R.k > R.n_bases)
+        return false;
+    const uint64_t kmask = R.k >= 64u ? ~0ull : ((1ull << R.k) - 1ull);
+    return ((mask64_at(R.inv, p) & kmask) | (mask64_at(R.rs, p) & kmask & ~1ull)) == 0;
+}
+
+// MurmurHash3_x86_32 of a 16-byte key from its four block mixes.
+KC_HD uint32_t mm3_seeded4(const uint32_t b[4], uint32_t seed) {
+    uint32_t h = seed;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        h ^= b[i];
+        h = rotl32(h, 13) * 5u + 0xe6546b64u;
+    }
+    h ^= 16u;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+KC_HD void key_blocks_wide(Key128 k, uint32_t b[4]) {
+    b[0] = mm3_block((uint32_t)k.lo);
+    b[1] = mm3_block((uint32_t)(k.lo >> 32));
+    b[2] = mm3_block((uint32_t)k.hi);
+    b[3] = mm3_block((uint32_t)(k.hi >> 32));
+}
+
+KC_HD uint64_t hash_a_wide(const uint32_t b[4], uint32_t a) {
+    return ((uint64_t)mm3_seeded4(b, 2u * a - 2u) << 32) | mm3_seeded4(b, 2u * a - 1u);
+}
+
+// Canonical 128-bit key and its H_1, as canonical_fast: the high words
+// (seed 0) of both strands decide unless equal; a tie of the full H_1 keeps
+// the reverse complement.
+struct CanonWide {
+    Key128 key;
+    uint64_t h1;
+    uint32_t b[4];
+};
+
+KC_HD CanonWide canonical_wide(Key128 fwd, uint32_t K) {
+    const Key128 rc = revcomp_wide(fwd, K);
+    uint32_t f[4], r[4];
+    key_blocks_wide(fwd, f);
+    key_blocks_wide(rc, r);
+    const uint32_t hf = mm3_seeded4(f, 0u), hr = mm3_seeded4(r, 0u);
+    bool take_fwd;
+    uint64_t Hf = 0, Hr = 0;
+    if (hf != hr) {
+        take_fwd = hf < hr;
+    } else {
+        Hf = ((uint64_t)hf << 32) | mm3_seeded4(f, 1u);
+        Hr = ((uint64_t)hr << 32) | mm3_seeded4(r, 1u);
+        take_fwd = Hf < Hr;
+    }
+    CanonWide c;
+    c.key = take_fwd ? fwd : rc;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        c.b[i] = take_fwd ? f[i] : r[i];
+    c.h1 = hf != hr ? (((uint64_t)(take_fwd ? hf : hr) << 32) | mm3_seeded4(c.b, 1u))
+                    : (take_fwd ? Hf : Hr);
+    return c;
+}
+
 // Saturating increment of counter l of a cell (64-bit CAS loop).  Returns
 // nothing; a saturated counter is left unchanged.
 __device__ __forceinline__ void saturating_increment(uint64_t *cell, uint32_t shift,

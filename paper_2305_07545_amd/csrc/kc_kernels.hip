@@ -224,6 +224,8 @@ __global__ void __launch_bounds__(kWG) k_tile_count(ReadsArgs R, const uint8_t *
 // first gathered into a wavefront-private list in position order (so that
 // only they are hashed), then each listed window's canonical key goes to the
 // distinct list and, when split, to the trustworthy or erroneous list.
+// kWide: k-mers of 33..64 bases, written as (low, high) word pairs.
+template <bool kWide>
 __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__restrict__ flags,
                                                  uint64_t n_tiles,
                                                  const uint64_t *__restrict__ off_d,
@@ -276,20 +278,35 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
         const uint64_t ot = split ? off_t[tile] : 0;
         for (uint32_t i = lane; i < tot_d; i += 64) {
             const uint64_t p = pos0 + lpos[i];
-            const uint64_t key = canonical_fast(window_key(R.codes, p, R.k), R.k).key;
+            uint64_t key, key_hi = 0;
+            if (kWide) {
+                const Key128 c = canonical_wide(window_key_wide(R.codes, p, R.k), R.k).key;
+                key = c.lo;
+                key_hi = c.hi;
+            } else {
+                key = canonical_fast(window_key(R.codes, p, R.k), R.k).key;
+            }
+            auto put = [&](uint64_t *out, uint64_t at) {
+                if (kWide) {
+                    out[2 * at] = key;
+                    out[2 * at + 1] = key_hi;
+                } else {
+                    out[at] = key;
+                }
+            };
             const uint64_t d = od + i;
             if (d < cap_d)
-                distinct[d] = key;
+                put(distinct, d);
             if (split) {
                 const uint32_t tb = ltb[i];
                 const uint64_t ti = ot + (tb & 0x7FFFu);  // trustworthy keys before this one
                 if (tb & 0x8000u) {
                     if (ti < cap_te)
-                        trust[ti] = key;
+                        put(trust, ti);
                 } else {
                     const uint64_t ei = (d - base) - ti;  // erroneous keys before this one
                     if (ei < cap_te)
-                        err[ei] = key;
+                        put(err, ei);
                 }
             }
         }
@@ -345,6 +362,31 @@ __device__ __forceinline__ uint64_t query_key(const FilterArgs &F, uint64_t key)
     return best;
 }
 
+// Query-II of a 33..64-base key (Algorithm 5 with the 16-byte hash)
+__device__ __forceinline__ uint64_t query_key_wide(const FilterArgs &F, Key128 key) {
+    uint32_t b[4];
+    key_blocks_wide(key, b);
+    uint64_t best = 0;
+    for (uint32_t a = 1; a <= F.k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        slot_of(F, hash_a_wide(b, a), word, l);
+        uint64_t v = read_counter(F, word, l);
+        if (v == 0)
+            return 0;
+        best = (a == 1 || v < best) ? v : best;
+    }
+    return best;
+}
+
+// Query-II of key i of a list: one uint64 per key, or (low, high) pairs.
+template <bool kWide>
+__device__ __forceinline__ uint64_t query_list(const FilterArgs &F, const uint64_t *keys,
+                                               uint64_t i) {
+    return kWide ? query_key_wide(F, Key128{keys[2 * i], keys[2 * i + 1]})
+                 : query_key(F, keys[i]);
+}
+
 // keys used: keys[b .. e), b = *key_base (0 when null), e = min(*n_keys, limit)
 __device__ __forceinline__ uint64_t key_count(const uint64_t *n_keys, const uint64_t *key_base,
                                               uint64_t limit, uint64_t &b) {
@@ -353,6 +395,7 @@ __device__ __forceinline__ uint64_t key_count(const uint64_t *n_keys, const uint
     return e > b ? e - b : 0;
 }
 
+template <bool kWide>
 __global__ void __launch_bounds__(kWG) k_classify_mark(FilterArgs F, const uint64_t *__restrict__ keys,
                                                        const uint64_t *__restrict__ n_keys,
                                                        const uint64_t *__restrict__ key_base,
@@ -362,7 +405,7 @@ __global__ void __launch_bounds__(kWG) k_classify_mark(FilterArgs F, const uint6
     __shared__ uint32_t s_cnt[kWG / 64];
     uint64_t b;
     const uint64_t n = key_count(n_keys, key_base, cap, b);
-    keys += b;
+    keys += kWide ? 2 * b : b;
     const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
@@ -377,7 +420,7 @@ __global__ void __launch_bounds__(kWG) k_classify_mark(FilterArgs F, const uint6
         uint64_t i = tile0 + (uint64_t)j * kWG + threadIdx.x;
         bool trust = false;
         if (i < n)
-            trust = query_key(F, keys[i]) > (uint64_t)tau;
+            trust = query_list<kWide>(F, keys, i) > (uint64_t)tau;
         uint64_t m = __ballot(trust);
         if (lane == 0) {
             tmask[(tile0 + (uint64_t)j * kWG) / 64 + wave] = m;
@@ -395,6 +438,7 @@ __global__ void __launch_bounds__(kWG) k_classify_mark(FilterArgs F, const uint6
     }
 }
 
+template <bool kWide>
 __global__ void __launch_bounds__(kWG) k_classify_scatter(const uint64_t *__restrict__ keys,
                                                           const uint64_t *__restrict__ n_keys,
                                                           const uint64_t *__restrict__ key_base,
@@ -406,10 +450,18 @@ __global__ void __launch_bounds__(kWG) k_classify_scatter(const uint64_t *__rest
                                                           uint64_t cap_out) {
     uint64_t b;
     const uint64_t n = key_count(n_keys, key_base, cap, b);
-    keys += b;
+    keys += kWide ? 2 * b : b;
     const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     if (tile0 >= n)
         return;
+    auto copy = [&](uint64_t *out, uint64_t at, uint64_t i) {
+        if (kWide) {
+            out[2 * at] = keys[2 * i];
+            out[2 * at + 1] = keys[2 * i + 1];
+        } else {
+            out[at] = keys[i];
+        }
+    };
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     const uint64_t *fw = tmask + tile0 / 64;
@@ -428,9 +480,9 @@ __global__ void __launch_bounds__(kWG) k_classify_scatter(const uint64_t *__rest
         uint64_t t_idx = base + before;  // trustworthy keys before i
         if ((word >> lane) & 1ull) {
             if (t_idx < cap_out)
-                trust[t_idx] = keys[i];
+                copy(trust, t_idx, i);
         } else if (i - t_idx < cap_out) {
-            err[i - t_idx] = keys[i];
+            copy(err, i - t_idx, i);
         }
     }
 }
@@ -450,11 +502,12 @@ __global__ void k_finish_classify(const uint64_t *__restrict__ n_keys,
         atomicOr(status, kStatusRange);
 }
 
+template <bool kWide>
 __global__ void k_query(FilterArgs F, const uint64_t *__restrict__ keys, uint64_t n,
                         uint32_t *__restrict__ freq) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
-        freq[i] = (uint32_t)query_key(F, keys[i]);
+        freq[i] = (uint32_t)query_list<kWide>(F, keys, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,11 +622,16 @@ hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *dis
     }
     if (P)
         P->end(s);
-    if (e == hipSuccess)
-        e = launch(P, kPhScatter, k_compact, grid, dim3(kWG), s, R, (const uint8_t *)W.flags8,
-                   n_tiles, (const uint64_t *)W.off_a, (const uint64_t *)W.off_b,
-                   (const uint64_t *)(W.totals + 3), distinct, cap_d, trust, err, cap_te,
-                   split ? 1 : 0);
+    if (e == hipSuccess && R.k > 32)
+        e = launch(P, kPhScatter, k_compact<true>, grid, dim3(kWG), s, R,
+                   (const uint8_t *)W.flags8, n_tiles, (const uint64_t *)W.off_a,
+                   (const uint64_t *)W.off_b, (const uint64_t *)(W.totals + 3), distinct, cap_d,
+                   trust, err, cap_te, split ? 1 : 0);
+    else if (e == hipSuccess)
+        e = launch(P, kPhScatter, k_compact<false>, grid, dim3(kWG), s, R,
+                   (const uint8_t *)W.flags8, n_tiles, (const uint64_t *)W.off_a,
+                   (const uint64_t *)W.off_b, (const uint64_t *)(W.totals + 3), distinct, cap_d,
+                   trust, err, cap_te, split ? 1 : 0);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_finish_insert, dim3(1), dim3(64), 0, s, n_distinct, n_windows,
                            split ? n_trust : (uint64_t *)nullptr, n_err,
@@ -588,23 +646,31 @@ hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint
                            const uint64_t *key_base, uint64_t grid_cap, uint64_t cap,
                            uint32_t tau, uint64_t *trust, uint64_t *n_trust, uint64_t *err,
                            uint64_t *n_err, uint64_t cap_out, uint32_t *status,
-                           const Workspace &W, hipStream_t s, Profiler *P) {
+                           const Workspace &W, hipStream_t s, Profiler *P, bool wide) {
     // `cap` bounds the key buffer (keys[.. cap)); grid_cap >= the number of
     // keys classified sizes the grid
     uint64_t n_tiles = (grid_cap + kTile - 1) / kTile;
     if (n_tiles == 0)
         n_tiles = 1;
-    hipError_t e = launch(P, kPhClassifyMark, k_classify_mark, dim3((unsigned)n_tiles), dim3(kWG),
-                          s, F, keys, n_keys, key_base, cap, tau, W.tmask, W.tile_a);
+    hipError_t e = wide ? launch(P, kPhClassifyMark, k_classify_mark<true>,
+                                 dim3((unsigned)n_tiles), dim3(kWG), s, F, keys, n_keys, key_base,
+                                 cap, tau, W.tmask, W.tile_a)
+                        : launch(P, kPhClassifyMark, k_classify_mark<false>,
+                                 dim3((unsigned)n_tiles), dim3(kWG), s, F, keys, n_keys, key_base,
+                                 cap, tau, W.tmask, W.tile_a);
     if (P)
         P->begin(kPhScan, s);
     if (e == hipSuccess)
         e = scan_u32_u64(W.tile_a, W.off_a, n_tiles, nullptr, W.totals + 4, W.partial64, s);
     if (P)
         P->end(s);
-    if (e == hipSuccess)
-        e = launch(P, kPhClassifyScatter, k_classify_scatter, dim3((unsigned)n_tiles), dim3(kWG),
-                   s, keys, n_keys, key_base, cap, (const uint64_t *)W.tmask,
+    if (e == hipSuccess && wide)
+        e = launch(P, kPhClassifyScatter, k_classify_scatter<true>, dim3((unsigned)n_tiles),
+                   dim3(kWG), s, keys, n_keys, key_base, cap, (const uint64_t *)W.tmask,
+                   (const uint64_t *)W.off_a, trust, err, cap_out);
+    else if (e == hipSuccess)
+        e = launch(P, kPhClassifyScatter, k_classify_scatter<false>, dim3((unsigned)n_tiles),
+                   dim3(kWG), s, keys, n_keys, key_base, cap, (const uint64_t *)W.tmask,
                    (const uint64_t *)W.off_a, trust, err, cap_out);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_finish_classify, dim3(1), dim3(64), 0, s, n_keys, key_base, cap,
@@ -615,10 +681,13 @@ hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint
 }
 
 hipError_t launch_query(const FilterArgs &F, const uint64_t *keys, uint64_t n, uint32_t *freq,
-                        hipStream_t s, Profiler *P) {
+                        hipStream_t s, Profiler *P, bool wide) {
     if (n == 0)
         return hipSuccess;
-    return launch(P, kPhQuery, k_query, dim3(grid_for(n, 256)), dim3(256), s, F, keys, n, freq);
+    return wide ? launch(P, kPhQuery, k_query<true>, dim3(grid_for(n, 256)), dim3(256), s, F, keys,
+                         n, freq)
+                : launch(P, kPhQuery, k_query<false>, dim3(grid_for(n, 256)), dim3(256), s, F,
+                         keys, n, freq);
 }
 
 }  // namespace kc

@@ -189,8 +189,9 @@ hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint
                            const uint64_t *key_base, uint64_t grid_cap, uint64_t cap,
                            uint32_t tau, uint64_t *trust, uint64_t *n_trust, uint64_t *err,
                            uint64_t *n_err, uint64_t cap_out, uint32_t *status,
-                           const Workspace &W, hipStream_t s, Profiler *P);
+                           const Workspace &W, hipStream_t s, Profiler *P, bool wide = false);
+// wide: keys of 33..64 bases, (low, high) word pairs
 hipError_t launch_query(const FilterArgs &F, const uint64_t *keys, uint64_t n, uint32_t *freq,
-                        hipStream_t s, Profiler *P);
+                        hipStream_t s, Profiler *P, bool wide = false);
 
 }  // namespace kc

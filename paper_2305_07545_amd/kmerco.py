@@ -173,6 +173,11 @@ def dims(n_items: float, fpp: float = 0.001):
 KC_FASTX_ONE_SEQUENCE = 1
 
 
+def key_words(k) -> int:
+    """uint64 words per k-mer key: 1 for k <= 32, 2 (low, high) for 33..64."""
+    return 2 if k is not None and k > 32 else 1
+
+
 def parse_fastx(data, one_sequence: bool = False):
     """FASTA or FASTQ text (bytes-like or a uint8 numpy array, host memory)
     -> (reads uint8, offsets uint64) for the insert calls, by
@@ -255,6 +260,7 @@ class CountBF:
             _check(self.lib.kc_create(ctypes.byref(self.layout), _ptr(words), int(zero),
                                       _stream_ptr(stream), ctypes.byref(h)), "kc_create")
         self._h = h
+        self.k = None  # k of the inserts (keys of k > 32 bases take two words)
         self.n_distinct = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.n_windows = torch.zeros(1, dtype=torch.int64, device=self.device)
 
@@ -287,16 +293,18 @@ class CountBF:
         n_bases = reads.numel()
         if n_reads < 0:
             raise ValueError("offsets needs n_reads + 1 entries")
+        w = key_words(k)
         if distinct is None:
-            distinct = torch.empty(max(1, n_bases), dtype=torch.int64, device=self.device)
+            distinct = torch.empty(max(1, n_bases) * w, dtype=torch.int64, device=self.device)
         _require(distinct, torch.int64, "distinct")
-        cap = distinct.numel() if distinct_cap is None else int(distinct_cap)
+        cap = distinct.numel() // w if distinct_cap is None else int(distinct_cap)
         n_distinct = self.n_distinct if n_distinct is None else n_distinct
         n_windows = self.n_windows if n_windows is None else n_windows
         with torch.cuda.device(self.device):
             _check(self.lib.kc_insert(self._h, _ptr(reads), _ptr(offsets), n_reads, n_bases, k,
                                       _ptr(distinct), cap, _ptr(n_distinct), _ptr(n_windows),
                                       _stream_ptr(stream)), "kc_insert")
+        self.k = k
         return distinct
 
     def insert_classify(self, reads, offsets, k: int, tau: int, distinct=None, trust=None,
@@ -311,7 +319,8 @@ class CountBF:
         n_bases = reads.numel()
         if n_reads < 0:
             raise ValueError("offsets needs n_reads + 1 entries")
-        room = max(1, n_bases)
+        w = key_words(k)
+        room = max(1, n_bases) * w
         if distinct is None:
             distinct = torch.empty(room, dtype=torch.int64, device=self.device)
         if trust is None:
@@ -320,7 +329,7 @@ class CountBF:
             err = torch.empty(room, dtype=torch.int64, device=self.device)
         for t, nm in ((distinct, "distinct"), (trust, "trust"), (err, "err")):
             _require(t, torch.int64, nm)
-        cap_te = min(trust.numel(), err.numel()) if class_cap is None else int(class_cap)
+        cap_te = min(trust.numel(), err.numel()) // w if class_cap is None else int(class_cap)
         n_distinct = self.n_distinct if n_distinct is None else n_distinct
         n_windows = self.n_windows if n_windows is None else n_windows
         if n_trust is None:
@@ -330,9 +339,10 @@ class CountBF:
         with torch.cuda.device(self.device):
             _check(self.lib.kc_insert_classify(
                 self._h, _ptr(reads), _ptr(offsets), n_reads, n_bases, k, int(tau),
-                _ptr(distinct), distinct.numel(), _ptr(n_distinct), _ptr(n_windows),
+                _ptr(distinct), distinct.numel() // w, _ptr(n_distinct), _ptr(n_windows),
                 _ptr(trust), _ptr(n_trust), _ptr(err), _ptr(n_err), cap_te,
                 _stream_ptr(stream)), "kc_insert_classify")
+        self.k = k
         return distinct, trust, n_trust, err, n_err
 
     def classify(self, keys, n_keys, tau: int, trust=None, err=None, n_trust=None, n_err=None,
@@ -340,11 +350,12 @@ class CountBF:
         """Classification phase (async); returns (trust, n_trust, err, n_err)
         device tensors."""
         _require(keys, torch.int64, "keys")
-        cap = keys.numel() if keys_cap is None else int(keys_cap)
+        w = key_words(self.k)
+        cap = keys.numel() // w if keys_cap is None else int(keys_cap)
         if trust is None:
-            trust = torch.empty(max(1, cap), dtype=torch.int64, device=self.device)
+            trust = torch.empty(max(1, cap) * w, dtype=torch.int64, device=self.device)
         if err is None:
-            err = torch.empty(max(1, cap), dtype=torch.int64, device=self.device)
+            err = torch.empty(max(1, cap) * w, dtype=torch.int64, device=self.device)
         if n_trust is None:
             n_trust = torch.zeros(1, dtype=torch.int64, device=self.device)
         if n_err is None:
@@ -357,17 +368,19 @@ class CountBF:
 
     def query(self, keys, freq=None, stream=None):
         _require(keys, torch.int64, "keys")
+        n = keys.numel() // key_words(self.k)
         if freq is None:
-            freq = torch.empty(max(1, keys.numel()), dtype=torch.int32, device=self.device)
+            freq = torch.empty(max(1, n), dtype=torch.int32, device=self.device)
         with torch.cuda.device(self.device):
-            _check(self.lib.kc_query(self._h, _ptr(keys), keys.numel(), _ptr(freq),
-                                     _stream_ptr(stream)), "kc_query")
-        return freq[:keys.numel()]
+            _check(self.lib.kc_query(self._h, _ptr(keys), n, _ptr(freq), _stream_ptr(stream)),
+                   "kc_query")
+        return freq[:n]
 
     def reset(self, stream=None):
         """Clear the countBF (async): empty filter, k unset."""
         with torch.cuda.device(self.device):
             _check(self.lib.kc_reset(self._h, _stream_ptr(stream)), "kc_reset")
+        self.k = None
 
     def profile(self, enable: bool = True, phases=None):
         """Time every phase (or only the named ones) of the following calls."""
@@ -412,8 +425,11 @@ def run_kmerco(reads, offsets, k: int, tau: int, X: int, Y: int, alpha: int = 8,
     nd = int(bf.n_distinct.item())
     nt = int(n_trust.item())
     ne = int(n_err.item())
+    w = key_words(k)
     u = lambda t: t.cpu().numpy().view("uint64")  # noqa: E731
-    out = (u(bf.words), u(distinct[:nd]), u(trust[:nt]), u(err[:ne]), int(bf.n_windows.item()))
+    lst = lambda t, n: u(t[:n * w]).reshape(-1, 2) if w == 2 else u(t[:n])  # noqa: E731
+    out = (u(bf.words), lst(distinct, nd), lst(trust, nt), lst(err, ne),
+           int(bf.n_windows.item()))
     bf.close()
     return out
 

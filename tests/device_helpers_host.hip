@@ -94,3 +94,39 @@ uint64_t kch_canonical_fast(uint64_t fwd, uint32_t K, uint64_t *h1) {
     return c.key;
 }
 }
+
+extern "C" {
+
+void kch_window_key_wide(const uint32_t *codes, uint64_t p, uint32_t K, uint64_t *lo,
+                         uint64_t *hi) {
+    kc::Key128 k = kc::window_key_wide(codes, p, K);
+    *lo = k.lo;
+    *hi = k.hi;
+}
+
+int kch_window_valid_wide(const uint32_t *codes, const uint32_t *inv, const uint32_t *rs,
+                          uint64_t n_bases, uint32_t k, uint64_t p) {
+    kc::ReadsArgs R{codes, inv, rs, n_bases, k};
+    return kc::window_valid_wide(R, p) ? 1 : 0;
+}
+
+void kch_revcomp_wide(uint64_t lo, uint64_t hi, uint32_t K, uint64_t *olo, uint64_t *ohi) {
+    kc::Key128 k = kc::revcomp_wide(kc::Key128{lo, hi}, K);
+    *olo = k.lo;
+    *ohi = k.hi;
+}
+
+uint64_t kch_hash_wide(uint64_t lo, uint64_t hi, uint32_t a) {
+    uint32_t b[4];
+    kc::key_blocks_wide(kc::Key128{lo, hi}, b);
+    return kc::hash_a_wide(b, a);
+}
+
+void kch_canonical_wide(uint64_t lo, uint64_t hi, uint32_t K, uint64_t *clo, uint64_t *chi,
+                        uint64_t *h1) {
+    kc::CanonWide c = kc::canonical_wide(kc::Key128{lo, hi}, K);
+    *clo = c.key.lo;
+    *chi = c.key.hi;
+    *h1 = c.h1;
+}
+}

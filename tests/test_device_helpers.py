@@ -40,6 +40,17 @@ def H(tmp_path_factory):
     L.kch_base.argtypes = [u32, ctypes.POINTER(u32)]; L.kch_base.restype = ctypes.c_int
     L.kch_wave_window.argtypes = [p32, p32, p32, u64, u32, u64, ctypes.POINTER(u64)]
     L.kch_wave_window.restype = ctypes.c_int
+    pu64 = ctypes.POINTER(u64)
+    L.kch_window_key_wide.argtypes = [p32, u64, u32, pu64, pu64]
+    L.kch_window_key_wide.restype = None
+    L.kch_window_valid_wide.argtypes = [p32, p32, p32, u64, u32, u64]
+    L.kch_window_valid_wide.restype = ctypes.c_int
+    L.kch_revcomp_wide.argtypes = [u64, u64, u32, pu64, pu64]
+    L.kch_revcomp_wide.restype = None
+    L.kch_hash_wide.argtypes = [u64, u64, u32]
+    L.kch_hash_wide.restype = u64
+    L.kch_canonical_wide.argtypes = [u64, u64, u32, pu64, pu64, pu64]
+    L.kch_canonical_wide.restype = None
     L.kch_canonical_fast.argtypes = [u64, u32, ctypes.POINTER(u64)]
     L.kch_canonical_fast.restype = u64
     return L
@@ -199,3 +210,54 @@ def test_window_extraction_matches_brute_force(H):
             assert wv == v, (K, p)
             if v:
                 assert fw.value == brute.key_of(buf[p:p + K].decode())
+
+
+def _wide(lo, hi):
+    return int(lo) | (int(hi) << 64)
+
+
+def test_wide_window_extraction_matches_brute_force(H):
+    """Keys of 33..64 bases from the packed layout: validity and the 128-bit
+    key of every window, against Python strings."""
+    rng = np.random.default_rng(15)
+    reads = []
+    for _ in range(25):
+        ln = int(rng.integers(0, 200))
+        reads.append("".join(rng.choice(list("ACGTN"), p=[.245, .245, .245, .245, .02], size=ln)))
+    buf = "".join(reads).encode()
+    starts = np.cumsum([0] + [len(r) for r in reads])[:-1]
+    codes, inv, rs = _pack(buf, starts)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))  # noqa: E731
+    lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+    for K in (33, 40, 55, 63, 64):
+        valid = set()
+        for r, o in zip(reads, starts):
+            for p in range(len(r) - K + 1):
+                if all(c in "ACGT" for c in r[p:p + K]):
+                    valid.add(int(o) + p)
+        for p in range(len(buf)):
+            v = H.kch_window_valid_wide(P(codes), P(inv), P(rs), len(buf), K, p)
+            assert v == (p in valid), (K, p)
+            if v:
+                H.kch_window_key_wide(P(codes), p, K, ctypes.byref(lo), ctypes.byref(hi))
+                assert _wide(lo.value, hi.value) == brute.key_of(buf[p:p + K].decode()), (K, p)
+
+
+def test_wide_revcomp_hash_canonical(H):
+    rng = np.random.default_rng(16)
+    lo, hi, h1 = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    for K in (33, 47, 55, 64):
+        for _ in range(60):
+            s = "".join(rng.choice(list("ACGT"), size=K))
+            key = brute.key_of(s)
+            k_lo, k_hi = key & ((1 << 64) - 1), key >> 64
+            H.kch_revcomp_wide(k_lo, k_hi, K, ctypes.byref(lo), ctypes.byref(hi))
+            assert _wide(lo.value, hi.value) == brute.key_of(brute.revcomp_str(s))
+            for a in (1, 2, 8):
+                assert H.kch_hash_wide(k_lo, k_hi, a) == brute.h64(key, a, 16)
+            H.kch_canonical_wide(k_lo, k_hi, K, ctypes.byref(lo), ctypes.byref(hi),
+                                 ctypes.byref(h1))
+            c = brute.canonical_str(s)
+            assert _wide(lo.value, hi.value) == c
+            assert h1.value == brute.h64(c, 1, 16)
+
