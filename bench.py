@@ -48,6 +48,10 @@ ALU_PEAK_GOPS = 256 * 64 * 2.4
 OPS_PER_WINDOW = 16 + 3 * 23 + 4 + 2 * 12 + 1 + 3
 # each further hash function H_a: 2 MurmurHash3 evaluations + its slot map
 OPS_PER_EXTRA_HASH = 2 * 23 + 2 * 12 + 1 + 3
+# k-mers of 33..64 bases: 128-bit keys (4 words) rolled for both strands
+# (2 x 16), MurmurHash3 over 16 bytes (4 blocks: 37 ops), a 4-word select (6)
+OPS_PER_WINDOW_WIDE = 2 * 16 + 3 * 37 + 6 + 2 * 12 + 1 + 3
+OPS_PER_EXTRA_HASH_WIDE = 2 * 37 + 2 * 12 + 1 + 3
 
 
 def parse():
@@ -60,6 +64,8 @@ def parse():
     ap.add_argument("--size", type=float, default=1.0,
                     help="countBF sized for this multiple of the workload's sizing count")
     ap.add_argument("--k-h", type=int, default=1, help="hash functions")
+    ap.add_argument("--k", type=int, default=0,
+                    help="k-mer length (0: the workload's own; 33..64 for two-word keys)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--cpu-sample-sets", type=int, default=64,
@@ -83,7 +89,7 @@ def sha(t) -> str:
 
 def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
                       n_words: int, n_chunks: int = 1, partitioned: bool = False,
-                      binned: bool = True) -> float:
+                      binned: bool = True, key_bytes: int = 8) -> float:
     """Bytes one step's launches of `phase` must move by their definition
     (logical accesses, not cache lines), summed over the step's launches:
     see the per-kernel table in the design notes."""
@@ -113,11 +119,11 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
     if phase == "ingest":            # ASCII in, packed codes + bitmaps out, flag bytes cleared
         return n_bases * 2.5
     if phase == "scatter":           # flag byte + packed input, keys out (distinct + split)
-        return n_bases * 1.5 + n_distinct * 16
+        return n_bases * 1.5 + n_distinct * 2 * key_bytes
     if phase == "classify_mark":     # key + cell per slot, mask out
-        return n_distinct * (8 + 8 * k_h + 0.125)
+        return n_distinct * (key_bytes + 8 * k_h + 0.125)
     if phase == "classify_scatter":  # key in, key out, mask
-        return n_distinct * (16 + 0.125)
+        return n_distinct * (2 * key_bytes + 0.125)
     return 0.0
 
 
@@ -148,7 +154,7 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def cpu_baseline(rs, X, Y, n_sample_reads):
+def cpu_baseline(rs, X, Y, n_sample_reads, k=0):
     """The oracle, as it is, on the first reads of the same workload with the
     same countBF dimensions, on one host core."""
     import oracle
@@ -156,7 +162,7 @@ def cpu_baseline(rs, X, Y, n_sample_reads):
     n = min(n_sample_reads, rs.n_reads)
     sub = rs.subset(0, n)
     t = time.perf_counter()
-    _, _, _, _, nw = oracle.run_kmerco(sub.reads, sub.offsets, rs.k, rs.tau, X, Y)
+    _, _, _, _, nw = oracle.run_kmerco(sub.reads, sub.offsets, k or rs.k, rs.tau, X, Y)
     secs = time.perf_counter() - t
     return {"value": nw / secs, "unit": "insertions/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} of {rs.n_reads} reads ({nw} k-mers), insert + classify, "
@@ -176,17 +182,19 @@ def set_baseline(n_sets: int):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def ops_per_window(k_h: int, alpha: int) -> int:
+def ops_per_window(k_h: int, alpha: int, k: int = 31) -> int:
     """Algorithmic integer ops per valid window: l = h mod eta is one AND
     when eta = 64 / alpha is a power of two, else a Barrett reduction
     (12 ops, like h mod X), once per hash function."""
     eta = 64 // alpha
     l_extra = 0 if eta & (eta - 1) == 0 else 11
-    return OPS_PER_WINDOW + l_extra + (k_h - 1) * (OPS_PER_EXTRA_HASH + l_extra)
+    first, extra = (OPS_PER_WINDOW_WIDE, OPS_PER_EXTRA_HASH_WIDE) if k > 32 else \
+        (OPS_PER_WINDOW, OPS_PER_EXTRA_HASH)
+    return first + l_extra + (k_h - 1) * (extra + l_extra)
 
 
 def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                n_chunks=1, partitioned=False, alpha=8):
+                n_chunks=1, partitioned=False, alpha=8, k=31):
     """Roofline of the phase with the largest total time: the hashing kernel
     against the integer-VALU peak (algorithmic ops per window), the others
     against HBM (algorithmic bytes), per launch over the average launch."""
@@ -195,17 +203,17 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
     dom = max(phases, key=lambda k: phases[k][0])
     avg_s = phases[dom][0] / phases[dom][1] / 1e3
     per_step = phases[dom][1] / max(1, steps)
-    traffic = traffic_for(dom, workload)
+    traffic = traffic_for(dom, workload) if k <= 32 else None
     if dom == "bin_count":
-        ops = n_windows * ops_per_window(k_h, alpha) / per_step
+        ops = n_windows * ops_per_window(k_h, alpha, k) / per_step
         achieved = ops / avg_s / 1e9
         return {"bound": "alu", "achieved": round(achieved, 1), "peak": round(ALU_PEAK_GOPS, 1),
                 "unit": "Gop/s", "frac": round(achieved / ALU_PEAK_GOPS, 4), "traffic": traffic,
                 "kernel": dom, "algorithmic_ops_per_launch": ops,
-                "ops_per_window": ops_per_window(k_h, alpha),
+                "ops_per_window": ops_per_window(k_h, alpha, k),
                 "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": per_step}
     nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                               partitioned) / per_step
+                               partitioned, key_bytes=8 if k <= 32 else 16) / per_step
     achieved = nbytes / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -215,19 +223,19 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
 
 
 def hbm_rooflines(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                  n_chunks=1, partitioned=False):
+                  n_chunks=1, partitioned=False, k=31):
     """The HBM roofline of every memory-bound phase (all but the hashing)."""
     out = {}
     for ph, (ms, launches) in phases.items():
         b = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                              partitioned)
+                              partitioned, key_bytes=8 if k <= 32 else 16)
         if ph == "bin_count" or b <= 0:
             continue
         per_step = launches / max(1, steps)
         avg_s = ms / launches / 1e3
         gbs = b / per_step / avg_s / 1e9
         out[ph] = {"achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                   "traffic": traffic_for(ph, workload)}
+                   "traffic": traffic_for(ph, workload) if k <= 32 else None}
     return out
 
 
@@ -491,13 +499,15 @@ def main():
     rs = synth.config(args.workload)
     X, Y = P.dims(rs.n_items * args.size)
     k_h, alpha = args.k_h, args.alpha
+    k = args.k or rs.k
+    w = P.key_words(k)  # words per key
     reads = torch.from_numpy(rs.reads).to(dev)
     offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
     n_bases = rs.n_bases
     cap = min(n_bases, 1 << 31)  # keys of room per output list (a shortfall raises)
-    distinct = torch.empty(cap, dtype=torch.int64, device=dev)
-    trust = torch.empty(cap, dtype=torch.int64, device=dev)
-    err = torch.empty(cap, dtype=torch.int64, device=dev)
+    distinct = torch.empty(cap * w, dtype=torch.int64, device=dev)
+    trust = torch.empty(cap * w, dtype=torch.int64, device=dev)
+    err = torch.empty(cap * w, dtype=torch.int64, device=dev)
     counters = torch.zeros(4, dtype=torch.int64, device=dev)  # distinct, windows, trust, err
     nd, nw, nt, ne = (counters[i:i + 1] for i in range(4))
     bf = P.CountBF(X, Y, alpha, k_h, device=dev)
@@ -507,7 +517,7 @@ def main():
     def step():
         bf.reset(stream)
         counters.zero_()
-        bf.insert_classify(reads, offs, rs.k, rs.tau, distinct=distinct, trust=trust, err=err,
+        bf.insert_classify(reads, offs, k, rs.tau, distinct=distinct, trust=trust, err=err,
                            n_distinct=nd, n_windows=nw, n_trust=nt, n_err=ne, stream=stream)
 
     for _ in range(args.warmup):
@@ -538,15 +548,17 @@ def main():
     n_distinct, n_windows, n_trust, n_err = (int(x) for x in counters.cpu().tolist())
     verified = None
     if not args.no_verify and (alpha, k_h, args.size) == (8, 1, 1.0):  # the digests' layout
-        ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_digests.json")
+        name = args.workload if k == rs.k else f"{args.workload}_k{k}"
+        ref_path = os.path.join(ROOT, "tests", "golden", f"{name}_digests.json")
         if os.path.exists(ref_path):
             ref = json.load(open(ref_path))
-            verified = (ref["X"] == X and ref["Y"] == Y and ref["n_windows"] == n_windows
+            verified = (ref["X"] == X and ref["Y"] == Y and ref["k"] == k
+                        and ref["n_windows"] == n_windows
                         and ref["n_distinct"] == n_distinct and ref["n_trust"] == n_trust
                         and sha(bf.words) == ref["words_sha256"]
-                        and sha(distinct[:n_distinct]) == ref["distinct_sha256"]
-                        and sha(trust[:n_trust]) == ref["trust_sha256"]
-                        and sha(err[:n_err]) == ref["err_sha256"])
+                        and sha(distinct[:n_distinct * w]) == ref["distinct_sha256"]
+                        and sha(trust[:n_trust * w]) == ref["trust_sha256"]
+                        and sha(err[:n_err * w]) == ref["err_sha256"])
 
     ms_step = elapsed * 1e3 / args.steps
     value = n_windows * args.steps / elapsed
@@ -559,7 +571,7 @@ def main():
     chunk = min(1 << 31, ((1 << 32) - 1) // k_h // 1024 * 1024) if partitioned else (1 << 28)
     n_chunks = (n_bases + chunk - 1) // chunk
     roofline = roofline_of(timed, args.steps, n_bases, n_windows, n_distinct, k_h, X * Y,
-                           args.workload, n_chunks, partitioned, alpha)
+                           args.workload, n_chunks, partitioned, alpha, k)
 
     out = {
         "metric": "k-mer insertions/s",
@@ -575,7 +587,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_reads": rs.n_reads, "n_bases": n_bases,
-                   "k": rs.k, "tau": rs.tau, "X": X, "Y": Y, "alpha": alpha, "k_h": k_h,
+                   "k": k, "tau": rs.tau, "X": X, "Y": Y, "alpha": alpha, "k_h": k_h,
                    "countbf_bytes": X * Y * 8, "n_windows": n_windows,
                    "n_distinct": n_distinct, "n_trust": n_trust, "n_err": n_err,
                    "parallelism": "single GPU"},
@@ -585,7 +597,7 @@ def main():
         "phases_profiled_steps": args.profile_steps,
         "hbm_rooflines": hbm_rooflines(phases, args.profile_steps, n_bases, n_windows,
                                        n_distinct, k_h, X * Y, args.workload, n_chunks,
-                                       partitioned),
+                                       partitioned, k),
     }
     bf.close()
     del reads, offs, distinct, trust, err
@@ -597,7 +609,7 @@ def main():
     if "serving" in forms:
         out["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(rs, X, Y, args.cpu_sample_reads)
+        out["cpu_baseline"] = cpu_baseline(rs, X, Y, args.cpu_sample_reads, k)
     print(json.dumps(out), flush=True)
 
 

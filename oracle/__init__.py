@@ -133,7 +133,7 @@ def mm3_32(data: bytes, seed: int) -> int:
 
 
 def hash_a(key: int, a: int, k: int = 32) -> int:
-    """H_a of a 2-bit key; keys of k > 32 bases (reading R10) as 16 bytes."""
+    """H_a of a 2-bit key; keys of k > 32 bases (reading R15) as 16 bytes."""
     if k > 32:
         return int(lib().kco_hash_wide(key & ((1 << 64) - 1), key >> 64, a))
     return int(lib().kco_hash(key, a))

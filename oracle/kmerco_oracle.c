@@ -35,7 +35,7 @@
  *       mask 0x00000000000000FF);
  *   R8  eta = floor(64 / alpha) counters per 64-bit cell (supplement table);
  *   R9  trustworthy iff frequency > tau, erroneous otherwise (Sec. 3);
- *   R10 K-mers of 33..64 bases (the paper's 55-mers, Sec. 4): the 2-bit key
+ *   R15 K-mers of 33..64 bases (the paper's 55-mers, Sec. 4): the 2-bit key
  *       is a 128-bit integer (first base most significant), hashed as its 16
  *       little-endian bytes (R1 with a 16-byte key), and stored as two
  *       uint64 words, low word first.
@@ -379,7 +379,7 @@ int kco_occurrences(const kco_layout *L, const uint8_t *reads, const uint64_t *o
 }
 
 /* ------------------------------------------------------------------------
- * K-mers of 33..64 bases (reading R10).  The same steps as above -- window
+ * K-mers of 33..64 bases (reading R15).  The same steps as above -- window
  * visiting order, reverse complement, canonical strand by H_1, Query-I
  * before the insert, Algorithm 3's saturating increments, Algorithm 2's
  * split -- on 128-bit keys.

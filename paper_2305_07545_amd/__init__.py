@@ -12,6 +12,7 @@ from .kmerco import (  # noqa: F401
     Server,
     dims,
     eta,
+    key_words,
     load_library,
     pack_read_sets,
     parse_fastx,

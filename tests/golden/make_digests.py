@@ -3,7 +3,7 @@
 Calls only ``oracle`` and ``synth``; the GPU parity tests compare the HIP
 path's outputs against these stored digests.  Usage:
 
-    python tests/golden/make_digests.py tiny bacterial batched
+    python tests/golden/make_digests.py tiny bacterial batched bacterial_k55
 
 The batched workload (256 independent read sets, each with its own countBF)
 is stored set by set; its sets run in parallel host processes.
@@ -28,14 +28,17 @@ def sha(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
 
 
-def digests(name: str, scale: float = 1.0) -> dict:
+def digests(name: str, scale: float = 1.0, k: int = 0) -> dict:
+    """k: the workload's own k when 0, else that k-mer length on its reads
+    (keys of k > 32 are digested as (low, high) word pairs)."""
     rs = synth.config(name, scale)
+    k = k or rs.k
     X, Y = oracle.dims(rs.n_items, 0.001)
     t = time.time()
-    words, distinct, trust, err, nw = oracle.run_kmerco(rs.reads, rs.offsets, rs.k, rs.tau, X, Y)
+    words, distinct, trust, err, nw = oracle.run_kmerco(rs.reads, rs.offsets, k, rs.tau, X, Y)
     secs = time.time() - t
     return {
-        "workload": name, "scale": scale, "k": rs.k, "tau": rs.tau, "X": X, "Y": Y,
+        "workload": name, "scale": scale, "k": k, "tau": rs.tau, "X": X, "Y": Y,
         "alpha": 8, "k_h": 1, "n_reads": rs.n_reads, "n_bases": rs.n_bases,
         "n_windows": nw, "n_distinct": len(distinct), "n_trust": len(trust), "n_err": len(err),
         "words_sha256": sha(words), "distinct_sha256": sha(distinct),
@@ -71,8 +74,10 @@ def batched_digests(scale: float = 1.0, workers: int = 8) -> dict:
 
 if __name__ == "__main__":
     oracle.build(force=False)
+    # names: tiny, bacterial, batched, large, or <workload>_k<k> (another k)
     for name in sys.argv[1:] or ["tiny", "bacterial"]:
-        d = batched_digests() if name == "batched" else digests(name)
+        base, _, kk = name.partition("_k")
+        d = batched_digests() if name == "batched" else digests(base, k=int(kk or 0))
         path = os.path.join(HERE, f"{name}_digests.json")
         with open(path, "w") as f:
             json.dump(d, f, indent=1)
