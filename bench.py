@@ -100,12 +100,13 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_bases * 5 * k_h + entries * 8
     if phase == "part_count":        # entries of the partition lists in
         return entries * 8
+    ent = 8 if partitioned else 6    # bytes per entry: the single-level path packs them in 6
     if phase == "bin_bucket":        # slot ids (or list entries) in, entries out
-        return entries * 16 if partitioned else n_bases * 4 * k_h + entries * 8
+        return entries * 16 if partitioned else n_bases * 4 * k_h + entries * ent
     if phase == "bin_region":        # entries in and out
-        return entries * 16
+        return entries * 2 * ent
     if phase == "region":            # entries in, countBF cells read + written per chunk, flags
-        return entries * 8 + n_chunks * n_words * 16 + n_distinct
+        return entries * ent + n_chunks * n_words * 16 + n_distinct
     if phase == "tile_count":        # flag byte per position (+ packed input when the
         return n_bases * (1.0 if binned else 1.5)  # insert passes did not count windows)
     if phase == "claim_increment":   # cell RMW + first-seen entry RMW per slot, packed input

@@ -64,6 +64,25 @@ __device__ __forceinline__ void write_bucket_sums(const uint32_t *s_hist, uint32
 }
 
 constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
+// Entries of the single-level binned path take 6 bytes, a 32-bit word and a
+// 16-bit half held in two arrays (the words, then the halves, in the space
+// of the 8-byte entries):
+//   level 1 (bucket lists): word = id within the bucket (region within the
+//     bucket << kLocalBits | counter) | low bits of ts << 22, half = the
+//     high bits, where ts = t - start of the slice of bin workgroups that
+//     level 2 reads the entry in (the workgroup's rank in the slice x tile
+//     + t - tile start);
+//   level 2 (region lists): word = counter | low bits of t << kLocalBits,
+//     half = the high bits (t chunk-relative).
+constexpr uint32_t kBucketIdBits = 22;
+constexpr uint32_t kMaxSliceLog = (32 - kBucketIdBits) + 16;  // ts: 26 bits
+static_assert((1u << (kBucketIdBits - kLocalBits)) == kMaxRegionsPerBucket, "bucket ids");
+static_assert((32 - kLocalBits) + 16 >= 32, "level-2 entries hold any 32-bit t");
+
+// An entry as loaded, either format (hi = ~0u: no entry)
+struct RawEntry {
+    uint32_t lo, hi;
+};
 static_assert(kStage == (1 << kStageLog), "stage size");
 static_assert(kRegionCounters == (1 << kLocalBits), "region size");
 static_assert(kMaxRegions == (1u << kPartLog), "partition size");
@@ -304,7 +323,8 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
                                                        BinPlan B,
                                                        const uint32_t *__restrict__ slots,
                                                        const uint32_t *__restrict__ coarse_off,
-                                                       uint64_t *__restrict__ bucketed) {
+                                                       uint32_t *__restrict__ out_word,
+                                                       uint16_t *__restrict__ out_half) {
     // 32-bit indices: a chunk of this path holds at most kBinChunk positions
     // and (positions x hash functions) < 2^32 slot ids and entries
     constexpr int kPer = kStage1 / kBinWG;
@@ -317,6 +337,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
     const uint32_t len = (uint32_t)(c1 - c0);
     const uint32_t g0 = blockIdx.x * (uint32_t)B.tile;  // chunk-relative
     const uint32_t g1 = g0 + (uint32_t)B.tile < len ? g0 + (uint32_t)B.tile : len;
+    const uint32_t s0 = (blockIdx.x & ~(B.slice - 1u)) * (uint32_t)B.tile;  // its slice's start
     // positions per batch: a power of two with batch * k_h <= kStage1
     uint32_t bl = 0;
     while ((1u << bl) < k_h)
@@ -374,7 +395,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot) {
                 const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
-                const uint32_t q = q0 + (i & (batch - 1u));
+                const uint32_t q = q0 - s0 + (i & (batch - 1u));  // ts: within the slice
                 const uint32_t b = id[u] >> bshift;
                 const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
                 s_stage[j] = ((uint64_t)q << 32) | id[u];
@@ -385,8 +406,11 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
             const uint64_t e = s_stage[j];
             const uint32_t b = (uint32_t)e >> bshift;
             const uint32_t dst = s_cursor[b] + (j - s_start[b]);
-            if (dst < cap)
-                bucketed[dst] = e;
+            const uint32_t q = (uint32_t)(e >> 32);
+            if (dst < cap) {
+                out_word[dst] = ((uint32_t)e & ((1u << bshift) - 1u)) | (q << kBucketIdBits);
+                out_half[dst] = (uint16_t)(q >> (32 - kBucketIdBits));
+            }
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
@@ -402,7 +426,10 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
 // (s+1)*slice) -> their regions' segments for those workgroups.  Batches of
 // kStage2 entries are counting-sorted by region in LDS and written as runs
 // (twice the level-1 batch: runs of 2 x 4096 / regions per bucket entries).
+// kCompact: 6-byte entries in and out (single-level path).  Else 8-byte
+// entries (t << 32 | slot id).
 constexpr int kStage2 = 2 * kStage;
+template <bool kCompact>
 __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
                                                        const uint32_t *__restrict__ coarse_off,
                                                        const uint32_t *__restrict__ n_entries,
@@ -445,30 +472,66 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
         e1 = cap;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    // entries of the batch at q0; the next batch's are requested before this
-    // one is sorted
-    auto load = [&](uint64_t q0, uint64_t(&v)[kPer]) {
+    const uint32_t *in_word = (const uint32_t *)bucketed;
+    const uint16_t *in_half = (const uint16_t *)(in_word + cap);
+    uint32_t *out_word = (uint32_t *)entries;
+    uint16_t *out_half = (uint16_t *)(out_word + cap);
+    const uint32_t slice0 = gs0 * (uint32_t)B.tile;  // chunk-relative start of the slice
+    // entries of the batch at q0 as loaded (lo, hi: the 8-byte entry's
+    // words, or the 6-byte entry's word and half; hi = ~0u past the end);
+    // the next batch's are requested before this one is sorted and decoded
+    // only then, so that their loads stay in flight meanwhile
+    auto load = [&](uint64_t q0, RawEntry(&v)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
             const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
-            v[u] = x < e1 ? bucketed[x] : ~0ull;
+            v[u] = RawEntry{~0u, ~0u};
+            if (x < e1) {
+                if (kCompact) {
+                    v[u].lo = in_word[x];
+                    v[u].hi = in_half[x];
+                } else {
+                    const uint2 p = ((const uint2 *)bucketed)[x];
+                    v[u].lo = p.x;
+                    v[u].hi = p.y;
+                }
+            }
         }
     };
-    uint64_t next[kPer];
+    RawEntry next[kPer];
     if (e0 < e1)
         load(e0, next);
     for (uint64_t q0 = e0; q0 < e1; q0 += kStage2) {
         uint64_t v[kPer];
         uint32_t ri[kPer];
+        RawEntry raw[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; u++)
-            v[u] = next[u];
+            raw[u] = next[u];
         if (q0 + kStage2 < e1)
             load(q0 + kStage2, next);
+        // kCompact: t << 32 | region within the bucket << kLocalBits | counter
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
-            const uint32_t r = ((uint32_t)v[u] >> kLocalBits) & ((1u << kLocalBits) - 1u);
-            ri[u] = (v[u] != ~0ull && r - r0l < nr) ? r - r0l : 0xFFFFFFFFu;
+            if (raw[u].hi == ~0u)
+                v[u] = ~0ull;
+            else if (kCompact)
+                v[u] = ((uint64_t)(slice0 + ((raw[u].lo >> kBucketIdBits) |
+                                             (raw[u].hi << (32 - kBucketIdBits))))
+                        << 32) |
+                       (raw[u].lo & ((1u << kBucketIdBits) - 1u));
+            else
+                v[u] = ((uint64_t)raw[u].hi << 32) | raw[u].lo;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            if (kCompact) {
+                const uint32_t r = (uint32_t)v[u] >> kLocalBits;
+                ri[u] = (v[u] != ~0ull && r < nr) ? r : 0xFFFFFFFFu;
+            } else {
+                const uint32_t r = ((uint32_t)v[u] >> kLocalBits) & ((1u << kLocalBits) - 1u);
+                ri[u] = (v[u] != ~0ull && r - r0l < nr) ? r - r0l : 0xFFFFFFFFu;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kPer; u++)
@@ -505,10 +568,21 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
             s_start[kMaxRegionsPerBucket - 1] + s_cnt[kMaxRegionsPerBucket - 1];
         for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
             const uint64_t e = s_stage[j];
-            const uint32_t r = (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
-            const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
-            if (dst < cap)
-                entries[dst] = e;
+            if (kCompact) {
+                const uint32_t r = (uint32_t)e >> kLocalBits;
+                const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
+                const uint32_t t = (uint32_t)(e >> 32);
+                if (dst < cap) {
+                    out_word[dst] = ((uint32_t)e & (kRegionCounters - 1u)) | (t << kLocalBits);
+                    out_half[dst] = (uint16_t)(t >> (32 - kLocalBits));
+                }
+            } else {
+                const uint32_t r =
+                    (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
+                const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
+                if (dst < cap)
+                    entries[dst] = e;
+            }
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kBinWG) {
@@ -805,6 +879,9 @@ __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &
         F.words[wbase + w] = next;
 }
 
+// kCompact: 6-byte entries (single-level path).  Else 8-byte entries
+// (t << 32 | slot id).
+template <bool kCompact>
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
@@ -829,15 +906,34 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     const uint64_t wbase = (uint64_t)(B.region0 + r) << B.region_shift;
     const uint64_t n_words = F.X * F.Y;
     const uint32_t nw = wbase + S <= n_words ? S : (uint32_t)(n_words - wbase);
+    const uint32_t *e_word = (const uint32_t *)entries;
+    const uint16_t *e_half = (const uint16_t *)(e_word + B.entries_cap);
+    // entry x as loaded (hi = ~0u past the end); decoded where it is used,
+    // so that prefetched loads stay in flight until then
+    auto fetch = [&](uint64_t x) -> RawEntry {
+        RawEntry e{~0u, ~0u};
+        if (x < e1) {
+            if (kCompact) {
+                e.lo = e_word[x];
+                e.hi = e_half[x];
+            } else {
+                const uint2 p = ((const uint2 *)entries)[x];
+                e.lo = p.x;
+                e.hi = p.y;
+            }
+        }
+        return e;
+    };
+    auto t_of = [](RawEntry e) -> uint32_t {
+        return kCompact ? (e.lo >> kLocalBits) | (e.hi << (32 - kLocalBits)) : e.hi;
+    };
     // the first entries and the region's cells are requested before the LDS
     // clear, so that their latency overlaps it (this workgroup alone writes
     // these cells)
-    uint64_t v[kUnroll];
+    RawEntry v[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
-        const uint64_t x = e0 + threadIdx.x + (uint64_t)u * kRegionWG;
-        v[u] = x < e1 ? entries[x] : ~0ull;
-    }
+    for (int u = 0; u < kUnroll; u++)
+        v[u] = fetch(e0 + threadIdx.x + (uint64_t)u * kRegionWG);
     const bool hold = nw <= (uint32_t)kHold * kRegionWG;
     uint64_t cell[kHold];
 #pragma unroll
@@ -857,8 +953,8 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         // can put two entries on one counter).
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
-            if (v[u] != ~0ull) {
-                const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+            if (v[u].hi != ~0u) {
+                const uint32_t local = v[u].lo & (kRegionCounters - 1);
                 hits[local] = 0;
                 first[local] = kIdle;
             }
@@ -871,17 +967,17 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
-            if (v[u] != ~0ull) {
-                const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+            if (v[u].hi != ~0u) {
+                const uint32_t local = v[u].lo & (kRegionCounters - 1);
                 atomicAdd(&hits[local], 1u);
-                atomicMin(&first[local], (uint32_t)(v[u] >> 32));
+                atomicMin(&first[local], t_of(v[u]));
             }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
-            if (v[u] != ~0ull) {
-                const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
-                const uint32_t t = (uint32_t)(v[u] >> 32);
+            if (v[u].hi != ~0u) {
+                const uint32_t local = v[u].lo & (kRegionCounters - 1);
+                const uint32_t t = t_of(v[u]);
                 if (atomicCAS(&first[local], t, kDone) != t)
                     continue;
                 const uint32_t w = local & (S - 1u);
@@ -912,19 +1008,17 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     for (uint64_t e = e0 + threadIdx.x;;) {
         // the next entries are requested before this batch's LDS atomics
         const uint64_t en = e + (uint64_t)kUnroll * kRegionWG;
-        uint64_t w[kUnroll];
+        RawEntry w[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            w[u] = fetch(en + (uint64_t)u * kRegionWG);
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
-            const uint64_t x = en + (uint64_t)u * kRegionWG;
-            w[u] = x < e1 ? entries[x] : ~0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-            if (v[u] == ~0ull)
+            if (v[u].hi == ~0u)
                 continue;
-            const uint32_t local = (uint32_t)v[u] & (kRegionCounters - 1);
+            const uint32_t local = v[u].lo & (kRegionCounters - 1);
             atomicAdd(&hits[local], 1u);
-            atomicMin(&first[local], (uint32_t)(v[u] >> 32));
+            atomicMin(&first[local], t_of(v[u]));
         }
         if (en >= e1)
             break;
@@ -1116,7 +1210,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinRegion, s);
-        hipLaunchKernelGGL(k_bin_region, dim3(Q.n_buckets * Q.n_slices), dim3(kBinWG), 0, s, Q,
+        hipLaunchKernelGGL(k_bin_region<false>, dim3(Q.n_buckets * Q.n_slices), dim3(kBinWG), 0, s, Q,
                            (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
                            (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
         if (P)
@@ -1126,7 +1220,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhRegion, s);
-        hipLaunchKernelGGL(k_region, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
+        hipLaunchKernelGGL(k_region<false>, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
                            (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
                            (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
         if (P)
@@ -1149,6 +1243,12 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     B.G = (uint32_t)((c1 - c0 + B.tile - 1) / B.tile);
     B.n_slices = (B.G + B.slice - 1) / B.slice;
     B.entries_cap = W.entries_cap;
+    // the 6-byte entries' fields (bucket ids, t - slice start)
+    if ((B.slice & (B.slice - 1)) || B.tile * B.slice > (1ull << kMaxSliceLog) ||
+        B.bucket_shift + kLocalBits > kBucketIdBits)
+        return hipErrorInvalidValue;
+    uint32_t *bucket_word = (uint32_t *)W.bucketed;
+    uint16_t *bucket_half = (uint16_t *)(bucket_word + W.entries_cap);
     const size_t lds = (size_t)B.n_regions * sizeof(uint32_t);
     const uint64_t n_fine = (uint64_t)B.n_regions * B.G;
     const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
@@ -1181,14 +1281,15 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (P)
         P->begin(kPhBinBucket, s);
     hipLaunchKernelGGL(k_bin_bucket, dim3(B.G), dim3(kBinWG), kLevel1Reserve, s, c0, c1, F.k_h, B,
-                       (const uint32_t *)W.slots, (const uint32_t *)W.coarse, W.bucketed);
+                       (const uint32_t *)W.slots, (const uint32_t *)W.coarse, bucket_word,
+                       bucket_half);
     if (P)
         P->end(s);
     e = hipGetLastError();
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinRegion, s);
-        hipLaunchKernelGGL(k_bin_region, dim3(B.n_buckets * B.n_slices), dim3(kBinWG), 0, s, B,
+        hipLaunchKernelGGL(k_bin_region<true>, dim3(B.n_buckets * B.n_slices), dim3(kBinWG), 0, s, B,
                            (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
                            (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
         if (P)
@@ -1199,7 +1300,7 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhRegion, s);
-    hipLaunchKernelGGL(k_region, dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
+    hipLaunchKernelGGL(k_region<true>, dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
                        (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
                        (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
     if (P)

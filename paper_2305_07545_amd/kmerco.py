@@ -408,6 +408,43 @@ class CountBF:
         with torch.cuda.device(self.device):
             _check(self.lib.kc_sync(self._h), "kc_sync")
 
+    def save(self, path, distinct=None, n_distinct=None):
+        """Checkpoint the countBF (its words, layout and k) to an ``.npz``
+        file, with the distinct list so far when ``distinct`` is given (its
+        first ``n_distinct`` keys; the filter's own count by default).  The
+        file holds plain arrays only (no pickles).  Synchronous."""
+        import numpy as np
+        self.sync()
+        layout = np.array([self.layout.X, self.layout.Y, self.layout.alpha, self.layout.k_h,
+                           0 if self.k is None else self.k], dtype=np.uint64)
+        arrays = {"layout": layout, "words": self.words.cpu().numpy().view(np.uint64)}
+        if distinct is not None:
+            n = int((self.n_distinct if n_distinct is None else n_distinct).item())
+            w = key_words(self.k)
+            arrays["distinct"] = distinct[:n * w].cpu().numpy().view(np.uint64)
+        with open(path, "wb") as fh:
+            np.savez(fh, **arrays)
+
+    @classmethod
+    def load(cls, path, device=None, stream=None):
+        """A countBF resumed from a ``save`` checkpoint: later inserts continue
+        it as if the saved inserts and they had been one call.  Returns
+        (countbf, distinct), distinct being the saved list as a device
+        tensor (None when none was saved); the filter's n_distinct starts at
+        its length."""
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            X, Y, alpha, k_h, k = (int(v) for v in z["layout"])
+            words = torch.from_numpy(z["words"].view(np.int64).copy())
+            distinct = z["distinct"].view(np.int64).copy() if "distinct" in z.files else None
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        bf = cls(X, Y, alpha, k_h, words=words.to(dev), zero=False, device=dev, stream=stream)
+        bf.k = k or None
+        if distinct is not None:
+            distinct = torch.from_numpy(distinct).to(dev)
+            bf.n_distinct.fill_(distinct.numel() // key_words(bf.k))
+        return bf, distinct
+
 
 def run_kmerco(reads, offsets, k: int, tau: int, X: int, Y: int, alpha: int = 8, k_h: int = 1,
                stream=None, fused: bool = True):

@@ -324,6 +324,45 @@ def test_paths_agree_on_bacterial_sample(monkeypatch):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("X,Y,what", [(4201, 4211, "8638 regions: tiles of 2^17 positions"),
+                                      (2621, 2657, "3400 regions: 4096 tiles, 128 slices")])
+def test_full_chunk_binned_equals_direct(monkeypatch, X, Y, what):
+    """A full binned chunk (2^28 positions) and a tail: the binned entries
+    hold positions relative to their tile (level 1) and slice of tiles
+    (level 2), so the largest tiles and the most slices a chunk can have are
+    checked against the direct path (itself checked against the oracle on
+    smaller inputs), output by output, on the device."""
+    rs = synth.random_reads(1500, 1_400_000, 150, 250, k=31, p_n=0.0005, tau=3)
+    assert rs.n_bases > (1 << 28)
+    print(f"case full chunk {what}: X={X} Y={Y} bases={rs.n_bases}", flush=True)
+    r, o = dev(rs)
+    outs = {}
+    for p in ("binned", "direct"):
+        monkeypatch.setenv("KMERCO_PATH", p)
+        bf = P.CountBF(X, Y)
+        bf.profile(True)
+        d, t, nt, e, ne = bf.insert_classify(r, o, rs.k, rs.tau)
+        bf.sync()
+        nd = int(bf.n_distinct.item())
+        outs[p] = [bf.words.clone(), d[:nd].clone(), t[:int(nt.item())].clone(),
+                   e[:int(ne.item())].clone(), int(bf.n_windows.item())]
+        phases = bf.profile_read()
+        assert (p == "binned") == ("bin_region" in phases), phases
+        assert p == "direct" or phases["bin_region"][1] == 2  # the full chunk and the tail
+        bf.close()
+        del d, t, e
+    a, b = outs["binned"], outs["direct"]
+    assert a[4] == b[4]
+    for n, x, y in zip(["words", "distinct", "trust", "err"], a[:4], b[:4]):
+        assert x.shape == y.shape, f"{what} {n}: {x.shape} != {y.shape}"
+        assert torch.equal(x, y), f"{what} {n} differs"
+    # random 31-mers are all different: a window is listed when its counter
+    # was still untouched, C (1 - exp(-W / C)) of W windows over C counters
+    c = X * Y * 8
+    want = c * (1 - np.exp(-a[4] / c))
+    assert abs(a[1].numel() - want) < 0.05 * want, (a[1].numel(), want)
+
+
 def test_errors_and_capacity():
     rs = synth.random_reads(1101, 100, 30, 100, k=21)
     r, o = dev(rs)
