@@ -119,6 +119,8 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_windows * k_h * 4 + n_distinct * 4 + n_bases * (0.5 + 0.125)
     if phase == "ingest":            # ASCII in, packed codes + bitmaps out, flag bytes cleared
         return n_bases * 2.5
+    if phase == "valid_windows":     # invalid-base and read-start bits in, valid-window bits out
+        return n_bases * 3 / 8
     if phase == "scatter":           # flag byte + packed input, keys out (distinct + split)
         return n_bases * 1.5 + n_distinct * 2 * key_bytes
     if phase == "classify_mark":     # key + cell per slot, mask out

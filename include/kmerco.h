@@ -240,7 +240,8 @@ typedef enum {
     KC_PHASE_BIN_REGION = 15,     /* binned path: bucket slices -> region segments */
     KC_PHASE_BIN_PART = 16,       /* partitioned path: entries grouped by partition */
     KC_PHASE_PART_COUNT = 17,     /* partitioned path: per-partition region counts */
-    KC_PHASE_COUNT = 18
+    KC_PHASE_VALID = 18,          /* binned paths: valid-window bitmap of the call's k */
+    KC_PHASE_COUNT = 19
 } kc_phase;
 
 kc_status kc_profile(kc_filter *f, int enable);

@@ -44,19 +44,23 @@ bool valid_layout(const kc_layout *L) {
 void wait_idle(kc_filter *f) { (void)hipStreamSynchronize(f->last); }
 
 // per-position buffers for inserts of up to n bases (waits for `wait_on`
-// before releasing smaller ones)
-kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
-    if (W.codes && n <= W.cap)
+// before releasing smaller ones); valid_bitmap: with the valid-window bitmap
+// of the binned paths
+kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n, bool valid_bitmap) {
+    if (W.codes && n <= W.cap && (W.valid || !valid_bitmap))
         return KC_OK;
     (void)hipStreamSynchronize(wait_on);
     dev_free(W.codes);
     dev_free(W.inv);
     dev_free(W.rs);
+    dev_free(W.valid);
     dev_free(W.flags8);
     uint64_t cap = n < 65536 ? 65536 : n + n / 8;
     W.cap = 0;
     if (!dev_alloc(&W.codes, kc::code_words(cap)) || !dev_alloc(&W.inv, kc::mask_words(cap)) ||
-        !dev_alloc(&W.rs, kc::mask_words(cap)) || !dev_alloc(&W.flags8, kc::tiles(cap) * kc::kTile))
+        !dev_alloc(&W.rs, kc::mask_words(cap)) ||
+        (valid_bitmap && !dev_alloc(&W.valid, kc::mask_words(cap))) ||
+        !dev_alloc(&W.flags8, kc::tiles(cap) * kc::kTile))
         return KC_ENOMEM;
     W.cap = cap;
     return KC_OK;
@@ -87,7 +91,9 @@ kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
     return KC_OK;
 }
 
-kc_status ensure_positions(kc_filter *f, uint64_t n) { return ensure_positions(*f->W, f->last, n); }
+kc_status ensure_positions(kc_filter *f, uint64_t n) {
+    return ensure_positions(*f->W, f->last, n, true);
+}
 kc_status ensure_tiles(kc_filter *f, uint64_t n) { return ensure_tiles(*f->W, f->last, n); }
 
 // binned-path buffers for one chunk of the given plan
@@ -222,6 +228,7 @@ void free_workspace(kc::Workspace &W) {
     dev_free(W.codes);
     dev_free(W.inv);
     dev_free(W.rs);
+    dev_free(W.valid);
     dev_free(W.flags8);
     dev_free(W.tile_a);
     dev_free(W.tile_b);
@@ -380,11 +387,13 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         return st;
     }
     hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, *f->W, s, &f->prof);
+    if (e == hipSuccess && binned)
+        e = kc::launch_valid_windows(n_bases, k, *f->W, s, &f->prof);
     if (e == hipSuccess && binned)  // valid windows, accumulated by the bin passes
         e = kc::fill_u64(f->W->totals + 5, 1, 0ull, s);
     if (e != hipSuccess)
         return KC_EDEVICE;
-    kc::ReadsArgs R{f->W->codes, f->W->inv, f->W->rs, n_bases, k};
+    kc::ReadsArgs R{f->W->codes, f->W->inv, f->W->rs, n_bases, k, f->W->valid};
     const uint64_t chunk = binned ? bchunk : f->chunk;
     // this call's classification can be taken from the region pass when the
     // final counter of each distinct k-mer's single slot is known there
@@ -696,7 +705,7 @@ const char *kc_phase_name(uint32_t phase) {
     static const char *names[kc::kPhCount] = {
         "ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
         "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
-        "region", "tile_count", "bin_region", "bin_part", "part_count"};
+        "region", "tile_count", "bin_region", "bin_part", "part_count", "valid_windows"};
     return phase < (uint32_t)kc::kPhCount ? names[phase] : "unknown";
 }
 

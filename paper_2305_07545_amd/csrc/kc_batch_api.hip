@@ -395,7 +395,7 @@ kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
     if (graph && !s)
         return KC_EINVAL;  // the null stream cannot be captured
     b->last = s;
-    if ((st = ensure_scalars(b->W)) != KC_OK || (st = ensure_positions(b->W, s, n_bases)) != KC_OK ||
+    if ((st = ensure_scalars(b->W)) != KC_OK || (st = ensure_positions(b->W, s, n_bases, false)) != KC_OK ||
         (st = ensure_tiles(b->W, s, n_bases)) != KC_OK)
         return st;
     if (flags & KC_BATCH_TUNE) {

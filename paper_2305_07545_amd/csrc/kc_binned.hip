@@ -120,10 +120,11 @@ __device__ __forceinline__ void bin_window(const FilterArgs &F, const BinPlan &B
 
 // kParts: the partitioned path; the slot id holds the region within its
 // partition, parts[] the partition, and the histogram counts partitions.
-// Each wavefront extracts windows 64 positions at a time and queues the
-// valid ones (key and position) in an LDS ring of its own; it hashes 64
-// queued windows at a time, so that no lane hashes an invalid window (the
-// last K-1 positions of every read, windows over 'N').
+// Each wavefront takes 64 positions at a time, their validity from the
+// valid-window bitmap (one 64-bit word), and queues the valid windows (key
+// and position) in an LDS ring of its own; it hashes 64 queued windows at a
+// time, so that no lane hashes an invalid window (the last K-1 positions of
+// every read, windows over 'N').
 template <bool kParts>
 __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                       uint64_t c1, BinPlan B,
@@ -152,16 +153,19 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
     for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
         WaveWords w;
-        wave_load(R, pb, w);
-        uint64_t fwd;
+        wave_load_codes(R, pb, w);
+        // the wave's valid windows (the bitmap; positions from g1 on cut)
+        uint64_t m = wave_valid(R, pb);
+        if (g1 - pb < 64u)
+            m &= (1ull << (g1 - pb)) - 1ull;
         const uint64_t p = pb + lane;
         const bool in = p < g1;
-        const bool valid = wave_window(w, pb, lane, R.k, R.n_bases, fwd) && in;
+        const bool valid = (m >> lane) & 1ull;
         if (!valid && in)
             for (uint32_t a = 1; a <= F.k_h; a++)
                 slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
-        const uint64_t m = __ballot(valid);
         if (valid) {
+            const uint64_t fwd = wave_key(w, lane, R.k);
             nv++;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -228,8 +232,8 @@ __device__ __forceinline__ void bin_window_wide(const FilterArgs &F, const BinPl
 }
 
 // k_bin_count for k-mers of 33..64 bases: each lane reads its own window
-// (five code words, 64-bit validity masks) and the ring holds 128-bit keys;
-// everything else is k_bin_count's.
+// (five code words) and the ring holds 128-bit keys; everything else is
+// k_bin_count's.
 template <bool kParts>
 __global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                            uint64_t c1, BinPlan B,
@@ -258,13 +262,15 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsAr
     uint32_t nv = 0;
     uint32_t head = 0, queued = 0;
     for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
+        uint64_t m = wave_valid(R, pb);  // the wave's valid windows
+        if (g1 - pb < 64u)
+            m &= (1ull << (g1 - pb)) - 1ull;
         const uint64_t p = pb + lane;
         const bool in = p < g1;
-        const bool valid = in && window_valid_wide(R, p);
+        const bool valid = (m >> lane) & 1ull;
         if (!valid && in)
             for (uint32_t a = 1; a <= F.k_h; a++)
                 slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
-        const uint64_t m = __ballot(valid);
         if (valid) {
             const Key128 fwd = window_key_wide(R.codes, p, R.k);
             nv++;
@@ -1235,6 +1241,8 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
                                uint32_t tau, hipStream_t s, Profiler *P) {
+    if ((c0 & 63u) || !R.valid)
+        return hipErrorInvalidValue;  // waves read 64 bits of the valid-window bitmap
     if (plan.n_parts)
         return launch_parts_chunk(F, R, c0, c1, plan, W, classify, tau, s, P);
     if (c1 - c0 > kBinChunk || (c1 - c0) * F.k_h >= (1ull << 32))

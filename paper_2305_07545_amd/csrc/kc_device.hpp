@@ -40,6 +40,7 @@ struct ReadsArgs {
     const uint32_t *rs;
     uint64_t n_bases;
     uint32_t k;
+    const uint32_t *valid;  // valid-window bitmap of k (valid_word), where computed
 };
 
 // ----------------------------------------------------------------------------
@@ -222,6 +223,44 @@ KC_HD bool window_valid(const ReadsArgs &R, uint64_t p) {
     return ((iv & kmask) | (st & kmask & ~1ull)) == 0;
 }
 
+// OR of the L consecutive bits of x starting at every bit (L = 0..64): the
+// runs are doubled up to the largest power of two c <= L, then two runs of
+// c that overlap cover L.
+KC_HD unsigned __int128 window_or(unsigned __int128 x, uint32_t L) {
+    if (L == 0)
+        return 0;
+    uint32_t c = 1;
+    while (2u * c <= L) {
+        x |= x >> c;
+        c *= 2u;
+    }
+    return x | (x >> (L - c));
+}
+
+// Bits of the valid-window bitmap for mask word i (positions 32 i + j):
+// bit j is set when the window of K bases there is valid (as window_valid:
+// inside the data, no invalid base, no read starting after its first base).
+// inv, rs: the mask words, n_words of them.
+KC_HD uint32_t valid_word(const uint32_t *inv, const uint32_t *rs, uint64_t n_words, uint64_t i,
+                          uint32_t K, uint64_t n_bases) {
+    const uint64_t p0 = i * 32u;
+    if (p0 + K > n_bases)
+        return 0;
+    unsigned __int128 xi = 0, xr = 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        if (i + d < n_words) {
+            xi |= (unsigned __int128)inv[i + d] << (32 * d);
+            xr |= (unsigned __int128)rs[i + d] << (32 * d);
+        }
+    const unsigned __int128 bad = window_or(xi, K) | window_or(xr >> 1, K - 1u);
+    uint32_t v = ~(uint32_t)bad;
+    const uint64_t last = n_bases - K - p0;  // windows j <= last end inside the data
+    if (last < 31u)
+        v &= (2u << last) - 1u;
+    return v;
+}
+
 // Canonical key and its H_1 value (Sec. 2.3: the strand with the smaller
 // hash; a tie keeps the reverse complement), plus the key's MM3 blocks for
 // the remaining hash functions.
@@ -303,6 +342,21 @@ KC_HD void wave_load(const ReadsArgs &R, uint64_t pb, WaveWords &w) {
     }
 }
 
+// The code words of positions pb .. pb + 95 only (validity from the
+// valid-window bitmap).
+KC_HD void wave_load_codes(const ReadsArgs &R, uint64_t pb, WaveWords &w) {
+    const uint32_t *cp = R.codes + (pb >> 4);
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+        w.c[i] = cp[i];
+}
+
+// Valid-window bits of positions pb .. pb + 63 (pb a multiple of 64).
+KC_HD uint64_t wave_valid(const ReadsArgs &R, uint64_t pb) {
+    const uint32_t *vp = R.valid + (pb >> 5);
+    return ((uint64_t)vp[1] << 32) | vp[0];
+}
+
 KC_HD uint32_t pick4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t i) {
     uint32_t lo = (i & 1u) ? a1 : a0;
     uint32_t hi = (i & 1u) ? a3 : a2;
@@ -318,9 +372,9 @@ KC_HD uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t s) {
 #endif
 }
 
-// Window at position pb + lane (lane < 64): validity and forward key.
-KC_HD bool wave_window(const WaveWords &w, uint64_t pb, uint32_t lane, uint32_t K,
-                       uint64_t n_bases, uint64_t &fwd) {
+// Forward key of the window at position pb + lane (lane < 64, K <= 32)
+// from the wave's code words.
+KC_HD uint64_t wave_key(const WaveWords &w, uint32_t lane, uint32_t K) {
     const uint32_t mo = lane >> 4;
     const uint32_t w0 = pick4(w.c[0], w.c[1], w.c[2], w.c[3], mo);
     const uint32_t w1 = pick4(w.c[1], w.c[2], w.c[3], w.c[4], mo);
@@ -330,7 +384,13 @@ KC_HD bool wave_window(const WaveWords &w, uint64_t pb, uint32_t lane, uint32_t 
     // window_key
     const uint32_t top_hi = (uint32_t)(((((uint64_t)w0 << 32) | w1) << s) >> 32);
     const uint32_t top_lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32u - s));
-    fwd = (((uint64_t)top_hi << 32) | top_lo) >> (64u - 2u * K);
+    return (((uint64_t)top_hi << 32) | top_lo) >> (64u - 2u * K);
+}
+
+// Window at position pb + lane (lane < 64): validity and forward key.
+KC_HD bool wave_window(const WaveWords &w, uint64_t pb, uint32_t lane, uint32_t K,
+                       uint64_t n_bases, uint64_t &fwd) {
+    fwd = wave_key(w, lane, K);
     // 32 mask bits starting at the window's first base
     const bool upper = (lane & 32u) != 0;
     const uint32_t o = lane & 31u;

@@ -50,7 +50,7 @@ void dev_free(T *&p) {
 }
 
 bool valid_layout(const kc_layout *L);
-kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n);
+kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n, bool valid_bitmap);
 kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n);
 kc_status ensure_scalars(kc::Workspace &W);
 void free_workspace(kc::Workspace &W);

@@ -64,6 +64,7 @@ struct Workspace {
     uint32_t *codes = nullptr;    // code_words(cap) 2-bit packed bases
     uint32_t *inv = nullptr;      // mask_words(cap) invalid-base bits
     uint32_t *rs = nullptr;       // mask_words(cap) read-start bits
+    uint32_t *valid = nullptr;    // mask_words(cap) valid-window bits (binned paths)
     uint8_t *flags8 = nullptr;    // tiles(cap)*kTile flag bytes
     uint64_t cap = 0;
     // per-tile buffers (tile_cap tiles of positions or keys)
@@ -144,7 +145,7 @@ inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 enum Phase {
     kPhIngest = 0, kPhClaim, kPhIncrement, kPhClaimIncrement, kPhResolve, kPhScan, kPhScatter,
     kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhBinCount, kPhBinBucket, kPhRegion,
-    kPhTileCount, kPhBinRegion, kPhBinPart, kPhPartCount, kPhCount
+    kPhTileCount, kPhBinRegion, kPhBinPart, kPhPartCount, kPhValid, kPhCount
 };
 
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
@@ -167,6 +168,10 @@ hipError_t scan_u32_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t 
 
 hipError_t launch_ingest(const uint8_t *reads, uint64_t n_bases, const uint64_t *offsets,
                          uint64_t n_reads, const Workspace &W, hipStream_t s, Profiler *P);
+// The valid-window bitmap of k-base windows into W.valid (binned paths),
+// from the bitmaps launch_ingest wrote.
+hipError_t launch_valid_windows(uint64_t n_bases, uint32_t k, const Workspace &W, hipStream_t s,
+                                Profiler *P);
 hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                bool zero_filter, const Workspace &W, hipStream_t s, Profiler *P);
 // Binned-path plan for chunks of chunk_positions; false when the countBF

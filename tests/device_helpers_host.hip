@@ -45,6 +45,16 @@ int kch_window_valid(const uint32_t *codes, const uint32_t *inv, const uint32_t 
     return kc::window_valid(R, p) ? 1 : 0;
 }
 
+uint32_t kch_valid_word(const uint32_t *inv, const uint32_t *rs, uint64_t n_words, uint64_t i,
+                        uint32_t k, uint64_t n_bases) {
+    return kc::valid_word(inv, rs, n_words, i, k, n_bases);
+}
+
+uint64_t kch_wave_valid(const uint32_t *valid, uint64_t pb) {
+    kc::ReadsArgs R{nullptr, nullptr, nullptr, 0, 0, valid};
+    return kc::wave_valid(R, pb);
+}
+
 uint64_t kch_hash(uint64_t key, uint32_t a) {
     uint32_t b0, b1;
     kc::key_blocks(key, b0, b1);

@@ -34,6 +34,8 @@ def H(tmp_path_factory):
     L.kch_window_key.argtypes = [p32, u64, u32]; L.kch_window_key.restype = u64
     L.kch_window_valid.argtypes = [p32, p32, p32, u64, u32, u64]; L.kch_window_valid.restype = ctypes.c_int
     L.kch_hash.argtypes = [u64, u32]; L.kch_hash.restype = u64
+    L.kch_valid_word.argtypes = [p32, p32, u64, u64, u32, u64]; L.kch_valid_word.restype = u32
+    L.kch_wave_valid.argtypes = [p32, u64]; L.kch_wave_valid.restype = u64
     L.kch_canonical.argtypes = [u64, u32, ctypes.POINTER(u64)]; L.kch_canonical.restype = u64
     L.kch_slot.argtypes = [u64, u64, u32, u64, ctypes.POINTER(u64), ctypes.POINTER(u32)]
     L.kch_slot.restype = None
@@ -210,6 +212,36 @@ def test_window_extraction_matches_brute_force(H):
             assert wv == v, (K, p)
             if v:
                 assert fw.value == brute.key_of(buf[p:p + K].decode())
+
+
+def test_valid_window_bitmap_matches_brute_force(H):
+    """The valid-window bitmap the binned paths read (bit p: the K-base
+    window at p is inside one read and holds only A, C, G, T), for short and
+    long K, against Python strings; and the 64-bit word a wavefront takes."""
+    rng = np.random.default_rng(25)
+    reads = []
+    for _ in range(60):
+        ln = int(rng.integers(0, 160))
+        reads.append("".join(rng.choice(list("ACGTNa"), p=[.2425, .2425, .2425, .2425, .02, .01],
+                                        size=ln)))
+    buf = "".join(reads).encode()
+    starts = np.cumsum([0] + [len(r) for r in reads])[:-1]
+    _, inv, rs = _pack(buf, starts)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))  # noqa: E731
+    n_words = len(inv)
+    for K in (1, 2, 5, 16, 21, 31, 32, 33, 40, 55, 63, 64):
+        valid = set()
+        for r, o in zip(reads, starts):
+            for p in range(len(r) - K + 1):
+                if all(c in "ACGT" for c in r[p:p + K]):
+                    valid.add(int(o) + p)
+        bits = np.array([H.kch_valid_word(P(inv), P(rs), n_words, i, K, len(buf))
+                         for i in range(n_words)], dtype=np.uint32)
+        got = {32 * i + j for i in range(n_words) for j in range(32) if (int(bits[i]) >> j) & 1}
+        assert got == valid, (K, sorted(got ^ valid)[:10])
+        for pb in range(0, 32 * (n_words - 1), 64):
+            want = sum(1 << (p - pb) for p in valid if pb <= p < pb + 64)
+            assert H.kch_wave_valid(P(bits), pb) == want, (K, pb)
 
 
 def _wide(lo, hi):
