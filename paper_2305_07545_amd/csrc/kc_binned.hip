@@ -152,8 +152,6 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     uint32_t nv = 0;
     uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
     for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
-        WaveWords w;
-        wave_load_codes(R, pb, w);
         // the wave's valid windows (the bitmap; positions from g1 on cut)
         uint64_t m = wave_valid(R, pb);
         if (g1 - pb < 64u)
@@ -165,7 +163,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
             for (uint32_t a = 1; a <= F.k_h; a++)
                 slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
         if (valid) {
-            const uint64_t fwd = wave_key(w, lane, R.k);
+            const uint64_t fwd = window_key(R.codes, p, R.k);  // the lane's three code words
             nv++;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
