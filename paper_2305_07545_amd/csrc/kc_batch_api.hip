@@ -211,7 +211,7 @@ kc_status launch_all(kc_batch *b, const kc::BatchPlan &P, const kc_set *sets, ui
                      const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads,
                      uint64_t n_bases, bool reset, hipStream_t s, kc::Profiler *prof) {
     hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, b->W, s, prof);
-    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0};
+    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0, b->W.valid};
     if (e == hipSuccess && P.n_sets)
         e = kc::launch_batch(P, b->B, R, reset, s, prof);
     if (e != hipSuccess)
@@ -251,7 +251,7 @@ kc_status autotune(kc_batch *b, const kc_set *sets, uint32_t n_sets, const uint8
         st = KC_EDEVICE;
     float best = 1e30f;
     uint64_t best_tile = b->tile;
-    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0};
+    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0, b->W.valid};
     for (uint64_t tile : kTileCandidates) {
         if (st != KC_OK)
             break;
@@ -395,7 +395,7 @@ kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
     if (graph && !s)
         return KC_EINVAL;  // the null stream cannot be captured
     b->last = s;
-    if ((st = ensure_scalars(b->W)) != KC_OK || (st = ensure_positions(b->W, s, n_bases, false)) != KC_OK ||
+    if ((st = ensure_scalars(b->W)) != KC_OK || (st = ensure_positions(b->W, s, n_bases, true)) != KC_OK ||
         (st = ensure_tiles(b->W, s, n_bases)) != KC_OK)
         return st;
     if (flags & KC_BATCH_TUNE) {

@@ -90,9 +90,23 @@ __device__ __forceinline__ void kb_bin_window(const SetDesc &S, const FilterArgs
     }
 }
 
+// The valid-window bitmap words of an item's positions, for its set's k
+// (items start at multiples of 64 positions, so that no word spans two).
+__global__ void __launch_bounds__(256) kb_valid(const SetDesc *__restrict__ sets,
+                                                const uint32_t *__restrict__ item_set,
+                                                ReadsArgs R, uint64_t tile, uint64_t n_words,
+                                                uint32_t *__restrict__ valid) {
+    const Item it = item_of(sets, item_set, blockIdx.x, tile);
+    const SetDesc &S = sets[it.s];
+    const uint64_t w1 = (it.g1 + 31u) / 32u;
+    for (uint64_t w = it.g0 / 32u + threadIdx.x; w < w1 && w < n_words; w += 256u)
+        valid[w] = valid_word(R.inv, R.rs, n_words, w, S.k, S.base + S.n_bases);
+}
+
 // Slot ids of an item's windows and its per-region counts.  As in the
-// single-set bin pass, each wavefront queues its valid windows in an LDS
-// ring and hashes 64 of them at a time.
+// single-set bin pass, each wavefront takes its positions' validity from
+// the valid-window bitmap, queues its valid windows in an LDS ring and
+// hashes 64 of them at a time.
 __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict__ sets,
                                                        const uint32_t *__restrict__ item_set,
                                                        ReadsArgs R, uint64_t tile,
@@ -118,17 +132,17 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
     uint32_t nv = 0;
     uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
     for (uint64_t pb = it.g0 + 64u * wv; pb < it.g1; pb += kBinWG) {
-        WaveWords w;
-        wave_load(R, pb, w);
-        uint64_t fwd;
+        uint64_t m = wave_valid(R, pb);  // the wave's valid windows
+        if (it.g1 - pb < 64u)
+            m &= (1ull << (it.g1 - pb)) - 1ull;
         const uint64_t p = pb + lane;
         const bool in = p < it.g1;
-        const bool ok = wave_window(w, pb, lane, S.k, R.n_bases, fwd) && in;
+        const bool ok = (m >> lane) & 1ull;
         if (!ok && in)
             for (uint32_t a = 1; a <= F.k_h; a++)
                 slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + (p - S.base)] = kNoSlot;
-        const uint64_t m = __ballot(ok);
         if (ok) {
+            const uint64_t fwd = window_key(R.codes, p, S.k);
             nv++;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -509,6 +523,17 @@ __global__ void kb_finish(const SetDesc *__restrict__ sets, uint32_t n_sets,
 // ---------------------------------------------------------------------------
 hipError_t launch_batch_bins(const BatchPlan &bp, const BatchBuffers &Bf, const ReadsArgs &R,
                              hipStream_t s, Profiler *P) {
+    if (!R.valid || (bp.tile & 63u))
+        return hipErrorInvalidValue;  // items must start at multiples of 64 positions
+    if (P)
+        P->begin(kPhValid, s);
+    hipLaunchKernelGGL(kb_valid, dim3(bp.n_items), dim3(256), 0, s, Bf.sets, Bf.item_set, R,
+                       bp.tile, mask_words(R.n_bases), (uint32_t *)R.valid);
+    if (P)
+        P->end(s);
+    const hipError_t ev = hipGetLastError();
+    if (ev != hipSuccess)
+        return ev;
     if (P)
         P->begin(kPhBinCount, s);
     hipLaunchKernelGGL(kb_bin_count, dim3(bp.n_items), dim3(kBinWG), 0, s, Bf.sets, Bf.item_set, R,
