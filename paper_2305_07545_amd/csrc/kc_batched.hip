@@ -434,19 +434,7 @@ __global__ void __launch_bounds__(kWG) kb_compact(const SetDesc *__restrict__ se
         uint32_t rt = wave_exclusive(ct, lane, tot_t);
         if (tot_d == 0)
             continue;
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-#pragma unroll
-            for (uint32_t sub = 0; sub < 4; sub++) {
-                const uint32_t fb = (x[u] >> (8u * sub)) & 0xFFu;
-                if (fb) {
-                    lpos[rd] = (uint16_t)(16u * lane + 4u * (uint32_t)u + sub);
-                    ltb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
-                    rd++;
-                    rt += fb == 3;
-                }
-            }
-        }
+        list_flags(x, lane, rd, rt, lpos, ltb);
         __builtin_amdgcn_wave_barrier();
         const SetDesc &S = sets[sidx];
         const uint64_t first_tile = S.base / kTile;

@@ -259,19 +259,7 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
         uint32_t tot_d, tot_t;
         uint32_t rd = wave_exclusive(cd, lane, tot_d);
         uint32_t rt = wave_exclusive(ct, lane, tot_t);
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-#pragma unroll
-            for (uint32_t sub = 0; sub < 4; sub++) {
-                const uint32_t fb = (x[u] >> (8u * sub)) & 0xFFu;
-                if (fb) {
-                    lpos[rd] = (uint16_t)(16u * lane + 4u * (uint32_t)u + sub);
-                    ltb[rd] = (uint16_t)(rt | (fb == 3 ? 0x8000u : 0u));
-                    rd++;
-                    rt += fb == 3;
-                }
-            }
-        }
+        list_flags(x, lane, rd, rt, lpos, ltb);
         __builtin_amdgcn_wave_barrier();
         const uint64_t pos0 = tile * kTile;
         const uint64_t od = off_d[tile];

@@ -138,6 +138,32 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t v, uint32_t lane, ui
     return incl - v;
 }
 
+// The flagged positions among a lane's 16 flag bytes x (flags are 0, 1 =
+// distinct or 3 = distinct and trustworthy; byte i is tile position
+// 16 lane + i), in position order: entry rd, rd + 1, ... of lpos gets the
+// tile position and of ltb the trustworthy count before it (from rt) with
+// bit 15 set for a trustworthy one.  Bit 0 and bit 1 of the bytes are
+// gathered into 16-bit masks four bytes at a time by one multiply (bits 0,
+// 8, 16, 24 -> bits 21..24), and only the set bits are visited.
+__device__ __forceinline__ void list_flags(const uint32_t (&x)[4], uint32_t lane, uint32_t rd,
+                                           uint32_t rt, uint16_t *lpos, uint16_t *ltb) {
+    uint32_t m16 = 0, t16 = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        m16 |= (((x[u] & 0x01010101u) * 0x204081u) >> 21 & 0xFu) << (4 * u);
+        t16 |= ((((x[u] >> 1) & 0x01010101u) * 0x204081u) >> 21 & 0xFu) << (4 * u);
+    }
+    while (m16) {
+        const uint32_t b = (uint32_t)__builtin_ctz(m16);
+        m16 &= m16 - 1u;
+        const uint32_t tr = (t16 >> b) & 1u;
+        lpos[rd] = (uint16_t)(16u * lane + b);
+        ltb[rd] = (uint16_t)(rt | (tr << 15));
+        rd++;
+        rt += tr;
+    }
+}
+
 inline uint64_t mask_words(uint64_t n) { return tiles(n) * (kTile / 32) + 2; }
 inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 
