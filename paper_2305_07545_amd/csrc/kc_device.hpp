@@ -342,15 +342,6 @@ KC_HD void wave_load(const ReadsArgs &R, uint64_t pb, WaveWords &w) {
     }
 }
 
-// The code words of positions pb .. pb + 95 only (validity from the
-// valid-window bitmap).
-KC_HD void wave_load_codes(const ReadsArgs &R, uint64_t pb, WaveWords &w) {
-    const uint32_t *cp = R.codes + (pb >> 4);
-#pragma unroll
-    for (int i = 0; i < 6; i++)
-        w.c[i] = cp[i];
-}
-
 // Valid-window bits of positions pb .. pb + 63 (pb a multiple of 64).
 KC_HD uint64_t wave_valid(const ReadsArgs &R, uint64_t pb) {
     const uint32_t *vp = R.valid + (pb >> 5);
@@ -444,23 +435,6 @@ KC_HD Key128 window_key_wide(const uint32_t *__restrict__ codes, uint64_t p, uin
     const uint64_t t1 = ((((((uint64_t)w2 << 32) | w3) << s) >> 32) << 32) |
                         (uint32_t)((((uint64_t)w3 << 32) | w4) >> (32u - s));
     return shr128(t0, t1, 128u - 2u * K);
-}
-
-// 64 mask bits from position p on (words b, b+1, b+2 of a bitmap)
-KC_HD uint64_t mask64_at(const uint32_t *__restrict__ m, uint64_t p) {
-    const uint64_t b = p >> 5;
-    const uint32_t o = (uint32_t)(p & 31u);
-    const uint64_t x = ((uint64_t)m[b + 1] << 32) | m[b];
-    return o ? ((x >> o) | ((uint64_t)m[b + 2] << (64u - o))) : x;
-}
-
-// Validity of the K-base window at p for K <= 64 (the rule of window_valid).
-// Needs inv/rs[p/32 + 2] to exist.
-KC_HD bool window_valid_wide(const ReadsArgs &R, uint64_t p) {
-    if (p + R.k > R.n_bases)
-        return false;
-    const uint64_t kmask = R.k >= 64u ? ~0ull : ((1ull << R.k) - 1ull);
-    return ((mask64_at(R.inv, p) & kmask) | (mask64_at(R.rs, p) & kmask & ~1ull)) == 0;
 }
 
 // MurmurHash3_x86_32 of a 16-byte key from its four block mixes.

@@ -114,12 +114,6 @@ void kch_window_key_wide(const uint32_t *codes, uint64_t p, uint32_t K, uint64_t
     *hi = k.hi;
 }
 
-int kch_window_valid_wide(const uint32_t *codes, const uint32_t *inv, const uint32_t *rs,
-                          uint64_t n_bases, uint32_t k, uint64_t p) {
-    kc::ReadsArgs R{codes, inv, rs, n_bases, k};
-    return kc::window_valid_wide(R, p) ? 1 : 0;
-}
-
 void kch_revcomp_wide(uint64_t lo, uint64_t hi, uint32_t K, uint64_t *olo, uint64_t *ohi) {
     kc::Key128 k = kc::revcomp_wide(kc::Key128{lo, hi}, K);
     *olo = k.lo;
