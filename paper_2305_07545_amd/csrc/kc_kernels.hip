@@ -246,9 +246,26 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
     const uint64_t base = split ? *call_base : 0;
     uint16_t *lpos = s_pos[wave];
     uint16_t *ltb = s_tb[wave];
-    for (uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave; tile < n_tiles;
-         tile += n_waves) {
-        const uint4 x4 = f128[tile * 64 + lane];
+    // each wavefront's next tile: its flags and offsets are requested before
+    // the current tile's keys are written
+    uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave;
+    uint4 nx = make_uint4(0u, 0u, 0u, 0u);
+    uint64_t nd = 0, nt = 0;
+    if (tile < n_tiles) {
+        nx = f128[tile * 64 + lane];
+        nd = off_d[tile];
+        nt = split ? off_t[tile] : 0;
+    }
+    for (; tile < n_tiles; tile += n_waves) {
+        const uint4 x4 = nx;
+        const uint64_t od = nd;
+        const uint64_t ot = nt;
+        const uint64_t next = tile + n_waves;
+        if (next < n_tiles) {
+            nx = f128[next * 64 + lane];
+            nd = off_d[next];
+            nt = split ? off_t[next] : 0;
+        }
         const uint32_t x[4] = {x4.x, x4.y, x4.z, x4.w};
         uint32_t cd = 0, ct = 0;
 #pragma unroll
@@ -262,8 +279,6 @@ __global__ void __launch_bounds__(kWG) k_compact(ReadsArgs R, const uint8_t *__r
         list_flags(x, lane, rd, rt, lpos, ltb);
         __builtin_amdgcn_wave_barrier();
         const uint64_t pos0 = tile * kTile;
-        const uint64_t od = off_d[tile];
-        const uint64_t ot = split ? off_t[tile] : 0;
         for (uint32_t i = lane; i < tot_d; i += 64) {
             const uint64_t p = pos0 + lpos[i];
             uint64_t key, key_hi = 0;
