@@ -91,8 +91,10 @@ static_assert(kMaxParts <= 256, "partition ids are bytes");
 }  // namespace
 
 // Slot ids of one valid window at chunk-relative position q (hash functions
-// 1..k_h), with the workgroup histogram update.
-template <bool kParts>
+// 1..k_h), with the workgroup histogram update.  kFast: the layout has one
+// hash function, eta a power of two and dimensions of mod_small (checked
+// by the launcher), so that the loop and the layout branches go.
+template <bool kParts, bool kFast>
 __device__ __forceinline__ void bin_window(const FilterArgs &F, const BinPlan &B, uint64_t fwd,
                                            uint32_t K, uint64_t q, uint64_t len,
                                            uint32_t *__restrict__ slots,
@@ -100,10 +102,18 @@ __device__ __forceinline__ void bin_window(const FilterArgs &F, const BinPlan &B
     const uint32_t shift = B.region_shift;
     const uint64_t smask = (1ull << shift) - 1ull;
     const Canon c = canonical_fast(fwd, K);
-    for (uint32_t a = 1; a <= F.k_h; a++) {
+    const uint32_t k_h = kFast ? 1u : F.k_h;
+    for (uint32_t a = 1; a <= k_h; a++) {
         uint64_t word;
         uint32_t l;
-        slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
+        const uint64_t h = a == 1 ? c.h1 : hash_a(c.b0, c.b1, a);
+        if (kFast) {
+            l = (uint32_t)h & (F.eta - 1u);
+            word = (uint64_t)mod_small(h, (uint32_t)F.X, F.mX) * (uint32_t)F.Y +
+                   mod_small(h, (uint32_t)F.Y, F.mY);
+        } else {
+            slot_of(F, h, word, l);
+        }
         const uint32_t r = (uint32_t)(word >> shift);
         const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
         const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
@@ -120,12 +130,13 @@ __device__ __forceinline__ void bin_window(const FilterArgs &F, const BinPlan &B
 
 // kParts: the partitioned path; the slot id holds the region within its
 // partition, parts[] the partition, and the histogram counts partitions.
+// kFast: see bin_window.
 // Each wavefront takes 64 positions at a time, their validity from the
 // valid-window bitmap (one 64-bit word), and queues the valid windows (key
 // and position) in an LDS ring of its own; it hashes 64 queued windows at a
 // time, so that no lane hashes an invalid window (the last K-1 positions of
 // every read, windows over 'N').
-template <bool kParts>
+template <bool kParts, bool kFast>
 __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                       uint64_t c1, BinPlan B,
                                                       uint32_t *__restrict__ slots,
@@ -180,12 +191,13 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
             __builtin_amdgcn_wave_barrier();
             head = (head + 64u) & (kRing - 1u);
             queued -= 64u;
-            bin_window<kParts>(F, B, key, R.k, q, len, slots, parts, s_hist);
+            bin_window<kParts, kFast>(F, B, key, R.k, q, len, slots, parts, s_hist);
         }
     }
     if (lane < queued) {  // the last windows of the wavefront's positions
         const uint32_t at = (head + lane) & (kRing - 1u);
-        bin_window<kParts>(F, B, s_key[wv][at], R.k, s_pos[wv][at], len, slots, parts, s_hist);
+        bin_window<kParts, kFast>(F, B, s_key[wv][at], R.k, s_pos[wv][at], len, slots, parts,
+                                  s_hist);
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
@@ -1116,6 +1128,11 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_
 
 namespace {
 
+// The layout the hashing kernel's fast variant takes (bin_window).
+bool fast_layout(const FilterArgs &F) {
+    return F.k_h == 1 && F.eta_pow2 && F.small_dims;
+}
+
 // Partitioned chunk: hash + partition counts, partition lists, then the
 // per-partition binning for all partitions at once (list workgroups size
 // their slices from the partition sizes on the device), level 2 and the
@@ -1135,9 +1152,10 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
                            (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
                            W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
     else
-        hipLaunchKernelGGL(k_bin_count<true>, dim3(B.G), dim3(kBinWG),
-                           (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
-                           W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
+        hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<true, true> : k_bin_count<true, false>),
+                           dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R,
+                           c0, c1, B, W.slots, W.parts, W.pmat, nullptr,
+                           (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -1265,9 +1283,9 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
                            B, W.slots, nullptr, W.matrix_t, W.coarse,
                            (unsigned long long *)(W.totals + 5));
     else
-        hipLaunchKernelGGL(k_bin_count<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B,
-                           W.slots, nullptr, W.matrix_t, W.coarse,
-                           (unsigned long long *)(W.totals + 5));
+        hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<false, true> : k_bin_count<false, false>),
+                           dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots, nullptr,
+                           W.matrix_t, W.coarse, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
