@@ -89,7 +89,7 @@ def sha(t) -> str:
 
 def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
                       n_words: int, n_chunks: int = 1, partitioned: bool = False,
-                      binned: bool = True, key_bytes: int = 8) -> float:
+                      binned: bool = True, key_bytes: int = 8, entry_bytes=None) -> float:
     """Bytes one step's launches of `phase` must move by their definition
     (logical accesses, not cache lines), summed over the step's launches:
     see the per-kernel table in the design notes."""
@@ -100,7 +100,9 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_bases * 5 * k_h + entries * 8
     if phase == "part_count":        # entries of the partition lists in
         return entries * 8
-    ent = 8 if partitioned else 6    # bytes per entry: the single-level path packs them in 6
+    # bytes per entry: the single-level path packs them in 6, the partitioned
+    # path and the batched form keep 8
+    ent = entry_bytes or (8 if partitioned else 6)
     if phase == "bin_bucket":        # slot ids (or list entries) in, entries out
         return entries * 16 if partitioned else n_bases * 4 * k_h + entries * ent
     if phase == "bin_region":        # entries in and out
@@ -197,7 +199,7 @@ def ops_per_window(k_h: int, alpha: int, k: int = 31) -> int:
 
 
 def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                n_chunks=1, partitioned=False, alpha=8, k=31):
+                n_chunks=1, partitioned=False, alpha=8, k=31, entry_bytes=None):
     """Roofline of the phase with the largest total time: the hashing kernel
     against the integer-VALU peak (algorithmic ops per window), the others
     against HBM (algorithmic bytes), per launch over the average launch."""
@@ -216,7 +218,8 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
                 "ops_per_window": ops_per_window(k_h, alpha, k),
                 "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": per_step}
     nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                               partitioned, key_bytes=8 if k <= 32 else 16) / per_step
+                               partitioned, key_bytes=8 if k <= 32 else 16,
+                               entry_bytes=entry_bytes) / per_step
     achieved = nbytes / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -370,7 +373,7 @@ def _batched_leg(args, dev, sets, stream, t_gen):
         "verified_vs_oracle_digests": {"batched": batch_ok, "plain": plain_ok},
         "phases": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()},
         "roofline": roofline_of(phases, steps, total, n_windows, n_distinct, 1, n_words,
-                                "batched"),
+                                "batched", entry_bytes=8),
         "input_generation_s": round(t_gen, 1),
     }
     for f in filters:

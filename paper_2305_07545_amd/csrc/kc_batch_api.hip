@@ -84,6 +84,7 @@ kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64
     kc::BatchPlan P{};
     P.tile = tile;
     P.n_tiles = kc::tiles(n_bases);
+    P.fast = 1;
     b->h_sets.clear();
     b->h_items.clear();
     b->h_regions.clear();
@@ -99,6 +100,8 @@ kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64
         (void)kc::bin_plan(f->F, q.n_bases, bp);  // validated by the caller
         kc::SetDesc d{};
         d.F = f->F;
+        if (!(f->F.k_h == 1 && f->F.eta_pow2 && f->F.small_dims))
+            P.fast = 0;
         d.base = q.first_base;
         d.n_bases = q.n_bases;
         d.slot_base = slot;
@@ -293,7 +296,8 @@ std::vector<uint8_t> call_key(const kc_batch *b, const kc_set *sets, uint32_t n_
                              n_bases, flags & ~(uint32_t)KC_BATCH_TUNE, (uint64_t)(uintptr_t)s,
                              b->tile, n_sets,
                              (uint64_t)(uintptr_t)W.codes, (uint64_t)(uintptr_t)W.inv,
-                             (uint64_t)(uintptr_t)W.rs, (uint64_t)(uintptr_t)W.flags8,
+                             (uint64_t)(uintptr_t)W.rs, (uint64_t)(uintptr_t)W.valid,
+                             (uint64_t)(uintptr_t)W.flags8,
                              (uint64_t)(uintptr_t)W.tile_a, (uint64_t)(uintptr_t)W.off_a,
                              (uint64_t)(uintptr_t)W.partial64, (uint64_t)(uintptr_t)W.totals,
                              (uint64_t)(uintptr_t)W.tmask};

@@ -73,16 +73,27 @@ __global__ void kb_zero_valid(unsigned long long *__restrict__ valid, uint32_t n
         valid[s] = 0;
 }
 
+// kFast: every set has one hash function, a power-of-two eta and
+// dimensions of mod_small (checked by the planner).
+template <bool kFast>
 __device__ __forceinline__ void kb_bin_window(const SetDesc &S, const FilterArgs &F, uint64_t fwd,
                                               uint64_t q, uint32_t *__restrict__ slots,
                                               uint32_t *s_hist) {
     const uint32_t shift = S.region_shift;
     const uint64_t smask = (1ull << shift) - 1ull;
     const Canon c = canonical_fast(fwd, S.k);
-    for (uint32_t a = 1; a <= F.k_h; a++) {
+    const uint32_t k_h = kFast ? 1u : F.k_h;
+    for (uint32_t a = 1; a <= k_h; a++) {
         uint64_t word;
         uint32_t l;
-        slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
+        const uint64_t h = a == 1 ? c.h1 : hash_a(c.b0, c.b1, a);
+        if (kFast) {
+            l = (uint32_t)h & (F.eta - 1u);
+            word = (uint64_t)mod_small(h, (uint32_t)F.X, F.mX) * (uint32_t)F.Y +
+                   mod_small(h, (uint32_t)F.Y, F.mY);
+        } else {
+            slot_of(F, h, word, l);
+        }
         const uint32_t r = (uint32_t)(word >> shift);
         slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + q] =
             (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
@@ -107,6 +118,7 @@ __global__ void __launch_bounds__(256) kb_valid(const SetDesc *__restrict__ sets
 // single-set bin pass, each wavefront takes its positions' validity from
 // the valid-window bitmap, queues its valid windows in an LDS ring and
 // hashes 64 of them at a time.
+template <bool kFast>
 __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict__ sets,
                                                        const uint32_t *__restrict__ item_set,
                                                        ReadsArgs R, uint64_t tile,
@@ -159,12 +171,12 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
             __builtin_amdgcn_wave_barrier();
             head = (head + 64u) & (kRing - 1u);
             queued -= 64u;
-            kb_bin_window(S, F, key, q, slots, s_hist);
+            kb_bin_window<kFast>(S, F, key, q, slots, s_hist);
         }
     }
     if (lane < queued) {
         const uint32_t at = (head + lane) & (kRing - 1u);
-        kb_bin_window(S, F, s_key[wv][at], s_pos[wv][at], slots, s_hist);
+        kb_bin_window<kFast>(S, F, s_key[wv][at], s_pos[wv][at], slots, s_hist);
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
@@ -524,8 +536,9 @@ hipError_t launch_batch_bins(const BatchPlan &bp, const BatchBuffers &Bf, const 
         return ev;
     if (P)
         P->begin(kPhBinCount, s);
-    hipLaunchKernelGGL(kb_bin_count, dim3(bp.n_items), dim3(kBinWG), 0, s, Bf.sets, Bf.item_set, R,
-                       bp.tile, Bf.slots, Bf.matrix_t, Bf.valid);
+    hipLaunchKernelGGL((bp.fast ? kb_bin_count<true> : kb_bin_count<false>), dim3(bp.n_items),
+                       dim3(kBinWG), 0, s, Bf.sets, Bf.item_set, R, bp.tile, Bf.slots,
+                       Bf.matrix_t, Bf.valid);
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();

@@ -46,6 +46,7 @@ struct BatchPlan {
     uint64_t n_tiles;         // 1024-position tiles of the whole buffer
     uint64_t n_slots;
     uint64_t entries_cap;
+    uint32_t fast;            // every set has the hashing kernel's fast layout
 };
 
 struct BatchBuffers {
