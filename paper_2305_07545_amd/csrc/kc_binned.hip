@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
 }
 
 // The same for k-mers of 33..64 bases (128-bit keys).
-template <bool kParts>
+template <bool kParts, bool kFast>
 __device__ __forceinline__ void bin_window_wide(const FilterArgs &F, const BinPlan &B,
                                                 Key128 fwd, uint32_t K, uint64_t q, uint64_t len,
                                                 uint32_t *__restrict__ slots,
@@ -223,10 +223,18 @@ __device__ __forceinline__ void bin_window_wide(const FilterArgs &F, const BinPl
     const uint32_t shift = B.region_shift;
     const uint64_t smask = (1ull << shift) - 1ull;
     const CanonWide c = canonical_wide(fwd, K);
-    for (uint32_t a = 1; a <= F.k_h; a++) {
+    const uint32_t k_h = kFast ? 1u : F.k_h;
+    for (uint32_t a = 1; a <= k_h; a++) {
         uint64_t word;
         uint32_t l;
-        slot_of(F, a == 1 ? c.h1 : hash_a_wide(c.b, a), word, l);
+        const uint64_t h = a == 1 ? c.h1 : hash_a_wide(c.b, a);
+        if (kFast) {
+            l = (uint32_t)h & (F.eta - 1u);
+            word = (uint64_t)mod_small(h, (uint32_t)F.X, F.mX) * (uint32_t)F.Y +
+                   mod_small(h, (uint32_t)F.Y, F.mY);
+        } else {
+            slot_of(F, h, word, l);
+        }
         const uint32_t r = (uint32_t)(word >> shift);
         const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
         const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
@@ -244,7 +252,7 @@ __device__ __forceinline__ void bin_window_wide(const FilterArgs &F, const BinPl
 // k_bin_count for k-mers of 33..64 bases: each lane reads its own window
 // (five code words) and the ring holds 128-bit keys; everything else is
 // k_bin_count's.
-template <bool kParts>
+template <bool kParts, bool kFast>
 __global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                            uint64_t c1, BinPlan B,
                                                            uint32_t *__restrict__ slots,
@@ -300,13 +308,13 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsAr
             __builtin_amdgcn_wave_barrier();
             head = (head + 64u) & (kRing - 1u);
             queued -= 64u;
-            bin_window_wide<kParts>(F, B, key, R.k, q, len, slots, parts, s_hist);
+            bin_window_wide<kParts, kFast>(F, B, key, R.k, q, len, slots, parts, s_hist);
         }
     }
     if (lane < queued) {
         const uint32_t at = (head + lane) & (kRing - 1u);
-        bin_window_wide<kParts>(F, B, Key128{s_klo[wv][at], s_khi[wv][at]}, R.k, s_pos[wv][at],
-                                len, slots, parts, s_hist);
+        bin_window_wide<kParts, kFast>(F, B, Key128{s_klo[wv][at], s_khi[wv][at]}, R.k,
+                                       s_pos[wv][at], len, slots, parts, s_hist);
     }
     atomicAdd(&s_valid, nv);
     __syncthreads();
@@ -1148,9 +1156,10 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (P)
         P->begin(kPhBinCount, s);
     if (R.k > 32)
-        hipLaunchKernelGGL(k_bin_count_wide<true>, dim3(B.G), dim3(kBinWG),
-                           (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, W.slots,
-                           W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
+        hipLaunchKernelGGL(
+            (fast_layout(F) ? k_bin_count_wide<true, true> : k_bin_count_wide<true, false>),
+            dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B,
+            W.slots, W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
     else
         hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<true, true> : k_bin_count<true, false>),
                            dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R,
@@ -1279,9 +1288,10 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (P)
         P->begin(kPhBinCount, s);
     if (R.k > 32)
-        hipLaunchKernelGGL(k_bin_count_wide<false>, dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1,
-                           B, W.slots, nullptr, W.matrix_t, W.coarse,
-                           (unsigned long long *)(W.totals + 5));
+        hipLaunchKernelGGL(
+            (fast_layout(F) ? k_bin_count_wide<false, true> : k_bin_count_wide<false, false>),
+            dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots, nullptr, W.matrix_t,
+            W.coarse, (unsigned long long *)(W.totals + 5));
     else
         hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<false, true> : k_bin_count<false, false>),
                            dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots, nullptr,
