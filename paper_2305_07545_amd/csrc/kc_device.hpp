@@ -342,9 +342,17 @@ KC_HD void wave_load(const ReadsArgs &R, uint64_t pb, WaveWords &w) {
     }
 }
 
-// Valid-window bits of positions pb .. pb + 63 (pb a multiple of 64).
+// Valid-window bits of positions pb .. pb + 63 (pb a multiple of 64).  On
+// the device the two words are read through a constant-address-space view
+// (they are wavefront-uniform and not written while a kernel reads them),
+// so that they come by a scalar load and stay in scalar registers.
 KC_HD uint64_t wave_valid(const ReadsArgs &R, uint64_t pb) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) uint32_t ConstWord;
+    ConstWord *vp = (ConstWord *)(R.valid + (pb >> 5));
+#else
     const uint32_t *vp = R.valid + (pb >> 5);
+#endif
     return ((uint64_t)vp[1] << 32) | vp[0];
 }
 
