@@ -143,24 +143,25 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
     R.k = S.k;
     uint32_t nv = 0;
     uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
+    // set-relative 32-bit positions (sets start at multiples of 4096)
+    const uint32_t *__restrict__ codes = R.codes + (S.base >> 4);
+    uint32_t *__restrict__ sl = slots + S.slot_base;
     for (uint64_t pb = it.g0 + 64u * wv; pb < it.g1; pb += kBinWG) {
-        uint64_t m = wave_valid(R, pb);  // the wave's valid windows
-        if (it.g1 - pb < 64u)
-            m &= (1ull << (it.g1 - pb)) - 1ull;
-        const uint64_t p = pb + lane;
-        const bool in = p < it.g1;
-        const bool ok = (m >> lane) & 1ull;
-        if (!ok && in)
+        const uint64_t m_in = it.g1 - pb < 64u ? (1ull << (it.g1 - pb)) - 1ull : ~0ull;
+        const uint64_t m = wave_valid(R, pb) & m_in;  // the wave's valid windows
+        const uint64_t m_skip = m_in & ~m;
+        const uint32_t pos = (uint32_t)(pb - S.base) + lane;
+        if ((m_skip >> lane) & 1ull)
             for (uint32_t a = 1; a <= F.k_h; a++)
-                slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + (p - S.base)] = kNoSlot;
-        if (ok) {
-            const uint64_t fwd = window_key(R.codes, p, S.k);
+                sl[(uint64_t)(a - 1) * S.n_bases + pos] = kNoSlot;
+        if ((m >> lane) & 1ull) {
+            const uint64_t fwd = window_key(codes, pos, S.k);
             nv++;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             const uint32_t at = (head + queued + rank) & (kRing - 1u);
             s_key[wv][at] = fwd;
-            s_pos[wv][at] = (uint32_t)(p - S.base);
+            s_pos[wv][at] = pos;
         }
         queued += (uint32_t)__popcll(m);
         __builtin_amdgcn_wave_barrier();

@@ -171,14 +171,14 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
         const uint64_t m_in = g1 - pb < 64u ? (1ull << (g1 - pb)) - 1ull : ~0ull;
         const uint64_t m = wave_valid(R, pb) & m_in;
         const uint64_t m_skip = m_in & ~m;
-        const uint32_t q = (uint32_t)(pb - c0) + lane;
+        const uint32_t pos = (uint32_t)(pb - c0) + lane;
         if ((m_skip >> lane) & 1ull)
             for (uint32_t a = 1; a <= F.k_h; a++)
-                slots[(uint64_t)(a - 1) * len + q] = kNoSlot;
+                slots[(uint64_t)(a - 1) * len + pos] = kNoSlot;
         if ((m >> lane) & 1ull) {
             // the lane's three code words
-            const uint32_t w = q >> 4;
-            const uint32_t sh = 2u * (q & 15u);
+            const uint32_t w = pos >> 4;
+            const uint32_t sh = 2u * (pos & 15u);
             const uint32_t w0 = codes[w], w1 = codes[w + 1], w2 = codes[w + 2];
             const uint32_t top_hi = (uint32_t)(((((uint64_t)w0 << 32) | w1) << sh) >> 32);
             const uint32_t top_lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32u - sh));
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             const uint32_t at = (head + queued + rank) & (kRing - 1u);
             s_key[wv][at] = fwd;
-            s_pos[wv][at] = q;
+            s_pos[wv][at] = pos;
         }
         queued += (uint32_t)__popcll(m);
         __builtin_amdgcn_wave_barrier();
@@ -287,25 +287,24 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsAr
     const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
     uint32_t nv = 0;
     uint32_t head = 0, queued = 0;
+    const uint32_t *__restrict__ codes = R.codes + (c0 >> 4);  // as in k_bin_count
     for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
-        uint64_t m = wave_valid(R, pb);  // the wave's valid windows
-        if (g1 - pb < 64u)
-            m &= (1ull << (g1 - pb)) - 1ull;
-        const uint64_t p = pb + lane;
-        const bool in = p < g1;
-        const bool valid = (m >> lane) & 1ull;
-        if (!valid && in)
+        const uint64_t m_in = g1 - pb < 64u ? (1ull << (g1 - pb)) - 1ull : ~0ull;
+        const uint64_t m = wave_valid(R, pb) & m_in;  // the wave's valid windows
+        const uint64_t m_skip = m_in & ~m;
+        const uint32_t pos = (uint32_t)(pb - c0) + lane;
+        if ((m_skip >> lane) & 1ull)
             for (uint32_t a = 1; a <= F.k_h; a++)
-                slots[(uint64_t)(a - 1) * len + (p - c0)] = kNoSlot;
-        if (valid) {
-            const Key128 fwd = window_key_wide(R.codes, p, R.k);
+                slots[(uint64_t)(a - 1) * len + pos] = kNoSlot;
+        if ((m >> lane) & 1ull) {
+            const Key128 fwd = window_key_wide(codes, pos, R.k);
             nv++;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             const uint32_t at = (head + queued + rank) & (kRing - 1u);
             s_klo[wv][at] = fwd.lo;
             s_khi[wv][at] = fwd.hi;
-            s_pos[wv][at] = (uint32_t)(p - c0);
+            s_pos[wv][at] = pos;
         }
         queued += (uint32_t)__popcll(m);
         __builtin_amdgcn_wave_barrier();
