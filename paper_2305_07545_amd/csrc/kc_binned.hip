@@ -386,7 +386,28 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
     // the slot ids of the batch at q0 (entry i: hash function i / batch,
     // position i % batch); the next batch's are requested before this one
     // is sorted, so that their latency overlaps the LDS work
+    // A full batch of one hash function is loaded 16 bytes per lane (a
+    // thread's entries 4v .. 4v + 3 are consecutive positions); other batches
+    // one slot id per lane.  pos_of: the batch index of a thread's entry u.
+    auto full = [&](uint32_t q0) { return k_h == 1u && q0 + batch <= g1; };
+    auto pos_of = [&](bool vec, int u) -> uint32_t {
+        return vec ? (uint32_t)(u >> 2) * (4u * kBinWG) + 4u * threadIdx.x + (uint32_t)(u & 3)
+                   : threadIdx.x + (uint32_t)u * kBinWG;
+    };
+    static_assert(kPer % 4 == 0, "whole 16-byte loads per thread");
     auto load = [&](uint32_t q0, uint32_t(&id)[kPer]) {
+        if (full(q0)) {
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(slots + q0);  // q0 % 4 == 0
+#pragma unroll
+            for (int v = 0; v < kPer / 4; v++) {
+                const uint4 x = p4[(uint32_t)v * kBinWG + threadIdx.x];
+                id[4 * v] = x.x;
+                id[4 * v + 1] = x.y;
+                id[4 * v + 2] = x.z;
+                id[4 * v + 3] = x.w;
+            }
+            return;
+        }
         const uint32_t nq = (q0 + batch < g1 ? q0 + batch : g1) - q0;
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
@@ -400,6 +421,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
     if (g0 < g1)
         load(g0, next);
     for (uint32_t q0 = g0; q0 < g1; q0 += batch) {
+        const bool vec = full(q0);
         uint32_t id[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; u++)
@@ -425,7 +447,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot) {
-                const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
+                const uint32_t i = pos_of(vec, u);
                 const uint32_t q = q0 - s0 + (i & (batch - 1u));  // ts: within the slice
                 const uint32_t b = id[u] >> bshift;
                 const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
