@@ -139,7 +139,7 @@ kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64
         P.max_G = d.G > P.max_G ? d.G : P.max_G;
         P.max_regions = d.n_regions > P.max_regions ? d.n_regions : P.max_regions;
         mat += (uint64_t)d.n_regions * d.G;
-        slot += q.n_bases * f->F.k_h;
+        slot += (q.n_bases * f->F.k_h + 3u) & ~3ull;  // slot bases stay 16-byte aligned
     }
     P.n_sets = (uint32_t)b->h_sets.size();
     P.n_items = item;

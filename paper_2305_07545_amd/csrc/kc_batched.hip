@@ -263,15 +263,37 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
     const uint32_t *__restrict__ sl = slots + S.slot_base;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
+    // A full batch of one hash function is loaded 16 bytes per lane (slot
+    // bases are multiples of 4 and q0 of 512: a thread's entries 4v .. 4v + 3
+    // are consecutive positions); other batches one slot id per lane.
+    // pos_of: the batch index of a thread's entry u.
+    static_assert(kPer % 4 == 0, "whole 16-byte loads per thread");
+    auto pos_of = [&](bool vec, int u) -> uint32_t {
+        return vec ? (uint32_t)(u >> 2) * (4u * kBinWG) + 4u * threadIdx.x + (uint32_t)(u & 3)
+                   : threadIdx.x + (uint32_t)u * kBinWG;
+    };
     for (uint32_t q0 = q_lo; q0 < q_hi; q0 += batch) {
         const uint32_t nq = (q_hi - q0 < batch ? q_hi - q0 : batch);
+        const bool vec = k_h == 1u && nq == batch;
         uint32_t id[kPer];
+        if (vec) {
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(sl + q0);
 #pragma unroll
-        for (int u = 0; u < kPer; u++) {
-            const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
-            const uint32_t a = i >> batch_log;
-            const uint32_t qq = i & (batch - 1u);
-            id[u] = (a < k_h && qq < nq) ? sl[a * nb + q0 + qq] : kNoSlot;
+            for (int v = 0; v < kPer / 4; v++) {
+                const uint4 x = p4[(uint32_t)v * kBinWG + threadIdx.x];
+                id[4 * v] = x.x;
+                id[4 * v + 1] = x.y;
+                id[4 * v + 2] = x.z;
+                id[4 * v + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kPer; u++) {
+                const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
+                const uint32_t a = i >> batch_log;
+                const uint32_t qq = i & (batch - 1u);
+                id[u] = (a < k_h && qq < nq) ? sl[a * nb + q0 + qq] : kNoSlot;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kPer; u++)
@@ -310,7 +332,7 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot) {
-                const uint32_t i = threadIdx.x + (uint32_t)u * kBinWG;
+                const uint32_t i = pos_of(vec, u);
                 const uint32_t q = q0 + (i & (batch - 1u));
                 const uint32_t r = id[u] >> kLocalBits;
                 const uint32_t j = s_start[r] + atomicAdd(&s_fill[r], 1u);
