@@ -149,10 +149,17 @@ def traffic_for(phase: str, workload: str):
     return None if ph is None else ph.get("bytes_per_launch")
 
 
+# the sources that define the kernels (host-only API code does not change
+# what a kernel moves)
+KERNEL_SOURCES = ["kc_batched.hip", "kc_batched.hpp", "kc_binned.hip", "kc_device.hpp",
+                  "kc_kernels.hip", "kc_kernels.hpp", "kc_scan.hip"]
+
+
 def source_digest() -> str:
+    """Digest of the kernel sources the committed traffic counters belong to."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2305_07545_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())

@@ -114,6 +114,19 @@ kc_status kc_dims(double n_items, double fpp, uint64_t *X, uint64_t *Y);
 /* Counters per 64-bit cell: floor(64 / alpha) (supplement counter table). */
 uint32_t kc_eta(uint32_t alpha);
 
+/* Bytes of the countBF words of a layout: X * Y * 8 (the caller allocates
+ * them, Sec. 2.1: X x Y cells of 64 bits).  0 for an invalid layout.  Host
+ * only, pure. */
+uint64_t kc_filter_bytes(const kc_layout *layout);
+
+/* Device bytes a handle of this layout allocates for inserts of up to
+ * max_bases bases (kc_reserve(max_bases) on a new handle: the per-position
+ * and per-tile buffers and the binned, partitioned or direct path's
+ * scratch, as kc_insert would size them), so that callers can budget HBM
+ * before creating handles.  0 for an invalid layout.  Host only, pure: it
+ * counts the allocations without making them and touches no device. */
+uint64_t kc_scratch_bytes(const kc_layout *layout, uint64_t max_bases);
+
 /* Create a countBF over caller-owned device memory `words_dev` (X*Y uint64,
  * 8-byte aligned).  zero != 0: the library clears the words (async on
  * `stream`) and the filter starts empty; zero == 0: the words are taken as

@@ -12,11 +12,13 @@ from .kmerco import (  # noqa: F401
     Server,
     dims,
     eta,
+    filter_bytes,
     key_words,
     load_library,
     pack_read_sets,
     parse_fastx,
     read_fastx,
     run_kmerco,
+    scratch_bytes,
     strerror,
 )

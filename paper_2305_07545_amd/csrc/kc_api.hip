@@ -41,7 +41,12 @@ bool valid_layout(const kc_layout *L) {
     return true;
 }
 
-void wait_idle(kc_filter *f) { (void)hipStreamSynchronize(f->last); }
+thread_local uint64_t *g_size_only = nullptr;
+
+void wait_idle(kc_filter *f) {
+    if (!g_size_only)
+        (void)hipStreamSynchronize(f->last);
+}
 
 // per-position buffers for inserts of up to n bases (waits for `wait_on`
 // before releasing smaller ones); valid_bitmap: with the valid-window bitmap
@@ -49,7 +54,8 @@ void wait_idle(kc_filter *f) { (void)hipStreamSynchronize(f->last); }
 kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n, bool valid_bitmap) {
     if (W.codes && n <= W.cap && (W.valid || !valid_bitmap))
         return KC_OK;
-    (void)hipStreamSynchronize(wait_on);
+    if (!g_size_only)
+        (void)hipStreamSynchronize(wait_on);
     dev_free(W.codes);
     dev_free(W.inv);
     dev_free(W.rs);
@@ -71,7 +77,8 @@ kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
     uint64_t nt = kc::tiles(n) + 1;
     if (W.tile_a && nt <= W.tile_cap)
         return KC_OK;
-    (void)hipStreamSynchronize(wait_on);
+    if (!g_size_only)
+        (void)hipStreamSynchronize(wait_on);
     dev_free(W.tile_a);
     dev_free(W.tile_b);
     dev_free(W.tile_c);
@@ -221,6 +228,8 @@ kc_status ensure_aux(kc_filter *f, hipStream_t s) {
     uint64_t n_aux = f->layout.X * f->layout.Y * f->F.eta;
     if (!dev_alloc(&f->F.aux, n_aux))
         return KC_ENOMEM;
+    if (g_size_only)
+        return KC_OK;
     return kc::fill_u32(f->F.aux, n_aux, kc::kIdle, s) == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
@@ -348,6 +357,33 @@ uint64_t filter_private_bytes(const kc_layout &layout) {
     return layout.X * layout.Y * F.eta * sizeof(uint32_t);
 }
 
+// The layout-derived state of a handle: dimensions and reduction constants,
+// chunk sizes and path choices (no device state).
+void init_filter(kc_filter *f, const kc_layout *layout) {
+    f->layout = *layout;
+    f->W = &f->own;
+    f->k = 0;
+    f->chunk = chunk_size(kc::kChunk);
+    f->bin_chunk = chunk_size(kc::kBinChunk);
+    f->part_chunk = chunk_size(kc::kPartChunk);
+    f->part_log = part_log_from_env();
+    f->path = path_from_env();
+    kc::FilterArgs &F = f->F;
+    F.words = nullptr;
+    F.aux = nullptr;
+    F.X = layout->X;
+    F.Y = layout->Y;
+    F.mX = UINT64_MAX / layout->X;
+    F.mY = UINT64_MAX / layout->Y;
+    F.alpha = layout->alpha;
+    F.eta = 64u / layout->alpha;
+    F.mEta = UINT64_MAX / F.eta;
+    F.eta_pow2 = (F.eta & (F.eta - 1)) == 0;
+    F.small_dims = layout->X <= kc::kSmallDivisor && layout->Y <= kc::kSmallDivisor;
+    F.k_h = layout->k_h;
+    F.field_max = (layout->alpha >= 64) ? ~0ull : ((1ull << layout->alpha) - 1ull);
+}
+
 }  // namespace kcapi
 
 namespace {
@@ -445,6 +481,35 @@ int kc_version(void) { return 2; }
 
 uint32_t kc_eta(uint32_t alpha) { return (alpha >= 1 && alpha <= 64) ? 64u / alpha : 0u; }
 
+uint64_t kc_filter_bytes(const kc_layout *layout) {
+    return valid_layout(layout) ? layout->X * layout->Y * sizeof(uint64_t) : 0u;
+}
+
+uint64_t kc_scratch_bytes(const kc_layout *layout, uint64_t max_bases) {
+    if (!valid_layout(layout))
+        return 0;
+    // kc_reserve's allocations on a handle of this layout, counted, not made
+    kc_filter f{};
+    init_filter(&f, layout);
+    uint64_t bytes = sizeof(uint32_t);  // the handle's status word
+    g_size_only = &bytes;
+    kc_status st = ensure_scalars(&f);
+    if (st == KC_OK)
+        st = ensure_positions(&f, max_bases);
+    if (st == KC_OK)
+        st = ensure_tiles(&f, max_bases);
+    if (st == KC_OK && max_bases > 0) {
+        kc::BinPlan plan{};
+        uint64_t bchunk = 0;
+        st = choose_plan(&f, max_bases, plan, bchunk) ? ensure_plan(&f, plan, bchunk)
+                                                      : ensure_aux(&f, nullptr);
+    }
+    g_size_only = nullptr;
+    f.own = kc::Workspace{};  // placeholders only
+    f.F.aux = nullptr;
+    return st == KC_OK ? bytes : 0u;
+}
+
 kc_status kc_dims(double n_items, double fpp, uint64_t *X, uint64_t *Y) {
     if (!X || !Y || !(n_items > 0) || !(fpp > 0) || !(fpp < 1))
         return KC_EINVAL;
@@ -472,31 +537,11 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     kc_filter *f = new (std::nothrow) kc_filter();
     if (!f)
         return KC_ENOMEM;
-    f->layout = *layout;
-    f->W = &f->own;
+    init_filter(f, layout);
     f->device = dev;
     f->zero = zero != 0;
-    f->k = 0;
     f->last = (hipStream_t)stream;
-    f->chunk = chunk_size(kc::kChunk);
-    f->bin_chunk = chunk_size(kc::kBinChunk);
-    f->part_chunk = chunk_size(kc::kPartChunk);
-    f->part_log = part_log_from_env();
-    f->path = path_from_env();
-    kc::FilterArgs &F = f->F;
-    F.words = words_dev;
-    F.aux = nullptr;
-    F.X = layout->X;
-    F.Y = layout->Y;
-    F.mX = UINT64_MAX / layout->X;
-    F.mY = UINT64_MAX / layout->Y;
-    F.alpha = layout->alpha;
-    F.eta = 64u / layout->alpha;
-    F.mEta = UINT64_MAX / F.eta;
-    F.eta_pow2 = (F.eta & (F.eta - 1)) == 0;
-    F.small_dims = layout->X <= kc::kSmallDivisor && layout->Y <= kc::kSmallDivisor;
-    F.k_h = layout->k_h;
-    F.field_max = (layout->alpha >= 64) ? ~0ull : ((1ull << layout->alpha) - 1ull);
+    f->F.words = words_dev;
     hipStream_t s = (hipStream_t)stream;
     if (!dev_alloc(&f->status, 1)) {
         delete f;

@@ -38,14 +38,26 @@ struct DeviceGuard {
     ~DeviceGuard();
 };
 
+// Sizing without a device (kc_scratch_bytes): while set, dev_alloc adds the
+// bytes it would allocate here and hands out a placeholder that is never
+// dereferenced, dev_free and the workspace waits do nothing.
+extern thread_local uint64_t *g_size_only;
+
 template <typename T>
 bool dev_alloc(T **p, uint64_t count) {
-    return hipMalloc((void **)p, (count ? count : 1) * sizeof(T)) == hipSuccess;
+    const uint64_t bytes = (count ? count : 1) * sizeof(T);
+    if (g_size_only) {
+        *g_size_only += bytes;
+        *p = reinterpret_cast<T *>((uintptr_t)256);
+        return true;
+    }
+    return hipMalloc((void **)p, bytes) == hipSuccess;
 }
 
 template <typename T>
 void dev_free(T *&p) {
-    (void)hipFree(p);
+    if (!g_size_only)
+        (void)hipFree(p);
     p = nullptr;
 }
 

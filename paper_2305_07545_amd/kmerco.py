@@ -93,6 +93,8 @@ SIGNATURES = {
     "kc_parse_fastx": (_i, [_vp, _u64, _u32, _vp, _u64, _vp, _u64, ctypes.POINTER(_u64),
                             ctypes.POINTER(_u64)]),
     "kc_eta": (_u32, [_u32]),
+    "kc_filter_bytes": (_u64, [ctypes.POINTER(kc_layout)]),
+    "kc_scratch_bytes": (_u64, [ctypes.POINTER(kc_layout), _u64]),
     "kc_create": (_i, [ctypes.POINTER(kc_layout), _vp, _i, _vp, ctypes.POINTER(_vp)]),
     "kc_destroy": (None, [_vp]),
     "kc_reserve": (_i, [_vp, _u64]),
@@ -216,6 +218,20 @@ def read_fastx(path: str, one_sequence: bool = False):
 
 def eta(alpha: int) -> int:
     return int(load_library().kc_eta(alpha))
+
+
+def filter_bytes(X: int, Y: int, alpha: int = 8, k_h: int = 1) -> int:
+    """Bytes of the countBF words of a layout (0 if invalid)."""
+    L = kc_layout(X, Y, alpha, k_h)
+    return int(load_library().kc_filter_bytes(ctypes.byref(L)))
+
+
+def scratch_bytes(X: int, Y: int, max_bases: int, alpha: int = 8, k_h: int = 1) -> int:
+    """Device bytes a handle of this layout allocates for inserts of up to
+    max_bases bases (what CountBF.reserve(max_bases) allocates; 0 if the
+    layout is invalid).  Host only."""
+    L = kc_layout(X, Y, alpha, k_h)
+    return int(load_library().kc_scratch_bytes(ctypes.byref(L), int(max_bases)))
 
 
 def _stream_ptr(stream) -> int:

@@ -69,3 +69,20 @@ def test_null_handle_calls_are_rejected():
     assert lib.kc_sync(None) == kmerco.KC_EINVAL
     assert lib.kc_reserve(None, 10) == kmerco.KC_EINVAL
     lib.kc_destroy(None)
+
+
+def test_filter_and_scratch_bytes_on_the_host():
+    """kc_filter_bytes is X*Y*8; kc_scratch_bytes counts what kc_reserve would
+    allocate without a device: about 22 bytes per base on the single-level
+    binned path (a 150 M-base insert into the 55.7 MB countBF), growing with
+    the reservation and with the hash functions, 0 for invalid layouts."""
+    assert P.filter_bytes(2621, 2657) == 2621 * 2657 * 8
+    assert P.filter_bytes(0, 5) == 0 and P.scratch_bytes(5, 7, 100, alpha=0) == 0
+    sizes = [P.scratch_bytes(2621, 2657, n) for n in (0, 1000, 10**6, 150 * 10**6, 2**28)]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:])) and sizes[0] > 0
+    per_base = sizes[3] / (150 * 10**6)
+    assert 20 < per_base < 25, per_base
+    assert P.scratch_bytes(2621, 2657, 10**7, k_h=3) > P.scratch_bytes(2621, 2657, 10**7)
+    # beyond one chunk of the binned path the per-chunk scratch stops growing
+    assert P.scratch_bytes(2621, 2657, 2**30) - P.scratch_bytes(2621, 2657, 2**29) < \
+        12 * 2**29
