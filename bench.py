@@ -178,7 +178,47 @@ def cpu_baseline(rs, X, Y, n_sample_reads, k=0):
     secs = time.perf_counter() - t
     return {"value": nw / secs, "unit": "insertions/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} of {rs.n_reads} reads ({nw} k-mers), insert + classify, "
-                      f"countBF {X}x{Y}, single-threaded C oracle, {secs:.1f} s"}
+                      f"countBF {X}x{Y}, single-threaded C oracle, {secs:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and logical CPU count (context for the oracle's
+    timing)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def h2d_reads(rs, dev, reps: int = 3) -> dict:
+    """The host-to-device copy of the workload's reads and offsets from
+    pinned memory (outside the timed steps, which start from device-resident
+    reads): its time, and the insertion rate a step would reach if the reads
+    had to cross PCIe first."""
+    import numpy as np
+    import torch
+    reads_h = torch.from_numpy(rs.reads).pin_memory()
+    offs_h = torch.from_numpy(rs.offsets.view(np.int64)).pin_memory()
+    reads_d = torch.empty_like(reads_h, device=dev)
+    offs_d = torch.empty_like(offs_h, device=dev)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reads_d.copy_(reads_h, non_blocking=True)
+        offs_d.copy_(offs_h, non_blocking=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    secs = sorted(times)[len(times) // 2]
+    nbytes = reads_h.numel() + offs_h.numel() * 8
+    return {"ms": secs * 1e3, "bytes": nbytes, "GBps": nbytes / secs / 1e9}
 
 
 def set_baseline(n_sets: int):
@@ -586,6 +626,8 @@ def main():
     roofline = roofline_of(timed, args.steps, n_bases, n_windows, n_distinct, k_h, X * Y,
                            args.workload, n_chunks, partitioned, alpha, k)
 
+    h2d = h2d_reads(rs, dev)
+    h2d["insertions_per_s_incl_h2d"] = n_windows / ((h2d["ms"] + ms_step) / 1e3)
     out = {
         "metric": "k-mer insertions/s",
         "value": value,
@@ -608,6 +650,7 @@ def main():
         "phases": per_phase,
         "roofline": roofline,
         "phases_profiled_steps": args.profile_steps,
+        "h2d_reads": h2d,
         "hbm_rooflines": hbm_rooflines(phases, args.profile_steps, n_bases, n_windows,
                                        n_distinct, k_h, X * Y, args.workload, n_chunks,
                                        partitioned, k),
