@@ -626,6 +626,22 @@ def main():
     roofline = roofline_of(timed, args.steps, n_bases, n_windows, n_distinct, k_h, X * Y,
                            args.workload, n_chunks, partitioned, alpha, k)
 
+    # classification on its own (kc_classify, Query-II over the step's
+    # distinct list): in the timed steps it is fused into the region pass
+    cls_ms = []
+    n_keys = torch.tensor([n_distinct], dtype=torch.int64, device=dev)
+    cls_out = [torch.empty(n_distinct * w, dtype=torch.int64, device=dev) for _ in range(2)]
+    for _ in range(4):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bf.classify(distinct, n_keys, rs.tau, trust=cls_out[0], err=cls_out[1],
+                    keys_cap=n_distinct, stream=stream)
+        torch.cuda.synchronize()
+        cls_ms.append((time.perf_counter() - t) * 1e3)
+    bf.sync()
+    cls = {"ms": sorted(cls_ms[1:])[1], "keys": n_distinct,
+           "keys_per_s": n_distinct / (sorted(cls_ms[1:])[1] / 1e3)}
+    del cls_out
     h2d = h2d_reads(rs, dev)
     h2d["insertions_per_s_incl_h2d"] = n_windows / ((h2d["ms"] + ms_step) / 1e3)
     out = {
@@ -651,6 +667,7 @@ def main():
         "roofline": roofline,
         "phases_profiled_steps": args.profile_steps,
         "h2d_reads": h2d,
+        "classify_separately": cls,
         "hbm_rooflines": hbm_rooflines(phases, args.profile_steps, n_bases, n_windows,
                                        n_distinct, k_h, X * Y, args.workload, n_chunks,
                                        partitioned, k),
