@@ -106,8 +106,11 @@ kc_status ensure_tiles(kc_filter *f, uint64_t n) { return ensure_tiles(*f->W, f-
 // binned-path buffers for one chunk of the given plan
 kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
     kc::Workspace &W = *f->W;
-    const uint64_t n_mat = (uint64_t)B.n_regions * B.G;
-    const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
+    // smaller chunks of the same countBF make at most kBinSpread workgroups:
+    // room for them too, so that a reservation covers every smaller insert
+    const uint64_t g = B.G > kc::kBinSpread ? B.G : kc::kBinSpread;
+    const uint64_t n_mat = (uint64_t)B.n_regions * g;
+    const uint64_t n_coarse = (uint64_t)B.n_buckets * g;
     const uint64_t n_slots = chunk_positions * f->layout.k_h;
     const uint64_t n_ent = n_slots;
     if (W.matrix && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap && n_slots <= W.slots_cap &&

@@ -1152,9 +1152,13 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_
         bshift++;
     B.bucket_shift = bshift;
     B.n_buckets = (uint32_t)((n_regions + (1ull << bshift) - 1) >> bshift);
-    // positions per bin workgroup: enough to amortise the histograms, and a
-    // region matrix of at most kMaxMatrix counts
-    uint64_t tile = kBinTileMin;
+    // positions per bin workgroup: kBinTileMin, enough to amortise the
+    // histograms (small chunks: fewer, down to kBinTileFloor, so that about
+    // kBinSpread workgroups still spread over the chip), and a region matrix
+    // of at most kMaxMatrix counts
+    uint64_t tile = (chunk_positions + kBinSpread - 1) / kBinSpread;
+    tile = (tile + kBinWG - 1) / kBinWG * kBinWG;
+    tile = tile < kBinTileFloor ? kBinTileFloor : (tile > kBinTileMin ? kBinTileMin : tile);
     while ((chunk_positions + tile - 1) / tile * n_regions > kMaxMatrix)
         tile *= 2;
     B.tile = tile;

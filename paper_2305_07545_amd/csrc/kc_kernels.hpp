@@ -20,6 +20,8 @@ constexpr uint64_t kChunk = 1ull << 31;
 // Binned path
 constexpr int kBinWG = 512;                  // threads per bin workgroup
 constexpr uint64_t kBinTileMin = 65536;      // positions per bin workgroup (at least)
+constexpr uint64_t kBinTileFloor = 4096;     // ... for chunks of fewer than kBinSpread tiles
+constexpr uint64_t kBinSpread = 2048;        // bin workgroups a small chunk is spread over
 constexpr int kRegionWG = 1024;              // threads per region workgroup
 constexpr int kRegionCounters = 16384;       // counters per region: hits + first = 128 KiB LDS
 constexpr uint32_t kMaxRegions = 16384;      // LDS histogram of the bin kernels: 64 KiB
