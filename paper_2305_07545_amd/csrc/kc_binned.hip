@@ -479,8 +479,9 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
 // (s+1)*slice) -> their regions' segments for those workgroups.  Batches of
 // kStage2 entries are counting-sorted by region in LDS and written as runs
 // (twice the level-1 batch: runs of 2 x 4096 / regions per bucket entries).
-// kCompact: 6-byte entries in and out (single-level path).  Else 8-byte
-// entries (t << 32 | slot id).
+// kCompact: 6-byte entries in (single-level path), else 8-byte entries
+// (t << 32 | slot id: the partitioned path's list binning); the region
+// lists are written as 6-byte entries either way.
 constexpr int kStage2 = 2 * kStage;
 template <bool kCompact>
 __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
@@ -633,8 +634,11 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
                 const uint32_t r =
                     (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
                 const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
-                if (dst < cap)
-                    entries[dst] = e;
+                const uint32_t t = (uint32_t)(e >> 32);  // < 2^31 on the partitioned path
+                if (dst < cap) {
+                    out_word[dst] = ((uint32_t)e & (kRegionCounters - 1u)) | (t << kLocalBits);
+                    out_half[dst] = (uint16_t)(t >> (32 - kLocalBits));
+                }
             }
         }
         __syncthreads();
@@ -932,9 +936,7 @@ __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &
         F.words[wbase + w] = next;
 }
 
-// kCompact: 6-byte entries (single-level path).  Else 8-byte entries
-// (t << 32 | slot id).
-template <bool kCompact>
+// Region lists of 6-byte entries (both binned paths).
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
@@ -966,19 +968,13 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     auto fetch = [&](uint64_t x) -> RawEntry {
         RawEntry e{~0u, ~0u};
         if (x < e1) {
-            if (kCompact) {
-                e.lo = e_word[x];
-                e.hi = e_half[x];
-            } else {
-                const uint2 p = ((const uint2 *)entries)[x];
-                e.lo = p.x;
-                e.hi = p.y;
-            }
+            e.lo = e_word[x];
+            e.hi = e_half[x];
         }
         return e;
     };
     auto t_of = [](RawEntry e) -> uint32_t {
-        return kCompact ? (e.lo >> kLocalBits) | (e.hi << (32 - kLocalBits)) : e.hi;
+        return (e.lo >> kLocalBits) | (e.hi << (32 - kLocalBits));
     };
     // the first entries and the region's cells are requested before the LDS
     // clear, so that their latency overlaps it (this workgroup alone writes
@@ -1284,7 +1280,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhRegion, s);
-        hipLaunchKernelGGL(k_region<false>, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
+        hipLaunchKernelGGL(k_region, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
                            (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
                            (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
         if (P)
@@ -1367,7 +1363,7 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhRegion, s);
-    hipLaunchKernelGGL(k_region<true>, dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
+    hipLaunchKernelGGL(k_region, dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
                        (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
                        (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
     if (P)
