@@ -363,6 +363,16 @@ def test_full_chunk_binned_equals_direct(monkeypatch, X, Y, what):
     assert abs(a[1].numel() - want) < 0.05 * want, (a[1].numel(), want)
 
 
+def test_small_chunk_spread_over_many_workgroups():
+    """About 9 M positions: the binned path hashes them in tiles of 4608
+    positions (between the 4096 floor and the 65536 of large chunks), about
+    1950 workgroups; all outputs against the oracle."""
+    rs = synth.random_reads(1600, 60_000, 100, 200, k=27, p_n=0.002, tau=2)
+    assert 8_000_000 < rs.n_bases < 10_000_000
+    X, Y = oracle.dims(rs.n_items)
+    check(rs, X, Y, what="9 M positions, small tiles")
+
+
 def test_errors_and_capacity():
     rs = synth.random_reads(1101, 100, 30, 100, k=21)
     r, o = dev(rs)
