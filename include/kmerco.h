@@ -83,10 +83,8 @@ int kc_version(void);
  * '+' line, quality lines of the same total length), the format taken from
  * the first line that is neither blank nor a comment; blank lines are
  * skipped.  Each record's sequence
- * lines are concatenated, line ends ("
-", "
-") removed and bytes kept
- * as they are (so 'N' and lower case stay invalid bases), into
+ * lines are concatenated, their line ends (LF or CR LF) removed and bytes
+ * kept as they are (so 'N' and lower case stay invalid bases), into
  * seq[0..*n_bases), and offsets[0..*n_reads] receives the CSR offsets
  * (offsets[0] = 0): one read per record, records with no bases included.
  * flags: KC_FASTX_ONE_SEQUENCE makes all records one read, so windows span
@@ -119,12 +117,15 @@ uint32_t kc_eta(uint32_t alpha);
  * only, pure. */
 uint64_t kc_filter_bytes(const kc_layout *layout);
 
-/* Device bytes a handle of this layout allocates for inserts of up to
- * max_bases bases (kc_reserve(max_bases) on a new handle: the per-position
- * and per-tile buffers and the binned, partitioned or direct path's
- * scratch, as kc_insert would size them), so that callers can budget HBM
- * before creating handles.  0 for an invalid layout.  Host only, pure: it
- * counts the allocations without making them and touches no device. */
+/* Device bytes a handle of this layout needs for inserts of up to max_bases
+ * bases and classifications of up to max_bases keys: its status word and
+ * what kc_reserve(max_bases) allocates on a new handle (the per-position and
+ * per-tile buffers and the binned, partitioned or direct path's scratch, as
+ * kc_insert would size them), each piece rounded up to 256 bytes.  It is the
+ * scratch_bytes kc_create_in needs for that max_bases, and lets callers
+ * budget HBM before creating handles.  0 for an invalid layout.  Host only,
+ * pure: it counts the allocations without making them and touches no
+ * device. */
 uint64_t kc_scratch_bytes(const kc_layout *layout, uint64_t max_bases);
 
 /* Create a countBF over caller-owned device memory `words_dev` (X*Y uint64,
@@ -136,16 +137,46 @@ uint64_t kc_scratch_bytes(const kc_layout *layout, uint64_t max_bases);
 kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void *stream,
                     kc_filter **out);
 
+/* kc_create with the handle's device state in caller memory and/or a k to
+ * resume with (the countBF of Sec. 2.1 over caller-owned words, as for
+ * kc_create; zero as for kc_create).
+ *
+ * k            0: no k-mer length yet (set by the first insert).  1..64: the
+ *              words already hold k-mers of this length (a resumed countBF,
+ *              zero must be 0): inserts must use it (else KC_ESTATE) and
+ *              kc_classify / kc_query read keys of its width at once.
+ * scratch_dev  NULL: the library allocates the handle's scratch (as
+ *              kc_create; max_bases > 0 reserves it at once, as kc_reserve).
+ *              Otherwise a caller-owned device buffer of scratch_bytes
+ *              bytes, 256-byte aligned, at least kc_scratch_bytes(layout,
+ *              max_bases): the handle's status word and every buffer its
+ *              calls use are laid out in it here, once.  The library then
+ *              never allocates device memory for the handle and its insert,
+ *              classify and query calls never wait on the host, so they may
+ *              be captured into a HIP graph by the caller; an insert of more
+ *              than max_bases bases or a classification of more than
+ *              max_bases keys returns KC_ERANGE and enqueues nothing.  The
+ *              buffer must outlive the handle; kc_destroy does not free it,
+ *              and its contents between calls are the library's.
+ * Errors: KC_EINVAL (bad layout, k > 64, k with zero != 0, a misaligned
+ * scratch_dev), KC_ERANGE (scratch_bytes below the need), KC_ENOMEM. */
+kc_status kc_create_in(const kc_layout *layout, uint64_t *words_dev, int zero, uint32_t k,
+                       void *scratch_dev, uint64_t scratch_bytes, uint64_t max_bases,
+                       void *stream, kc_filter **out);
+
 /* Release the handle and its workspace (not the caller's words).  Waits for
  * the handle's outstanding work first.  NULL is ignored. */
 void kc_destroy(kc_filter *f);
 
 /* Pre-size the handle's scratch for inserts of up to `max_bases` bases so
  * that later kc_insert calls of that size allocate nothing.  Synchronous.
+ * KC_ERANGE on a handle whose scratch is the caller's (kc_create_in) when
+ * max_bases exceeds what it was laid out for.
  * Sizes, k_h = 1: countBFs of up to 16384 regions (256 MB at alpha = 8) take
  * the binned path, about 22 bytes per base (packed codes and bitmaps, a flag
  * byte, slot ids, two entry lists); larger countBFs take the partitioned
- * path, about 31 bytes per base of a chunk of up to 2^31 bases; the direct
+ * path, about 19 bytes per base of a chunk of up to 2^32 - 2^16 bases (two
+ * 8-byte entry lists, each holding two kinds of data in turn); the direct
  * path (forced, or beyond 256 partitions) takes 4 bytes per counter plus
  * about 2 bytes per base.  Scratch grows, and is never shrunk, by calls
  * larger than the reservation. */
@@ -165,7 +196,10 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases);
  *              KC_ESTATE).
  * distinct_dev receives this call's distinct k-mers (canonical keys) in
  *              first-seen order (reads in input order, windows by start
- *              position), appended at index *n_distinct_dev.
+ *              position), appended at index *n_distinct_dev.  This is the
+ *              listing of distinct k-mers the insertion phase produces
+ *              (Algorithm 1): the list is the caller's buffer, so there is
+ *              no separate call to fetch it.
  * distinct_cap capacity of distinct_dev in keys.  Keys that do not fit are
  *              dropped, *n_distinct_dev still counts them and the handle
  *              records KC_ERANGE (returned by kc_sync).

@@ -4,6 +4,12 @@ The compute lives in ``libkmerco_hip.so`` (hand-written HIP kernels behind the
 C ABI of ``include/kmerco.h``); this package is its Python binding.
 """
 from .kmerco import (  # noqa: F401
+    KC_EDEVICE,
+    KC_EINVAL,
+    KC_ENOMEM,
+    KC_ERANGE,
+    KC_ESTATE,
+    KC_OK,
     Batch,
     CountBF,
     KmercoError,

@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <new>
 
 #include "kc_kernels.hpp"
@@ -42,9 +43,15 @@ bool valid_layout(const kc_layout *L) {
 }
 
 thread_local uint64_t *g_size_only = nullptr;
+thread_local Carve *g_carve = nullptr;
+
+uint64_t next_generation() {
+    static std::atomic<uint64_t> counter{1};
+    return counter.fetch_add(1);
+}
 
 void wait_idle(kc_filter *f) {
-    if (!g_size_only)
+    if (!g_size_only && !g_carve)
         (void)hipStreamSynchronize(f->last);
 }
 
@@ -54,7 +61,9 @@ void wait_idle(kc_filter *f) {
 kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n, bool valid_bitmap) {
     if (W.codes && n <= W.cap && (W.valid || !valid_bitmap))
         return KC_OK;
-    if (!g_size_only)
+    if (W.fixed)
+        return KC_ERANGE;  // larger than the caller's scratch was sized for
+    if (!g_size_only && !g_carve)
         (void)hipStreamSynchronize(wait_on);
     dev_free(W.codes);
     dev_free(W.inv);
@@ -77,7 +86,9 @@ kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n) {
     uint64_t nt = kc::tiles(n) + 1;
     if (W.tile_a && nt <= W.tile_cap)
         return KC_OK;
-    if (!g_size_only)
+    if (W.fixed)
+        return KC_ERANGE;
+    if (!g_size_only && !g_carve)
         (void)hipStreamSynchronize(wait_on);
     dev_free(W.tile_a);
     dev_free(W.tile_b);
@@ -116,6 +127,8 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     if (W.matrix && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap && n_slots <= W.slots_cap &&
         n_ent <= W.entries_cap)
         return KC_OK;
+    if (W.fixed)
+        return KC_ERANGE;
     wait_idle(f);
     if (!W.matrix || n_mat > W.matrix_cap || n_coarse > W.coarse_cap) {
         dev_free(W.matrix);
@@ -131,9 +144,6 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     }
     if (!W.slots || n_slots > W.slots_cap) {
         dev_free(W.slots);
-        // the partitioned path's arrays are sized with the slots: drop them
-        dev_free(W.parts);
-        dev_free(W.plist);
         W.slots_cap = 0;
         if (!dev_alloc(&W.slots, n_slots))
             return KC_ENOMEM;
@@ -150,7 +160,13 @@ kc_status ensure_binned(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_posit
     return KC_OK;
 }
 
-// partitioned binned-path buffers for one chunk of the given plan
+// partitioned binned-path buffers for one chunk of the given plan.  The
+// path needs two entry-sized buffers besides its count matrices, each used
+// twice (kernels of one stream, in this order):
+//   bucketed: slot ids and partition bytes (hashing -> partition scatter),
+//             then the bucket lists (list binning -> region binning);
+//   entries:  the partition lists (partition scatter -> list binning), then
+//             the region lists (region binning -> region pass).
 kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positions) {
     kc::Workspace &W = *f->W;
     const uint64_t n_slots = chunk_positions * f->layout.k_h;
@@ -164,9 +180,11 @@ kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positi
     uint64_t n_mat = n_fine > n_pmat ? n_fine : n_pmat;
     if (n_rows > n_mat)
         n_mat = n_rows;
-    if (W.plist && W.pbounds && W.pdesc && n_slots <= W.slots_cap && n_slots <= W.entries_cap &&
-        n_pmat <= W.pmat_cap && n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap)
+    if (W.entries && W.pbounds && W.pdesc && n_slots <= W.entries_cap && n_pmat <= W.pmat_cap &&
+        n_mat <= W.matrix_cap && n_coarse <= W.coarse_cap)
         return KC_OK;
+    if (W.fixed)
+        return KC_ERANGE;
     wait_idle(f);
     if (!W.pbounds && !dev_alloc(&W.pbounds, kc::kMaxParts + 1))
         return KC_ENOMEM;
@@ -193,16 +211,6 @@ kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positi
             return KC_ENOMEM;
         W.pmat_cap = n_pmat;
     }
-    if (!W.slots || !W.plist || n_slots > W.slots_cap) {
-        dev_free(W.slots);
-        dev_free(W.parts);
-        dev_free(W.plist);
-        W.slots_cap = 0;
-        if (!dev_alloc(&W.slots, n_slots) || !dev_alloc(&W.parts, n_slots) ||
-            !dev_alloc(&W.plist, n_slots))
-            return KC_ENOMEM;
-        W.slots_cap = n_slots;
-    }
     if (!W.entries || n_slots > W.entries_cap) {
         dev_free(W.entries);
         dev_free(W.bucketed);
@@ -217,6 +225,8 @@ kc_status ensure_parts(kc_filter *f, const kc::BinPlan &B, uint64_t chunk_positi
 kc_status ensure_scalars(kc::Workspace &W) {
     if (W.totals)
         return KC_OK;
+    if (W.fixed)
+        return KC_ERANGE;
     if (!dev_alloc(&W.totals, 8) || !dev_alloc(&W.n_entries, 4))
         return KC_ENOMEM;
     return KC_OK;
@@ -228,6 +238,8 @@ kc_status ensure_scalars(kc_filter *f) { return ensure_scalars(*f->W); }
 kc_status ensure_aux(kc_filter *f, hipStream_t s) {
     if (f->F.aux)
         return KC_OK;
+    if (f->W->fixed)
+        return KC_ERANGE;
     uint64_t n_aux = f->layout.X * f->layout.Y * f->F.eta;
     if (!dev_alloc(&f->F.aux, n_aux))
         return KC_ENOMEM;
@@ -257,8 +269,6 @@ void free_workspace(kc::Workspace &W) {
     dev_free(W.slots);
     dev_free(W.bucketed);
     dev_free(W.entries);
-    dev_free(W.parts);
-    dev_free(W.plist);
     dev_free(W.pmat);
     dev_free(W.pbounds);
     dev_free(W.pdesc);
@@ -268,6 +278,12 @@ void free_workspace(kc::Workspace &W) {
 }
 
 void free_all(kc_filter *f) {
+    if (f->caller_scratch) {  // every buffer is a piece of the caller's scratch
+        f->own = kc::Workspace{};
+        f->F.aux = nullptr;
+        f->status = nullptr;
+        return;
+    }
     free_workspace(f->own);
     dev_free(f->F.aux);
     dev_free(f->status);
@@ -347,6 +363,24 @@ uint64_t next_prime_after(uint64_t n) {
     }
 }
 
+// Every buffer inserts of up to max_bases bases (and classifications of up
+// to max_bases keys) need, in the current dev_alloc mode: kc_reserve
+// allocates them, kc_scratch_bytes counts them, kc_create_in carves them.
+kc_status reserve_all(kc_filter *f, uint64_t max_bases) {
+    kc_status st = ensure_scalars(f);
+    if (st == KC_OK)
+        st = ensure_positions(f, max_bases);
+    if (st == KC_OK)
+        st = ensure_tiles(f, max_bases);
+    if (st != KC_OK || max_bases == 0)
+        return st;
+    kc::BinPlan plan{};
+    uint64_t bchunk = 0;
+    if (choose_plan(f, max_bases, plan, bchunk))
+        return ensure_plan(f, plan, bchunk);
+    return ensure_aux(f, f->last);
+}
+
 void share_workspace(kc_filter *f, kc::Workspace *W) { f->W = W ? W : &f->own; }
 
 uint64_t filter_private_bytes(const kc_layout &layout) {
@@ -400,7 +434,6 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
                       uint64_t cap_te, hipStream_t s) {
     const bool split = trust != nullptr;
     f->last = s;
-    f->k = k;
     kc_status st = ensure_scalars(f);
     if (st != KC_OK)
         return st;
@@ -408,6 +441,7 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         if (split && (kc::fill_u64(n_trust, 1, 0, s) != hipSuccess ||
                       kc::fill_u64(n_err, 1, 0, s) != hipSuccess))
             return KC_EDEVICE;
+        f->k = k;
         return KC_OK;
     }
     if ((st = ensure_positions(f, n_bases)) != KC_OK || (st = ensure_tiles(f, n_bases)) != KC_OK)
@@ -425,6 +459,7 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     } else if ((st = ensure_aux(f, s)) != KC_OK) {
         return st;
     }
+    f->k = k;  // every check passed: the filter now holds k-mers of this length
     hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, *f->W, s, &f->prof);
     if (e == hipSuccess && binned)
         e = kc::launch_valid_windows(n_bases, k, *f->W, s, &f->prof);
@@ -491,25 +526,19 @@ uint64_t kc_filter_bytes(const kc_layout *layout) {
 uint64_t kc_scratch_bytes(const kc_layout *layout, uint64_t max_bases) {
     if (!valid_layout(layout))
         return 0;
-    // kc_reserve's allocations on a handle of this layout, counted, not made
+    // the status word and kc_reserve's allocations on a handle of this
+    // layout, counted, not made (the order kc_create_in carves them in)
     kc_filter f{};
     init_filter(&f, layout);
-    uint64_t bytes = sizeof(uint32_t);  // the handle's status word
-    g_size_only = &bytes;
-    kc_status st = ensure_scalars(&f);
-    if (st == KC_OK)
-        st = ensure_positions(&f, max_bases);
-    if (st == KC_OK)
-        st = ensure_tiles(&f, max_bases);
-    if (st == KC_OK && max_bases > 0) {
-        kc::BinPlan plan{};
-        uint64_t bchunk = 0;
-        st = choose_plan(&f, max_bases, plan, bchunk) ? ensure_plan(&f, plan, bchunk)
-                                                      : ensure_aux(&f, nullptr);
+    uint64_t bytes = 0;
+    kc_status st = KC_OK;
+    {
+        SizeOnly mode(&bytes);
+        st = dev_alloc(&f.status, 1) ? reserve_all(&f, max_bases) : KC_ENOMEM;
     }
-    g_size_only = nullptr;
     f.own = kc::Workspace{};  // placeholders only
     f.F.aux = nullptr;
+    f.status = nullptr;
     return st == KC_OK ? bytes : 0u;
 }
 
@@ -529,11 +558,16 @@ kc_status kc_dims(double n_items, double fpp, uint64_t *X, uint64_t *Y) {
     return KC_OK;
 }
 
-kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void *stream,
-                    kc_filter **out) {
-    if (!out || !words_dev || !valid_layout(layout))
+kc_status kc_create_in(const kc_layout *layout, uint64_t *words_dev, int zero, uint32_t k,
+                       void *scratch_dev, uint64_t scratch_bytes, uint64_t max_bases,
+                       void *stream, kc_filter **out) {
+    if (!out)
         return KC_EINVAL;
     *out = nullptr;
+    if (!words_dev || !valid_layout(layout) || k > 64 || (k != 0 && zero))
+        return KC_EINVAL;
+    if (scratch_dev && (uintptr_t)scratch_dev % kAllocAlign != 0)
+        return KC_EINVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return KC_EDEVICE;
@@ -543,12 +577,36 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     init_filter(f, layout);
     f->device = dev;
     f->zero = zero != 0;
+    f->k = k;
     f->last = (hipStream_t)stream;
     f->F.words = words_dev;
+    f->generation = next_generation();
     hipStream_t s = (hipStream_t)stream;
-    if (!dev_alloc(&f->status, 1)) {
+    kc_status st = KC_OK;
+    if (scratch_dev) {
+        // every device buffer of the handle is a piece of the caller's
+        // scratch, laid out once here in the order kc_scratch_bytes counts
+        f->caller_scratch = true;
+        Carve c;
+        c.base = (uint8_t *)scratch_dev;
+        c.size = scratch_bytes;
+        {
+            Carving mode(&c);
+            st = dev_alloc(&f->status, 1) ? reserve_all(f, max_bases) : KC_ENOMEM;
+        }
+        if (st == KC_ENOMEM)
+            st = KC_ERANGE;  // smaller than kc_scratch_bytes(layout, max_bases)
+        f->own.fixed = true;
+    } else {
+        st = dev_alloc(&f->status, 1) ? KC_OK : KC_ENOMEM;
+        if (st == KC_OK && max_bases > 0)
+            st = reserve_all(f, max_bases);
+    }
+    if (st != KC_OK) {
+        (void)hipStreamSynchronize(s);
+        free_all(f);
         delete f;
-        return KC_ENOMEM;
+        return st;
     }
     hipError_t e = kc::fill_u32(f->status, 1, 0u, s);
     if (e == hipSuccess && zero)
@@ -561,6 +619,11 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
     }
     *out = f;
     return KC_OK;
+}
+
+kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void *stream,
+                    kc_filter **out) {
+    return kc_create_in(layout, words_dev, zero, 0, nullptr, 0, 0, stream, out);
 }
 
 void kc_destroy(kc_filter *f) {
@@ -579,18 +642,7 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases) {
     DeviceGuard g(f->device);
     if (!g.ok)
         return KC_EDEVICE;
-    kc_status st = ensure_scalars(f);
-    if (st == KC_OK)
-        st = ensure_positions(f, max_bases);
-    if (st == KC_OK)
-        st = ensure_tiles(f, max_bases);
-    if (st != KC_OK || max_bases == 0)
-        return st;
-    kc::BinPlan plan{};
-    uint64_t bchunk = 0;
-    if (choose_plan(f, max_bases, plan, bchunk))
-        return ensure_plan(f, plan, bchunk);
-    return ensure_aux(f, f->last);
+    return reserve_all(f, max_bases);
 }
 
 kc_status kc_get_layout(const kc_filter *f, kc_layout *out) {

@@ -301,9 +301,21 @@ std::vector<uint8_t> call_key(const kc_batch *b, const kc_set *sets, uint32_t n_
                              (uint64_t)(uintptr_t)W.tile_a, (uint64_t)(uintptr_t)W.off_a,
                              (uint64_t)(uintptr_t)W.partial64, (uint64_t)(uintptr_t)W.totals,
                              (uint64_t)(uintptr_t)W.tmask};
-    std::vector<uint8_t> k(n_sets * sizeof(kc_set) + sizeof tail);
+    // each set's filter by its generation (a destroyed handle's host address
+    // can be reused) and the device state its launches bake in
+    std::vector<uint64_t> filt;
+    for (uint32_t i = 0; i < n_sets; i++) {
+        const kc_filter *f = sets[i].filter;
+        filt.insert(filt.end(), {f->generation, (uint64_t)(uintptr_t)f->F.words,
+                                 (uint64_t)(uintptr_t)f->status, f->layout.X, f->layout.Y,
+                                 f->layout.alpha, f->layout.k_h});
+    }
+    const size_t nf = filt.size() * sizeof(uint64_t);
+    std::vector<uint8_t> k(n_sets * sizeof(kc_set) + sizeof tail + nf);
     std::memcpy(k.data(), sets, n_sets * sizeof(kc_set));
     std::memcpy(k.data() + n_sets * sizeof(kc_set), tail, sizeof tail);
+    if (nf)
+        std::memcpy(k.data() + n_sets * sizeof(kc_set) + sizeof tail, filt.data(), nf);
     return k;
 }
 

@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
                 const uint32_t r =
                     (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
                 const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
-                const uint32_t t = (uint32_t)(e >> 32);  // < 2^31 on the partitioned path
+                const uint32_t t = (uint32_t)(e >> 32);  // chunk-relative: < 2^32 - 1
                 if (dst < cap) {
                     out_word[dst] = ((uint32_t)e & (kRegionCounters - 1u)) | (t << kLocalBits);
                     out_half[dst] = (uint16_t)(t >> (32 - kLocalBits));
@@ -1182,17 +1182,23 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     B.n_slices = (B.G + B.slice - 1) / B.slice;
     B.entries_cap = W.entries_cap;
     const uint64_t n_pmat = (uint64_t)B.n_parts * B.G;
+    // slot ids (positions x hash functions) and their partition bytes live
+    // in `bucketed` until the partition scatter has read them; the partition
+    // lists in `entries` until the list binning has read them
+    uint32_t *slots = (uint32_t *)W.bucketed;
+    uint8_t *parts = (uint8_t *)(slots + W.entries_cap);
+    uint64_t *plist = W.entries;
     if (P)
         P->begin(kPhBinCount, s);
     if (R.k > 32)
         hipLaunchKernelGGL(
             (fast_layout(F) ? k_bin_count_wide<true, true> : k_bin_count_wide<true, false>),
             dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B,
-            W.slots, W.parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
+            slots, parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
     else
         hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<true, true> : k_bin_count<true, false>),
                            dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R,
-                           c0, c1, B, W.slots, W.parts, W.pmat, nullptr,
+                           c0, c1, B, slots, parts, W.pmat, nullptr,
                            (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
@@ -1213,8 +1219,8 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         if (P)
             P->begin(kPhBinPart, s);
         hipLaunchKernelGGL(k_part_scatter, dim3(B.G), dim3(kBinWG), 0, s, c0, c1, F.k_h, B,
-                           (const uint32_t *)W.slots, (const uint8_t *)W.parts,
-                           (const uint32_t *)W.pmat, W.plist);
+                           (const uint32_t *)slots, (const uint8_t *)parts,
+                           (const uint32_t *)W.pmat, plist);
         if (P)
             P->end(s);
         e = hipGetLastError();
@@ -1241,7 +1247,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (P)
         P->begin(kPhPartCount, s);
     hipLaunchKernelGGL(k_list_count, dim3(n_list), dim3(kBinWG), (size_t)hist * sizeof(uint32_t),
-                       s, (const uint64_t *)W.plist, (const uint64_t *)W.pdesc, Q, W.matrix_t,
+                       s, (const uint64_t *)plist, (const uint64_t *)W.pdesc, Q, W.matrix_t,
                        W.coarse);
     if (P)
         P->end(s);
@@ -1261,7 +1267,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         if (P)
             P->begin(kPhBinBucket, s);
         hipLaunchKernelGGL(k_bin_bucket_list, dim3(n_list), dim3(kBinWG), 0, s,
-                           (const uint64_t *)W.plist, (const uint64_t *)W.pdesc, Q,
+                           (const uint64_t *)plist, (const uint64_t *)W.pdesc, Q,
                            (const uint32_t *)W.coarse, W.bucketed);
         if (P)
             P->end(s);

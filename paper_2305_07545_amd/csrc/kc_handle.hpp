@@ -11,7 +11,8 @@ enum class KcPath { Auto, Direct, Binned };
 struct kc_filter {
     kc_layout layout;
     kc::FilterArgs F;
-    kc::Workspace own;     // scratch of this handle's calls
+    kc::Workspace own;     // scratch of this handle's calls (library-allocated, or
+                           // carved from the caller's scratch: own.fixed)
     kc::Workspace *W;      // &own, or a workspace shared by handles whose calls
                            // are all ordered on one stream
 
@@ -26,6 +27,8 @@ struct kc_filter {
     uint32_t part_log;     // partitioned binned path: log2(regions per partition)
     KcPath path;
     kc::Profiler prof;     // optional per-kernel timing
+    bool caller_scratch;   // status word and workspace live in the caller's buffer
+    uint64_t generation;   // unique per handle of the process (graph keys)
 };
 
 // helpers shared by the single-set and batch entry points (kc_api.hip)
@@ -38,17 +41,45 @@ struct DeviceGuard {
     ~DeviceGuard();
 };
 
-// Sizing without a device (kc_scratch_bytes): while set, dev_alloc adds the
-// bytes it would allocate here and hands out a placeholder that is never
-// dereferenced, dev_free and the workspace waits do nothing.
+// Device allocations of the library go through dev_alloc, which has three
+// modes:
+//  - sizing (kc_scratch_bytes): while g_size_only is set, dev_alloc adds the
+//    bytes it would allocate there and hands out a placeholder that is never
+//    dereferenced; dev_free and the workspace waits do nothing;
+//  - carving (caller-owned scratch): while g_carve is set, dev_alloc hands
+//    out consecutive pieces of the caller's buffer and fails when it is
+//    exhausted; dev_free does nothing;
+//  - otherwise hipMalloc / hipFree.
+// Every piece is a multiple of kAllocAlign bytes in the first two modes, so
+// that a size counted in the first is exactly what the second carves.
+constexpr uint64_t kAllocAlign = 256;
+
+struct Carve {
+    uint8_t *base = nullptr;
+    uint64_t size = 0, used = 0;
+};
+
 extern thread_local uint64_t *g_size_only;
+extern thread_local Carve *g_carve;
+
+inline uint64_t alloc_round(uint64_t bytes) {
+    return (bytes + kAllocAlign - 1) / kAllocAlign * kAllocAlign;
+}
 
 template <typename T>
 bool dev_alloc(T **p, uint64_t count) {
     const uint64_t bytes = (count ? count : 1) * sizeof(T);
     if (g_size_only) {
-        *g_size_only += bytes;
+        *g_size_only += alloc_round(bytes);
         *p = reinterpret_cast<T *>((uintptr_t)256);
+        return true;
+    }
+    if (g_carve) {
+        const uint64_t need = alloc_round(bytes);
+        if (need > g_carve->size - g_carve->used)
+            return false;
+        *p = reinterpret_cast<T *>(g_carve->base + g_carve->used);
+        g_carve->used += need;
         return true;
     }
     return hipMalloc((void **)p, bytes) == hipSuccess;
@@ -56,12 +87,25 @@ bool dev_alloc(T **p, uint64_t count) {
 
 template <typename T>
 void dev_free(T *&p) {
-    if (!g_size_only)
+    if (!g_size_only && !g_carve)
         (void)hipFree(p);
     p = nullptr;
 }
 
+// Sets a mode of dev_alloc for the lifetime of the object.
+struct SizeOnly {
+    explicit SizeOnly(uint64_t *bytes) { g_size_only = bytes; }
+    ~SizeOnly() { g_size_only = nullptr; }
+};
+struct Carving {
+    explicit Carving(Carve *c) { g_carve = c; }
+    ~Carving() { g_carve = nullptr; }
+};
+
 bool valid_layout(const kc_layout *L);
+// A number no other handle of the process has had (keys of captured graphs
+// name handles by it, not by their reusable host addresses).
+uint64_t next_generation();
 kc_status ensure_positions(kc::Workspace &W, hipStream_t wait_on, uint64_t n, bool valid_bitmap);
 kc_status ensure_tiles(kc::Workspace &W, hipStream_t wait_on, uint64_t n);
 kc_status ensure_scalars(kc::Workspace &W);

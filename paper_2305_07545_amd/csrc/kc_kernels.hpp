@@ -37,8 +37,11 @@ constexpr int kTileGrid = 2048;              // workgroups of the persistent til
 // partition p holds regions [p * kMaxRegions, (p + 1) * kMaxRegions)
 constexpr uint32_t kPartLog = 14;            // kMaxRegions == 1 << kPartLog
 constexpr uint32_t kMaxParts = 256;          // partitions (4M regions: 64 GB at alpha = 8)
-constexpr uint64_t kPartChunk = 1ull << 31;  // positions per partitioned chunk (k_h = 1;
-                                             // entry offsets are 32-bit: chunk * k_h < 2^32)
+// positions per partitioned chunk: entry offsets and chunk-relative positions
+// are 32-bit (chunk * k_h < 2^32, t < 2^32 - 1, the idle first-seen value),
+// and a multiple of the largest bin tile; the countBF is read and written
+// once per chunk, so an 8 Gbase insert takes two passes over it
+constexpr uint64_t kPartChunk = (1ull << 32) - (1ull << 16);
 constexpr uint32_t kListWGs = 4096;          // list workgroups over all partitions, about
 constexpr uint32_t kMaxListG = 512;          // list workgroups per partition (at most)
 constexpr uint64_t kMaxCoarse = 1ull << 19;  // (partition bucket, list workgroup) counts
@@ -87,9 +90,8 @@ struct Workspace {
     uint64_t *bucketed = nullptr; // entries_cap entries grouped by bucket
     uint64_t *entries = nullptr;  // entries_cap entries grouped by region
     uint64_t entries_cap = 0;
-    // partitioned binned path (per chunk)
-    uint8_t *parts = nullptr;     // slots_cap partition ids, beside the slot ids
-    uint64_t *plist = nullptr;    // slots_cap entries grouped by partition
+    // partitioned binned path (per chunk): slot ids and partition bytes in
+    // `bucketed`, the partition lists in `entries` (see launch_parts_chunk)
     uint32_t *pmat = nullptr;     // pmat_cap (partition, bin workgroup) counts -> offsets
     uint64_t pmat_cap = 0;
     uint32_t *pbounds = nullptr;  // kMaxParts + 1 partition starts in plist
@@ -97,6 +99,9 @@ struct Workspace {
     // scalars
     uint64_t *totals = nullptr;   // 8 scan totals / saved counters
     uint32_t *n_entries = nullptr;  // 4 entry totals
+    // the buffers were carved from caller memory once: they never grow, and a
+    // call that needs more than they hold fails instead
+    bool fixed = false;
 };
 
 inline uint64_t tiles(uint64_t n) { return (n + kTile - 1) / kTile; }

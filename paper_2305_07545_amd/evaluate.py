@@ -114,10 +114,12 @@ def placement(nbytes: int) -> str:
     return "HBM"
 
 
-def evaluate(rs, sizes, steps: int = 5, alpha: int = 8, k_h: int = 1, device="cuda"):
+def evaluate(rs, sizes, steps: int = 5, alpha: int = 8, k_h: int = 1, device="cuda",
+             lists: dict | None = None):
     """One result per size factor f: countBF from Eq. (1) at f x the
     workload's sizing count, timed insert + classify, lists compared with
-    the exact counts."""
+    the exact counts.  ``lists``, when given, receives per size factor the
+    host arrays that were scored: (words, distinct, trust, err)."""
     import torch
 
     from . import kmerco as K
@@ -159,8 +161,10 @@ def evaluate(rs, sizes, steps: int = 5, alpha: int = 8, k_h: int = 1, device="cu
         r = {"size_factor": f, "X": X, "Y": Y, "countbf_bytes": X * Y * 8,
              "placement": placement(X * Y * 8), "n_windows": nw,
              "insertions_per_s": nw / secs, "ms_per_step": secs * 1e3}
-        r.update(compare(ex_keys, ex_cnt, host(outs[0], nd), host(outs[1], nt),
-                         host(outs[2], ne), rs.k, rs.tau))
+        d, t, e = host(outs[0], nd), host(outs[1], nt), host(outs[2], ne)
+        r.update(compare(ex_keys, ex_cnt, d, t, e, rs.k, rs.tau))
+        if lists is not None:
+            lists[f] = (bf.words.cpu().numpy().view(np.uint64), d, t, e)
         r["exact_windows"] = int(ex_cnt.sum())
         r["exact_counting_s"] = t_exact
         results.append(r)

@@ -96,6 +96,8 @@ SIGNATURES = {
     "kc_filter_bytes": (_u64, [ctypes.POINTER(kc_layout)]),
     "kc_scratch_bytes": (_u64, [ctypes.POINTER(kc_layout), _u64]),
     "kc_create": (_i, [ctypes.POINTER(kc_layout), _vp, _i, _vp, ctypes.POINTER(_vp)]),
+    "kc_create_in": (_i, [ctypes.POINTER(kc_layout), _vp, _i, _u32, _vp, _u64, _u64, _vp,
+                          ctypes.POINTER(_vp)]),
     "kc_destroy": (None, [_vp]),
     "kc_reserve": (_i, [_vp, _u64]),
     "kc_insert": (_i, [_vp, _vp, _vp, _u64, _u64, _u32, _vp, _u64, _vp, _vp, _vp]),
@@ -257,10 +259,16 @@ class CountBF:
     """A countBF resident in device memory, driven by the HIP library.
 
     ``words`` (int64[X*Y]) is allocated here unless given; with ``zero=True``
-    the library clears it and the filter starts empty."""
+    the library clears it and the filter starts empty.  ``k``: the k-mer
+    length the given words already hold (a resumed countBF).  ``scratch``: a
+    device uint8 tensor of at least ``scratch_bytes(X, Y, max_bases, ...)``
+    bytes that holds every buffer of the handle (kc_create_in): no call then
+    allocates device memory, and inserts of more than ``max_bases`` bases
+    fail."""
 
     def __init__(self, X: int, Y: int, alpha: int = 8, k_h: int = 1, words=None,
-                 zero: bool = True, device=None, stream=None):
+                 zero: bool = True, device=None, stream=None, k: int = 0, scratch=None,
+                 max_bases: int = 0):
         self.lib = load_library()
         self.layout = kc_layout(X, Y, alpha, k_h)
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -271,12 +279,19 @@ class CountBF:
             raise ValueError("words must hold X*Y cells")
         self.words = words
         self.device = words.device
+        if scratch is not None:
+            _require(scratch, torch.uint8, "scratch")
+            if scratch.device != self.device:
+                raise ValueError("scratch must be on the words' device")
+        self.scratch = scratch  # kept alive as long as the handle
         h = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):
-            _check(self.lib.kc_create(ctypes.byref(self.layout), _ptr(words), int(zero),
-                                      _stream_ptr(stream), ctypes.byref(h)), "kc_create")
+            _check(self.lib.kc_create_in(
+                ctypes.byref(self.layout), _ptr(words), int(zero), int(k), _ptr(scratch),
+                0 if scratch is None else scratch.numel(), int(max_bases), _stream_ptr(stream),
+                ctypes.byref(h)), "kc_create_in")
         self._h = h
-        self.k = None  # k of the inserts (keys of k > 32 bases take two words)
+        self.k = k or None  # k of the inserts (keys of k > 32 bases take two words)
         self.n_distinct = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.n_windows = torch.zeros(1, dtype=torch.int64, device=self.device)
 
@@ -454,8 +469,9 @@ class CountBF:
             words = torch.from_numpy(z["words"].view(np.int64).copy())
             distinct = z["distinct"].view(np.int64).copy() if "distinct" in z.files else None
         dev = torch.device("cuda") if device is None else torch.device(device)
-        bf = cls(X, Y, alpha, k_h, words=words.to(dev), zero=False, device=dev, stream=stream)
-        bf.k = k or None
+        # the handle itself resumes with k: classify and query read keys of
+        # its width, and inserts of another k are refused
+        bf = cls(X, Y, alpha, k_h, words=words.to(dev), zero=False, device=dev, stream=stream, k=k)
         if distinct is not None:
             distinct = torch.from_numpy(distinct).to(dev)
             bf.n_distinct.fill_(distinct.numel() // key_words(bf.k))

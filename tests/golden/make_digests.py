@@ -4,6 +4,7 @@ Calls only ``oracle`` and ``synth``; the GPU parity tests compare the HIP
 path's outputs against these stored digests.  Usage:
 
     python tests/golden/make_digests.py tiny bacterial batched bacterial_k55
+    python tests/golden/make_digests.py fullchunk_4201x4211 fullchunk_2621x2657
 
 The batched workload (256 independent read sets, each with its own countBF)
 is stored set by set; its sets run in parallel host processes.
@@ -47,6 +48,36 @@ def digests(name: str, scale: float = 1.0, k: int = 0) -> dict:
     }
 
 
+# seeded inputs of the parity tests that are not workloads: name ->
+# (read-set builder, X, Y)
+def _full_chunk_reads():
+    """About 280 M bases of random reads: one full binned chunk (2^28
+    positions) and a tail."""
+    return synth.random_reads(1500, 1_400_000, 150, 250, k=31, p_n=0.0005, tau=3)
+
+
+INPUTS = {
+    "fullchunk_4201x4211": (_full_chunk_reads, 4201, 4211),
+    "fullchunk_2621x2657": (_full_chunk_reads, 2621, 2657),
+}
+
+
+def input_digests(name: str) -> dict:
+    build, X, Y = INPUTS[name]
+    rs = build()
+    t = time.time()
+    words, distinct, trust, err, nw = oracle.run_kmerco(rs.reads, rs.offsets, rs.k, rs.tau, X, Y)
+    secs = time.time() - t
+    return {
+        "input": name, "k": rs.k, "tau": rs.tau, "X": X, "Y": Y, "alpha": 8, "k_h": 1,
+        "n_reads": rs.n_reads, "n_bases": rs.n_bases,
+        "n_windows": nw, "n_distinct": len(distinct), "n_trust": len(trust), "n_err": len(err),
+        "words_sha256": sha(words), "distinct_sha256": sha(distinct),
+        "trust_sha256": sha(trust), "err_sha256": sha(err),
+        "oracle_seconds": round(secs, 2),
+    }
+
+
 _SETS = []
 
 
@@ -77,7 +108,12 @@ if __name__ == "__main__":
     # names: tiny, bacterial, batched, large, or <workload>_k<k> (another k)
     for name in sys.argv[1:] or ["tiny", "bacterial"]:
         base, _, kk = name.partition("_k")
-        d = batched_digests() if name == "batched" else digests(base, k=int(kk or 0))
+        if name == "batched":
+            d = batched_digests()
+        elif name in INPUTS:
+            d = input_digests(name)
+        else:
+            d = digests(base, k=int(kk or 0))
         path = os.path.join(HERE, f"{name}_digests.json")
         with open(path, "w") as f:
             json.dump(d, f, indent=1)

@@ -86,3 +86,29 @@ def test_filter_and_scratch_bytes_on_the_host():
     # beyond one chunk of the binned path the per-chunk scratch stops growing
     assert P.scratch_bytes(2621, 2657, 2**30) - P.scratch_bytes(2621, 2657, 2**29) < \
         12 * 2**29
+
+
+def test_scratch_bytes_rounds_every_piece():
+    """Every piece kc_scratch_bytes counts is rounded up to 256 bytes (the
+    carving of a caller's scratch lays them out at that alignment), and the
+    partitioned path's need per base (about 19 bytes) is below the
+    single-level path's (about 22)."""
+    for X, Y, n in [(269, 281, 10**6), (2621, 2657, 10**7), (31627, 31657, 10**8)]:
+        assert P.scratch_bytes(X, Y, n) % 256 == 0
+    big = P.scratch_bytes(31627, 31657, 2**32) / 2**32
+    assert 15 < big < 22, big
+
+
+def test_create_in_rejects_bad_arguments_on_the_host():
+    """k above 64, a k with zero != 0, and a misaligned scratch buffer are
+    refused before any device call."""
+    lib = P.load_library()
+    h = ctypes.c_void_p(None)
+    L = kmerco.kc_layout(5, 7, 8, 1)
+    w = ctypes.c_void_p(0x1000)
+    assert lib.kc_create_in(ctypes.byref(L), w, 0, 65, None, 0, 0, None,
+                            ctypes.byref(h)) == kmerco.KC_EINVAL
+    assert lib.kc_create_in(ctypes.byref(L), w, 1, 21, None, 0, 0, None,
+                            ctypes.byref(h)) == kmerco.KC_EINVAL
+    assert lib.kc_create_in(ctypes.byref(L), w, 1, 0, ctypes.c_void_p(0x1010), 1 << 20, 0, None,
+                            ctypes.byref(h)) == kmerco.KC_EINVAL

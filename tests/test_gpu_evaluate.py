@@ -2,8 +2,10 @@
 k-mers exist, are unique, the trustworthy / erroneous lists partition them,
 no reported k-mer above tau is called erroneous (counters never under-count),
 and a countBF much larger than the sizing count misses under 1%."""
+import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -27,3 +29,27 @@ def test_evaluation_properties():
     # Eq. (1) gives about 1.8 n counters at alpha = 8, so even 50x the
     # sizing count leaves a k-mer a ~0.5% chance of a colliding first slot
     assert res[2]["distinct_recall"] > 0.99 and res[2]["trustworthy_precision"] > 0.99
+
+
+def test_evaluated_lists_equal_the_oracle():
+    """The lists evaluate() scores at each countBF size are the oracle's for
+    that size, element by element (so its rates are the method's)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    rs = synth.config("bacterial", scale=0.01)
+    sizes = [0.0625, 1.0, 16.0]
+    print("case evaluate lists vs oracle, bacterial x0.01 sizes", sizes, flush=True)
+    lists = {}
+    res = E.evaluate(rs, sizes, steps=1, lists=lists)
+    for f, r in zip(sizes, res):
+        X, Y = oracle.dims(f * rs.n_items)
+        assert (X, Y) == (r["X"], r["Y"])
+        words, distinct, trust, err, nw = oracle.run_kmerco(rs.reads, rs.offsets, rs.k, rs.tau,
+                                                            X, Y)
+        assert r["n_windows"] == nw
+        for name, a, b in zip(("words", "distinct", "trust", "err"), lists[f],
+                              (words, distinct, trust, err)):
+            assert np.array_equal(np.asarray(a, dtype=np.uint64),
+                                  np.asarray(b, dtype=np.uint64)), (f, name)
+        assert r["kmerco_distinct"] == len(distinct) and r["kmerco_trustworthy"] == len(trust)

@@ -326,19 +326,22 @@ def test_paths_agree_on_bacterial_sample(monkeypatch):
 
 @pytest.mark.parametrize("X,Y,what", [(4201, 4211, "8638 regions: tiles of 2^17 positions"),
                                       (2621, 2657, "3400 regions: 4096 tiles, 128 slices")])
-def test_full_chunk_binned_equals_direct(monkeypatch, X, Y, what):
+def test_full_chunk_against_oracle_digests(monkeypatch, X, Y, what):
     """A full binned chunk (2^28 positions) and a tail: the binned entries
     hold positions relative to their tile (level 1) and slice of tiles
     (level 2), so the largest tiles and the most slices a chunk can have are
-    checked against the direct path (itself checked against the oracle on
-    smaller inputs), output by output, on the device."""
+    checked against the oracle's digests of this seeded input (written by
+    tests/golden/make_digests.py), and the direct path against the same."""
+    ref = json.load(open(os.path.join(GOLDEN, f"fullchunk_{X}x{Y}_digests.json")))
     rs = synth.random_reads(1500, 1_400_000, 150, 250, k=31, p_n=0.0005, tau=3)
-    assert rs.n_bases > (1 << 28)
+    assert rs.n_bases > (1 << 28) and rs.n_bases == ref["n_bases"]
+    assert (X, Y, rs.k, rs.tau) == (ref["X"], ref["Y"], ref["k"], ref["tau"])
     print(f"case full chunk {what}: X={X} Y={Y} bases={rs.n_bases}", flush=True)
     r, o = dev(rs)
     outs = {}
     for p in ("binned", "direct"):
         monkeypatch.setenv("KMERCO_PATH", p)
+        print(f"case full chunk {what}: path {p}", flush=True)
         bf = P.CountBF(X, Y)
         bf.profile(True)
         d, t, nt, e, ne = bf.insert_classify(r, o, rs.k, rs.tau)
@@ -351,16 +354,17 @@ def test_full_chunk_binned_equals_direct(monkeypatch, X, Y, what):
         assert p == "direct" or phases["bin_region"][1] == 2  # the full chunk and the tail
         bf.close()
         del d, t, e
+    for p, (words, distinct, trust, err, nw) in outs.items():
+        assert nw == ref["n_windows"], p
+        assert (distinct.numel(), trust.numel(), err.numel()) == \
+            (ref["n_distinct"], ref["n_trust"], ref["n_err"]), p
+        assert _sha(words.cpu().numpy()) == ref["words_sha256"], p
+        assert _sha(distinct.cpu().numpy()) == ref["distinct_sha256"], p
+        assert _sha(trust.cpu().numpy()) == ref["trust_sha256"], p
+        assert _sha(err.cpu().numpy()) == ref["err_sha256"], p
     a, b = outs["binned"], outs["direct"]
-    assert a[4] == b[4]
     for n, x, y in zip(["words", "distinct", "trust", "err"], a[:4], b[:4]):
-        assert x.shape == y.shape, f"{what} {n}: {x.shape} != {y.shape}"
         assert torch.equal(x, y), f"{what} {n} differs"
-    # random 31-mers are all different: a window is listed when its counter
-    # was still untouched, C (1 - exp(-W / C)) of W windows over C counters
-    c = X * Y * 8
-    want = c * (1 - np.exp(-a[4] / c))
-    assert abs(a[1].numel() - want) < 0.05 * want, (a[1].numel(), want)
 
 
 def test_small_chunk_spread_over_many_workgroups():
@@ -433,3 +437,22 @@ def test_large_full_size_digests():
     assert h(out["t"][:nt]) == ref["trust_sha256"]
     assert h(out["e"][:ne]) == ref["err_sha256"]
     bf.close()
+
+
+def test_bacterial_k55_full_size_digests():
+    """The bacterial workload's reads at k = 55 (two-word keys, the paper's
+    longer k-mers) at full size, in the benchmark's launch configuration,
+    against the oracle's digests."""
+    ref = json.load(open(os.path.join(GOLDEN, "bacterial_k55_digests.json")))
+    rs = synth.config("bacterial")
+    X, Y = oracle.dims(rs.n_items)
+    assert (X, Y, 55) == (ref["X"], ref["Y"], ref["k"]) and rs.n_bases == ref["n_bases"]
+    print(f"case bacterial k=55 full: X={X} Y={Y} bases={rs.n_bases}", flush=True)
+    words, distinct, trust, err, nw = gpu_run(rs, X, Y, k=55)
+    assert nw == ref["n_windows"]
+    assert (len(distinct), len(trust), len(err)) == \
+        (ref["n_distinct"], ref["n_trust"], ref["n_err"])
+    assert _sha(words) == ref["words_sha256"]
+    assert _sha(distinct) == ref["distinct_sha256"]
+    assert _sha(trust) == ref["trust_sha256"]
+    assert _sha(err) == ref["err_sha256"]

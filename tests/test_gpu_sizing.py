@@ -28,6 +28,6 @@ def test_scratch_bytes_is_what_reserve_allocates(X, Y, n, alpha, k_h):
     torch.cuda.synchronize()
     free1, _ = torch.cuda.mem_get_info()
     used = free0 - free1
-    want = P.scratch_bytes(X, Y, n, alpha, k_h) - 4  # the status word came with the handle
+    want = P.scratch_bytes(X, Y, n, alpha, k_h) - 256  # the status word came with the handle
     bf.close()
     assert abs(used - want) <= 64 * 2**20 + 0.02 * want, (used, want)
