@@ -381,6 +381,12 @@ kc_status reserve_all(kc_filter *f, uint64_t max_bases) {
     return ensure_aux(f, f->last);
 }
 
+bool takes_binned_path(const kc_filter *f, uint64_t n_bases) {
+    kc::BinPlan plan{};
+    uint64_t chunk = 0;
+    return n_bases == 0 || choose_plan(f, n_bases, plan, chunk);
+}
+
 void share_workspace(kc_filter *f, kc::Workspace *W) { f->W = W ? W : &f->own; }
 
 uint64_t filter_private_bytes(const kc_layout &layout) {
@@ -421,10 +427,53 @@ void init_filter(kc_filter *f, const kc_layout *layout) {
     F.field_max = (layout->alpha >= 64) ? ~0ull : ((1ull << layout->alpha) - 1ull);
 }
 
-}  // namespace kcapi
-
-namespace {
-using namespace kcapi;
+// Everything of an insert after its reads are ingested into W's
+// per-position buffers (codes, bitmaps and flag bytes of positions
+// 0..n_bases): the valid-window bitmap, the chunks, the distinct output and
+// the split; W's other buffers are prepared for n_bases.  Kernels only.
+kc_status insert_core(kc_filter *f, const kc::Workspace &W, uint64_t n_bases, uint32_t k,
+                      bool binned, const kc::BinPlan &plan, uint64_t bchunk, uint64_t *distinct,
+                      uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows, uint32_t tau,
+                      uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                      uint64_t cap_te, hipStream_t s, kc::Profiler *P) {
+    const bool split = trust != nullptr;
+    hipError_t e = hipSuccess;
+    if (binned)
+        e = kc::launch_valid_windows(n_bases, k, W, s, P);
+    if (e == hipSuccess && binned)  // valid windows, accumulated by the bin passes
+        e = kc::fill_u64(W.totals + 5, 1, 0ull, s);
+    if (e != hipSuccess)
+        return KC_EDEVICE;
+    kc::ReadsArgs R{W.codes, W.inv, W.rs, n_bases, k, W.valid};
+    const uint64_t chunk = binned ? bchunk : f->chunk;
+    // this call's classification can be taken from the region pass when the
+    // final counter of each distinct k-mer's single slot is known there
+    const bool fused = split && binned && f->F.k_h == 1 && n_bases <= chunk;
+    for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk) {
+        uint64_t c1 = c0 + chunk < n_bases ? c0 + chunk : n_bases;
+        if (binned)
+            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, W, fused, tau, s, P);
+        else
+            e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, W, s, P);
+        if (e != hipSuccess)
+            return KC_EDEVICE;
+        f->zero = false;
+    }
+    e = kc::launch_distinct(R, W, distinct, cap_d, n_distinct, n_windows,
+                            fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status,
+                            binned, s, P);
+    if (e != hipSuccess)
+        return KC_EDEVICE;
+    if (split && !fused) {
+        // classify the keys this call appended: distinct[base .. *n_distinct),
+        // base saved by the distinct output step
+        e = kc::launch_classify(f->F, distinct, n_distinct, W.totals + 3, n_bases, cap_d, tau,
+                                trust, n_trust, err, n_err, cap_te, f->status, W, s, P, k > 32);
+        if (e != hipSuccess)
+            return KC_EDEVICE;
+    }
+    return KC_OK;
+}
 
 // Both phases for one call.  trust == nullptr: insertion only.
 kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offsets,
@@ -460,46 +509,89 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
         return st;
     }
     f->k = k;  // every check passed: the filter now holds k-mers of this length
-    hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, *f->W, s, &f->prof);
-    if (e == hipSuccess && binned)
-        e = kc::launch_valid_windows(n_bases, k, *f->W, s, &f->prof);
-    if (e == hipSuccess && binned)  // valid windows, accumulated by the bin passes
-        e = kc::fill_u64(f->W->totals + 5, 1, 0ull, s);
-    if (e != hipSuccess)
+    if (kc::launch_ingest(reads, n_bases, offsets, n_reads, *f->W, s, &f->prof) != hipSuccess)
         return KC_EDEVICE;
-    kc::ReadsArgs R{f->W->codes, f->W->inv, f->W->rs, n_bases, k, f->W->valid};
-    const uint64_t chunk = binned ? bchunk : f->chunk;
-    // this call's classification can be taken from the region pass when the
-    // final counter of each distinct k-mer's single slot is known there
-    const bool fused = split && binned && f->F.k_h == 1 && n_bases <= chunk;
-    for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk) {
-        uint64_t c1 = c0 + chunk < n_bases ? c0 + chunk : n_bases;
-        if (binned)
-            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, *f->W, fused, tau, s, &f->prof);
-        else
-            e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, *f->W, s, &f->prof);
-        if (e != hipSuccess)
-            return KC_EDEVICE;
-        f->zero = false;
-    }
-    e = kc::launch_distinct(R, *f->W, distinct, cap_d, n_distinct, n_windows,
-                            fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status,
-                            binned, s, &f->prof);
-    if (e != hipSuccess)
-        return KC_EDEVICE;
-    if (split && !fused) {
-        // classify the keys this call appended: distinct[base .. *n_distinct),
-        // base saved by the distinct output step
-        e = kc::launch_classify(f->F, distinct, n_distinct, f->W->totals + 3, n_bases, cap_d, tau,
-                                trust, n_trust, err, n_err, cap_te, f->status, *f->W, s,
-                                &f->prof, k > 32);
-        if (e != hipSuccess)
-            return KC_EDEVICE;
-    }
+    return insert_core(f, *f->W, n_bases, k, binned, plan, bchunk, distinct, cap_d, n_distinct,
+                       n_windows, tau, trust, n_trust, err, n_err, cap_te, s, &f->prof);
+}
+
+kc_status check_range(const kc_filter *f, uint64_t n_bases, uint32_t k) {
+    if (k < 1 || k > 64)
+        return KC_EINVAL;
+    if (f->k != 0 && f->k != k)
+        return KC_ESTATE;
+    kc::BinPlan plan{};
+    uint64_t bchunk = 0;
+    const bool binned = n_bases == 0 || choose_plan(f, n_bases, plan, bchunk);
+    if ((f->path == KcPath::Binned || k > 32) && !binned)
+        return KC_EINVAL;
     return KC_OK;
 }
 
-}  // namespace
+kc_status prepare_range(kc_filter *f, uint64_t n_bases) {
+    kc_status st = ensure_scalars(f);
+    if (st == KC_OK)
+        st = ensure_tiles(f, n_bases);
+    if (st != KC_OK || n_bases == 0)
+        return st;
+    kc::BinPlan plan{};
+    uint64_t bchunk = 0;
+    if (choose_plan(f, n_bases, plan, bchunk))
+        return ensure_plan(f, plan, bchunk);
+    return ensure_aux(f, f->last);
+}
+
+kc_status insert_range(kc_filter *f, const kc::Workspace &pos, uint64_t base, uint64_t n_bases,
+                       uint32_t k, bool reset, bool replayed, uint64_t *distinct,
+                       uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows, uint32_t tau,
+                       uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                       uint64_t cap_te, hipStream_t s, kc::Profiler *P) {
+    if (base % kc::kTile != 0)
+        return KC_EINVAL;
+    hipError_t e = hipSuccess;
+    if (reset) {
+        if (P)
+            P->begin(kc::kPhReset, s);
+        e = kc::fill_u64(f->F.words, f->layout.X * f->layout.Y, 0ull, s);
+        if (P)
+            P->end(s);
+        if (e == hipSuccess)
+            e = kc::fill_u64(n_distinct, 1, 0ull, s);
+        if (e == hipSuccess && n_windows)
+            e = kc::fill_u64(n_windows, 1, 0ull, s);
+        if (e != hipSuccess)
+            return KC_EDEVICE;
+    }
+    // the direct path's empty-filter variant only when the filter is known
+    // to be empty whenever these launches run (a graph replays them later)
+    f->zero = reset || (f->zero && !replayed);
+    if (n_bases == 0) {
+        if (trust && (kc::fill_u64(n_trust, 1, 0, s) != hipSuccess ||
+                      kc::fill_u64(n_err, 1, 0, s) != hipSuccess))
+            return KC_EDEVICE;
+        f->k = k;
+        return KC_OK;
+    }
+    kc::BinPlan plan{};
+    uint64_t bchunk = 0;
+    const bool binned = choose_plan(f, n_bases, plan, bchunk);
+    f->k = k;
+    // the set's positions in the shared per-position buffers (base is a
+    // multiple of the 1024-position tile: whole bitmap words, code words and
+    // flag tiles); every other buffer is f's
+    kc::Workspace V = *f->W;
+    V.codes = pos.codes + base / 16;
+    V.inv = pos.inv + base / 32;
+    V.rs = pos.rs + base / 32;
+    V.valid = pos.valid + base / 32;
+    V.flags8 = pos.flags8 + base;
+    return insert_core(f, V, n_bases, k, binned, plan, bchunk, distinct, cap_d, n_distinct,
+                       n_windows, tau, trust, n_trust, err, n_err, cap_te, s, P);
+}
+
+}  // namespace kcapi
+
+using namespace kcapi;
 
 extern "C" {
 

@@ -1,6 +1,13 @@
 // C ABI of the batched form (declared in include/kmerco.h): many read sets,
 // each with its own countBF, inserted (and classified) by one launch per
 // phase; optional HIP-graph capture and replay; work-item size autotuning.
+//
+// Sets the fused phase kernels cannot take (a countBF of more than
+// kBatchMaxRegions regions, more than kBinChunk bases, or k > 32) run the
+// single-set pipeline over their range of the batch's ingested buffer, on up
+// to kSideLanes side streams forked from the call's stream after the ingest
+// and joined before the call ends, each lane with a workspace of its own, so
+// that they overlap each other and the fused phases.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,9 +22,18 @@
 
 using namespace kcapi;
 
+constexpr int kSideLanes = 3;
+
 struct kc_batch {
     int device = 0;
     kc::Workspace W;
+    // side lanes for the sets of the single-set pipeline
+    hipStream_t side[kSideLanes] = {};
+    hipEvent_t forked = nullptr, joined[kSideLanes] = {};
+    kc::Workspace side_ws[kSideLanes];
+    std::vector<uint32_t> big;       // the call's sets of the single-set pipeline
+    std::vector<int> big_lane;       // their lanes
+    uint32_t lanes_used = 0;
     kc::BatchBuffers B;
     uint64_t cap_sets = 0, cap_items = 0, cap_regions = 0, cap_tiles = 0, cap_slots = 0,
              cap_matrix = 0, cap_entries = 0;
@@ -35,6 +51,14 @@ struct kc_batch {
 namespace {
 
 constexpr uint64_t kTileCandidates[] = {16384, 32768, 65536, 131072, 262144};
+
+// Whether the fused phase kernels take a set (else the single-set pipeline).
+bool fused_form(const kc_set &q) {
+    kc::BinPlan bp{};
+    return q.k <= 32 && q.n_bases <= kc::kBinChunk && kc::bin_plan(q.filter->F, q.n_bases, bp) &&
+           bp.n_regions <= kc::kBatchMaxRegions;
+}
+
 
 void free_batch_buffers(kc_batch *b) {
     kc::BatchBuffers &B = b->B;
@@ -93,7 +117,7 @@ kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64
     uint32_t reg = 0, item = 0;
     for (uint32_t i = 0; i < n_sets; i++) {
         const kc_set &q = sets[i];
-        if (q.n_bases == 0)
+        if (q.n_bases == 0 || !fused_form(q))
             continue;
         kc_filter *f = q.filter;
         kc::BinPlan bp{};
@@ -208,26 +232,100 @@ kc_status upload(kc_batch *b, const kc::BatchPlan &P, hipStream_t s) {
     return e == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
-// Launch sequence of one call (ingest, batch pipeline, per-set split for
-// sets the region pass cannot classify).
+// The call's sets of the single-set pipeline (and its empty sets, which only
+// reset and zero their outputs), largest first, each on the least loaded
+// side lane; their lanes' workspaces are sized for them (this may allocate,
+// and waits for a lane's earlier work before its workspace moves).
+kc_status plan_side(kc_batch *b, const kc_set *sets, uint32_t n_sets) {
+    b->big.clear();
+    b->big_lane.clear();
+    b->lanes_used = 0;
+    for (uint32_t i = 0; i < n_sets; i++)
+        if (sets[i].n_bases == 0 || !fused_form(sets[i]))
+            b->big.push_back(i);
+    if (b->big.empty())
+        return KC_OK;
+    std::stable_sort(b->big.begin(), b->big.end(), [&](uint32_t x, uint32_t y) {
+        return sets[x].n_bases > sets[y].n_bases;
+    });
+    uint64_t load[kSideLanes] = {};
+    for (uint32_t i : b->big) {
+        int l = 0;
+        for (int j = 1; j < kSideLanes; j++)
+            if (load[j] < load[l])
+                l = j;
+        load[l] += sets[i].n_bases + 1;
+        b->big_lane.push_back(l);
+        if ((uint32_t)l + 1 > b->lanes_used)
+            b->lanes_used = (uint32_t)l + 1;
+    }
+    if (!b->forked && hipEventCreateWithFlags(&b->forked, hipEventDisableTiming) != hipSuccess)
+        return KC_EDEVICE;
+    for (uint32_t l = 0; l < b->lanes_used; l++) {
+        // default priority (the streams of one process share the hardware
+        // queues fairly)
+        if (!b->side[l] && hipStreamCreateWithFlags(&b->side[l], hipStreamNonBlocking) != hipSuccess)
+            return KC_EDEVICE;
+        if (!b->joined[l] &&
+            hipEventCreateWithFlags(&b->joined[l], hipEventDisableTiming) != hipSuccess)
+            return KC_EDEVICE;
+    }
+    for (size_t j = 0; j < b->big.size(); j++) {
+        kc_filter *f = sets[b->big[j]].filter;
+        const int l = b->big_lane[j];
+        kc::Workspace *own = f->W;
+        f->W = &b->side_ws[l];
+        f->last = b->side[l];
+        const kc_status st = prepare_range(f, sets[b->big[j]].n_bases);
+        f->W = own;
+        if (st != KC_OK)
+            return st;
+    }
+    return KC_OK;
+}
+
+// Launch sequence of one call: the ingest of the whole buffer; the side
+// lanes' sets forked after it; the fused phases and the per-set split of the
+// sets the region pass cannot classify; the join.
 kc_status launch_all(kc_batch *b, const kc::BatchPlan &P, const kc_set *sets, uint32_t n_sets,
                      const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads,
-                     uint64_t n_bases, bool reset, hipStream_t s, kc::Profiler *prof) {
+                     uint64_t n_bases, bool reset, bool replayed, hipStream_t s,
+                     kc::Profiler *prof) {
     hipError_t e = kc::launch_ingest(reads, n_bases, offsets, n_reads, b->W, s, prof);
-    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0, b->W.valid};
-    if (e == hipSuccess && P.n_sets)
-        e = kc::launch_batch(P, b->B, R, reset, s, prof);
     if (e != hipSuccess)
         return KC_EDEVICE;
-    uint32_t di = 0;
-    for (uint32_t i = 0; i < n_sets; i++) {
-        const kc_set &q = sets[i];
-        if (q.n_bases == 0) {
-            if (q.trust_dev && (kc::fill_u64(q.n_trust_dev, 1, 0, s) != hipSuccess ||
-                                kc::fill_u64(q.n_err_dev, 1, 0, s) != hipSuccess))
+    kc_status st = KC_OK;
+    const bool side = !b->big.empty();
+    if (side) {
+        if (hipEventRecord(b->forked, s) != hipSuccess)
+            return KC_EDEVICE;
+        for (uint32_t l = 0; l < b->lanes_used; l++)
+            if (hipStreamWaitEvent(b->side[l], b->forked, 0) != hipSuccess)
                 return KC_EDEVICE;
-            continue;
+        for (size_t j = 0; j < b->big.size() && st == KC_OK; j++) {
+            const kc_set &q = sets[b->big[j]];
+            const int l = b->big_lane[j];
+            kc_filter *f = q.filter;
+            kc::Workspace *own = f->W;
+            f->W = &b->side_ws[l];
+            st = insert_range(f, b->W, q.first_base, q.n_bases, q.k, reset, replayed,
+                              q.distinct_dev, q.distinct_cap, q.n_distinct_dev, q.n_windows_dev,
+                              q.tau, q.trust_dev, q.n_trust_dev, q.err_dev, q.n_err_dev,
+                              q.class_cap, b->side[l], prof);
+            f->W = own;
         }
+        for (uint32_t l = 0; l < b->lanes_used; l++)
+            if (hipEventRecord(b->joined[l], b->side[l]) != hipSuccess)
+                st = KC_EDEVICE;
+    }
+    kc::ReadsArgs R{b->W.codes, b->W.inv, b->W.rs, n_bases, 0, b->W.valid};
+    if (st == KC_OK && P.n_sets && kc::launch_batch(P, b->B, R, reset, s, prof) != hipSuccess)
+        st = KC_EDEVICE;
+    uint32_t di = 0;
+    for (uint32_t i = 0; i < n_sets && st == KC_OK; i++) {
+        const kc_set &q = sets[i];
+        if (q.n_bases == 0 || !fused_form(q))
+            continue;
         const kc::SetDesc &d = b->h_sets[di++];
         if (q.trust_dev && !d.fused) {
             // split of the keys this set appended: distinct[saved .. *n_distinct)
@@ -236,10 +334,88 @@ kc_status launch_all(kc_batch *b, const kc::BatchPlan &P, const kc_set *sets, ui
                                     q.trust_dev, q.n_trust_dev, q.err_dev, q.n_err_dev,
                                     q.class_cap, q.filter->status, b->W, s, prof);
             if (e != hipSuccess)
-                return KC_EDEVICE;
+                st = KC_EDEVICE;
         }
     }
-    return KC_OK;
+    // joined even after a failure, so that a capture ends with every stream
+    for (uint32_t l = 0; side && l < b->lanes_used; l++)
+        if (hipStreamWaitEvent(s, b->joined[l], 0) != hipSuccess)
+            st = KC_EDEVICE;
+    return st;
+}
+
+// Positions per chunk of the single-set pipeline tried by the tuner for a
+// filter whose inserts take the partitioned path (more chunks: less
+// scratch, more passes over the countBF) or the single-level binned path.
+constexpr uint64_t kPartChunkCandidates[] = {1ull << 30, 1ull << 31, kc::kPartChunk};
+constexpr uint64_t kBinChunkCandidates[] = {1ull << 26, 1ull << 27, kc::kBinChunk};
+
+// Tune the chunk size of each side-lane set on this input, timing its whole
+// pipeline once per candidate (reset first, so only with KC_BATCH_RESET: the
+// real run resets again); the handle keeps the fastest.
+kc_status tune_side(kc_batch *b, const kc_set *sets, hipStream_t s) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return KC_EDEVICE;
+    kc_status st = KC_OK;
+    if (hipStreamSynchronize(s) != hipSuccess)  // the ingest of the buffer is done
+        st = KC_EDEVICE;
+    for (size_t j = 0; j < b->big.size() && st == KC_OK; j++) {
+        const kc_set &q = sets[b->big[j]];
+        kc_filter *f = q.filter;
+        if (q.n_bases == 0 || !takes_binned_path(f, q.n_bases))
+            continue;
+        kc::BinPlan bp{};
+        if (!kc::bin_plan(f->F, q.n_bases < kc::kBinChunk ? q.n_bases : kc::kBinChunk, bp))
+            continue;
+        const bool parts = bp.n_parts > 0;
+        const uint64_t *cand = parts ? kPartChunkCandidates : kBinChunkCandidates;
+        const int l = b->big_lane[j];
+        kc::Workspace *own = f->W;
+        f->W = &b->side_ws[l];
+        f->last = b->side[l];
+        uint64_t &knob = parts ? f->part_chunk : f->bin_chunk;
+        const uint64_t keep = knob;
+        uint64_t best = keep;
+        float best_ms = 1e30f;
+        uint64_t tried_last = 0;
+        for (int c = 0; c < 3 && st == KC_OK; c++) {
+            const uint64_t chunk = cand[c];
+            // candidates at or above the insert's size are the same plan
+            const uint64_t eff = chunk < q.n_bases ? chunk : q.n_bases;
+            if (eff == tried_last)
+                continue;
+            tried_last = eff;
+            knob = chunk;
+            if ((st = prepare_range(f, q.n_bases)) != KC_OK)
+                break;
+            float ms = 0.f;
+            if (hipEventRecord(e0, b->side[l]) != hipSuccess ||
+                (st = insert_range(f, b->W, q.first_base, q.n_bases, q.k, true, false,
+                                   q.distinct_dev, q.distinct_cap, q.n_distinct_dev,
+                                   q.n_windows_dev, q.tau, q.trust_dev, q.n_trust_dev, q.err_dev,
+                                   q.n_err_dev, q.class_cap, b->side[l], nullptr)) != KC_OK ||
+                hipEventRecord(e1, b->side[l]) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                if (st == KC_OK)
+                    st = KC_EDEVICE;
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = chunk;
+            }
+        }
+        knob = st == KC_OK ? best : keep;
+        if (st == KC_OK)
+            st = prepare_range(f, q.n_bases);
+        f->W = own;
+        f->last = s;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
 }
 
 // Fastest work-item size for this input, timed on the binning kernels only
@@ -286,6 +462,18 @@ kc_status autotune(kc_batch *b, const kc_set *sets, uint32_t n_sets, const uint8
     return st;
 }
 
+// Every buffer address of a workspace (a captured graph bakes them in).
+void workspace_pointers(const kc::Workspace &W, std::vector<uint64_t> &out) {
+    const void *p[] = {W.codes, W.inv, W.rs, W.valid, W.flags8, W.tile_a, W.tile_b, W.tile_c,
+                       W.off_a, W.off_b, W.off_c, W.tmask, W.partial64, W.matrix, W.matrix_t,
+                       W.coarse, W.partial32, W.slots, W.bucketed, W.entries, W.pmat, W.pbounds,
+                       W.pdesc, W.totals, W.n_entries};
+    for (const void *x : p)
+        out.push_back((uint64_t)(uintptr_t)x);
+    out.insert(out.end(), {W.cap, W.tile_cap, W.matrix_cap, W.coarse_cap, W.slots_cap,
+                           W.entries_cap, W.pmat_cap});
+}
+
 // Everything a captured graph depends on: the arguments, the work-item size
 // and the workspace addresses baked into its kernels.
 std::vector<uint8_t> call_key(const kc_batch *b, const kc_set *sets, uint32_t n_sets,
@@ -302,14 +490,21 @@ std::vector<uint8_t> call_key(const kc_batch *b, const kc_set *sets, uint32_t n_
                              (uint64_t)(uintptr_t)W.partial64, (uint64_t)(uintptr_t)W.totals,
                              (uint64_t)(uintptr_t)W.tmask};
     // each set's filter by its generation (a destroyed handle's host address
-    // can be reused) and the device state its launches bake in
+    // can be reused), the device state and plan its launches bake in, and
+    // the side lanes' workspaces
     std::vector<uint64_t> filt;
     for (uint32_t i = 0; i < n_sets; i++) {
         const kc_filter *f = sets[i].filter;
         filt.insert(filt.end(), {f->generation, (uint64_t)(uintptr_t)f->F.words,
-                                 (uint64_t)(uintptr_t)f->status, f->layout.X, f->layout.Y,
-                                 f->layout.alpha, f->layout.k_h});
+                                 (uint64_t)(uintptr_t)f->status, (uint64_t)(uintptr_t)f->F.aux,
+                                 f->layout.X, f->layout.Y, f->layout.alpha, f->layout.k_h,
+                                 f->chunk, f->bin_chunk, f->part_chunk, f->part_log,
+                                 (uint64_t)f->path});
     }
+    for (uint32_t l = 0; l < b->lanes_used; l++)
+        workspace_pointers(b->side_ws[l], filt);
+    filt.insert(filt.end(), b->big.begin(), b->big.end());
+    filt.insert(filt.end(), b->big_lane.begin(), b->big_lane.end());
     const size_t nf = filt.size() * sizeof(uint64_t);
     std::vector<uint8_t> k(n_sets * sizeof(kc_set) + sizeof tail + nf);
     std::memcpy(k.data(), sets, n_sets * sizeof(kc_set));
@@ -329,7 +524,7 @@ kc_status validate(const kc_set *sets, uint32_t n_sets, const uint8_t *reads,
     for (uint32_t i = 0; i < n_sets; i++) {
         const kc_set &q = sets[i];
         kc_filter *f = q.filter;
-        if (!f || f->device != device || q.k < 1 || q.k > 32 || !q.n_distinct_dev)
+        if (!f || f->device != device || q.k < 1 || q.k > 64 || !q.n_distinct_dev)
             return KC_EINVAL;
         if (f->k != 0 && f->k != q.k)
             return KC_ESTATE;
@@ -343,13 +538,13 @@ kc_status validate(const kc_set *sets, uint32_t n_sets, const uint8_t *reads,
         for (uint32_t j = 0; j < i; j++)
             if (sets[j].filter == f)
                 return KC_EINVAL;  // one filter per set
-        if (q.n_bases > 0) {
-            kc::BinPlan bp{};
-            if (q.n_bases > kc::kBinChunk || !kc::bin_plan(f->F, q.n_bases, bp) ||
-                bp.n_regions > kc::kBatchMaxRegions)
-                return KC_EINVAL;  // too large for the batched form: use kc_insert
+        if (q.n_bases > 0 && fused_form(q)) {
+            entries += q.n_bases * f->F.k_h;
+        } else {
+            const kc_status st = check_range(f, q.n_bases, q.k);
+            if (st != KC_OK)
+                return st;
         }
-        entries += q.n_bases * f->F.k_h;
         end = q.first_base + q.n_bases;
     }
     if (entries >= (1ull << 32))
@@ -391,6 +586,15 @@ void kc_batch_destroy(kc_batch *b) {
     b->prof.release();
     free_batch_buffers(b);
     free_workspace(b->W);
+    for (int l = 0; l < kSideLanes; l++) {
+        free_workspace(b->side_ws[l]);
+        if (b->side[l])
+            (void)hipStreamDestroy(b->side[l]);
+        if (b->joined[l])
+            (void)hipEventDestroy(b->joined[l]);
+    }
+    if (b->forked)
+        (void)hipEventDestroy(b->forked);
     delete b;
 }
 
@@ -414,10 +618,20 @@ kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
     if ((st = ensure_scalars(b->W)) != KC_OK || (st = ensure_positions(b->W, s, n_bases, true)) != KC_OK ||
         (st = ensure_tiles(b->W, s, n_bases)) != KC_OK)
         return st;
+    if ((st = plan_side(b, sets, n_sets)) != KC_OK)
+        return st;
     if (flags & KC_BATCH_TUNE) {
         drop_graph(b);  // tuning rewrites the device descriptor table
-        if ((st = autotune(b, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, s)) != KC_OK)
+        if (b->big.size() < n_sets &&
+            (st = autotune(b, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, s)) != KC_OK)
             return st;
+        if (reset && !b->big.empty()) {
+            if (kc::launch_ingest(reads_dev, n_bases, offsets_dev, n_reads, b->W, s, nullptr) !=
+                hipSuccess)
+                return KC_EDEVICE;
+            if ((st = tune_side(b, sets, s)) != KC_OK)
+                return st;
+        }
     }
     std::vector<uint8_t> key;
     if (graph) {
@@ -425,7 +639,7 @@ kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
         if (b->exec && key == b->graph_key) {
             if (hipGraphLaunch(b->exec, s) != hipSuccess)
                 return KC_EDEVICE;
-            for (uint32_t i = 0; i < n_sets; i++) {
+            for (uint32_t i = 0; i < n_sets; i++) {  // as after the captured call
                 sets[i].filter->zero = false;
                 sets[i].filter->k = sets[i].k;
                 sets[i].filter->last = s;
@@ -441,8 +655,8 @@ kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
     if (graph) {
         if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess)
             return KC_EDEVICE;
-        st = launch_all(b, P, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, reset, s,
-                        nullptr);
+        st = launch_all(b, P, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, reset, true,
+                        s, nullptr);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(s, &gr);
         if (st != KC_OK || e != hipSuccess) {
@@ -461,8 +675,8 @@ kc_status kc_batch_insert(kc_batch *b, const kc_set *sets, uint32_t n_sets,
         if (hipGraphLaunch(ex, s) != hipSuccess)
             return KC_EDEVICE;
     } else {
-        st = launch_all(b, P, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, reset, s,
-                        &b->prof);
+        st = launch_all(b, P, sets, n_sets, reads_dev, offsets_dev, n_reads, n_bases, reset, false,
+                        s, &b->prof);
         if (st != KC_OK)
             return st;
     }

@@ -121,5 +121,35 @@ void share_workspace(kc_filter *f, kc::Workspace *W);
 uint64_t filter_private_bytes(const kc_layout &layout);
 // Whether a handle can be a set of a kc_batch_insert call.
 bool batchable(const kc_filter *f);
+// Every buffer inserts of up to max_bases bases need, in the current
+// dev_alloc mode, in f->W.
+kc_status reserve_all(kc_filter *f, uint64_t max_bases);
+// Whether inserts of n_bases into f take a binned path (else the direct
+// path, which keeps per-counter state of its own).
+bool takes_binned_path(const kc_filter *f, uint64_t n_bases);
+// One read set of a larger ingested buffer (the batched form's sets that its
+// fused kernels do not take): check_range validates it against f,
+// prepare_range sizes f->W for it (may allocate and wait on f->last), and
+// insert_range enqueues its insertion (and split, when trust != nullptr) on
+// s, kernels only, reading the set's positions [base, base + n_bases) from
+// pos's codes, bitmaps and flag bytes (base a multiple of kc::kTile) and
+// using f->W for everything else.  reset: clear the countBF and the
+// distinct / window counters first.  replayed: the launches are captured
+// into a graph (the direct path then never assumes an empty filter unless
+// reset).
+kc_status check_range(const kc_filter *f, uint64_t n_bases, uint32_t k);
+kc_status prepare_range(kc_filter *f, uint64_t n_bases);
+kc_status insert_range(kc_filter *f, const kc::Workspace &pos, uint64_t base, uint64_t n_bases,
+                       uint32_t k, bool reset, bool replayed, uint64_t *distinct,
+                       uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows, uint32_t tau,
+                       uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                       uint64_t cap_te, hipStream_t s, kc::Profiler *P);
+// kc_insert / kc_insert_classify after the argument checks (trust ==
+// nullptr: insertion only), with f's device current, in f->W.
+kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offsets,
+                      uint64_t n_reads, uint64_t n_bases, uint32_t k, uint64_t *distinct,
+                      uint64_t cap_d, uint64_t *n_distinct, uint64_t *n_windows, uint32_t tau,
+                      uint64_t *trust, uint64_t *n_trust, uint64_t *err, uint64_t *n_err,
+                      uint64_t cap_te, hipStream_t s);
 
 }  // namespace kcapi

@@ -554,24 +554,28 @@ static hipError_t launch(Profiler *P, int phase, K kernel, dim3 grid, dim3 block
 }
 
 // The valid-window bitmap of K-base windows (valid_word), one mask word per
-// thread.
+// thread.  Only the words of the call's tiles are written (n_out), so that a
+// read set inside a larger buffer leaves its neighbours' words alone; the
+// bin passes read no word past them.
 __global__ void __launch_bounds__(256) k_valid_windows(const uint32_t *__restrict__ inv,
                                                        const uint32_t *__restrict__ rs,
-                                                       uint64_t n_words, uint64_t n_bases,
-                                                       uint32_t K, uint32_t *__restrict__ valid) {
+                                                       uint64_t n_words, uint64_t n_out,
+                                                       uint64_t n_bases, uint32_t K,
+                                                       uint32_t *__restrict__ valid) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride)
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride)
         valid[i] = valid_word(inv, rs, n_words, i, K, n_bases);
 }
 
 hipError_t launch_valid_windows(uint64_t n_bases, uint32_t k, const Workspace &W, hipStream_t s,
                                 Profiler *P) {
     const uint64_t n_mask = mask_words(n_bases);
+    const uint64_t n_out = tiles(n_bases) * (kTile / 32);
     if (P)
         P->begin(kPhValid, s);
-    hipLaunchKernelGGL(k_valid_windows, dim3(grid_for(n_mask, 256)), dim3(256), 0, s,
-                       (const uint32_t *)W.inv, (const uint32_t *)W.rs, n_mask, n_bases, k,
-                       W.valid);
+    hipLaunchKernelGGL(k_valid_windows, dim3(grid_for(n_out, 256)), dim3(256), 0, s,
+                       (const uint32_t *)W.inv, (const uint32_t *)W.rs, n_mask, n_out, n_bases,
+                       k, W.valid);
     if (P)
         P->end(s);
     return hipGetLastError();

@@ -4,7 +4,7 @@ Calls only ``oracle`` and ``synth``; the GPU parity tests compare the HIP
 path's outputs against these stored digests.  Usage:
 
     python tests/golden/make_digests.py tiny bacterial batched bacterial_k55
-    python tests/golden/make_digests.py fullchunk_4201x4211 fullchunk_2621x2657
+    python tests/golden/make_digests.py fullchunk_4201x4211 fullchunk_2621x2657 fullchunk_5801x5807
 
 The batched workload (256 independent read sets, each with its own countBF)
 is stored set by set; its sets run in parallel host processes.
@@ -59,6 +59,8 @@ def _full_chunk_reads():
 INPUTS = {
     "fullchunk_4201x4211": (_full_chunk_reads, 4201, 4211),
     "fullchunk_2621x2657": (_full_chunk_reads, 2621, 2657),
+    # a countBF of 16,448 regions (269 MB): the partitioned path
+    "fullchunk_5801x5807": (_full_chunk_reads, 5801, 5807),
 }
 
 

@@ -38,7 +38,7 @@ class BatchRun:
         self.entries = []
         for (rs, (X, Y, a, kh), split), (base, nb, _, _) in zip(cases, self.spans):
             f = P.CountBF(X, Y, a, kh, stream=stream)
-            room = nb + extra + 64  # distinct <= windows <= bases
+            room = (nb + extra + 64) * P.key_words(rs.k)  # distinct <= windows <= bases
             e = {"filter": f, "first_base": base, "n_bases": nb, "k": rs.k, "tau": rs.tau,
                  "distinct": torch.empty(room, dtype=torch.int64, device="cuda"),
                  "n_distinct": torch.zeros(1, dtype=torch.int64, device="cuda"),
@@ -55,12 +55,14 @@ class BatchRun:
         out = []
         for e in self.entries:
             e["filter"].sync()
+            w = P.key_words(e["k"])
+            lst = lambda t, n: u(t[:n * w]).reshape(-1, 2) if w == 2 else u(t[:n])  # noqa: E731
             nd = int(e["n_distinct"].item())
-            r = {"words": u(e["filter"].words), "distinct": u(e["distinct"][:nd]),
+            r = {"words": u(e["filter"].words), "distinct": lst(e["distinct"], nd),
                  "nw": int(e["n_windows"].item())}
             if "trust" in e:
-                r["trust"] = u(e["trust"][:int(e["n_trust"].item())])
-                r["err"] = u(e["err"][:int(e["n_err"].item())])
+                r["trust"] = lst(e["trust"], int(e["n_trust"].item()))
+                r["err"] = lst(e["err"], int(e["n_err"].item()))
             out.append(r)
         return out
 
@@ -195,10 +197,10 @@ def test_batch_argument_errors():
     dup[2]["filter"] = dup[0]["filter"]  # one filter for two sets
     with pytest.raises(P.KmercoError):
         b.insert(dup, run.reads, run.offs)
-    big = [dict(e) for e in run.entries]
-    big[0]["filter"] = P.CountBF(4099, 4111)  # 2^14 regions: beyond the batched limit
+    wide = [dict(e) for e in run.entries]
+    wide[0]["k"] = 65  # beyond the longest k-mer
     with pytest.raises(P.KmercoError):
-        b.insert(big, run.reads, run.offs)
+        b.insert(wide, run.reads, run.offs)
     with pytest.raises(P.KmercoError):
         b.insert(run.entries, run.reads, run.offs, graph=True, stream=torch.cuda.default_stream())
 
@@ -232,3 +234,82 @@ def test_batched_workload_full_size_digests():
         assert h(g["distinct"]) == r["distinct_sha256"], f"set {i} distinct"
         assert h(g["trust"]) == r["trust_sha256"], f"set {i} trust"
         assert h(g["err"]) == r["err_sha256"], f"set {i} err"
+
+
+def side_lane_cases():
+    """Sets the fused phase kernels do not take, mixed with ones they do: a
+    countBF of 8229 regions (single-level binned, beyond the fused form's
+    2048), one of 16,448 regions (the partitioned path), 40-mers (two-word
+    keys), an empty set, and small sets around them."""
+    small = mixed_cases(7)
+    big_reads = synth.random_reads(8100, 9000, 80, 250, k=31, tau=3, p_n=0.002)
+    part_reads = synth.random_reads(8200, 6000, 60, 200, k=27, tau=2, p_n=0.002)
+    wide_reads = synth.random_reads(8300, 3000, 50, 220, k=40, tau=2, p_n=0.002,
+                                    alphabet=b"ACGT")
+    empty = synth.reads_from_strings([], k=21, tau=2)
+    return [small[0], (big_reads, (4099, 4111, 8, 1), True), small[1],
+            (part_reads, (5801, 5807, 8, 1), True), (wide_reads, (307, 311, 8, 1), True),
+            small[2], (empty, (101, 103, 8, 1), True), small[3]]
+
+
+def test_side_lane_sets_eager_graph_and_tuned():
+    """Every set equals the oracle run on it alone: eager, then captured and
+    replayed three times with unrelated eager work between the replays, then
+    with the tuner (work-item size and the side sets' chunk sizes)."""
+    cases = side_lane_cases()
+    want = oracle_each(cases)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        run = BatchRun(cases, stream=stream)
+        b = P.Batch()
+        print("case side lanes: eager", flush=True)
+        b.insert(run.entries, run.reads, run.offs, reset=True, stream=stream)
+        assert_sets_equal(run.results(), want, "side lanes eager")
+        for rep in range(3):
+            print(f"case side lanes: graph replay {rep}", flush=True)
+            b.insert(run.entries, run.reads, run.offs, reset=True, graph=True, stream=stream)
+            assert_sets_equal(run.results(), want, f"side lanes graph {rep}")
+            x = torch.arange(1 << 20, device="cuda").sum()
+            torch.cuda.synchronize()
+            assert int(x.item()) == (1 << 20) * ((1 << 20) - 1) // 2
+        print("case side lanes: tuned", flush=True)
+        b.insert(run.entries, run.reads, run.offs, reset=True, tune=True, stream=stream)
+        assert_sets_equal(run.results(), want, "side lanes tuned")
+        b.insert(run.entries, run.reads, run.offs, reset=True, graph=True, stream=stream)
+        assert_sets_equal(run.results(), want, "side lanes tuned, graph")
+
+
+def test_side_lane_full_chunk_partitioned_digests():
+    """A set of 280 M bases (more than one 2^28-base chunk of the fused form)
+    into a 269 MB countBF (16,448 regions: the partitioned path) between two
+    small sets, tuned and graph-captured, against the oracle's digests of
+    that input and the oracle on the small sets."""
+    import hashlib
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "fullchunk_5801x5807_digests.json")))
+    rs = synth.random_reads(1500, 1_400_000, 150, 250, k=31, p_n=0.0005, tau=3)
+    assert rs.n_bases == ref["n_bases"] and rs.n_bases > (1 << 28)
+    small = mixed_cases(8)
+    cases = [small[0], (rs, (5801, 5807, 8, 1), True), small[1]]
+    print(f"case side lane full chunk partitioned: {rs.n_bases} bases", flush=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        run = BatchRun(cases, stream=stream)
+        b = P.Batch()
+        b.insert(run.entries, run.reads, run.offs, reset=True, tune=True, stream=stream)
+        b.insert(run.entries, run.reads, run.offs, reset=True, graph=True, stream=stream)
+        got = run.results()
+
+    def h(a):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
+
+    g = got[1]
+    assert g["nw"] == ref["n_windows"]
+    assert (len(g["distinct"]), len(g["trust"]), len(g["err"])) == \
+        (ref["n_distinct"], ref["n_trust"], ref["n_err"])
+    assert h(g["words"]) == ref["words_sha256"] and h(g["distinct"]) == ref["distinct_sha256"]
+    assert h(g["trust"]) == ref["trust_sha256"] and h(g["err"]) == ref["err_sha256"]
+    want = oracle_each([small[0], small[1]])
+    assert_sets_equal([got[0], got[2]], want, "small sets beside the large one")
