@@ -231,6 +231,29 @@ kc_status kc_insert_classify(kc_filter *f, const uint8_t *reads_dev, const uint6
                              uint64_t *trust_dev, uint64_t *n_trust_dev, uint64_t *err_dev,
                              uint64_t *n_err_dev, uint64_t class_cap, void *stream);
 
+/* kc_insert_classify for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same outputs, but every scratch buffer of the
+ * call is a piece of one fixed device array of KC_NOALLOC_SCRATCH_BYTES
+ * bytes that the library holds per device from its load until the process
+ * ends, so the call allocates nothing (the handle's own scratch is not
+ * used).  The inputs and outputs are still the caller's.
+ * Limits: the call's scratch (about kc_scratch_bytes(layout, n_bases)) must
+ * fit the array, else KC_ERANGE and nothing is enqueued: about 2.5 M bases
+ * for countBFs of up to a few hundred regions; filters that take the direct
+ * path (KMERCO_PATH=direct) are refused with KC_EINVAL.
+ * Every call on one device uses that device's one array: calls that overlap
+ * on a device (other host threads, other streams not ordered with this
+ * one) race and give wrong results; calls ordered on one stream are safe. */
+#define KC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+kc_status kc_insert_classify_noalloc(kc_filter *f, const uint8_t *reads_dev,
+                                     const uint64_t *offsets_dev, uint64_t n_reads,
+                                     uint64_t n_bases, uint32_t k, uint32_t tau,
+                                     uint64_t *distinct_dev, uint64_t distinct_cap,
+                                     uint64_t *n_distinct_dev, uint64_t *n_windows_dev,
+                                     uint64_t *trust_dev, uint64_t *n_trust_dev, uint64_t *err_dev,
+                                     uint64_t *n_err_dev, uint64_t class_cap, void *stream);
+
 /* Classification phase (Algorithm 2 with Query-II / Algorithm 5), async.
  * keys_dev / n_keys_dev: the k-mers to classify (typically the distinct list
  * and its device count); n = min(*n_keys_dev, keys_cap) keys are used.

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkmerco_hip.so")
-SOURCES = ["kc_kernels.hip", "kc_binned.hip", "kc_batched.hip", "kc_scan.hip", "kc_api.hip", "kc_batch_api.hip", "kc_serve.hip", "kc_fastx.hip"]
+SOURCES = ["kc_kernels.hip", "kc_binned.hip", "kc_batched.hip", "kc_scan.hip", "kc_api.hip", "kc_batch_api.hip", "kc_serve.hip", "kc_fastx.hip", "kc_noalloc.hip"]
 MICROBENCH_LIB = os.path.join(HERE, "libkmerco_microbench.so")
 MICROBENCH_SOURCES = ["kc_microbench.hip"]
 

@@ -104,6 +104,8 @@ SIGNATURES = {
     "kc_classify": (_i, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp, _vp, _vp]),
     "kc_insert_classify": (_i, [_vp, _vp, _vp, _u64, _u64, _u32, _u32, _vp, _u64, _vp, _vp,
                                 _vp, _vp, _vp, _vp, _u64, _vp]),
+    "kc_insert_classify_noalloc": (_i, [_vp, _vp, _vp, _u64, _u64, _u32, _u32, _vp, _u64, _vp,
+                                        _vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "kc_query": (_i, [_vp, _vp, _u64, _vp, _vp]),
     "kc_sync": (_i, [_vp]),
     "kc_get_layout": (_i, [_vp, ctypes.POINTER(kc_layout)]),
@@ -375,6 +377,27 @@ class CountBF:
                 _stream_ptr(stream)), "kc_insert_classify")
         self.k = k
         return distinct, trust, n_trust, err, n_err
+
+    def insert_classify_noalloc(self, reads, offsets, k: int, tau: int, distinct, trust, err,
+                                n_distinct, n_windows, n_trust, n_err, stream=None):
+        """insert_classify through kc_insert_classify_noalloc: the call's
+        scratch is the library's fixed per-device array, nothing is
+        allocated (every output buffer and counter must be given)."""
+        for t, nm in ((distinct, "distinct"), (trust, "trust"), (err, "err"),
+                      (n_distinct, "n_distinct"), (n_windows, "n_windows"),
+                      (n_trust, "n_trust"), (n_err, "n_err")):
+            _require(t, torch.int64, nm)
+        _require(reads, torch.uint8, "reads")
+        _require(offsets, torch.int64, "offsets")
+        w = key_words(k)
+        with torch.cuda.device(self.device):
+            _check(self.lib.kc_insert_classify_noalloc(
+                self._h, _ptr(reads), _ptr(offsets), offsets.numel() - 1, reads.numel(), k,
+                int(tau), _ptr(distinct), distinct.numel() // w, _ptr(n_distinct),
+                _ptr(n_windows), _ptr(trust), _ptr(n_trust), _ptr(err), _ptr(n_err),
+                min(trust.numel(), err.numel()) // w, _stream_ptr(stream)),
+                "kc_insert_classify_noalloc")
+        self.k = k
 
     def classify(self, keys, n_keys, tau: int, trust=None, err=None, n_trust=None, n_err=None,
                  keys_cap=None, stream=None):
