@@ -1,26 +1,32 @@
 """KmerCo on one MI355X: k-mer insertions/s of the full hot path.
 
-One step = one KmerCo pass over the workload with its reads already resident
-in HBM: clear the countBF, then kc_insert_classify: the insertion phase
-(ingest, binned counting + first-seen in LDS, ordered distinct output) and the
-classification phase (Query-II of each distinct k-mer against the final
-countBF, ordered trustworthy / erroneous split).
-The metric counts one insertion per valid k-mer window, as the paper's
-insertions-per-second figure does (number of insertions / insertion time).
+Headline (the default workload, "large"): 32 M reads of 250 bases (8 Gbases)
+into an 8 GB countBF (31627 x 31657 cells), k = 31, tau = 5.  One step is
+one KmerCo pass over that input with its reads already resident in HBM:
+clear the countBF, then kc_insert_classify (the insertion phase: ingest,
+binned counting and first-seen resolution in LDS, ordered distinct output;
+the classification phase: Query-II of each distinct k-mer against the final
+countBF, ordered trustworthy / erroneous split).  The metric counts one
+insertion per valid k-mer window, as the paper's insertions-per-second
+figure does (number of insertions / insertion time).
+
+The same line carries, on the same input and the same countBF words, the
+batched form (kc_batch_insert with the whole input as one set: tuned, then
+replayed from a HIP graph), and as extra keys the bacterial workload (plain),
+the 256-set workload (256 plain calls vs one batched call) and the serving
+form.  Every leg is checked against the oracle's digests.
 
 Kernel times: a few untimed steps with every kernel bracketed by HIP events
 give the per-phase breakdown ("phases"); during the timed steps the library
 records events around the dominant kernel only, whose average launch gives
-the roofline.
-
-The same line carries the batched form measured against the plain kernel on
-the 256-set workload (each set with its own countBF): one step inserts and
-classifies every set, either as 256 plain calls in sequence or as one batched
-call captured in a HIP graph; both are checked against the oracle's digests.
+the roofline.  "step_roofline" prices the whole step: the survey's per-
+insertion byte model against 8 TB/s, and this design's own bound (each
+phase's algorithmic bytes at the copy bandwidth measured in the same run,
+plus the hashing kernel's integer operations at the VALU peak).
 
 Prints one JSON line.  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bacterial]
-                    [--forms batched|none]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
+                    [--forms batched,bacterial,sets,serving|none]
 """
 from __future__ import annotations
 
@@ -59,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bacterial", choices=["tiny", "bacterial", "large"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "bacterial", "large"])
     ap.add_argument("--alpha", type=int, default=8, help="counter length (bits)")
     ap.add_argument("--size", type=float, default=1.0,
                     help="countBF sized for this multiple of the workload's sizing count")
@@ -67,12 +73,15 @@ def parse():
     ap.add_argument("--k", type=int, default=0,
                     help="k-mer length (0: the workload's own; 33..64 for two-word keys)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
+    ap.add_argument("--cpu-sample-reads", type=int, default=0,
+                    help="reads of the oracle's sample (0: about 20 s of oracle work)")
     ap.add_argument("--cpu-sample-sets", type=int, default=64,
                     help="sets of the 256-set workload in the parallel oracle baseline")
     ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--forms", default="batched,serving",
-                    help="comma list of extra forms to measure: batched, serving, or none")
+    ap.add_argument("--forms", default="batched,bacterial,sets,serving",
+                    help="comma list of extra legs: batched (same input, batched form), "
+                         "bacterial (plain, bacterial workload), sets (the 256-set workload, "
+                         "plain vs batched), serving; or none")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--serving-lanes", type=int, default=2)
     ap.add_argument("--form-steps", type=int, default=5)
@@ -100,13 +109,14 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_bases * 5 * k_h + entries * 8
     if phase == "part_count":        # entries of the partition lists in
         return entries * 8
-    # bytes per entry: the single-level path packs them in 6, the partitioned
-    # path and the batched form keep 8
-    ent = entry_bytes or (8 if partitioned else 6)
-    if phase == "bin_bucket":        # slot ids (or list entries) in, entries out
+    # bytes per entry: the single-level path's lists are 6-byte entries; the
+    # partitioned path's partition and bucket lists are 8-byte entries and its
+    # region lists 6-byte ones; the batched form's fused kernels keep 8
+    ent = entry_bytes or 6
+    if phase == "bin_bucket":        # slot ids (or partition-list entries) in, entries out
         return entries * 16 if partitioned else n_bases * 4 * k_h + entries * ent
-    if phase == "bin_region":        # entries in and out
-        return entries * 2 * ent
+    if phase == "bin_region":        # bucket-list entries in, region-list entries out
+        return entries * (8 + ent) if partitioned else entries * 2 * ent
     if phase == "region":            # entries in, countBF cells read + written per chunk, flags
         return entries * ent + n_chunks * n_words * 16 + n_distinct
     if phase == "tile_count":        # flag byte per position (+ packed input when the
@@ -119,6 +129,8 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_windows * k_h * 16 + n_bases * 0.5
     if phase == "resolve":           # entry read per slot, winner reset, flags
         return n_windows * k_h * 4 + n_distinct * 4 + n_bases * (0.5 + 0.125)
+    if phase == "reset":             # the countBF's cells written (cleared)
+        return n_words * 8
     if phase == "ingest":            # ASCII in, packed codes + bitmaps out, flag bytes cleared
         return n_bases * 2.5
     if phase == "valid_windows":     # invalid-base and read-start bits in, valid-window bits out
@@ -421,6 +433,7 @@ def _batched_leg(args, dev, sets, stream, t_gen):
         "phases": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()},
         "roofline": roofline_of(phases, steps, total, n_windows, n_distinct, 1, n_words,
                                 "batched", entry_bytes=8),
+        "tuned": {"work_item_positions": batch.tile},
         "input_generation_s": round(t_gen, 1),
     }
     for f in filters:
@@ -520,15 +533,329 @@ def serving_leg(args, dev):
         "staging_bytes": st["staging_bytes"], "batches": st["batches"],
         "batched_requests": st["batched_requests"], "plain_requests": st["plain_requests"],
         "max_batch": st["max_batch"], "lanes": args.serving_lanes,
+        "lanes_in_flight_max": st["lanes_in_flight_max"],
         "saturated": {"value": windows / sat_span, "unit": "insertions/s",
                       "makespan_s": sat_span, "latency": serve.latency_summary(res_sat),
                       "batches": sat_st["batches"], "max_batch": sat_st["max_batch"],
+                      "lanes_in_flight_max": sat_st["lanes_in_flight_max"],
                       "same_counts_as_paced_run": bool(sat_ok)},
         "countbf_bytes": [X * Y * 8 for X, Y in dims],
         "input_generation_s": round(t_gen, 1),
     }
     sat.close_server()
     return out
+
+
+# per-workload oracle sample (reads) of about 10-30 s of single-core work
+CPU_SAMPLE_READS = {"tiny": 10_000, "bacterial": 300_000, "large": 200_000}
+
+
+def copy_bandwidth(dev, nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Bytes moved per second (read + write) by a device-to-device copy of
+    nbytes: the streaming rate this part reaches, measured in this run."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return 2 * nbytes / best
+
+
+def random_read_rate(words, n: int = 1 << 26, reps: int = 3) -> float:
+    """8-byte reads per second at uniformly random positions of `words` (a
+    gather over the countBF's own footprint, measured in this run)."""
+    import torch
+    g = torch.Generator(device=words.device)
+    g.manual_seed(7)
+    idx = torch.randint(0, words.numel(), (n,), device=words.device, generator=g)
+    out = torch.empty(n, dtype=words.dtype, device=words.device)
+    torch.index_select(words, 0, idx, out=out)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.index_select(words, 0, idx, out=out)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del idx, out
+    return n / best
+
+
+def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
+                  partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate):
+    """The whole step against two bounds.
+    survey_model: the per-insertion byte model of a countBF insert (k_h
+    random 64-bit read-modify-writes of 16 B, one 8 B pre-chunk counter read
+    for first-seen, 16 B per new k-mer for its claim and its key, the input
+    bytes per insertion and 1/8 B of flags) at the nominal 8 TB/s.
+    design_bound: this design's own floor, each phase's algorithmic bytes at
+    the copy bandwidth measured in this run, the hashing kernel's integer
+    operations at the VALU peak, and the classification's random countBF
+    reads at the random-read rate measured over the countBF in this run."""
+    secs = ms_per_step / 1e3
+    f_new = n_distinct / max(1, n_windows)
+    b_ins = 16 * k_h + 8 + 16 * f_new + n_bases / max(1, n_windows) + 0.125
+    achieved = n_windows * b_ins / secs / 1e9
+    kb = 8 if k <= 32 else 16
+    per_phase = {}
+    for ph in phases:
+        if ph == "bin_count":
+            t = n_windows * ops_per_window(k_h, alpha, k) / (ALU_PEAK_GOPS * 1e9)
+        elif ph == "classify_mark":
+            t = n_distinct * k_h / rand_rate + n_distinct * (kb + 0.125) / copy_Bps
+        else:
+            t = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
+                                  partitioned, key_bytes=kb) / copy_Bps
+        per_phase[ph] = round(t * 1e3, 3)
+    bound_ms = sum(per_phase.values())
+    return {
+        "survey_model": {"bytes_per_insertion": round(b_ins, 3),
+                         "achieved_GBps": round(achieved, 1), "peak_GBps": HBM_PEAK_GBS,
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
+        "design_bound": {"bound_ms": round(bound_ms, 3), "measured_ms": round(ms_per_step, 3),
+                         "frac": round(bound_ms / ms_per_step, 4),
+                         "copy_GBps_measured": round(copy_Bps / 1e9, 1),
+                         "random_8B_reads_per_s_measured": round(rand_rate / 1e9, 2) * 1e9,
+                         "valu_peak_Gops": round(ALU_PEAK_GOPS, 1),
+                         "per_phase_bound_ms": per_phase},
+    }
+
+
+def digests_ok(ref, X, Y, k, words, lists, counts, w) -> bool:
+    """The outputs against the oracle's digests of this workload and layout."""
+    nd, nw, nt, ne = counts
+    distinct, trust, err = lists
+    return (ref["X"] == X and ref["Y"] == Y and ref["k"] == k and ref["n_windows"] == nw
+            and ref["n_distinct"] == nd and ref["n_trust"] == nt and ref["n_err"] == ne
+            and sha(words) == ref["words_sha256"]
+            and sha(distinct[:nd * w]) == ref["distinct_sha256"]
+            and sha(trust[:nt * w]) == ref["trust_sha256"]
+            and sha(err[:ne * w]) == ref["err_sha256"])
+
+
+def load_digests(args, workload, k, rs_k):
+    if args.no_verify or (args.alpha, args.k_h, args.size) != (8, 1, 1.0):
+        return None  # the digests' layout only
+    name = workload if k == rs_k else f"{workload}_k{k}"
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_digests.json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, extras=True):
+    """The plain call on one workload: timed steps of kc_reset +
+    kc_insert_classify, the per-phase breakdown, the dominant kernel's
+    roofline, the whole step's roofline and the digest check."""
+    import numpy as np
+    import torch
+
+    import paper_2305_07545_amd as P
+    import synth
+
+    t_gen = time.perf_counter()
+    rs = synth.config(workload)
+    t_gen = time.perf_counter() - t_gen
+    X, Y = P.dims(rs.n_items * args.size)
+    k_h, alpha = args.k_h, args.alpha
+    k = args.k or rs.k
+    w = P.key_words(k)
+    reads = torch.from_numpy(rs.reads).to(dev)
+    offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
+    n_bases = rs.n_bases
+    words = torch.empty(X * Y, dtype=torch.int64, device=dev)
+    bf = P.CountBF(X, Y, alpha, k_h, words=words, device=dev)
+    bf.reserve(n_bases)
+    plan = bf.plan(n_bases)
+    stream = torch.cuda.current_stream()
+    counters = torch.zeros(4, dtype=torch.int64, device=dev)  # distinct, windows, trust, err
+    nd_, nw_, nt_, ne_ = (counters[i:i + 1] for i in range(4))
+
+    # list capacities from a first pass with room for one key: the distinct
+    # count reports what the list needs (the overflow is sticky, read by
+    # sync), and the trustworthy and erroneous lists split it
+    one = [torch.empty(w, dtype=torch.int64, device=dev) for _ in range(3)]
+    bf.insert_classify(reads, offs, k, rs.tau, distinct=one[0], trust=one[1], err=one[2],
+                       n_distinct=nd_, n_windows=nw_, n_trust=nt_, n_err=ne_, stream=stream)
+    try:
+        bf.sync()
+    except P.KmercoError as e:
+        if e.status != P.KC_ERANGE:
+            raise
+    need = int(counters[0].item())
+    room = need + need // 64 + 4096
+    distinct, trust, err = (torch.empty(room * w, dtype=torch.int64, device=dev)
+                            for _ in range(3))
+    del one
+
+    def step():
+        bf.reset(stream)
+        counters.zero_()
+        bf.insert_classify(reads, offs, k, rs.tau, distinct=distinct, trust=trust, err=err,
+                           n_distinct=nd_, n_windows=nw_, n_trust=nt_, n_err=ne_, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    bf.sync()
+    torch.cuda.synchronize()
+    # per-phase breakdown: every kernel bracketed by events, untimed steps
+    bf.profile(True)
+    for _ in range(profile_steps):
+        step()
+    phases = bf.profile_read()
+    bf.profile(False)
+    dom = max(phases, key=lambda p: phases[p][0])
+    # timed steps: events around the dominant kernel only (its roofline)
+    bf.profile(True, phases=[dom])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timed = bf.profile_read()
+    bf.profile(False)
+    bf.sync()
+    counts = [int(x) for x in counters.cpu().tolist()]
+    n_distinct, n_windows, n_trust, n_err = counts
+    ref = load_digests(args, workload, k, rs.k)
+    verified = None if ref is None else digests_ok(
+        ref, X, Y, k, words, (distinct, trust, err), counts, w)
+    ms_step = elapsed * 1e3 / steps
+    partitioned = plan["path"] == "partitioned"
+    n_chunks = plan["n_chunks"]
+    per_phase = {p: {"avg_ms": v[0] / v[1], "launches": v[1]} for p, v in phases.items()}
+    per_phase[dom]["timed_avg_ms"] = timed[dom][0] / timed[dom][1]
+    roofline = roofline_of(timed, steps, n_bases, n_windows, n_distinct, k_h, X * Y, workload,
+                           n_chunks, partitioned, alpha, k)
+    copy_Bps = copy_bandwidth(dev)
+    rand = random_read_rate(words)
+    out = {
+        "value": n_windows * steps / elapsed, "unit": "insertions/s", "ms_per_step": ms_step,
+        "steps": steps, "warmup": warmup,
+        "config": {"workload": workload, "n_reads": rs.n_reads, "n_bases": n_bases, "k": k,
+                   "tau": rs.tau, "X": X, "Y": Y, "alpha": alpha, "k_h": k_h,
+                   "countbf_bytes": X * Y * 8, "n_windows": n_windows,
+                   "n_distinct": n_distinct, "n_trust": n_trust, "n_err": n_err,
+                   "plan": plan, "parallelism": "single GPU"},
+        "verified_vs_oracle_digests": verified,
+        "phases": per_phase,
+        "phases_profiled_steps": profile_steps,
+        "roofline": roofline,
+        "step_roofline": step_roofline(phases_per_step(phases, profile_steps), 1, n_bases,
+                                       n_windows, n_distinct, k_h, X * Y, n_chunks, partitioned,
+                                       alpha, k, ms_step, copy_Bps, rand),
+        "hbm_rooflines": hbm_rooflines(phases, profile_steps, n_bases, n_windows, n_distinct,
+                                       k_h, X * Y, workload, n_chunks, partitioned, k),
+        "input_generation_s": round(t_gen, 1),
+    }
+    if extras:
+        # classification on its own (kc_classify, Query-II over the step's
+        # distinct list): within the timed steps it is fused into the region
+        # pass when the insert is one chunk
+        cls_ms = []
+        n_keys = torch.tensor([n_distinct], dtype=torch.int64, device=dev)
+        cls_out = [torch.empty(max(1, n_distinct) * w, dtype=torch.int64, device=dev)
+                   for _ in range(2)]
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            bf.classify(distinct, n_keys, rs.tau, trust=cls_out[0], err=cls_out[1],
+                        keys_cap=n_distinct, stream=stream)
+            torch.cuda.synchronize()
+            cls_ms.append((time.perf_counter() - t) * 1e3)
+        bf.sync()
+        med = sorted(cls_ms[1:])[1]
+        out["classify_separately"] = {"ms": med, "keys": n_distinct,
+                                      "keys_per_s": n_distinct / (med / 1e3)}
+        del cls_out
+        h2d = h2d_reads(rs, dev)
+        h2d["insertions_per_s_incl_h2d"] = n_windows / ((h2d["ms"] + ms_step) / 1e3)
+        out["h2d_reads"] = h2d
+    bf.close()
+    ctx = {"rs": rs}
+    if keep:
+        ctx.update({"reads": reads, "offs": offs, "words": words, "X": X, "Y": Y, "k": k,
+                    "w": w, "lists": (distinct, trust, err), "counters": counters, "ref": ref,
+                    "plain_ms": ms_step})
+    else:
+        del reads, offs, words, distinct, trust, err
+    torch.cuda.empty_cache()
+    return out, ctx
+
+
+def phases_per_step(phases, steps):
+    """{phase: (ms, launches)} totals over `steps` steps -> per step."""
+    return {p: (v[0] / steps, v[1] / steps) for p, v in phases.items()}
+
+
+def batched_same_input(args, dev, ctx, steps, warmup):
+    """The batched form on the headline's input and countBF words: one
+    kc_batch_insert call with the whole input as one set, tuned once, then
+    captured into a HIP graph and replayed; outputs against the digests."""
+    import torch
+
+    import paper_2305_07545_amd as P
+    rs, X, Y, k, w = ctx["rs"], ctx["X"], ctx["Y"], ctx["k"], ctx["w"]
+    distinct, trust, err = ctx["lists"]
+    counters = ctx["counters"]
+    n_bases = rs.n_bases
+    f = P.CountBF(X, Y, args.alpha, args.k_h, words=ctx["words"], device=dev)
+    entry = {"filter": f, "first_base": 0, "n_bases": n_bases, "k": k, "tau": rs.tau,
+             "distinct": distinct, "n_distinct": counters[0:1], "n_windows": counters[1:2],
+             "trust": trust, "n_trust": counters[2:3], "err": err, "n_err": counters[3:4]}
+    batch = P.Batch()
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        batch.insert([entry], ctx["reads"], ctx["offs"], reset=True, tune=True, stream=stream)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t
+        for _ in range(max(1, warmup)):  # the first call captures the graph
+            batch.insert([entry], ctx["reads"], ctx["offs"], reset=True, graph=True,
+                         stream=stream)
+        batch.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.insert([entry], ctx["reads"], ctx["offs"], reset=True, graph=True,
+                         stream=stream)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        batch.sync()
+        f.sync()
+        counts = [int(x) for x in counters.cpu().tolist()]
+        verified = None if ctx["ref"] is None else digests_ok(
+            ctx["ref"], X, Y, k, ctx["words"], ctx["lists"], counts, w)
+        # per-phase times from eager launches (events are not recorded
+        # inside graph replays)
+        batch.profile(True)
+        for _ in range(2):
+            batch.insert([entry], ctx["reads"], ctx["offs"], reset=True, stream=stream)
+        phases = batch.profile_read()
+        batch.profile(False)
+        batch.sync()
+    ms = elapsed * 1e3 / steps
+    res = {
+        "workload": "the headline's input as one set of kc_batch_insert, same countBF words",
+        "value": counts[1] * steps / elapsed, "unit": "insertions/s", "ms_per_step": ms,
+        "steps": steps, "graph": True, "speedup_vs_plain": ctx["plain_ms"] / ms,
+        "tuned": {"plan": f.plan(n_bases), "work_item_positions": batch.tile,
+                  "tune_s": round(tune_s, 2)},
+        "verified_vs_oracle_digests": verified,
+        "phases": {p: {"avg_ms": v[0] / v[1], "launches": v[1]} for p, v in phases.items()},
+    }
+    f.close()
+    batch.close()
+    return res
 
 
 def main():
@@ -539,150 +866,55 @@ def main():
                           "--gpus must be 1 (no multi-GPU path is built)"}), flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2305_07545_amd as P
-    import synth
 
     P.load_library()  # fails loudly when the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
 
-    rs = synth.config(args.workload)
-    X, Y = P.dims(rs.n_items * args.size)
-    k_h, alpha = args.k_h, args.alpha
-    k = args.k or rs.k
-    w = P.key_words(k)  # words per key
-    reads = torch.from_numpy(rs.reads).to(dev)
-    offs = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
-    n_bases = rs.n_bases
-    cap = min(n_bases, 1 << 31)  # keys of room per output list (a shortfall raises)
-    distinct = torch.empty(cap * w, dtype=torch.int64, device=dev)
-    trust = torch.empty(cap * w, dtype=torch.int64, device=dev)
-    err = torch.empty(cap * w, dtype=torch.int64, device=dev)
-    counters = torch.zeros(4, dtype=torch.int64, device=dev)  # distinct, windows, trust, err
-    nd, nw, nt, ne = (counters[i:i + 1] for i in range(4))
-    bf = P.CountBF(X, Y, alpha, k_h, device=dev)
-    bf.reserve(n_bases)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        bf.reset(stream)
-        counters.zero_()
-        bf.insert_classify(reads, offs, k, rs.tau, distinct=distinct, trust=trust, err=err,
-                           n_distinct=nd, n_windows=nw, n_trust=nt, n_err=ne, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    bf.sync()
-    torch.cuda.synchronize()
-
-    # per-phase breakdown: every kernel bracketed by events, untimed steps
-    bf.profile(True)
-    for _ in range(args.profile_steps):
-        step()
-    phases = bf.profile_read()
-    bf.profile(False)
-    dom = max(phases, key=lambda k: phases[k][0])
-
-    # timed steps: events around the dominant kernel only (its roofline)
-    bf.profile(True, phases=[dom])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timed = bf.profile_read()
-    bf.profile(False)
-    bf.sync()
-
-    n_distinct, n_windows, n_trust, n_err = (int(x) for x in counters.cpu().tolist())
-    verified = None
-    if not args.no_verify and (alpha, k_h, args.size) == (8, 1, 1.0):  # the digests' layout
-        name = args.workload if k == rs.k else f"{args.workload}_k{k}"
-        ref_path = os.path.join(ROOT, "tests", "golden", f"{name}_digests.json")
-        if os.path.exists(ref_path):
-            ref = json.load(open(ref_path))
-            verified = (ref["X"] == X and ref["Y"] == Y and ref["k"] == k
-                        and ref["n_windows"] == n_windows
-                        and ref["n_distinct"] == n_distinct and ref["n_trust"] == n_trust
-                        and sha(bf.words) == ref["words_sha256"]
-                        and sha(distinct[:n_distinct * w]) == ref["distinct_sha256"]
-                        and sha(trust[:n_trust * w]) == ref["trust_sha256"]
-                        and sha(err[:n_err * w]) == ref["err_sha256"])
-
-    ms_step = elapsed * 1e3 / args.steps
-    value = n_windows * args.steps / elapsed
-    per_phase = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items()}
-    per_phase[dom]["timed_avg_ms"] = timed[dom][0] / timed[dom][1]
-    # the binned path's chunking (the partitioned path beyond 16384 regions)
-    eta = 64 // alpha
-    region_cells = 1 << ((16384 // eta).bit_length() - 1)  # power of two, eta counters each
-    partitioned = X * Y > 16384 * region_cells
-    chunk = min(1 << 31, ((1 << 32) - 1) // k_h // 1024 * 1024) if partitioned else (1 << 28)
-    n_chunks = (n_bases + chunk - 1) // chunk
-    roofline = roofline_of(timed, args.steps, n_bases, n_windows, n_distinct, k_h, X * Y,
-                           args.workload, n_chunks, partitioned, alpha, k)
-
-    # classification on its own (kc_classify, Query-II over the step's
-    # distinct list): in the timed steps it is fused into the region pass
-    cls_ms = []
-    n_keys = torch.tensor([n_distinct], dtype=torch.int64, device=dev)
-    cls_out = [torch.empty(n_distinct * w, dtype=torch.int64, device=dev) for _ in range(2)]
-    for _ in range(4):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        bf.classify(distinct, n_keys, rs.tau, trust=cls_out[0], err=cls_out[1],
-                    keys_cap=n_distinct, stream=stream)
-        torch.cuda.synchronize()
-        cls_ms.append((time.perf_counter() - t) * 1e3)
-    bf.sync()
-    cls = {"ms": sorted(cls_ms[1:])[1], "keys": n_distinct,
-           "keys_per_s": n_distinct / (sorted(cls_ms[1:])[1] / 1e3)}
-    del cls_out
-    h2d = h2d_reads(rs, dev)
-    h2d["insertions_per_s_incl_h2d"] = n_windows / ((h2d["ms"] + ms_step) / 1e3)
+    head, ctx = plain_leg(args, dev, args.workload, args.steps, args.warmup,
+                          args.profile_steps, keep="batched" in forms)
     out = {
         "metric": "k-mer insertions/s",
-        "value": value,
+        "value": head["value"],
         "unit": "insertions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_reads": rs.n_reads, "n_bases": n_bases,
-                   "k": k, "tau": rs.tau, "X": X, "Y": Y, "alpha": alpha, "k_h": k_h,
-                   "countbf_bytes": X * Y * 8, "n_windows": n_windows,
-                   "n_distinct": n_distinct, "n_trust": n_trust, "n_err": n_err,
-                   "parallelism": "single GPU"},
-        "verified_vs_oracle_digests": verified,
-        "phases": per_phase,
-        "roofline": roofline,
-        "phases_profiled_steps": args.profile_steps,
-        "h2d_reads": h2d,
-        "classify_separately": cls,
-        "hbm_rooflines": hbm_rooflines(phases, args.profile_steps, n_bases, n_windows,
-                                       n_distinct, k_h, X * Y, args.workload, n_chunks,
-                                       partitioned, k),
     }
-    bf.close()
-    del reads, offs, distinct, trust, err
-    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    out.update({k: v for k, v in head.items() if k not in out})
+    rs_head = ctx.pop("rs")
     if "batched" in forms:
-        out["batched"] = batched_leg(args, dev)
+        out["batched"] = batched_same_input(args, dev, dict(ctx, rs=rs_head),
+                                            max(1, args.form_steps), max(1, args.warmup // 2))
+    del ctx
+    torch.cuda.empty_cache()
+    if "bacterial" in forms and args.workload != "bacterial":
+        leg, _ = plain_leg(args, dev, "bacterial", args.steps, args.warmup, 2, extras=False)
+        out["bacterial"] = {k: leg[k] for k in ("value", "unit", "ms_per_step", "config",
+                                                "verified_vs_oracle_digests", "roofline",
+                                                "step_roofline", "phases")}
+    if "sets" in forms:
+        out["sets"] = batched_leg(args, dev)
         if not args.no_cpu_baseline:
-            out["batched"]["cpu_baseline"] = set_baseline(args.cpu_sample_sets)
+            out["sets"]["cpu_baseline"] = set_baseline(args.cpu_sample_sets)
     if "serving" in forms:
         out["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(rs, X, Y, args.cpu_sample_reads, k)
+        import synth
+        rs = rs_head or synth.config(args.workload)
+        n = args.cpu_sample_reads or CPU_SAMPLE_READS[args.workload]
+        out["cpu_baseline"] = cpu_baseline(rs, out["config"]["X"], out["config"]["Y"], n,
+                                           out["config"]["k"])
     print(json.dumps(out), flush=True)
 
 

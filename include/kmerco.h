@@ -18,8 +18,9 @@
  *    For K <= 32 a key is one uint64.  For K = 33..64 (the paper's 55-mers,
  *    Sec. 4) it is a 128-bit integer stored as two uint64 words, low word
  *    first, in every key array (capacities still count keys); such keys are
- *    taken by the binned insertion paths, kc_classify and kc_query (not the
- *    direct path, the batched form or the server: KC_EINVAL).
+ *    taken by the binned insertion paths (also inside the batched form and
+ *    the server), kc_classify and kc_query, not by the direct path
+ *    (KC_EINVAL).
  *    Reads are ASCII bytes; any byte other than
  *    'A','C','G','T' (upper case) is an invalid base and every window that
  *    contains one is skipped.  Windows never span two reads.
@@ -137,14 +138,15 @@ uint64_t kc_scratch_bytes(const kc_layout *layout, uint64_t max_bases);
 kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void *stream,
                     kc_filter **out);
 
-/* kc_create with the handle's device state in caller memory and/or a k to
- * resume with (the countBF of Sec. 2.1 over caller-owned words, as for
- * kc_create; zero as for kc_create).
+/* kc_create with the handle's device state in caller memory and/or its k
+ * fixed from the start (the countBF of Sec. 2.1 over caller-owned words, as
+ * for kc_create; zero as for kc_create).
  *
  * k            0: no k-mer length yet (set by the first insert).  1..64: the
- *              words already hold k-mers of this length (a resumed countBF,
- *              zero must be 0): inserts must use it (else KC_ESTATE) and
- *              kc_classify / kc_query read keys of its width at once.
+ *              handle's k-mer length (for zero == 0, that of the k-mers the
+ *              words already hold: a resumed countBF): inserts must use it
+ *              (else KC_ESTATE) and kc_classify / kc_query read keys of its
+ *              width from the start.
  * scratch_dev  NULL: the library allocates the handle's scratch (as
  *              kc_create; max_bases > 0 reserves it at once, as kc_reserve).
  *              Otherwise a caller-owned device buffer of scratch_bytes
@@ -158,8 +160,8 @@ kc_status kc_create(const kc_layout *layout, uint64_t *words_dev, int zero, void
  *              max_bases keys returns KC_ERANGE and enqueues nothing.  The
  *              buffer must outlive the handle; kc_destroy does not free it,
  *              and its contents between calls are the library's.
- * Errors: KC_EINVAL (bad layout, k > 64, k with zero != 0, a misaligned
- * scratch_dev), KC_ERANGE (scratch_bytes below the need), KC_ENOMEM. */
+ * Errors: KC_EINVAL (bad layout, k > 64, a misaligned scratch_dev),
+ * KC_ERANGE (scratch_bytes below the need), KC_ENOMEM. */
 kc_status kc_create_in(const kc_layout *layout, uint64_t *words_dev, int zero, uint32_t k,
                        void *scratch_dev, uint64_t scratch_bytes, uint64_t max_bases,
                        void *stream, kc_filter **out);
@@ -276,6 +278,27 @@ kc_status kc_query(kc_filter *f, const uint64_t *keys_dev, uint64_t n, uint32_t 
  * device-side status: KC_OK or KC_ERANGE; KC_EDEVICE if the runtime failed. */
 kc_status kc_sync(kc_filter *f);
 
+/* The insertion plan of a handle for an insert of n_bases bases (host only,
+ * touches no device): the path (the single-level binned path for countBFs
+ * of up to 16384 regions, the partitioned one for larger ones, the direct
+ * path when forced or beyond 256 partitions), cells per region and the
+ * number of regions and partitions of the binned paths, and the positions
+ * per chunk (the countBF's cells are read and written once per chunk) with
+ * the chunks of this insert.  The batched form's tuner may change a
+ * handle's chunk size; this reports the one in use. */
+#define KC_PATH_DIRECT 0u
+#define KC_PATH_BINNED 1u
+#define KC_PATH_PARTITIONED 2u
+typedef struct {
+    uint32_t path;
+    uint32_t region_cells;
+    uint32_t n_regions;
+    uint32_t n_parts;
+    uint64_t chunk;
+    uint64_t n_chunks;
+} kc_plan;
+kc_status kc_get_plan(const kc_filter *f, uint64_t n_bases, kc_plan *out);
+
 /* Layout of a handle (host copy). */
 kc_status kc_get_layout(const kc_filter *f, kc_layout *out);
 
@@ -323,9 +346,9 @@ const char *kc_phase_name(uint32_t phase);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent read sets, each with its own countBF, k and
- * tau, inserted (and classified) together by one launch per phase.  The
- * result for every set is identical to kc_insert_classify (or kc_insert when
- * trust_dev is NULL) on that set's reads alone.
+ * tau, inserted (and classified) together by one call.  The result for every
+ * set is identical to kc_insert_classify (or kc_insert when trust_dev is
+ * NULL) on that set's reads alone.
  *
  * All sets' reads live in one buffer (reads_dev, offsets_dev as for
  * kc_insert, n_bases bytes in total).  Set i owns bases
@@ -333,13 +356,19 @@ const char *kc_phase_name(uint32_t phase);
  * first_base a multiple of 4096, sets sorted by first_base and disjoint
  * (padding between sets must be reads of invalid bases, e.g. 'N', which add
  * no k-mer).  Each set has its own filter handle (at most one set per
- * handle), created on the batch's device; its countBF may span at most 2048
- * regions (a region is the largest power-of-two number of cells whose
- * counters number at most 16384: 2048 cells at alpha = 8, so at most 32 MB
- * of countBF) and hold at most 2^28 bases; larger sets go through kc_insert.  The total number of
- * (base, hash function) pairs must stay below 2^32.  Outputs per set have the
- * meaning of kc_insert_classify; distinct capacity overflows are sticky in
- * the set's filter (kc_sync on it).
+ * handle), created on the batch's device.  The whole buffer is ingested once;
+ * sets whose countBF spans at most 2048 regions (a region is the largest
+ * power-of-two number of cells whose counters number at most 16384: 2048
+ * cells at alpha = 8, so at most 32 MB of countBF), that hold at most 2^28
+ * bases and use k <= 32 then go through one launch per phase for all of
+ * them (the total number of their (base, hash function) pairs must stay
+ * below 2^32); every other set (up to k = 64, any countBF kc_insert takes)
+ * runs the single-set pipeline over its range of the buffer on one of up to
+ * three side streams the call forks from `stream` after the ingest and joins
+ * before it returns, each side lane with scratch of its own (held by the
+ * batch), so that such sets overlap one another and the fused phases.
+ * Outputs per set have the meaning of kc_insert_classify; distinct capacity
+ * overflows are sticky in the set's filter (kc_sync on it).
  * ---------------------------------------------------------------------- */
 typedef struct kc_batch kc_batch;
 
@@ -362,7 +391,11 @@ typedef struct {
 #define KC_BATCH_RESET 1u  /* first clear every set's countBF and zero its distinct/window counters */
 #define KC_BATCH_GRAPH 2u  /* capture the launches into a HIP graph; a later call with the same
                               arguments replays it (stream must not be the null stream) */
-#define KC_BATCH_TUNE 4u   /* time the candidate work-item sizes on this input, keep the fastest */
+#define KC_BATCH_TUNE 4u   /* time the candidate work-item sizes of the fused phases on this
+                              input and keep the fastest; with KC_BATCH_RESET also time each
+                              side-lane set's whole pipeline at several chunk sizes (positions
+                              per pass over its countBF, kc_get_plan) and keep the fastest in
+                              its handle */
 
 kc_status kc_batch_create(kc_batch **out);
 void kc_batch_destroy(kc_batch *b);
@@ -389,21 +422,27 @@ kc_status kc_batch_sync(kc_batch *b);
  * have released enough; admission is in order of kc_server_open.
  *
  * kc_server_pump() runs the loop once without blocking: it retires finished
- * batches, admits waiting sessions, and issues new batches while a staging
- * lane is free.  A batch takes queued requests in arrival order, at most one
- * per session (a session's requests run in submission order), copies their
- * reads to the lane on a copy stream and runs them on a compute stream:
- * the requests whose countBF and size fit the batched form go through one
- * kc_batch_insert call, the others through kc_insert, then the classify
- * requests through kc_classify.  With two or more lanes, requests that
- * arrive while a batch runs are copied in meanwhile and form the next one.
- * A request's outputs do not depend on which other requests share its batch.
+ * batches, admits waiting sessions, and issues new batches while a lane is
+ * free.  A lane is a slot for one batch in flight with its own staging,
+ * copy and compute streams and batched-form scratch; lanes run concurrently
+ * on the device.  A batch takes queued requests in arrival order, at most
+ * one per session, copies their reads to the lane on its copy stream and
+ * runs them on its compute stream: every insert of the batch goes through
+ * one kc_batch_insert call (large countBFs and requests on its side lanes),
+ * then the classify requests through kc_classify.  A session's requests run
+ * in submission order: a lane that takes a request of a session whose
+ * previous request is still in flight on another lane waits for it on the
+ * device.  Requests that arrive while batches run are copied in and issued
+ * as soon as a lane is free, and overlap the batches already running.  A
+ * request's outputs do not depend on which other requests share its batch
+ * or run beside it.
  *
  * Memory: the server allocates, and frees on close/destroy, each session's
- * countBF (8*X*Y bytes), distinct list (8*distinct_cap bytes) and the
- * per-counter first-seen entries of countBFs too large for the binned path
- * (4 bytes per counter); these count against memory_budget.  Staging lanes and the shared
- * scratch of the insert calls are the server's own and do not.
+ * countBF (8*X*Y bytes), distinct list (8*distinct_cap bytes, twice that for
+ * k > 32), its classification scratch (about 0.17 bytes per key of room) and
+ * the per-counter first-seen entries of countBFs too large for the binned
+ * path (4 bytes per counter); these count against memory_budget.  The
+ * lanes' staging and insert scratch are the server's own and do not.
  * Host memory passed in a request (reads, offsets) must stay valid and
  * unchanged until the request is done; pinned memory lets the copies run
  * asynchronously.  Not thread-safe: one host thread drives a server.
@@ -454,18 +493,19 @@ typedef struct {
     uint32_t sessions_waiting;   /* opened, waiting for memory */
     uint64_t requests_done;
     uint64_t batches;            /* lanes issued */
-    uint64_t batched_requests;   /* requests inserted through kc_batch_insert */
-    uint64_t plain_requests;     /* requests inserted through kc_insert */
+    uint64_t batched_requests;   /* requests inserted through kc_batch_insert (all inserts) */
+    uint64_t plain_requests;     /* requests inserted through kc_insert (none since every
+                                    insert goes through the batched call) */
     uint32_t max_batch;          /* most requests in one issued lane */
-    uint32_t reserved;
+    uint32_t lanes_in_flight_max;  /* most lanes with work on the device at once */
 } kc_server_stats;
 
 /* Create a server on the current device.  KC_EINVAL for a bad config. */
 kc_status kc_server_create(const kc_server_config *cfg, kc_server **out);
 /* Wait for all work, free every session and the staging. */
 void kc_server_destroy(kc_server *s);
-/* Open a session for a countBF of this layout and k-mer length k, with room
- * for distinct_cap distinct k-mers; *session receives its id at once, and
+/* Open a session for a countBF of this layout and k-mer length k (1..64),
+ * with room for distinct_cap distinct k-mers; *session receives its id at once, and
  * the session is admitted when its bytes fit the budget.  KC_ENOMEM if they
  * exceed the whole budget, KC_EINVAL for a bad layout or k. */
 kc_status kc_server_open(kc_server *s, const kc_layout *layout, uint32_t k,
@@ -489,7 +529,8 @@ kc_status kc_server_result(const kc_server *s, uint64_t ticket, kc_result *out);
  * while the request is not done, KC_EINVAL for an unknown ticket. */
 kc_status kc_server_release(kc_server *s, uint64_t ticket);
 /* Copy n keys of a session's distinct list, from index first, to host
- * memory (waits for the session's issued work).  KC_ERANGE past the end. */
+ * memory (waits for the server's issued work); keys of k > 32 take two words
+ * each (2n words).  KC_ERANGE past the end. */
 kc_status kc_server_read_distinct(kc_server *s, uint32_t session, uint64_t first, uint64_t n,
                                   uint64_t *dst_host);
 /* Copy a session's countBF cells (8*X*Y bytes) to host memory (waits). */

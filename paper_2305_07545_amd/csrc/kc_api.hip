@@ -656,7 +656,7 @@ kc_status kc_create_in(const kc_layout *layout, uint64_t *words_dev, int zero, u
     if (!out)
         return KC_EINVAL;
     *out = nullptr;
-    if (!words_dev || !valid_layout(layout) || k > 64 || (k != 0 && zero))
+    if (!words_dev || !valid_layout(layout) || k > 64)
         return KC_EINVAL;
     if (scratch_dev && (uintptr_t)scratch_dev % kAllocAlign != 0)
         return KC_EINVAL;
@@ -735,6 +735,26 @@ kc_status kc_reserve(kc_filter *f, uint64_t max_bases) {
     if (!g.ok)
         return KC_EDEVICE;
     return reserve_all(f, max_bases);
+}
+
+kc_status kc_get_plan(const kc_filter *f, uint64_t n_bases, kc_plan *out) {
+    if (!f || !out)
+        return KC_EINVAL;
+    *out = kc_plan{};
+    kc::BinPlan plan{};
+    uint64_t chunk = 0;
+    if (n_bases > 0 && choose_plan(f, n_bases, plan, chunk)) {
+        out->path = plan.n_parts ? KC_PATH_PARTITIONED : KC_PATH_BINNED;
+        out->region_cells = 1u << plan.region_shift;
+        out->n_regions = plan.n_regions;
+        out->n_parts = plan.n_parts;
+        out->chunk = chunk;
+    } else {
+        out->path = n_bases > 0 ? KC_PATH_DIRECT : KC_PATH_BINNED;
+        out->chunk = n_bases > 0 ? f->chunk : 0;
+    }
+    out->n_chunks = out->chunk ? (n_bases + out->chunk - 1) / out->chunk : 0;
+    return KC_OK;
 }
 
 kc_status kc_get_layout(const kc_filter *f, kc_layout *out) {

@@ -31,6 +31,9 @@ struct kc_batch {
     hipStream_t side[kSideLanes] = {};
     hipEvent_t forked = nullptr, joined[kSideLanes] = {};
     kc::Workspace side_ws[kSideLanes];
+    uint8_t *stage = nullptr;        // pinned staging of the plan's tables
+    uint64_t stage_cap = 0;
+    hipEvent_t staged = nullptr;     // the last upload from it
     std::vector<uint32_t> big;       // the call's sets of the single-set pipeline
     std::vector<int> big_lane;       // their lanes
     uint32_t lanes_used = 0;
@@ -214,21 +217,46 @@ kc_status ensure_batch(kc_batch *b, const kc::BatchPlan &P, hipStream_t s) {
     return KC_OK;
 }
 
+// The plan's tables to the device through pinned staging: the copies are
+// asynchronous, and only a later upload waits for them (before it rewrites
+// the staging), so that the host never waits for the stream here.
 kc_status upload(kc_batch *b, const kc::BatchPlan &P, hipStream_t s) {
     kc::BatchBuffers &B = b->B;
-    hipError_t e = hipMemcpyAsync(B.sets, b->h_sets.data(), P.n_sets * sizeof(kc::SetDesc),
-                                  hipMemcpyHostToDevice, s);
+    const uint64_t b_sets = P.n_sets * sizeof(kc::SetDesc);
+    const uint64_t b_items = P.n_items * sizeof(uint32_t);
+    const uint64_t b_regions = P.n_regions * sizeof(uint32_t);
+    const uint64_t b_tiles = b->h_tiles.size() * sizeof(uint32_t);
+    const uint64_t need = b_sets + b_items + b_regions + b_tiles;
+    if (b->staged && hipEventSynchronize(b->staged) != hipSuccess)
+        return KC_EDEVICE;
+    if (need > b->stage_cap) {
+        if (b->stage)
+            (void)hipHostFree(b->stage);
+        b->stage = nullptr;
+        b->stage_cap = 0;
+        const uint64_t cap = need + need / 4 + 4096;
+        if (hipHostMalloc((void **)&b->stage, cap, hipHostMallocDefault) != hipSuccess)
+            return KC_ENOMEM;
+        b->stage_cap = cap;
+    }
+    if (!b->staged && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess)
+        return KC_EDEVICE;
+    uint8_t *h = b->stage;
+    std::memcpy(h, b->h_sets.data(), b_sets);
+    std::memcpy(h + b_sets, b->h_items.data(), b_items);
+    std::memcpy(h + b_sets + b_items, b->h_regions.data(), b_regions);
+    std::memcpy(h + b_sets + b_items + b_regions, b->h_tiles.data(), b_tiles);
+    hipError_t e = hipMemcpyAsync(B.sets, h, b_sets, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && P.n_items)
-        e = hipMemcpyAsync(B.item_set, b->h_items.data(), P.n_items * sizeof(uint32_t),
-                           hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(B.item_set, h + b_sets, b_items, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && P.n_regions)
-        e = hipMemcpyAsync(B.region_set, b->h_regions.data(), P.n_regions * sizeof(uint32_t),
+        e = hipMemcpyAsync(B.region_set, h + b_sets + b_items, b_regions, hipMemcpyHostToDevice,
+                           s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B.tile_set, h + b_sets + b_items + b_regions, b_tiles,
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(B.tile_set, b->h_tiles.data(), b->h_tiles.size() * sizeof(uint32_t),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)  // the host vectors may change on the next call
-        e = hipStreamSynchronize(s);
+        e = hipEventRecord(b->staged, s);
     return e == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
@@ -595,6 +623,10 @@ void kc_batch_destroy(kc_batch *b) {
     }
     if (b->forked)
         (void)hipEventDestroy(b->forked);
+    if (b->staged)
+        (void)hipEventDestroy(b->staged);
+    if (b->stage)
+        (void)hipHostFree(b->stage);
     delete b;
 }
 

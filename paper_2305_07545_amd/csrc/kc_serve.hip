@@ -1,15 +1,20 @@
 // Serving form: a request loop over device-resident countBFs (the request
 // and session model is documented with the kc_server entry points).
 //
-// Each lane owns device staging for one batch: the reads of its requests at
-// 4096-aligned bases with 'N' gaps, their raw CSR offsets one request after
-// another, the combined offsets of the whole buffer, a small table and the
-// per-request result words (mirrored to pinned host memory).  Issuing a lane
-// enqueues its host-to-device copies on the copy stream and everything else
-// on the compute stream behind an event, so the copies of one lane overlap
-// the kernels of the previous one.  All insert and classify calls of all
-// sessions run on the compute stream, which orders a session's requests and
-// lets every session share one scratch workspace.
+// A lane is a slot for one batch of requests in flight.  Each lane owns
+// device staging for its batch (the reads of its requests at 4096-aligned
+// bases with 'N' gaps, their raw CSR offsets one request after another, the
+// combined offsets of the whole buffer, a small table and the per-request
+// result words, mirrored to pinned host memory), a copy stream, a compute
+// stream and a kc_batch of its own (its scratch).  Issuing a lane enqueues
+// its host-to-device copies on its copy stream and everything else on its
+// compute stream behind an event: every request's insert goes through one
+// kc_batch_insert call (whose large sets run on side lanes of their own),
+// then the classifications.  Lanes run concurrently, so requests admitted
+// while other batches are on the device overlap them.  A session's requests
+// stay in submission order: a lane that takes a request of a session whose
+// previous request is still in flight on another lane first waits for that
+// session's event, recorded after each of its requests.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -31,7 +36,6 @@ using kcapi::dev_free;
 constexpr uint32_t kRes = 8;  // result words per request
 enum : uint32_t { kResWindows = 0, kResBefore = 1, kResAfter = 2, kResTrust = 3, kResErr = 4 };
 constexpr uint64_t kAlign = 4096;   // set alignment of the batched form
-constexpr uint64_t kBatchBases = 1ull << 28;  // largest set of the batched form
 constexpr uint32_t kMaxLanes = 8;
 constexpr uint32_t kMaxLaneRequests = 4096;
 
@@ -81,7 +85,7 @@ struct Session {
     uint64_t *distinct = nullptr;
     uint64_t *counter = nullptr;  // running distinct count (device)
     kc_filter *f = nullptr;
-    bool batchable = false;
+    hipEvent_t done = nullptr;   // recorded after each of its requests
     std::deque<uint64_t> queue;  // submitted, not issued (tickets)
     uint32_t inflight = 0;
 };
@@ -96,7 +100,9 @@ struct Lane {
     uint8_t *reads = nullptr;
     uint64_t *raw = nullptr, *comb = nullptr, *tab = nullptr, *res = nullptr;
     uint64_t *tab_host = nullptr, *res_host = nullptr;  // pinned
+    hipStream_t copy = nullptr, compute = nullptr;
     hipEvent_t copied = nullptr, done = nullptr;
+    kc_batch *batch = nullptr;
     bool busy = false;
     std::vector<uint64_t> tickets;
     std::vector<uint8_t> classify;  // per ticket
@@ -107,9 +113,7 @@ struct Lane {
 struct kc_server {
     int device = 0;
     kc_server_config cfg{};
-    hipStream_t copy = nullptr, compute = nullptr;
-    kc_batch *batch = nullptr;
-    kc::Workspace ws{};
+    hipStream_t admin = nullptr;  // session set-up (clears, classify scratch)
     std::vector<Session> sessions;
     std::deque<uint32_t> waiting;  // sessions to admit, in open order
     std::deque<uint64_t> order;    // submitted, not issued, in arrival order
@@ -128,14 +132,25 @@ double now_s(const kc_server *s) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
-uint64_t session_bytes(const kc_layout &L, uint64_t cap) {
-    return L.X * L.Y * 8 + cap * 8 + 8 + kcapi::filter_private_bytes(L);
+uint64_t key_words(uint32_t k) { return k > 32 ? 2 : 1; }
+
+// A session's device bytes: countBF, distinct list, its count, the direct
+// path's per-counter entries when the countBF takes that path, and the
+// classification scratch for its whole list.
+uint64_t session_bytes(const kc_layout &L, uint32_t k, uint64_t cap) {
+    const uint64_t tiles = kc::tiles(cap) + 1;
+    return L.X * L.Y * 8 + cap * 8 * key_words(k) + 8 + kcapi::filter_private_bytes(L) +
+           tiles * (3 * 4 + 3 * 8 + kc::kTile / 8) + 64;
 }
 
 void release(kc_server *s, Session &S) {
     if (S.f) {
         kc_destroy(S.f);
         S.f = nullptr;
+    }
+    if (S.done) {
+        (void)hipEventDestroy(S.done);
+        S.done = nullptr;
     }
     dev_free(S.words);
     dev_free(S.distinct);
@@ -145,17 +160,28 @@ void release(kc_server *s, Session &S) {
     S.state = SState::Closed;
 }
 
+// Allocate and clear a session on the admin stream; its event marks the
+// clears, so that the first lane to take one of its requests waits for them.
 kc_status admit_one(kc_server *s, Session &S) {
-    if (!dev_alloc(&S.words, S.layout.X * S.layout.Y) || !dev_alloc(&S.distinct, S.cap) ||
-        !dev_alloc(&S.counter, 1))
+    if (!dev_alloc(&S.words, S.layout.X * S.layout.Y) ||
+        !dev_alloc(&S.distinct, S.cap * key_words(S.k)) || !dev_alloc(&S.counter, 1))
         return KC_ENOMEM;
-    if (kc::fill_u64(S.counter, 1, 0, s->compute) != hipSuccess)
+    if (kc::fill_u64(S.counter, 1, 0, s->admin) != hipSuccess)
         return KC_EDEVICE;
-    kc_status st = kc_create(&S.layout, S.words, 1, s->compute, &S.f);
+    // the handle knows its k from the start (classify requests before any
+    // insert read keys of that width)
+    kc_status st = kc_create_in(&S.layout, S.words, 1, S.k, nullptr, 0, 0, s->admin, &S.f);
     if (st != KC_OK)
         return st;
-    kcapi::share_workspace(S.f, &s->ws);
-    S.batchable = kcapi::batchable(S.f);
+    // classification scratch for the session's whole list, so that a lane
+    // never allocates (or waits) when it classifies
+    kcapi::DeviceGuard g(s->device);
+    if ((st = kcapi::ensure_scalars(*S.f->W)) != KC_OK ||
+        (st = kcapi::ensure_tiles(*S.f->W, s->admin, S.cap)) != KC_OK)
+        return st;
+    if (hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(S.done, s->admin) != hipSuccess)
+        return KC_EDEVICE;
     return KC_OK;
 }
 
@@ -196,6 +222,10 @@ void admit(kc_server *s) {
                 S.f = nullptr;
             }
             S.state = SState::Failed;
+            if (S.done) {
+                (void)hipEventDestroy(S.done);
+                S.done = nullptr;
+            }
             fail_queue(s, S, st);
             continue;
         }
@@ -252,29 +282,16 @@ uint32_t retire(kc_server *s) {
     return n;
 }
 
-// Enqueue one lane: copies on the copy stream, calls on the compute stream.
+// Enqueue one lane: copies on its copy stream, calls on its compute stream.
 kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
-    // requests that go through the batched form first, so that the batched
-    // call covers a prefix of the lane's buffer
-    std::vector<uint64_t> b, p;
-    for (uint64_t tk : picked) {
-        const Req &R = s->reqs[tk];
-        const Session &S = s->sessions[R.q.session];
-        const bool ins = (R.q.op & KC_OP_INSERT) && R.n_bases > 0;
-        (ins && S.batchable && R.n_bases <= kBatchBases ? b : p).push_back(tk);
-    }
-    const bool use_batch = b.size() >= 2;
-    if (!use_batch) {
-        p.insert(p.begin(), b.begin(), b.end());
-        b.clear();
-    }
-    std::vector<uint64_t> all(b);
-    all.insert(all.end(), p.begin(), p.end());
+    const std::vector<uint64_t> &all = picked;
     const uint32_t n = (uint32_t)all.size();
     L.classify.assign(n, 0);
-    // layout of the lane buffers
+    // layout of the lane buffers: each inserting request's reads at a
+    // 4096-aligned base, its raw offsets after the previous request's
     std::vector<uint64_t> base(n), rawpos(n);
-    uint64_t pos = 0, raw = 0, batch_end = 0, batch_raw = 0;
+    uint64_t pos = 0, raw = 0;
+    uint32_t n_ins = 0;
     for (uint32_t i = 0; i < n; i++) {
         const Req &R = s->reqs[all[i]];
         base[i] = align_up(pos);
@@ -282,10 +299,7 @@ kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
         const bool ins = R.q.op & KC_OP_INSERT;
         pos = base[i] + (ins ? R.n_bases : 0);
         raw += ins ? R.q.n_reads + 1 : 0;
-        if (i < b.size()) {
-            batch_end = pos;
-            batch_raw = raw;
-        }
+        n_ins += ins;
     }
     // the lane buffers: lane_bases + lane_requests * kAlign bases, lane_reads
     // + lane_requests raw offsets (+1 combined)
@@ -298,7 +312,7 @@ kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
         L.busy = true;
         for (uint64_t tk : all)
             s->sessions[s->reqs[tk].q.session].inflight++;
-        (void)hipEventRecord(L.done, s->compute);
+        (void)hipEventRecord(L.done, L.compute);
         return KC_EINVAL;
     }
     uint64_t *tab = L.tab_host;  // (raw_start, base) per request, then counter pointers
@@ -314,42 +328,48 @@ kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
         if (!(R.q.op & KC_OP_INSERT))
             continue;
         if (base[i] > end)
-            e = hipMemsetAsync(L.reads + end, 'N', base[i] - end, s->copy);
+            e = hipMemsetAsync(L.reads + end, 'N', base[i] - end, L.copy);
         if (e == hipSuccess && R.n_bases)
             e = hipMemcpyAsync(L.reads + base[i], R.q.reads_host, R.n_bases,
-                               hipMemcpyHostToDevice, s->copy);
+                               hipMemcpyHostToDevice, L.copy);
         if (e == hipSuccess)
             e = hipMemcpyAsync(L.raw + rawpos[i], R.q.offsets_host,
                                (R.q.n_reads + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
-                               s->copy);
+                               L.copy);
         end = base[i] + R.n_bases;
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(L.tab, tab, 3 * (uint64_t)n * sizeof(uint64_t), hipMemcpyHostToDevice,
-                           s->copy);
+                           L.copy);
     if (e == hipSuccess)
-        e = hipEventRecord(L.copied, s->copy);
+        e = hipEventRecord(L.copied, L.copy);
     if (e == hipSuccess)
-        e = hipStreamWaitEvent(s->compute, L.copied, 0);
+        e = hipStreamWaitEvent(L.compute, L.copied, 0);
+    // each session's previous request (on any lane) and its admission
+    for (uint32_t i = 0; i < n && e == hipSuccess; i++)
+        e = hipStreamWaitEvent(L.compute, s->sessions[s->reqs[all[i]].q.session].done, 0);
     const uint64_t *const *ctrs = (const uint64_t *const *)(L.tab + 2 * n);
     const uint32_t tb = 256, grid_n = (n + tb - 1) / tb;
     if (e == hipSuccess)
-        e = kc::fill_u64(L.res, (uint64_t)n * kRes, 0, s->compute);
+        e = kc::fill_u64(L.res, (uint64_t)n * kRes, 0, L.compute);
     if (e == hipSuccess) {
-        k_serve_snap<<<grid_n, tb, 0, s->compute>>>(ctrs, n, L.res, kResBefore);
+        k_serve_snap<<<grid_n, tb, 0, L.compute>>>(ctrs, n, L.res, kResBefore);
         e = hipGetLastError();
     }
     kc_status st = e == hipSuccess ? KC_OK : KC_EDEVICE;
-    if (st == KC_OK && use_batch) {
-        const uint64_t blocks = (batch_raw + tb - 1) / tb;
-        k_serve_rebase<<<(uint32_t)blocks, tb, 0, s->compute>>>(L.raw, batch_raw, L.tab,
-                                                                 (uint32_t)b.size(), L.comb);
+    if (st == KC_OK && n_ins > 0) {
+        // one batched call for every insert of the lane: the combined CSR has
+        // one (gap) read before each request plus its reads
+        const uint64_t blocks = (raw + tb - 1) / tb;
+        k_serve_rebase<<<(uint32_t)blocks, tb, 0, L.compute>>>(L.raw, raw, L.tab, n, L.comb);
         st = hipGetLastError() == hipSuccess ? KC_OK : KC_EDEVICE;
-        std::vector<kc_set> sets(b.size());
-        for (size_t i = 0; i < b.size(); i++) {
-            const Req &R = s->reqs[b[i]];
+        std::vector<kc_set> sets;
+        for (uint32_t i = 0; i < n; i++) {
+            const Req &R = s->reqs[all[i]];
+            if (!(R.q.op & KC_OP_INSERT))
+                continue;
             const Session &S = s->sessions[R.q.session];
-            kc_set &q = sets[i];
+            kc_set q;
             std::memset(&q, 0, sizeof q);
             q.filter = S.f;
             q.first_base = base[i];
@@ -358,23 +378,13 @@ kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
             q.distinct_dev = S.distinct;
             q.distinct_cap = S.cap;
             q.n_distinct_dev = S.counter;
-            q.n_windows_dev = L.res + i * kRes + kResWindows;
+            q.n_windows_dev = L.res + (uint64_t)i * kRes + kResWindows;
+            sets.push_back(q);
         }
-        // combined CSR: one (gap) read before each request plus its reads
         if (st == KC_OK)
-            st = kc_batch_insert(s->batch, sets.data(), (uint32_t)sets.size(), L.reads, L.comb,
-                                 batch_raw, batch_end, 0, s->compute);
-        s->st.batched_requests += b.size();
-    }
-    for (uint32_t i = (uint32_t)b.size(); i < n && st == KC_OK; i++) {
-        const Req &R = s->reqs[all[i]];
-        const Session &S = s->sessions[R.q.session];
-        if (!(R.q.op & KC_OP_INSERT) || R.q.n_reads == 0)
-            continue;
-        st = kc_insert(S.f, L.reads + base[i], L.raw + rawpos[i], R.q.n_reads, R.n_bases, S.k,
-                       S.distinct, S.cap, S.counter, L.res + (uint64_t)i * kRes + kResWindows,
-                       s->compute);
-        s->st.plain_requests++;
+            st = kc_batch_insert(L.batch, sets.data(), (uint32_t)sets.size(), L.reads, L.comb,
+                                 raw, pos, 0, L.compute);
+        s->st.batched_requests += sets.size();
     }
     for (uint32_t i = 0; i < n && st == KC_OK; i++) {
         const Req &R = s->reqs[all[i]];
@@ -385,16 +395,18 @@ kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
         const uint64_t cap = S.cap < R.q.class_cap ? S.cap : R.q.class_cap;
         st = kc_classify(S.f, S.distinct, S.counter, cap, R.q.tau, R.q.trust_dev,
                          L.res + (uint64_t)i * kRes + kResTrust, R.q.err_dev,
-                         L.res + (uint64_t)i * kRes + kResErr, s->compute);
+                         L.res + (uint64_t)i * kRes + kResErr, L.compute);
     }
     if (st == KC_OK) {
-        k_serve_snap<<<grid_n, tb, 0, s->compute>>>(ctrs, n, L.res, kResAfter);
+        k_serve_snap<<<grid_n, tb, 0, L.compute>>>(ctrs, n, L.res, kResAfter);
         e = hipGetLastError();
+        for (uint32_t i = 0; i < n && e == hipSuccess; i++)
+            e = hipEventRecord(s->sessions[s->reqs[all[i]].q.session].done, L.compute);
         if (e == hipSuccess)
             e = hipMemcpyAsync(L.res_host, L.res, (uint64_t)n * kRes * sizeof(uint64_t),
-                               hipMemcpyDeviceToHost, s->compute);
+                               hipMemcpyDeviceToHost, L.compute);
         if (e == hipSuccess)
-            e = hipEventRecord(L.done, s->compute);
+            e = hipEventRecord(L.done, L.compute);
         if (e != hipSuccess)
             st = KC_EDEVICE;
     }
@@ -411,10 +423,12 @@ kc_status issue_lane(kc_server *s, Lane &L, std::vector<uint64_t> &picked) {
         s->st.max_batch = n;
     if (st != KC_OK) {
         // the lane's work may be partly enqueued: wait for it, then report
-        (void)hipStreamSynchronize(s->compute);
-        for (uint32_t i = 0; i < n; i++)
+        (void)hipStreamSynchronize(L.compute);
+        for (uint32_t i = 0; i < n; i++) {
             s->reqs[all[i]].res.status = st;
-        (void)hipEventRecord(L.done, s->compute);
+            (void)hipEventRecord(s->sessions[s->reqs[all[i]].q.session].done, L.compute);
+        }
+        (void)hipEventRecord(L.done, L.compute);
     }
     return st;
 }
@@ -462,7 +476,24 @@ void issue(kc_server *s) {
                 }
         }
         (void)issue_lane(s, L, picked);
+        uint32_t busy = 0;
+        for (const Lane &M : s->lanes)
+            busy += M.busy;
+        if (busy > s->st.lanes_in_flight_max)
+            s->st.lanes_in_flight_max = busy;
     }
+}
+
+// Wait for everything the server has enqueued.
+bool sync_all(kc_server *s) {
+    bool ok = !s->admin || hipStreamSynchronize(s->admin) == hipSuccess;
+    for (Lane &L : s->lanes) {
+        if (L.copy)
+            ok &= hipStreamSynchronize(L.copy) == hipSuccess;
+        if (L.compute)
+            ok &= hipStreamSynchronize(L.compute) == hipSuccess;
+    }
+    return ok;
 }
 
 void free_lane(Lane &L) {
@@ -479,6 +510,12 @@ void free_lane(Lane &L) {
         (void)hipEventDestroy(L.copied);
     if (L.done)
         (void)hipEventDestroy(L.done);
+    if (L.batch)
+        kc_batch_destroy(L.batch);
+    if (L.copy)
+        (void)hipStreamDestroy(L.copy);
+    if (L.compute)
+        (void)hipStreamDestroy(L.compute);
     L = Lane{};
 }
 
@@ -499,12 +536,10 @@ kc_status kc_server_create(const kc_server_config *cfg, kc_server **out) {
     s->cfg = *cfg;
     s->t0 = std::chrono::steady_clock::now();
     kc_status st = KC_OK;
+    // every stream at the default priority
     if (hipGetDevice(&s->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess)
+        hipStreamCreateWithFlags(&s->admin, hipStreamNonBlocking) != hipSuccess)
         st = KC_EDEVICE;
-    if (st == KC_OK)
-        st = kc_batch_create(&s->batch);
     const uint64_t nb = cfg->lane_bases + (uint64_t)cfg->lane_requests * kAlign;
     const uint64_t nr = cfg->lane_reads + cfg->lane_requests;
     s->lanes.resize(cfg->lanes);
@@ -521,8 +556,12 @@ kc_status kc_server_create(const kc_server_config *cfg, kc_server **out) {
                           hipHostMallocDefault) != hipSuccess)
             st = KC_ENOMEM;
         else if (hipEventCreateWithFlags(&L.copied, hipEventDisableTiming) != hipSuccess ||
-                 hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
+                 hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
+                 hipStreamCreateWithFlags(&L.copy, hipStreamNonBlocking) != hipSuccess ||
+                 hipStreamCreateWithFlags(&L.compute, hipStreamNonBlocking) != hipSuccess)
             st = KC_EDEVICE;
+        else
+            st = kc_batch_create(&L.batch);
         s->staging += nb + (2 * nr + 1 + 3ull * cfg->lane_requests +
                             (uint64_t)kRes * cfg->lane_requests) * sizeof(uint64_t);
     }
@@ -538,34 +577,26 @@ void kc_server_destroy(kc_server *s) {
     if (!s)
         return;
     kcapi::DeviceGuard g(s->device);
-    if (s->compute)
-        (void)hipStreamSynchronize(s->compute);
-    if (s->copy)
-        (void)hipStreamSynchronize(s->copy);
+    sync_all(s);
     for (Session &S : s->sessions)
         if (S.state == SState::Open)
             release(s, S);
     for (Lane &L : s->lanes)
         free_lane(L);
-    if (s->batch)
-        kc_batch_destroy(s->batch);
-    kcapi::free_workspace(s->ws);
-    if (s->copy)
-        (void)hipStreamDestroy(s->copy);
-    if (s->compute)
-        (void)hipStreamDestroy(s->compute);
+    if (s->admin)
+        (void)hipStreamDestroy(s->admin);
     delete s;
 }
 
 kc_status kc_server_open(kc_server *s, const kc_layout *layout, uint32_t k,
                          uint64_t distinct_cap, uint32_t *session) {
-    if (!s || !session || !layout || !kcapi::valid_layout(layout) || k < 1 || k > 32)
+    if (!s || !session || !layout || !kcapi::valid_layout(layout) || k < 1 || k > 64)
         return KC_EINVAL;
     Session S;
     S.layout = *layout;
     S.k = k;
     S.cap = distinct_cap;
-    S.bytes = session_bytes(*layout, distinct_cap);
+    S.bytes = session_bytes(*layout, k, distinct_cap);
     if (S.bytes > s->cfg.memory_budget)
         return KC_ENOMEM;
     *session = (uint32_t)s->sessions.size();
@@ -690,7 +721,7 @@ kc_status kc_server_read_distinct(kc_server *s, uint32_t session, uint64_t first
     if (S.state != SState::Open)
         return KC_ESTATE;
     kcapi::DeviceGuard g(s->device);
-    if (hipStreamSynchronize(s->compute) != hipSuccess)
+    if (!sync_all(s))
         return KC_EDEVICE;
     uint64_t nd = 0;
     if (hipMemcpy(&nd, S.counter, sizeof nd, hipMemcpyDeviceToHost) != hipSuccess)
@@ -698,7 +729,8 @@ kc_status kc_server_read_distinct(kc_server *s, uint32_t session, uint64_t first
     const uint64_t have = nd < S.cap ? nd : S.cap;
     if (first > have || n > have - first)
         return KC_ERANGE;
-    if (n && hipMemcpy(dst_host, S.distinct + first, n * sizeof(uint64_t),
+    const uint64_t w = key_words(S.k);
+    if (n && hipMemcpy(dst_host, S.distinct + first * w, n * w * sizeof(uint64_t),
                        hipMemcpyDeviceToHost) != hipSuccess)
         return KC_EDEVICE;
     return KC_OK;
@@ -711,7 +743,7 @@ kc_status kc_server_read_words(kc_server *s, uint32_t session, uint64_t *dst_hos
     if (S.state != SState::Open)
         return KC_ESTATE;
     kcapi::DeviceGuard g(s->device);
-    if (hipStreamSynchronize(s->compute) != hipSuccess)
+    if (!sync_all(s))
         return KC_EDEVICE;
     if (hipMemcpy(dst_host, S.words, S.layout.X * S.layout.Y * sizeof(uint64_t),
                   hipMemcpyDeviceToHost) != hipSuccess)

@@ -47,6 +47,15 @@ KC_BATCH_RESET, KC_BATCH_GRAPH, KC_BATCH_TUNE = 1, 2, 4
 SET_ALIGN = 4096
 
 
+class kc_plan(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_uint32), ("region_cells", ctypes.c_uint32),
+                ("n_regions", ctypes.c_uint32), ("n_parts", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint64), ("n_chunks", ctypes.c_uint64)]
+
+
+PATH_NAMES = {0: "direct", 1: "binned", 2: "partitioned"}
+
+
 class kc_server_config(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_uint64), ("lane_bases", ctypes.c_uint64),
                 ("lane_reads", ctypes.c_uint64), ("lane_requests", ctypes.c_uint32),
@@ -74,7 +83,7 @@ class kc_server_stats(ctypes.Structure):
                 ("sessions_open", ctypes.c_uint32), ("sessions_waiting", ctypes.c_uint32),
                 ("requests_done", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("batched_requests", ctypes.c_uint64), ("plain_requests", ctypes.c_uint64),
-                ("max_batch", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("max_batch", ctypes.c_uint32), ("lanes_in_flight_max", ctypes.c_uint32)]
 
 
 KC_OP_INSERT, KC_OP_CLASSIFY = 1, 2
@@ -109,6 +118,7 @@ SIGNATURES = {
     "kc_query": (_i, [_vp, _vp, _u64, _vp, _vp]),
     "kc_sync": (_i, [_vp]),
     "kc_get_layout": (_i, [_vp, ctypes.POINTER(kc_layout)]),
+    "kc_get_plan": (_i, [_vp, _u64, ctypes.POINTER(kc_plan)]),
     "kc_reset": (_i, [_vp, _vp]),
     "kc_profile": (_i, [_vp, _i]),
     "kc_profile_phases": (_i, [_vp, _u32]),
@@ -429,6 +439,15 @@ class CountBF:
             _check(self.lib.kc_query(self._h, _ptr(keys), n, _ptr(freq), _stream_ptr(stream)),
                    "kc_query")
         return freq[:n]
+
+    def plan(self, n_bases: int) -> dict:
+        """kc_get_plan: path, region size, regions, partitions and chunking
+        of an insert of n_bases bases."""
+        p = kc_plan()
+        _check(self.lib.kc_get_plan(self._h, int(n_bases), ctypes.byref(p)), "kc_get_plan")
+        d = {f: getattr(p, f) for f, _ in kc_plan._fields_}
+        d["path"] = PATH_NAMES.get(d["path"], str(d["path"]))
+        return d
 
     def reset(self, stream=None):
         """Clear the countBF (async): empty filter, k unset."""

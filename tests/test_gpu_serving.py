@@ -96,6 +96,7 @@ def test_alone_equals_mix_equals_oracle(workload):
     st = mix.stats()
     assert st["requests_done"] == len(w.requests)
     assert st["batched_requests"] > 0 and st["max_batch"] >= 2, st
+    assert st["plain_requests"] == 0 and st["lanes_in_flight_max"] == 2, st
     words_mix = [mix.read_words(s, X * Y) for s, (X, Y) in zip(cm.sessions, cm.dims)]
 
     print("case serving alone: one request per batch, in order", flush=True)
@@ -106,7 +107,8 @@ def test_alone_equals_mix_equals_oracle(workload):
         tk = ca.submit(i)
         alone.wait(tk)
         out_alone.append(ca.outputs(i, alone.result(tk)))
-    assert alone.stats()["batched_requests"] == 0
+    st_alone = alone.stats()
+    assert st_alone["max_batch"] == 1 and st_alone["lanes_in_flight_max"] == 1, st_alone
     for i, (a, m) in enumerate(zip(out_alone, out_mix)):
         assert a["nw"] == m["nw"] and a["first"] == m["first"], f"request {i}"
         assert np.array_equal(a["new"], m["new"]), f"request {i}: new distinct"
