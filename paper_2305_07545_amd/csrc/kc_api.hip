@@ -326,20 +326,28 @@ uint32_t part_log_from_env() {
     return v > kc::kPartLog ? kc::kPartLog : (uint32_t)v;
 }
 
+// Counters per region of the binned paths: KMERCO_REGION_COUNTERS (8192 or
+// 16384) when set, else 16384.
+uint32_t region_counters_from_env() {
+    const uint64_t v = env_u64("KMERCO_REGION_COUNTERS", kc::kRegionCounters);
+    return v == (uint64_t)kc::kSmallRegionCounters ? kc::kSmallRegionCounters
+                                                   : kc::kRegionCounters;
+}
+
 // The binned plan and chunk size for an insert of n_bases positions; false
 // when the direct path is taken.
 bool choose_plan(const kc_filter *f, uint64_t n_bases, kc::BinPlan &plan, uint64_t &chunk) {
     if (f->path == KcPath::Direct)
         return false;
     chunk = n_bases < f->bin_chunk ? n_bases : f->bin_chunk;
-    if (!kc::bin_plan(f->F, chunk, plan, f->part_log))
+    if (!kc::bin_plan(f->F, chunk, plan, f->part_log, f->region_counters))
         return false;
     if (plan.n_parts) {
         // entries of a chunk (positions x hash functions) index 32-bit offsets
         const uint64_t most = ((1ull << 32) - 1) / f->layout.k_h / kc::kTile * kc::kTile;
         const uint64_t pc = f->part_chunk < most ? f->part_chunk : most;
         chunk = n_bases < pc ? n_bases : pc;
-        return kc::bin_plan(f->F, chunk, plan, f->part_log);
+        return kc::bin_plan(f->F, chunk, plan, f->part_log, f->region_counters);
     }
     return true;
 }
@@ -395,7 +403,8 @@ uint64_t filter_private_bytes(const kc_layout &layout) {
     F.Y = layout.Y;
     F.eta = 64u / layout.alpha;
     kc::BinPlan plan{};
-    if (path_from_env() != KcPath::Direct && kc::bin_plan(F, 1u << 16, plan, part_log_from_env()))
+    if (path_from_env() != KcPath::Direct &&
+        kc::bin_plan(F, 1u << 16, plan, part_log_from_env(), region_counters_from_env()))
         return 0;
     return layout.X * layout.Y * F.eta * sizeof(uint32_t);
 }
@@ -410,6 +419,7 @@ void init_filter(kc_filter *f, const kc_layout *layout) {
     f->bin_chunk = chunk_size(kc::kBinChunk);
     f->part_chunk = chunk_size(kc::kPartChunk);
     f->part_log = part_log_from_env();
+    f->region_counters = region_counters_from_env();
     f->path = path_from_env();
     kc::FilterArgs &F = f->F;
     F.words = nullptr;
@@ -446,33 +456,33 @@ kc_status insert_core(kc_filter *f, const kc::Workspace &W, uint64_t n_bases, ui
         return KC_EDEVICE;
     kc::ReadsArgs R{W.codes, W.inv, W.rs, n_bases, k, W.valid};
     const uint64_t chunk = binned ? bchunk : f->chunk;
-    // this call's classification can be taken from the region pass when the
-    // final counter of each distinct k-mer's single slot is known there
-    const bool fused = split && binned && f->F.k_h == 1 && n_bases <= chunk;
+    // The split is taken from marks on the distinct flags: the region pass
+    // of the last chunk marks the k-mers first seen in it (one hash function:
+    // their one counter's final value is known there); the flags of earlier
+    // chunks (and every flag with several hash functions or on the direct
+    // path) are marked afterwards against the final countBF.
+    const bool region_marks = split && binned && f->F.k_h == 1;
+    uint64_t last_c0 = 0;
     for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk) {
         uint64_t c1 = c0 + chunk < n_bases ? c0 + chunk : n_bases;
+        last_c0 = c0;
         if (binned)
-            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, W, fused, tau, s, P);
+            e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, W, region_marks && c1 == n_bases,
+                                        tau, s, P);
         else
             e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, W, s, P);
         if (e != hipSuccess)
             return KC_EDEVICE;
         f->zero = false;
     }
-    e = kc::launch_distinct(R, W, distinct, cap_d, n_distinct, n_windows,
-                            fused ? trust : nullptr, n_trust, err, n_err, cap_te, f->status,
-                            binned, s, P);
-    if (e != hipSuccess)
-        return KC_EDEVICE;
-    if (split && !fused) {
-        // classify the keys this call appended: distinct[base .. *n_distinct),
-        // base saved by the distinct output step
-        e = kc::launch_classify(f->F, distinct, n_distinct, W.totals + 3, n_bases, cap_d, tau,
-                                trust, n_trust, err, n_err, cap_te, f->status, W, s, P, k > 32);
-        if (e != hipSuccess)
+    if (split) {
+        const uint64_t unmarked = region_marks ? last_c0 : n_bases;
+        if (kc::launch_classify_flags(f->F, R, W, unmarked, tau, s, P) != hipSuccess)
             return KC_EDEVICE;
     }
-    return KC_OK;
+    e = kc::launch_distinct(R, W, distinct, cap_d, n_distinct, n_windows, trust, n_trust, err,
+                            n_err, cap_te, f->status, binned, s, P);
+    return e == hipSuccess ? KC_OK : KC_EDEVICE;
 }
 
 // Both phases for one call.  trust == nullptr: insertion only.

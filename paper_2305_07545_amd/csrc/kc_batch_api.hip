@@ -372,15 +372,26 @@ kc_status launch_all(kc_batch *b, const kc::BatchPlan &P, const kc_set *sets, ui
     return st;
 }
 
-// Positions per chunk of the single-set pipeline tried by the tuner for a
-// filter whose inserts take the partitioned path (more chunks: less
-// scratch, more passes over the countBF) or the single-level binned path.
-constexpr uint64_t kPartChunkCandidates[] = {1ull << 30, 1ull << 31, kc::kPartChunk};
-constexpr uint64_t kBinChunkCandidates[] = {1ull << 26, 1ull << 27, kc::kBinChunk};
+// The single-set pipeline's knobs tried by the tuner: counters per region
+// (the region pass's LDS tile: 16384, one workgroup per CU, or 8192, two per
+// CU) and positions per chunk (a pass over the countBF per chunk; larger
+// chunks take more scratch) for a filter whose inserts take the partitioned
+// path, or the single-level binned path.
+struct SideKnobs {
+    uint32_t counters;
+    uint64_t chunk;
+};
+constexpr SideKnobs kPartCandidates[] = {{kc::kRegionCounters, kc::kPartChunk},
+                                         {kc::kSmallRegionCounters, kc::kPartChunk},
+                                         {kc::kRegionCounters, 1ull << 31},
+                                         {kc::kSmallRegionCounters, 1ull << 31}};
+constexpr SideKnobs kBinCandidates[] = {{kc::kRegionCounters, kc::kBinChunk},
+                                        {kc::kSmallRegionCounters, kc::kBinChunk},
+                                        {kc::kRegionCounters, 1ull << 27}};
 
-// Tune the chunk size of each side-lane set on this input, timing its whole
-// pipeline once per candidate (reset first, so only with KC_BATCH_RESET: the
-// real run resets again); the handle keeps the fastest.
+// Tune each side-lane set's knobs on this input, timing its whole pipeline
+// once per candidate (reset first, so only with KC_BATCH_RESET: the real run
+// resets again); the handle keeps the fastest.
 kc_status tune_side(kc_batch *b, const kc_set *sets, hipStream_t s) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -394,27 +405,30 @@ kc_status tune_side(kc_batch *b, const kc_set *sets, hipStream_t s) {
         if (q.n_bases == 0 || !takes_binned_path(f, q.n_bases))
             continue;
         kc::BinPlan bp{};
-        if (!kc::bin_plan(f->F, q.n_bases < kc::kBinChunk ? q.n_bases : kc::kBinChunk, bp))
+        if (!kc::bin_plan(f->F, q.n_bases < kc::kBinChunk ? q.n_bases : kc::kBinChunk, bp,
+                          f->part_log, f->region_counters))
             continue;
         const bool parts = bp.n_parts > 0;
-        const uint64_t *cand = parts ? kPartChunkCandidates : kBinChunkCandidates;
+        const SideKnobs *cand = parts ? kPartCandidates : kBinCandidates;
+        const int n_cand = parts ? 4 : 3;
         const int l = b->big_lane[j];
         kc::Workspace *own = f->W;
         f->W = &b->side_ws[l];
         f->last = b->side[l];
-        uint64_t &knob = parts ? f->part_chunk : f->bin_chunk;
-        const uint64_t keep = knob;
-        uint64_t best = keep;
+        uint64_t &chunk_knob = parts ? f->part_chunk : f->bin_chunk;
+        const SideKnobs keep{f->region_counters, chunk_knob};
+        SideKnobs best = keep;
         float best_ms = 1e30f;
-        uint64_t tried_last = 0;
-        for (int c = 0; c < 3 && st == KC_OK; c++) {
-            const uint64_t chunk = cand[c];
-            // candidates at or above the insert's size are the same plan
-            const uint64_t eff = chunk < q.n_bases ? chunk : q.n_bases;
-            if (eff == tried_last)
+        for (int c = 0; c < n_cand && st == KC_OK; c++) {
+            f->region_counters = cand[c].counters;
+            chunk_knob = cand[c].chunk;
+            // a candidate whose plan is another path (or none) is skipped, and
+            // chunks at or above the insert's size repeat the whole-insert plan
+            if (cand[c].chunk >= q.n_bases && c > 0 && cand[c - 1].counters == cand[c].counters &&
+                cand[c - 1].chunk >= q.n_bases)
                 continue;
-            tried_last = eff;
-            knob = chunk;
+            if (!takes_binned_path(f, q.n_bases))
+                continue;
             if ((st = prepare_range(f, q.n_bases)) != KC_OK)
                 break;
             float ms = 0.f;
@@ -432,10 +446,12 @@ kc_status tune_side(kc_batch *b, const kc_set *sets, hipStream_t s) {
             }
             if (ms < best_ms) {
                 best_ms = ms;
-                best = chunk;
+                best = cand[c];
             }
         }
-        knob = st == KC_OK ? best : keep;
+        const SideKnobs use = st == KC_OK ? best : keep;
+        f->region_counters = use.counters;
+        chunk_knob = use.chunk;
         if (st == KC_OK)
             st = prepare_range(f, q.n_bases);
         f->W = own;
@@ -527,7 +543,7 @@ std::vector<uint8_t> call_key(const kc_batch *b, const kc_set *sets, uint32_t n_
                                  (uint64_t)(uintptr_t)f->status, (uint64_t)(uintptr_t)f->F.aux,
                                  f->layout.X, f->layout.Y, f->layout.alpha, f->layout.k_h,
                                  f->chunk, f->bin_chunk, f->part_chunk, f->part_log,
-                                 (uint64_t)f->path});
+                                 f->region_counters, (uint64_t)f->path});
     }
     for (uint32_t l = 0; l < b->lanes_used; l++)
         workspace_pointers(b->side_ws[l], filt);

@@ -936,7 +936,11 @@ __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &
         F.words[wbase + w] = next;
 }
 
-// Region lists of 6-byte entries (both binned paths).
+// Region lists of 6-byte entries (both binned paths).  kCounters: the LDS
+// arrays' size, the plan's counters per region (16384: 144 KiB of LDS, one
+// workgroup per CU; 8192: 72 KiB, two per CU, so that one workgroup's loads
+// overlap the other's LDS work).
+template <int kCounters>
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
@@ -945,11 +949,12 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                                                       uint32_t tau) {
     constexpr int kUnroll = 8;
     constexpr int kHold = 4;  // cells per thread held in registers (regions <= 4096 cells)
-    constexpr uint32_t kSparseCells = 2048;  // cells of a region the sparse path stages
+    constexpr uint32_t kSparseCells = kCounters / 8;  // cells of a region the sparse path stages
     constexpr uint32_t kDone = 0xFFFFFFFEu;  // first[] of a counter already updated
     static_assert(kSparseCells <= (uint32_t)kHold * kRegionWG, "sparse cells are held");
-    __shared__ uint32_t hits[kRegionCounters];
-    __shared__ uint32_t first[kRegionCounters];
+    static_assert(kCounters <= kRegionCounters, "local counter ids are 14-bit");
+    __shared__ uint32_t hits[kCounters];
+    __shared__ uint32_t first[kCounters];
     __shared__ unsigned long long s_cell[kSparseCells];
     const uint32_t r = blockIdx.x;
     const uint32_t S = 1u << B.region_shift;
@@ -1094,12 +1099,15 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
-bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_t part_log) {
+bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_t part_log,
+              uint32_t region_counters) {
+    if (region_counters != kRegionCounters && region_counters != kSmallRegionCounters)
+        return false;
     // largest power-of-two cell count whose eta counters fit the LDS arrays
     uint32_t shift = 0;
-    while (((2ull << shift) * F.eta) <= (uint64_t)kRegionCounters)
+    while (((2ull << shift) * F.eta) <= (uint64_t)region_counters)
         shift++;
-    if (((1ull << shift) * F.eta) > (uint64_t)kRegionCounters)
+    if (((1ull << shift) * F.eta) > (uint64_t)region_counters)
         return false;
     if (part_log > kPartLog)
         part_log = kPartLog;
@@ -1107,6 +1115,7 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_
     const uint64_t n_regions = (n_words + (1ull << shift) - 1) >> shift;
     B = BinPlan{};
     B.region_shift = shift;
+    B.region_counters = region_counters;
     B.slice = kSlice;
     if (n_regions > (1ull << part_log)) {
         // partitioned: bin workgroups count partitions, passes over each
@@ -1286,7 +1295,10 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhRegion, s);
-        hipLaunchKernelGGL(k_region, dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
+        hipLaunchKernelGGL((Q.region_counters == kSmallRegionCounters
+                                ? k_region<kSmallRegionCounters>
+                                : k_region<kRegionCounters>),
+                           dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
                            (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
                            (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
         if (P)
@@ -1369,7 +1381,10 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhRegion, s);
-    hipLaunchKernelGGL(k_region, dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
+    hipLaunchKernelGGL((B.region_counters == kSmallRegionCounters
+                            ? k_region<kSmallRegionCounters>
+                            : k_region<kRegionCounters>),
+                       dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
                        (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
                        (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
     if (P)

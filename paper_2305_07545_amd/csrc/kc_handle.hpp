@@ -25,6 +25,7 @@ struct kc_filter {
     uint64_t bin_chunk;    // binned path: positions per chunk
     uint64_t part_chunk;   // partitioned binned path: positions per chunk
     uint32_t part_log;     // partitioned binned path: log2(regions per partition)
+    uint32_t region_counters;  // binned paths: counters per region (the region pass's LDS)
     KcPath path;
     kc::Profiler prof;     // optional per-kernel timing
     bool caller_scratch;   // status word and workspace live in the caller's buffer

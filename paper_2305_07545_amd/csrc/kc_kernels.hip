@@ -382,6 +382,85 @@ __device__ __forceinline__ uint64_t query_key_wide(const FilterArgs &F, Key128 k
     return best;
 }
 
+// Query-II of a canonical key from its H_1 and MM3 blocks (as the hashing
+// passes compute them): H_1 is not recomputed.
+__device__ __forceinline__ uint64_t query_canon(const FilterArgs &F, const Canon &c) {
+    uint64_t best = 0;
+    for (uint32_t a = 1; a <= F.k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        slot_of(F, a == 1 ? c.h1 : hash_a(c.b0, c.b1, a), word, l);
+        const uint64_t v = read_counter(F, word, l);
+        if (v == 0)
+            return 0;
+        best = (a == 1 || v < best) ? v : best;
+    }
+    return best;
+}
+
+__device__ __forceinline__ uint64_t query_canon_wide(const FilterArgs &F, const CanonWide &c) {
+    uint64_t best = 0;
+    for (uint32_t a = 1; a <= F.k_h; a++) {
+        uint64_t word;
+        uint32_t l;
+        slot_of(F, a == 1 ? c.h1 : hash_a_wide(c.b, a), word, l);
+        const uint64_t v = read_counter(F, word, l);
+        if (v == 0)
+            return 0;
+        best = (a == 1 || v < best) ? v : best;
+    }
+    return best;
+}
+
+// Classification in the position domain (Algorithm 2 with Query-II): every
+// position of [0, n_tiles * kTile) flagged distinct (1) whose k-mer's
+// frequency in the countBF as it stands is above tau becomes 3 (distinct
+// and trustworthy), the mark the region pass gives the first-seen k-mers
+// whose final counter it knows; the ordered compaction then splits the
+// distinct list by the marks.  One wavefront per tile of 1024 flag bytes
+// (16 per lane): the flagged positions are listed in LDS, then each lane
+// takes one, rebuilds its canonical k-mer from the packed codes and reads
+// its k_h counters.
+template <bool kWide>
+__global__ void __launch_bounds__(kWG) k_classify_flags(FilterArgs F, ReadsArgs R,
+                                                        uint8_t *__restrict__ flags,
+                                                        uint64_t n_tiles, uint32_t tau) {
+    static_assert(kTile == 64 * 16, "16 flag bytes per lane and tile");
+    __shared__ uint16_t s_pos[kWG / 64][kTile];
+    __shared__ uint16_t s_tb[kWG / 64][kTile];  // list_flags' second list (unused here)
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kWG / 64);
+    const uint4 *f128 = reinterpret_cast<const uint4 *>(flags);
+    uint16_t *lpos = s_pos[wave];
+    uint16_t *ltb = s_tb[wave];
+    for (uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave; tile < n_tiles;
+         tile += n_waves) {
+        const uint4 x4 = f128[tile * 64 + lane];
+        const uint32_t x[4] = {x4.x, x4.y, x4.z, x4.w};
+        uint32_t cd = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            cd += (uint32_t)__popc(x[u] & 0x01010101u);
+        uint32_t tot_d;
+        const uint32_t rd = wave_exclusive(cd, lane, tot_d);
+        if (tot_d == 0)
+            continue;
+        list_flags(x, lane, rd, 0, lpos, ltb);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t pos0 = tile * kTile;
+        for (uint32_t i = lane; i < tot_d; i += 64) {
+            const uint64_t p = pos0 + lpos[i];
+            const uint64_t f =
+                kWide ? query_canon_wide(F, canonical_wide(window_key_wide(R.codes, p, R.k), R.k))
+                      : query_canon(F, canonical_fast(window_key(R.codes, p, R.k), R.k));
+            if (f > (uint64_t)tau)
+                flags[p] = 3;
+        }
+        __builtin_amdgcn_wave_barrier();  // the list is rewritten by the next tile
+    }
+}
+
 // Query-II of key i of a list: one uint64 per key, or (low, high) pairs.
 template <bool kWide>
 __device__ __forceinline__ uint64_t query_list(const FilterArgs &F, const uint64_t *keys,
@@ -709,6 +788,19 @@ hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint
         e = hipGetLastError();
     }
     return e;
+}
+
+hipError_t launch_classify_flags(const FilterArgs &F, const ReadsArgs &R, const Workspace &W,
+                                 uint64_t n_positions, uint32_t tau, hipStream_t s,
+                                 Profiler *P) {
+    const uint64_t n_tiles = tiles(n_positions);
+    if (n_tiles == 0)
+        return hipSuccess;
+    const dim3 grid((unsigned)(n_tiles < (uint64_t)kTileGrid ? n_tiles : kTileGrid));
+    return R.k > 32 ? launch(P, kPhClassifyMark, k_classify_flags<true>, grid, dim3(kWG), s, F, R,
+                             W.flags8, n_tiles, tau)
+                    : launch(P, kPhClassifyMark, k_classify_flags<false>, grid, dim3(kWG), s, F,
+                             R, W.flags8, n_tiles, tau);
 }
 
 hipError_t launch_query(const FilterArgs &F, const uint64_t *keys, uint64_t n, uint32_t *freq,

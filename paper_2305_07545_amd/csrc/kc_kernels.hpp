@@ -24,6 +24,7 @@ constexpr uint64_t kBinTileFloor = 4096;     // ... for chunks of fewer than kBi
 constexpr uint64_t kBinSpread = 2048;        // bin workgroups a small chunk is spread over
 constexpr int kRegionWG = 1024;              // threads per region workgroup
 constexpr int kRegionCounters = 16384;       // counters per region: hits + first = 128 KiB LDS
+constexpr int kSmallRegionCounters = 8192;   // the smaller region choice: 64 KiB
 constexpr uint32_t kMaxRegions = 16384;      // LDS histogram of the bin kernels: 64 KiB
 constexpr uint64_t kMaxMatrix = 1ull << 25;  // (region, bin workgroup) counts per chunk
 constexpr uint64_t kBinChunk = 1ull << 28;   // positions per binned chunk (entries < 2^31)
@@ -61,6 +62,7 @@ struct BinPlan {
     uint32_t part_log;      // partitioned path: log2(regions per partition) <= kPartLog
     uint32_t region0;       // global index of region 0 of the launch (0 but in tests)
     uint32_t list_g;        // partitioned path: list workgroups per partition
+    uint32_t region_counters;  // counters per region (kRegionCounters or kSmallRegionCounters)
 };
 
 // Per-handle workspace (device memory owned by the handle).
@@ -211,7 +213,7 @@ hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
 // has too many regions even for the partitioned path.  part_log sets the
 // partition size (regions) for countBFs of more than 2^part_log regions.
 bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B,
-              uint32_t part_log = kPartLog);
+              uint32_t part_log = kPartLog, uint32_t region_counters = kRegionCounters);
 // plan.n_parts > 0 takes the partitioned path
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
@@ -228,6 +230,11 @@ hipError_t launch_classify(const FilterArgs &F, const uint64_t *keys, const uint
                            uint32_t tau, uint64_t *trust, uint64_t *n_trust, uint64_t *err,
                            uint64_t *n_err, uint64_t cap_out, uint32_t *status,
                            const Workspace &W, hipStream_t s, Profiler *P, bool wide = false);
+// Marks the distinct flags of positions [0, n_positions) (a multiple of
+// kTile, or the call's end) trustworthy where the k-mer's frequency in the
+// countBF is above tau (Query-II), so that launch_distinct splits the list.
+hipError_t launch_classify_flags(const FilterArgs &F, const ReadsArgs &R, const Workspace &W,
+                                 uint64_t n_positions, uint32_t tau, hipStream_t s, Profiler *P);
 // wide: keys of 33..64 bases, (low, high) word pairs
 hipError_t launch_query(const FilterArgs &F, const uint64_t *keys, uint64_t n, uint32_t *freq,
                         hipStream_t s, Profiler *P, bool wide = false);

@@ -456,3 +456,33 @@ def test_bacterial_k55_full_size_digests():
     assert _sha(distinct) == ref["distinct_sha256"]
     assert _sha(trust) == ref["trust_sha256"]
     assert _sha(err) == ref["err_sha256"]
+
+
+# ---------------------------------------------------------------------------
+# regions of 8192 counters (the region pass's smaller LDS tile)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,k_h", [(8, 1), (8, 2), (5, 1), (16, 3), (4, 1), (32, 1)])
+def test_small_regions(monkeypatch, alpha, k_h):
+    """Regions of 8192 counters on both binned paths: sparse and dense
+    regions, heavy collisions, several chunks, fused and unfused split."""
+    monkeypatch.setenv("KMERCO_REGION_COUNTERS", "8192")
+    rnd = synth.random_reads(2700 + alpha + k_h, 400, 50, 300, k=21, tau=3, p_n=0.01)
+    extra = synth.reads_from_strings(["A" * 9000, "ACGT" * 2000], k=21, tau=3)
+    rs = synth.concat_reads([rnd, extra], name="small regions")
+    check(rs, 1009, 1013, alpha=alpha, k_h=k_h, what=f"small regions a={alpha} kh={k_h}")
+    check(rs, 1009, 1013, alpha=alpha, k_h=k_h, what="small regions unfused", fused=False)
+    check(rs, 3, 5, alpha=alpha, k_h=k_h, what="small regions, 3x5 filter")
+    monkeypatch.setenv("KMERCO_PART_LOG", "2")
+    check(rs, 401, 409, alpha=alpha, k_h=k_h, what="small regions, partitions of 4")
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "50000")
+    check(rs, 401, 409, alpha=alpha, k_h=k_h, what="small regions, partitioned chunks")
+
+
+def test_small_regions_bacterial_sample(monkeypatch):
+    monkeypatch.setenv("KMERCO_REGION_COUNTERS", "8192")
+    rs = synth.config("bacterial", scale=0.05)
+    X, Y = oracle.dims(rs.n_items)
+    check(rs, X, Y, what="bacterial x0.05, regions of 8192 counters")
+    monkeypatch.setenv("KMERCO_PART_LOG", "3")
+    check(rs, X, Y, what="bacterial x0.05, regions of 8192 counters, partitions of 8")
