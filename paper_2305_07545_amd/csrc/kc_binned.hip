@@ -24,6 +24,8 @@
 // independent, so the outputs are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "kc_device.hpp"
 #include "kc_kernels.hpp"
 
@@ -482,21 +484,24 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
 // kCompact: 6-byte entries in (single-level path), else 8-byte entries
 // (t << 32 | slot id: the partitioned path's list binning); the region
 // lists are written as 6-byte entries either way.
-constexpr int kStage2 = 2 * kStage;
-template <bool kCompact>
-__global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
+// kThreads: the workgroup (16 entries per thread and batch): 512 threads,
+// batches of 8192 entries, two workgroups per CU; or 1024 threads, batches of
+// 16384 (runs twice as long per region), one per CU.
+template <bool kCompact, int kThreads>
+__global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
                                                        const uint32_t *__restrict__ coarse_off,
                                                        const uint32_t *__restrict__ n_entries,
                                                        const uint32_t *__restrict__ fine_off,
                                                        const uint64_t *__restrict__ bucketed,
                                                        uint64_t *__restrict__ entries) {
-    constexpr int kPer = kStage2 / kBinWG;
+    constexpr int kStage2 = 16 * kThreads;
+    constexpr int kPer = kStage2 / kThreads;
     __shared__ uint64_t s_stage[kStage2];
     __shared__ uint32_t s_cursor[kMaxRegionsPerBucket];
     __shared__ uint32_t s_cnt[kMaxRegionsPerBucket];
     __shared__ uint32_t s_start[kMaxRegionsPerBucket];
     __shared__ uint32_t s_fill[kMaxRegionsPerBucket];
-    __shared__ uint32_t s_wave[kBinWG / 64];
+    __shared__ uint32_t s_wave[kThreads / 64];
     const uint32_t b = blockIdx.x / B.n_slices;
     const uint32_t s = blockIdx.x % B.n_slices;
     const uint32_t gs0 = s * B.slice;
@@ -509,7 +514,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
     // slot ids name the region within its partition (buckets never straddle
     // partitions)
     const uint32_t r0l = B.n_parts ? (r0 & ((1u << B.part_log) - 1u)) : r0;
-    for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kBinWG) {
+    for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kThreads) {
         s_cursor[i] = i < nr ? fine_off[(uint64_t)(r0 + i) * B.G + gs0] : 0u;
         s_cnt[i] = 0;
         s_fill[i] = 0;
@@ -538,7 +543,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
     auto load = [&](uint64_t q0, RawEntry(&v)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
-            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
+            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kThreads;
             v[u] = RawEntry{~0u, ~0u};
             if (x < e1) {
                 if (kCompact) {
@@ -592,7 +597,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
             if (ri[u] != 0xFFFFFFFFu)
                 atomicAdd(&s_cnt[ri[u]], 1u);
         __syncthreads();
-        // exclusive scan of the region counts (kMaxRegionsPerBucket <= kBinWG)
+        // exclusive scan of the region counts (kMaxRegionsPerBucket <= kThreads)
         {
             const uint32_t c = threadIdx.x < kMaxRegionsPerBucket ? s_cnt[threadIdx.x] : 0u;
             uint32_t incl = c;
@@ -620,7 +625,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
         __syncthreads();
         const uint32_t n_stage =
             s_start[kMaxRegionsPerBucket - 1] + s_cnt[kMaxRegionsPerBucket - 1];
-        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kThreads) {
             const uint64_t e = s_stage[j];
             if (kCompact) {
                 const uint32_t r = (uint32_t)e >> kLocalBits;
@@ -642,7 +647,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_region(BinPlan B,
             }
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kBinWG) {
+        for (uint32_t i = threadIdx.x; i < kMaxRegionsPerBucket; i += kThreads) {
             s_cursor[i] += s_cnt[i];
             s_cnt[i] = 0;
             s_fill[i] = 0;
@@ -665,32 +670,38 @@ __global__ void k_part_bounds(const uint32_t *__restrict__ pmat, uint32_t G, uin
 
 // Slot ids of this workgroup's positions -> runs of the partition list
 // (entry = t << 32 | slot id), counting-sorted by partition in LDS batches of
-// kStage entries like the level-1 pass.
-__global__ void __launch_bounds__(kBinWG) k_part_scatter(uint64_t c0, uint64_t c1, uint32_t k_h,
+// kStage entries like the level-1 pass.  The next batch's slot ids and
+// partition bytes are requested before the current one is sorted; a full
+// batch of one hash function is loaded 16 bytes of slot ids and 4 partition
+// bytes per lane (a thread's entries 4v .. 4v + 3 are consecutive positions).
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) k_part_scatter(uint64_t c0, uint64_t c1, uint32_t k_h,
                                                          BinPlan B,
                                                          const uint32_t *__restrict__ slots,
                                                          const uint8_t *__restrict__ parts,
                                                          const uint32_t *__restrict__ pmat_off,
                                                          uint64_t *__restrict__ plist) {
-    constexpr int kPer = kStage / kBinWG;
-    __shared__ uint64_t s_stage[kStage];
-    __shared__ uint8_t s_tag[kStage];  // partition of each staged entry
+    constexpr int kBatch = 8 * kThreads;
+    constexpr int kPer = kBatch / kThreads;
+    static_assert(kPer % 4 == 0, "whole 16-byte loads per thread");
+    __shared__ uint64_t s_stage[kBatch];
+    __shared__ uint8_t s_tag[kBatch];  // partition of each staged entry
     __shared__ uint32_t s_cnt[kMaxParts];
     __shared__ uint32_t s_start[kMaxParts];
     __shared__ uint32_t s_fill[kMaxParts];
     __shared__ uint32_t s_cursor[kMaxParts];
-    __shared__ uint32_t s_wave[kBinWG / 64];
-    static_assert(kMaxParts <= kBinWG, "one thread per partition count");
+    __shared__ uint32_t s_wave[kThreads / 64];
+    static_assert(kMaxParts <= kThreads, "one thread per partition count");
     const uint64_t len = c1 - c0;
     const uint64_t g0 = (uint64_t)blockIdx.x * B.tile;
     const uint64_t g1 = g0 + B.tile < len ? g0 + B.tile : len;
     uint32_t bl = 0;
     while ((1u << bl) < k_h)
         bl++;
-    const uint32_t batch_log = kStageLog - bl;
+    const uint32_t batch_log = (kThreads == 1024 ? 13u : kStageLog) - bl;
     const uint64_t batch = 1ull << batch_log;
     const uint64_t cap = B.entries_cap;
-    for (uint32_t i = threadIdx.x; i < kMaxParts; i += kBinWG) {
+    for (uint32_t i = threadIdx.x; i < kMaxParts; i += kThreads) {
         s_cursor[i] = i < B.n_parts ? pmat_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
         s_cnt[i] = 0;
         s_fill[i] = 0;
@@ -698,19 +709,57 @@ __global__ void __launch_bounds__(kBinWG) k_part_scatter(uint64_t c0, uint64_t c
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    for (uint64_t q0 = g0; q0 < g1; q0 += batch) {
+    // tiles and batches start at multiples of 4 positions, the slot and
+    // partition arrays at 16- and 4-byte boundaries
+    auto full = [&](uint64_t q0) { return k_h == 1u && q0 + batch <= g1; };
+    // the batch offset of a thread's entry u
+    auto pos_of = [&](bool vec, int u) -> uint64_t {
+        return vec ? (uint64_t)(u >> 2) * (4u * kThreads) + 4u * threadIdx.x + (uint32_t)(u & 3)
+                   : (((uint64_t)threadIdx.x + (uint64_t)u * kThreads) & (batch - 1));
+    };
+    auto load = [&](uint64_t q0, uint32_t(&id)[kPer], uint32_t(&pt)[kPer]) {
+        if (full(q0)) {
+            const uint4 *s4 = reinterpret_cast<const uint4 *>(slots + q0);
+            const uint32_t *p4 = reinterpret_cast<const uint32_t *>(parts + q0);
+#pragma unroll
+            for (int v = 0; v < kPer / 4; v++) {
+                const uint32_t at = (uint32_t)v * kThreads + threadIdx.x;
+                const uint4 x = s4[at];
+                const uint32_t pp = p4[at];
+                id[4 * v] = x.x;
+                id[4 * v + 1] = x.y;
+                id[4 * v + 2] = x.z;
+                id[4 * v + 3] = x.w;
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    pt[4 * v + j] = (pp >> (8 * j)) & 0xFFu;
+            }
+            return;
+        }
         const uint64_t nq = (q0 + batch < g1 ? q0 + batch : g1) - q0;
-        uint32_t id[kPer];
-        uint32_t pt[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
-            const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
+            const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kThreads;
             const uint64_t a = i >> batch_log;
             const uint64_t q = q0 + (i & (batch - 1));
             const bool ok = a < k_h && q - q0 < nq;
             id[u] = ok ? slots[a * len + q] : kNoSlot;
             pt[u] = (id[u] != kNoSlot) ? (uint32_t)parts[a * len + q] : 0u;
         }
+    };
+    uint32_t nid[kPer], npt[kPer];
+    if (g0 < g1)
+        load(g0, nid, npt);
+    for (uint64_t q0 = g0; q0 < g1; q0 += batch) {
+        const bool vec = full(q0);
+        uint32_t id[kPer], pt[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            id[u] = nid[u];
+            pt[u] = npt[u];
+        }
+        if (q0 + batch < g1)
+            load(q0 + batch, nid, npt);
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot)
@@ -737,22 +786,21 @@ __global__ void __launch_bounds__(kBinWG) k_part_scatter(uint64_t c0, uint64_t c
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot) {
-                const uint64_t i = (uint64_t)threadIdx.x + (uint64_t)u * kBinWG;
-                const uint64_t q = q0 + (i & (batch - 1));
+                const uint64_t q = q0 + pos_of(vec, u);
                 const uint32_t j = s_start[pt[u]] + atomicAdd(&s_fill[pt[u]], 1u);
                 s_stage[j] = (q << 32) | id[u];
                 s_tag[j] = (uint8_t)pt[u];
             }
         __syncthreads();
         const uint32_t n_stage = s_start[kMaxParts - 1] + s_cnt[kMaxParts - 1];
-        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kThreads) {
             const uint32_t pj = s_tag[j];
             const uint64_t dst = (uint64_t)s_cursor[pj] + (j - s_start[pj]);
             if (dst < cap)
                 plist[dst] = s_stage[j];
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < kMaxParts; i += kBinWG) {
+        for (uint32_t i = threadIdx.x; i < kMaxParts; i += kThreads) {
             s_cursor[i] += s_cnt[i];
             s_cnt[i] = 0;
             s_fill[i] = 0;
@@ -835,13 +883,15 @@ __global__ void __launch_bounds__(kBinWG) k_list_count(const uint64_t *__restric
 
 // Level 1 over every partition's list: the entries of list workgroup g of
 // partition p -> runs of the partition's bucket segments.
-__global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__restrict__ plist,
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__restrict__ plist,
                                                             const uint64_t *__restrict__ pdesc,
                                                             BinPlan B,
                                                             const uint32_t *__restrict__ coarse_off,
                                                             uint64_t *__restrict__ bucketed) {
-    constexpr int kPer = kStage / kBinWG;
-    __shared__ uint64_t s_stage[kStage];
+    constexpr int kBatch = 8 * kThreads;
+    constexpr int kPer = kBatch / kThreads;
+    __shared__ uint64_t s_stage[kBatch];
     __shared__ uint32_t s_cnt[kMaxBuckets];
     __shared__ uint32_t s_start[kMaxBuckets];
     __shared__ uint32_t s_fill[kMaxBuckets];
@@ -853,20 +903,31 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
     const ListTile t = list_tile(pdesc, p, g);
     const uint64_t *__restrict__ list = plist + t.lo;
     const uint64_t cap = B.entries_cap;
-    for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
+    for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kThreads) {
         s_cursor[i] = i < nbp ? coarse_off[((uint64_t)p * nbp + i) * B.list_g + g] : 0u;
         s_cnt[i] = 0;
         s_fill[i] = 0;
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint64_t q0 = 0; q0 < t.n; q0 += kStage) {
-        uint64_t v[kPer];
+    // the next batch is requested before the current one is sorted
+    auto load = [&](uint64_t q0, uint64_t(&v)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
-            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kBinWG;
+            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kThreads;
             v[u] = x < t.n ? list[x] : ~0ull;
         }
+    };
+    uint64_t nv[kPer];
+    if (t.n > 0)
+        load(0, nv);
+    for (uint64_t q0 = 0; q0 < t.n; q0 += kBatch) {
+        uint64_t v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++)
+            v[u] = nv[u];
+        if (q0 + kBatch < t.n)
+            load(q0 + kBatch, nv);
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (v[u] != ~0ull)
@@ -892,7 +953,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
             }
         __syncthreads();
         const uint32_t n_stage = s_start[kMaxBuckets - 1] + s_cnt[kMaxBuckets - 1];
-        for (uint32_t j = threadIdx.x; j < n_stage; j += kBinWG) {
+        for (uint32_t j = threadIdx.x; j < n_stage; j += kThreads) {
             const uint64_t e = s_stage[j];
             const uint32_t b = ((uint32_t)e >> bshift) & (kMaxBuckets - 1u);
             const uint64_t dst = (uint64_t)s_cursor[b] + (j - s_start[b]);
@@ -900,7 +961,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket_list(const uint64_t *__re
                 bucketed[dst] = e;
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
+        for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kThreads) {
             s_cursor[i] += s_cnt[i];
             s_cnt[i] = 0;
             s_fill[i] = 0;
@@ -1174,6 +1235,20 @@ bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B, uint32_
 
 namespace {
 
+// Workgroup size of a partitioned-path scatter pass (its batches hold 8 or
+// 16 entries per thread): the environment variable `name` (512 or 1024) when
+// set, else dflt.  Levels 1 and 2 (KMERCO_L1_THREADS, KMERCO_L2_THREADS)
+// take 1024 by default: with batches twice as large their runs are twice as
+// long (per 8 Gbase step, level 1 26.8 against 30.2 ms, level 2 31.7 against
+// 37.2 ms); the partition scatter (KMERCO_L0_THREADS) keeps 512 (22.2 against
+// 24.6 ms).
+int pass_threads(const char *name, int dflt) {
+    const char *e = std::getenv(name);
+    if (!e || !*e)
+        return dflt;
+    return std::atoi(e) == 1024 ? 1024 : kBinWG;
+}
+
 // The layout the hashing kernel's fast variant takes (bin_window).
 bool fast_layout(const FilterArgs &F) {
     return F.k_h == 1 && F.eta_pow2 && F.small_dims;
@@ -1227,9 +1302,14 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinPart, s);
-        hipLaunchKernelGGL(k_part_scatter, dim3(B.G), dim3(kBinWG), 0, s, c0, c1, F.k_h, B,
-                           (const uint32_t *)slots, (const uint8_t *)parts,
-                           (const uint32_t *)W.pmat, plist);
+        if (pass_threads("KMERCO_L0_THREADS", kBinWG) == 1024)
+            hipLaunchKernelGGL(k_part_scatter<1024>, dim3(B.G), dim3(1024), 0, s, c0, c1, F.k_h,
+                               B, (const uint32_t *)slots, (const uint8_t *)parts,
+                               (const uint32_t *)W.pmat, plist);
+        else
+            hipLaunchKernelGGL(k_part_scatter<kBinWG>, dim3(B.G), dim3(kBinWG), 0, s, c0, c1,
+                               F.k_h, B, (const uint32_t *)slots, (const uint8_t *)parts,
+                               (const uint32_t *)W.pmat, plist);
         if (P)
             P->end(s);
         e = hipGetLastError();
@@ -1275,9 +1355,14 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinBucket, s);
-        hipLaunchKernelGGL(k_bin_bucket_list, dim3(n_list), dim3(kBinWG), 0, s,
-                           (const uint64_t *)plist, (const uint64_t *)W.pdesc, Q,
-                           (const uint32_t *)W.coarse, W.bucketed);
+        if (pass_threads("KMERCO_L1_THREADS", 1024) == 1024)
+            hipLaunchKernelGGL(k_bin_bucket_list<1024>, dim3(n_list), dim3(1024), 0, s,
+                               (const uint64_t *)plist, (const uint64_t *)W.pdesc, Q,
+                               (const uint32_t *)W.coarse, W.bucketed);
+        else
+            hipLaunchKernelGGL(k_bin_bucket_list<kBinWG>, dim3(n_list), dim3(kBinWG), 0, s,
+                               (const uint64_t *)plist, (const uint64_t *)W.pdesc, Q,
+                               (const uint32_t *)W.coarse, W.bucketed);
         if (P)
             P->end(s);
         e = hipGetLastError();
@@ -1285,9 +1370,16 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinRegion, s);
-        hipLaunchKernelGGL(k_bin_region<false>, dim3(Q.n_buckets * Q.n_slices), dim3(kBinWG), 0, s, Q,
-                           (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
-                           (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
+        if (pass_threads("KMERCO_L2_THREADS", 1024) == 1024)
+            hipLaunchKernelGGL((k_bin_region<false, 1024>), dim3(Q.n_buckets * Q.n_slices),
+                               dim3(1024), 0, s, Q, (const uint32_t *)W.coarse,
+                               (const uint32_t *)(W.n_entries + 1), (const uint32_t *)W.matrix,
+                               (const uint64_t *)W.bucketed, W.entries);
+        else
+            hipLaunchKernelGGL((k_bin_region<false, kBinWG>), dim3(Q.n_buckets * Q.n_slices),
+                               dim3(kBinWG), 0, s, Q, (const uint32_t *)W.coarse,
+                               (const uint32_t *)(W.n_entries + 1), (const uint32_t *)W.matrix,
+                               (const uint64_t *)W.bucketed, W.entries);
         if (P)
             P->end(s);
         e = hipGetLastError();
@@ -1370,7 +1462,7 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhBinRegion, s);
-        hipLaunchKernelGGL(k_bin_region<true>, dim3(B.n_buckets * B.n_slices), dim3(kBinWG), 0, s, B,
+        hipLaunchKernelGGL((k_bin_region<true, kBinWG>), dim3(B.n_buckets * B.n_slices), dim3(kBinWG), 0, s, B,
                            (const uint32_t *)W.coarse, (const uint32_t *)(W.n_entries + 1),
                            (const uint32_t *)W.matrix, (const uint64_t *)W.bucketed, W.entries);
         if (P)
