@@ -129,6 +129,9 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_windows * k_h * 16 + n_bases * 0.5
     if phase == "resolve":           # entry read per slot, winner reset, flags
         return n_windows * k_h * 4 + n_distinct * 4 + n_bases * (0.5 + 0.125)
+    if phase == "winners":           # first-seen records: two distribution passes (6 B in,
+        return n_distinct * 22 + n_bases  # 4 B out, 4 B in and out), 4 B into the flag blocks,
+                                          # flag bytes written in 16-byte groups
     if phase == "reset":             # the countBF's cells written (cleared)
         return n_words * 8
     if phase == "ingest":            # ASCII in, packed codes + bitmaps out, flag bytes cleared

@@ -334,7 +334,9 @@ typedef enum {
     KC_PHASE_BIN_PART = 16,       /* partitioned path: entries grouped by partition */
     KC_PHASE_PART_COUNT = 17,     /* partitioned path: per-partition region counts */
     KC_PHASE_VALID = 18,          /* binned paths: valid-window bitmap of the call's k */
-    KC_PHASE_COUNT = 19
+    KC_PHASE_WINNERS = 19,        /* binned paths, chunks beyond 2^28 positions: first-seen
+                                     records -> flag bytes */
+    KC_PHASE_COUNT = 20
 } kc_phase;
 
 kc_status kc_profile(kc_filter *f, int enable);

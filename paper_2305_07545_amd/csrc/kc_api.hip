@@ -227,7 +227,8 @@ kc_status ensure_scalars(kc::Workspace &W) {
         return KC_OK;
     if (W.fixed)
         return KC_ERANGE;
-    if (!dev_alloc(&W.totals, 8) || !dev_alloc(&W.n_entries, 4))
+    if (!dev_alloc(&W.totals, 8) || !dev_alloc(&W.n_entries, 4) ||
+        !dev_alloc(&W.win_cursors, kc::kWinCursors))
         return KC_ENOMEM;
     return KC_OK;
 }
@@ -275,6 +276,7 @@ void free_workspace(kc::Workspace &W) {
     W.slots_cap = W.entries_cap = W.matrix_cap = W.coarse_cap = W.pmat_cap = 0;
     dev_free(W.totals);
     dev_free(W.n_entries);
+    dev_free(W.win_cursors);
 }
 
 void free_all(kc_filter *f) {
@@ -927,7 +929,8 @@ const char *kc_phase_name(uint32_t phase) {
     static const char *names[kc::kPhCount] = {
         "ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
         "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
-        "region", "tile_count", "bin_region", "bin_part", "part_count", "valid_windows"};
+        "region", "tile_count", "bin_region", "bin_part", "part_count", "valid_windows",
+        "winners"};
     return phase < (uint32_t)kc::kPhCount ? names[phase] : "unknown";
 }
 

@@ -511,7 +511,7 @@ void workspace_pointers(const kc::Workspace &W, std::vector<uint64_t> &out) {
     const void *p[] = {W.codes, W.inv, W.rs, W.valid, W.flags8, W.tile_a, W.tile_b, W.tile_c,
                        W.off_a, W.off_b, W.off_c, W.tmask, W.partial64, W.matrix, W.matrix_t,
                        W.coarse, W.partial32, W.slots, W.bucketed, W.entries, W.pmat, W.pbounds,
-                       W.pdesc, W.totals, W.n_entries};
+                       W.pdesc, W.totals, W.n_entries, W.win_cursors};
     for (const void *x : p)
         out.push_back((uint64_t)(uintptr_t)x);
     out.insert(out.end(), {W.cap, W.tile_cap, W.matrix_cap, W.coarse_cap, W.slots_cap,

@@ -970,11 +970,35 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
     }
 }
 
+// Where the region pass puts a first-seen occurrence (chunk-relative t and
+// its mark: 1 distinct, 3 distinct and trustworthy): its flag byte, or, in
+// records mode, a record in the region's own entry segment (whose entries
+// the workgroup has read by then: every winner is one of them), which the
+// winner passes below turn into flag bytes written in whole 16-byte groups.
+struct WinnerSink {
+    uint8_t *flags;
+    uint64_t c0;
+    uint32_t *rec_t;  // records mode: the entry lists' word array (null: flag mode)
+    uint16_t *rec_m;  // ... and half array
+    uint64_t e0;      // the region's first entry
+    uint32_t *count;  // LDS: records written so far
+};
+
+__device__ __forceinline__ void put_winner(const WinnerSink &o, uint32_t t, uint32_t mark) {
+    if (!o.rec_t) {
+        o.flags[o.c0 + t] = (uint8_t)mark;
+        return;
+    }
+    const uint32_t i = atomicAdd(o.count, 1u);
+    o.rec_t[o.e0 + i] = t;
+    o.rec_m[o.e0 + i] = (uint16_t)mark;
+}
+
 // Counter update of cell w of the region (pre = its value before the chunk).
 __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &B, uint64_t wbase,
                                             uint32_t w, uint64_t pre, const uint32_t *hits,
-                                            const uint32_t *first, uint8_t *__restrict__ flags,
-                                            uint64_t c0, int classify, uint32_t tau) {
+                                            const uint32_t *first, const WinnerSink &out,
+                                            int classify, uint32_t tau) {
     uint64_t next = pre;
     for (uint32_t l = 0; l < F.eta; l++) {
         const uint32_t idx = (l << B.region_shift) | w;
@@ -986,12 +1010,8 @@ __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &
         const uint64_t room = F.field_max - pf;
         const uint64_t nf = pf + (h < room ? h : room);
         next = (next & ~(F.field_max << sh)) | (nf << sh);
-        if (pf == 0) {
-            uint8_t flag = 1;
-            if (classify && nf > (uint64_t)tau)
-                flag = 3;
-            flags[c0 + first[idx]] = flag;
-        }
+        if (pf == 0)
+            put_winner(out, first[idx], (classify && nf > (uint64_t)tau) ? 3u : 1u);
     }
     if (next != pre)
         F.words[wbase + w] = next;
@@ -1005,9 +1025,9 @@ template <int kCounters>
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
-                                                      const uint64_t *__restrict__ entries,
+                                                      uint64_t *__restrict__ entries,
                                                       uint8_t *__restrict__ flags, int classify,
-                                                      uint32_t tau) {
+                                                      uint32_t tau, uint32_t *__restrict__ n_win) {
     constexpr int kUnroll = 8;
     constexpr int kHold = 4;  // cells per thread held in registers (regions <= 4096 cells)
     constexpr uint32_t kSparseCells = kCounters / 8;  // cells of a region the sparse path stages
@@ -1017,6 +1037,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     __shared__ uint32_t hits[kCounters];
     __shared__ uint32_t first[kCounters];
     __shared__ unsigned long long s_cell[kSparseCells];
+    __shared__ uint32_t s_nwin;
     const uint32_t r = blockIdx.x;
     const uint32_t S = 1u << B.region_shift;
     const uint32_t n_ctr = S * F.eta;
@@ -1027,8 +1048,11 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     const uint64_t wbase = (uint64_t)(B.region0 + r) << B.region_shift;
     const uint64_t n_words = F.X * F.Y;
     const uint32_t nw = wbase + S <= n_words ? S : (uint32_t)(n_words - wbase);
-    const uint32_t *e_word = (const uint32_t *)entries;
-    const uint16_t *e_half = (const uint16_t *)(e_word + B.entries_cap);
+    uint32_t *e_word = (uint32_t *)entries;
+    uint16_t *e_half = (uint16_t *)(e_word + B.entries_cap);
+    if (threadIdx.x == 0)
+        s_nwin = 0;
+    const WinnerSink out{flags, c0, n_win ? e_word : nullptr, e_half, e0, &s_nwin};
     // entry x as loaded (hi = ~0u past the end); decoded where it is used,
     // so that prefetched loads stay in flight until then
     auto fetch = [&](uint64_t x) -> RawEntry {
@@ -1104,7 +1128,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                 if (nf != pf)
                     atomicAdd(&s_cell[w], (unsigned long long)((nf - pf) << sh));
                 if (pf == 0)
-                    flags[c0 + t] = (classify && nf > (uint64_t)tau) ? 3 : 1;
+                    put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u);
             }
         __syncthreads();
 #pragma unroll
@@ -1113,6 +1137,8 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             if (w < nw && s_cell[w] != cell[k])
                 F.words[wbase + w] = s_cell[w];
         }
+        if (n_win && threadIdx.x == 0)
+            n_win[r] = s_nwin;  // its own atomics are done (the barrier above)
         return;
     }
     for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
@@ -1148,13 +1174,230 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         for (int k = 0; k < kHold; k++) {
             const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
             if (w < nw)
-                region_cell(F, B, wbase, w, cell[k], hits, first, flags, c0, classify, tau);
+                region_cell(F, B, wbase, w, cell[k], hits, first, out, classify, tau);
         }
     } else {
         for (uint32_t w = threadIdx.x; w < nw; w += kRegionWG)
-            region_cell(F, B, wbase, w, F.words[wbase + w], hits, first, flags, c0, classify,
-                        tau);
+            region_cell(F, B, wbase, w, F.words[wbase + w], hits, first, out, classify, tau);
     }
+    if (n_win) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            n_win[r] = s_nwin;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// winner passes (records mode): the region pass's first-seen records, grouped
+// by region, become flag bytes written in whole 16-byte groups.  Records are
+// distributed by position in two counting-sort passes (by t >> 24, then by
+// the next 5 bits) into blocks of 2^19 positions, whose flags are built in
+// LDS bitmaps.  Runs are appended to each bucket at an atomic cursor (the
+// order of records inside a bucket does not matter: a bitmap is built from
+// them), in areas of the two entry buffers sized by the positions they
+// cover, so that they always fit.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kWinA = 24;             // level-A digit: t >> 24 (256 buckets)
+constexpr uint32_t kWinB = 19;             // level-B digit: (t >> 19) & 31 (2^19 positions)
+constexpr int kWinThreads = 1024;
+constexpr int kWinBatch = 8192;            // records per LDS batch
+constexpr uint32_t kWinRegions = 64;       // regions per level-A workgroup
+constexpr uint32_t kWinSlices = 64;        // level-B workgroups per level-A bucket
+constexpr uint32_t kWinBuckets = 256;
+constexpr uint32_t kWinBlocksPerBucket = 1u << (kWinA - kWinB);
+
+// The batch s_rec[0..n) appended to buckets by digit (rec >> shift) & (nd - 1)
+// (nd <= kWinThreads): counted in LDS, one cursor bump per digit, then each
+// record written at its digit's base plus its rank (the records of a digit
+// fill one run; their order inside it does not matter).  keep(rec) is the
+// record written.  Ends with a barrier, so that the batch can be refilled.
+template <typename Rec, typename Keep>
+__device__ void win_flush(const Rec *s_rec, uint32_t n, uint32_t shift, uint32_t nd,
+                          uint32_t bucket0, uint32_t area_log, uint32_t *s_cnt, uint32_t *s_base,
+                          uint32_t *__restrict__ cursor, uint32_t *__restrict__ out, Keep keep) {
+    for (uint32_t i = threadIdx.x; i < nd; i += kWinThreads)
+        s_cnt[i] = 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < n; j += kWinThreads)
+        atomicAdd(&s_cnt[(uint32_t)(s_rec[j] >> shift) & (nd - 1u)], 1u);
+    __syncthreads();
+    if (threadIdx.x < nd) {
+        const uint32_t c = s_cnt[threadIdx.x];
+        s_base[threadIdx.x] = c ? atomicAdd(&cursor[bucket0 + threadIdx.x], c) : 0u;
+        s_cnt[threadIdx.x] = 0;  // reused as each digit's rank counter
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < n; j += kWinThreads) {
+        const Rec r = s_rec[j];
+        const uint32_t d = (uint32_t)(r >> shift) & (nd - 1u);
+        const uint32_t rank = atomicAdd(&s_cnt[d], 1u);
+        out[((uint64_t)(bucket0 + d) << area_log) + s_base[d] + rank] = keep(r);
+    }
+    __syncthreads();
+}
+
+// Level A: the records of regions [kWinRegions * blockIdx.x, ...) (region r's
+// n_win[r] records start at its first entry) -> bucket t >> 24, record
+// (t & (2^24 - 1)) | mark << 24.
+__global__ void __launch_bounds__(kWinThreads) k_win_a(BinPlan B, const uint32_t *__restrict__ offsets,
+                                                       const uint32_t *__restrict__ n_win,
+                                                       const uint64_t *__restrict__ entries,
+                                                       uint32_t *__restrict__ cursor,
+                                                       uint32_t *__restrict__ out) {
+    __shared__ uint64_t s_rec[kWinBatch];
+    __shared__ uint32_t s_cnt[kWinBuckets], s_base[kWinBuckets];
+    const uint32_t *e_word = (const uint32_t *)entries;
+    const uint16_t *e_half = (const uint16_t *)(e_word + B.entries_cap);
+    const uint32_t r0 = blockIdx.x * kWinRegions;
+    const uint32_t r1 = r0 + kWinRegions < B.n_regions ? r0 + kWinRegions : B.n_regions;
+    auto keep = [](uint64_t r) -> uint32_t {
+        return ((uint32_t)r & ((1u << kWinA) - 1u)) | ((uint32_t)(r >> 32) << kWinA);
+    };
+    uint32_t fill = 0;  // the same in every thread
+    for (uint32_t r = r0; r < r1; r++) {
+        const uint64_t base = offsets[(uint64_t)r * B.G];
+        const uint32_t n = n_win[r];
+        for (uint32_t done = 0; done < n;) {
+            const uint32_t take = n - done < kWinBatch - fill ? n - done : kWinBatch - fill;
+            for (uint32_t i = threadIdx.x; i < take; i += kWinThreads) {
+                const uint64_t x = base + done + i;
+                s_rec[fill + i] = ((uint64_t)e_half[x] << 32) | e_word[x];
+            }
+            fill += take;
+            done += take;
+            if (fill == kWinBatch) {
+                __syncthreads();
+                win_flush(s_rec, fill, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_base, cursor, out,
+                          keep);
+                fill = 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (fill)
+        win_flush(s_rec, fill, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_base, cursor, out, keep);
+}
+
+// Level B: slice blockIdx.y of level-A bucket a = blockIdx.x -> block
+// (a << 5) | ((t24 >> 19) & 31), record (t & (2^19 - 1)) | mark << 19.
+__global__ void __launch_bounds__(kWinThreads) k_win_b(const uint32_t *__restrict__ in,
+                                                       const uint32_t *__restrict__ cursor_a,
+                                                       uint32_t *__restrict__ cursor_b,
+                                                       uint32_t *__restrict__ out) {
+    __shared__ uint32_t s_rec[kWinBatch];
+    __shared__ uint32_t s_cnt[kWinBlocksPerBucket], s_base[kWinBlocksPerBucket];
+    const uint32_t a = blockIdx.x;
+    const uint32_t n = cursor_a[a];
+    const uint32_t per = ((1u << kWinA) + kWinSlices - 1) / kWinSlices;
+    const uint32_t q0 = blockIdx.y * per;
+    const uint32_t q1 = q0 + per < n ? q0 + per : n;
+    const uint32_t *src = in + ((uint64_t)a << kWinA);
+    auto keep = [](uint32_t v) -> uint32_t {
+        return (v & ((1u << kWinB) - 1u)) | ((v >> kWinA) << kWinB);
+    };
+    for (uint32_t q = q0; q < q1; q += kWinBatch) {
+        const uint32_t m = q1 - q < (uint32_t)kWinBatch ? q1 - q : (uint32_t)kWinBatch;
+        for (uint32_t i = threadIdx.x; i < m; i += kWinThreads)
+            s_rec[i] = src[q + i];
+        __syncthreads();
+        // digit (t24 >> 19) & 31 of the record (t24 | mark << 24)
+        win_flush(s_rec, m, kWinB, kWinBlocksPerBucket, a * kWinBlocksPerBucket, kWinB, s_cnt,
+                  s_base, cursor_b, out, keep);
+    }
+}
+
+// The flag bytes of block g = blockIdx.x (positions [g << 19, ...) of the
+// chunk, flags at c0 + those) from its records: distinct and trustworthy
+// bitmaps in LDS, then every 16-position group with a mark written whole
+// (the others keep the zeros the ingest wrote).
+__global__ void __launch_bounds__(kWinThreads) k_win_flags(const uint32_t *__restrict__ in,
+                                                           const uint32_t *__restrict__ cursor_b,
+                                                           uint64_t c0, uint64_t len,
+                                                           uint8_t *__restrict__ flags) {
+    constexpr uint32_t kWords = (1u << kWinB) / 32;
+    __shared__ uint32_t s_d[kWords];
+    __shared__ uint32_t s_t[kWords];
+    const uint32_t g = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < kWords; i += kWinThreads) {
+        s_d[i] = 0;
+        s_t[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t n = cursor_b[g];
+    const uint32_t *src = in + ((uint64_t)g << kWinB);
+    for (uint32_t i = threadIdx.x; i < n; i += kWinThreads) {
+        const uint32_t v = src[i];
+        const uint32_t p = v & ((1u << kWinB) - 1u);
+        atomicOr(&s_d[p >> 5], 1u << (p & 31u));
+        if ((v >> kWinB) & 2u)
+            atomicOr(&s_t[p >> 5], 1u << (p & 31u));
+    }
+    __syncthreads();
+    const uint64_t p0 = (uint64_t)g << kWinB;
+    uint4 *f128 = reinterpret_cast<uint4 *>(flags + c0 + p0);
+    const uint32_t groups = (uint32_t)((len - p0 < (1u << kWinB) ? len - p0 : (1u << kWinB)) + 15) / 16;
+    for (uint32_t q = threadIdx.x; q < groups; q += kWinThreads) {
+        const uint32_t d16 = (s_d[q >> 1] >> ((q & 1u) * 16)) & 0xFFFFu;
+        if (!d16)
+            continue;
+        const uint32_t t16 = (s_t[q >> 1] >> ((q & 1u) * 16)) & 0xFFFFu;
+        uint32_t w[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t b = 4 * u + j;
+                x |= (((d16 >> b) & 1u) | (((t16 >> b) & 1u) << 1)) << (8 * j);
+            }
+            w[u] = x;
+        }
+        f128[q] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Records mode when a chunk's flag bytes are larger than the Infinity
+// Cache (256 MB): random single-byte flag stores into HBM-resident flags
+// cost the 8 Gbase insert's region pass about 20 ms; KMERCO_WINNER_RECORDS=1
+// forces records mode for every chunk (tests), 0 turns it off.
+bool records_mode(uint64_t len) {
+    const char *e = std::getenv("KMERCO_WINNER_RECORDS");
+    if (e && *e)
+        return std::atoi(e) != 0;
+    return len > (1ull << 28);
+}
+
+// The winner passes of one chunk [c0, c0 + len) after its region pass.
+hipError_t launch_winner_passes(const BinPlan &Q, uint64_t c0, uint64_t len, const Workspace &W,
+                                const uint32_t *n_win, hipStream_t s, Profiler *P) {
+    uint32_t *cursors = W.win_cursors;  // kWinBuckets level-A, then the blocks' level-B cursors
+    const uint32_t n_a = (uint32_t)((len + (1ull << kWinA) - 1) >> kWinA);
+    const uint32_t n_blocks = (uint32_t)((len + (1ull << kWinB) - 1) >> kWinB);
+    if (P)
+        P->begin(kPhWinners, s);
+    static_assert(kWinBuckets + kWinBuckets * kWinBlocksPerBucket == kWinCursors, "cursors");
+    hipError_t e = fill_u32(cursors, kWinCursors, 0u, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_win_a, dim3((Q.n_regions + kWinRegions - 1) / kWinRegions),
+                           dim3(kWinThreads), 0, s, Q, (const uint32_t *)W.matrix, n_win,
+                           (const uint64_t *)W.entries, cursors, (uint32_t *)W.bucketed);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_win_b, dim3(n_a, kWinSlices), dim3(kWinThreads), 0, s,
+                           (const uint32_t *)W.bucketed, (const uint32_t *)cursors,
+                           cursors + kWinBuckets, (uint32_t *)W.entries);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_win_flags, dim3(n_blocks), dim3(kWinThreads), 0, s,
+                           (const uint32_t *)W.entries, (const uint32_t *)(cursors + kWinBuckets),
+                           c0, len, W.flags8);
+        e = hipGetLastError();
+    }
+    if (P)
+        P->end(s);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -1387,15 +1630,18 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhRegion, s);
+        const bool rec = records_mode(c1 - c0);
         hipLaunchKernelGGL((Q.region_counters == kSmallRegionCounters
                                 ? k_region<kSmallRegionCounters>
                                 : k_region<kRegionCounters>),
                            dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
-                           (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
-                           (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
+                           (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
+                           W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr);
         if (P)
             P->end(s);
         e = hipGetLastError();
+        if (e == hipSuccess && rec)
+            e = launch_winner_passes(Q, c0, c1 - c0, W, W.matrix_t, s, P);
     }
     return e;
 }
@@ -1473,15 +1719,19 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhRegion, s);
+    const bool rec = records_mode(c1 - c0);
     hipLaunchKernelGGL((B.region_counters == kSmallRegionCounters
                             ? k_region<kSmallRegionCounters>
                             : k_region<kRegionCounters>),
                        dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
-                       (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries,
-                       (const uint64_t *)W.entries, W.flags8, classify ? 1 : 0, tau);
+                       (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
+                       W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr);
     if (P)
         P->end(s);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e == hipSuccess && rec)
+        e = launch_winner_passes(B, c0, c1 - c0, W, W.matrix_t, s, P);
+    return e;
 }
 
 }  // namespace kc

@@ -47,6 +47,7 @@ constexpr uint32_t kListWGs = 4096;          // list workgroups over all partiti
 constexpr uint32_t kMaxListG = 512;          // list workgroups per partition (at most)
 constexpr uint64_t kMaxCoarse = 1ull << 19;  // (partition bucket, list workgroup) counts
 constexpr int kSuper = 4;                    // tiles per iteration of the tile kernels
+constexpr uint32_t kWinCursors = 256 + 256 * 32;  // winner passes: level-A and block cursors
 
 struct BinPlan {
     uint32_t region_shift;  // log2(cells per region)
@@ -101,6 +102,7 @@ struct Workspace {
     // scalars
     uint64_t *totals = nullptr;   // 8 scan totals / saved counters
     uint32_t *n_entries = nullptr;  // 4 entry totals
+    uint32_t *win_cursors = nullptr;  // kWinCursors: the winner passes' bucket cursors
     // the buffers were carved from caller memory once: they never grow, and a
     // call that needs more than they hold fails instead
     bool fixed = false;
@@ -180,7 +182,7 @@ inline uint64_t code_words(uint64_t n) { return tiles(n) * (kTile / 16) + 4; }
 enum Phase {
     kPhIngest = 0, kPhClaim, kPhIncrement, kPhClaimIncrement, kPhResolve, kPhScan, kPhScatter,
     kPhClassifyMark, kPhClassifyScatter, kPhQuery, kPhReset, kPhBinCount, kPhBinBucket, kPhRegion,
-    kPhTileCount, kPhBinRegion, kPhBinPart, kPhPartCount, kPhValid, kPhCount
+    kPhTileCount, kPhBinRegion, kPhBinPart, kPhPartCount, kPhValid, kPhWinners, kPhCount
 };
 
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);

@@ -149,7 +149,8 @@ SIGNATURES = {
 
 PHASES = ["ingest", "claim", "increment", "claim_increment", "resolve", "scan", "scatter",
           "classify_mark", "classify_scatter", "query", "reset", "bin_count", "bin_bucket",
-          "region", "tile_count", "bin_region", "bin_part", "part_count", "valid_windows"]
+          "region", "tile_count", "bin_region", "bin_part", "part_count", "valid_windows",
+          "winners"]
 
 
 def load_library():

@@ -486,3 +486,35 @@ def test_small_regions_bacterial_sample(monkeypatch):
     check(rs, X, Y, what="bacterial x0.05, regions of 8192 counters")
     monkeypatch.setenv("KMERCO_PART_LOG", "3")
     check(rs, X, Y, what="bacterial x0.05, regions of 8192 counters, partitions of 8")
+
+
+# ---------------------------------------------------------------------------
+# first-seen records turned into flag bytes by the winner passes (the mode of
+# chunks beyond 2^28 positions, forced here on small inputs)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,k_h,counters", [(8, 1, "16384"), (8, 2, "16384"), (5, 1, "8192"),
+                                                (16, 3, "16384"), (4, 1, "8192")])
+def test_winner_records(monkeypatch, alpha, k_h, counters):
+    monkeypatch.setenv("KMERCO_WINNER_RECORDS", "1")
+    monkeypatch.setenv("KMERCO_REGION_COUNTERS", counters)
+    rnd = synth.random_reads(2900 + alpha + k_h, 600, 50, 300, k=23, tau=2, p_n=0.01)
+    extra = synth.reads_from_strings(["A" * 9000, "ACGT" * 2000, "GATTACA" * 500], k=23, tau=2)
+    rs = synth.concat_reads([rnd, extra], name="winner records")
+    check(rs, 1009, 1013, alpha=alpha, k_h=k_h, what=f"records a={alpha} kh={k_h}")
+    check(rs, 1009, 1013, alpha=alpha, k_h=k_h, what="records unfused", fused=False)
+    check(rs, 3, 5, alpha=alpha, k_h=k_h, what="records, 3x5 filter")
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "40000")
+    check(rs, 1009, 1013, alpha=alpha, k_h=k_h, what="records, chunks of 40000")
+    monkeypatch.setenv("KMERCO_PART_LOG", "2")
+    check(rs, 401, 409, alpha=alpha, k_h=k_h, what="records, partitioned chunks")
+
+
+def test_winner_records_bacterial_and_wide(monkeypatch):
+    monkeypatch.setenv("KMERCO_WINNER_RECORDS", "1")
+    rs = synth.config("bacterial", scale=0.05)
+    X, Y = oracle.dims(rs.n_items)
+    check(rs, X, Y, what="records, bacterial x0.05")
+    check(rs, X, Y, k=45, what="records, bacterial x0.05, k=45")
+    monkeypatch.setenv("KMERCO_PART_LOG", "3")
+    check(rs, X, Y, what="records, bacterial x0.05, partitions of 8")
