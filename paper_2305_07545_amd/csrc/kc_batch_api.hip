@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "kc_batched.hpp"
+#include "kc_bin_hash.hpp"
 #include "kc_handle.hpp"
 #include "kc_kernels.hpp"
 #include "kmerco.h"
@@ -127,7 +128,7 @@ kc::BatchPlan make_plan(kc_batch *b, const kc_set *sets, uint32_t n_sets, uint64
         (void)kc::bin_plan(f->F, q.n_bases, bp);  // validated by the caller
         kc::SetDesc d{};
         d.F = f->F;
-        if (!(f->F.k_h == 1 && f->F.eta_pow2 && f->F.small_dims))
+        if (!kc::fast_layout(f->F))
             P.fast = 0;
         d.base = q.first_base;
         d.n_bases = q.n_bases;

@@ -15,19 +15,13 @@
 #include <hip/hip_runtime.h>
 
 #include "kc_batched.hpp"
+#include "kc_bin_hash.hpp"
 #include "kc_device.hpp"
 #include "kc_kernels.hpp"
 
 namespace kc {
 
 namespace {
-
-constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
-constexpr uint32_t kLocalBits = 14;
-
-__device__ __forceinline__ uint32_t wave_id() {
-    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-}
 
 // Positions of work item i: set s, tile j of the set.
 struct Item {
@@ -73,34 +67,6 @@ __global__ void kb_zero_valid(unsigned long long *__restrict__ valid, uint32_t n
         valid[s] = 0;
 }
 
-// kFast: every set has one hash function, a power-of-two eta and
-// dimensions of mod_small (checked by the planner).
-template <bool kFast>
-__device__ __forceinline__ void kb_bin_window(const SetDesc &S, const FilterArgs &F, uint64_t fwd,
-                                              uint64_t q, uint32_t *__restrict__ slots,
-                                              uint32_t *s_hist) {
-    const uint32_t shift = S.region_shift;
-    const uint64_t smask = (1ull << shift) - 1ull;
-    const Canon c = canonical_fast(fwd, S.k);
-    const uint32_t k_h = kFast ? 1u : F.k_h;
-    for (uint32_t a = 1; a <= k_h; a++) {
-        uint64_t word;
-        uint32_t l;
-        const uint64_t h = a == 1 ? c.h1 : hash_a(c.b0, c.b1, a);
-        if (kFast) {
-            l = (uint32_t)h & (F.eta - 1u);
-            word = (uint64_t)mod_small(h, (uint32_t)F.X, F.mX) * (uint32_t)F.Y +
-                   mod_small(h, (uint32_t)F.Y, F.mY);
-        } else {
-            slot_of(F, h, word, l);
-        }
-        const uint32_t r = (uint32_t)(word >> shift);
-        slots[S.slot_base + (uint64_t)(a - 1) * S.n_bases + q] =
-            (r << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
-        atomicAdd(&s_hist[r], 1u);
-    }
-}
-
 // The valid-window bitmap words of an item's positions, for its set's k
 // (items start at multiples of 64 positions, so that no word spans two).
 __global__ void __launch_bounds__(256) kb_valid(const SetDesc *__restrict__ sets,
@@ -114,10 +80,9 @@ __global__ void __launch_bounds__(256) kb_valid(const SetDesc *__restrict__ sets
         valid[w] = valid_word(R.inv, R.rs, n_words, w, S.k, S.base + S.n_bases);
 }
 
-// Slot ids of an item's windows and its per-region counts.  As in the
-// single-set bin pass, each wavefront takes its positions' validity from
-// the valid-window bitmap, queues its valid windows in an LDS ring and
-// hashes 64 of them at a time.
+// Slot ids of an item's windows and its per-region counts, hashed as in the
+// single-set bin pass (walk_windows, window_counters); kFast: every set has
+// the fast layout (checked by the planner).
 template <bool kFast>
 __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict__ sets,
                                                        const uint32_t *__restrict__ item_set,
@@ -125,10 +90,8 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
                                                        uint32_t *__restrict__ slots,
                                                        uint32_t *__restrict__ matrix,
                                                        unsigned long long *__restrict__ valid) {
-    constexpr uint32_t kRing = 128;
     __shared__ uint32_t s_hist[kBatchMaxRegions];
-    __shared__ uint64_t s_key[kBinWG / 64][kRing];
-    __shared__ uint32_t s_pos[kBinWG / 64][kRing];
+    __shared__ uint32_t s_ring[kBinWG / 64][kWindowRing];
     __shared__ uint32_t s_valid;
     const Item it = item_of(sets, item_set, blockIdx.x, tile);
     const SetDesc &S = sets[it.s];
@@ -138,48 +101,27 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_count(const SetDesc *__restrict
     if (threadIdx.x == 0)
         s_valid = 0;
     __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = wave_id();
     R.k = S.k;
-    uint32_t nv = 0;
-    uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
     // set-relative 32-bit positions (sets start at multiples of 4096)
     const uint32_t *__restrict__ codes = R.codes + (S.base >> 4);
     uint32_t *__restrict__ sl = slots + S.slot_base;
-    for (uint64_t pb = it.g0 + 64u * wv; pb < it.g1; pb += kBinWG) {
-        const uint64_t m_in = it.g1 - pb < 64u ? (1ull << (it.g1 - pb)) - 1ull : ~0ull;
-        const uint64_t m = wave_valid(R, pb) & m_in;  // the wave's valid windows
-        const uint64_t m_skip = m_in & ~m;
-        const uint32_t pos = (uint32_t)(pb - S.base) + lane;
-        if ((m_skip >> lane) & 1ull)
-            for (uint32_t a = 1; a <= F.k_h; a++)
-                sl[(uint64_t)(a - 1) * S.n_bases + pos] = kNoSlot;
-        if ((m >> lane) & 1ull) {
-            const uint64_t fwd = window_key(codes, pos, S.k);
-            nv++;
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const uint32_t at = (head + queued + rank) & (kRing - 1u);
-            s_key[wv][at] = fwd;
-            s_pos[wv][at] = pos;
-        }
-        queued += (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
-        if (queued >= 64u) {
-            const uint32_t at = (head + lane) & (kRing - 1u);
-            const uint64_t key = s_key[wv][at];
-            const uint32_t q = s_pos[wv][at];
-            __builtin_amdgcn_wave_barrier();
-            head = (head + 64u) & (kRing - 1u);
-            queued -= 64u;
-            kb_bin_window<kFast>(S, F, key, q, slots, s_hist);
-        }
-    }
-    if (lane < queued) {
-        const uint32_t at = (head + lane) & (kRing - 1u);
-        kb_bin_window<kFast>(S, F, s_key[wv][at], s_pos[wv][at], slots, s_hist);
-    }
-    atomicAdd(&s_valid, nv);
+    const uint64_t nb = S.n_bases;
+    const uint32_t K = S.k, shift = S.region_shift, k_h = kFast ? 1u : F.k_h;
+    const uint32_t nv = walk_windows(
+        R, it.g0, it.g1, S.base, s_ring[wave_id()],
+        [&](uint32_t q) {
+            for (uint32_t a = 0; a < k_h; a++)
+                sl[(uint64_t)a * nb + q] = kNoSlot;
+        },
+        [&](uint32_t q) {
+            window_counters<kFast, false>(F, codes, q, K, shift, [&](uint32_t a, uint32_t r,
+                                                                       uint32_t local) {
+                sl[(uint64_t)(a - 1) * nb + q] = (r << kLocalBits) | local;
+                atomicAdd(&s_hist[r], 1u);
+            });
+        });
+    if ((threadIdx.x & 63u) == 0)
+        atomicAdd(&s_valid, nv);
     __syncthreads();
     // the item's counts as one contiguous row of the set's block (kb_transpose
     // makes the block region-major)

@@ -26,18 +26,13 @@
 
 #include <cstdlib>
 
+#include "kc_bin_hash.hpp"
 #include "kc_device.hpp"
 #include "kc_kernels.hpp"
 
 namespace kc {
 
 namespace {
-
-__device__ __forceinline__ uint32_t wave_id() {
-    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-}
-
-constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // slot id of an invalid window
 
 // coarse[b * G + g] = sum of the region counts s_hist[r] over the regions r
 // of bucket b (after the histogram is complete in LDS), for n_regions
@@ -65,7 +60,6 @@ __device__ __forceinline__ void write_bucket_sums(const uint32_t *s_hist, uint32
         coarse[(uint64_t)b * G + g] = sum;
 }
 
-constexpr uint32_t kLocalBits = 14;        // kRegionCounters == 1 << kLocalBits
 // Entries of the single-level binned path take 6 bytes, a 32-bit word and a
 // 16-bit half held in two arrays (the words, then the halves, in the space
 // of the 8-byte entries):
@@ -92,53 +86,13 @@ static_assert(kMaxParts <= 256, "partition ids are bytes");
 
 }  // namespace
 
-// Slot ids of one valid window at chunk-relative position q (hash functions
-// 1..k_h), with the workgroup histogram update.  kFast: the layout has one
-// hash function, eta a power of two and dimensions of mod_small (checked
-// by the launcher), so that the loop and the layout branches go.
-template <bool kParts, bool kFast>
-__device__ __forceinline__ void bin_window(const FilterArgs &F, const BinPlan &B, uint64_t fwd,
-                                           uint32_t K, uint64_t q, uint64_t len,
-                                           uint32_t *__restrict__ slots,
-                                           uint8_t *__restrict__ parts, uint32_t *s_hist) {
-    const uint32_t shift = B.region_shift;
-    const uint64_t smask = (1ull << shift) - 1ull;
-    const Canon c = canonical_fast(fwd, K);
-    const uint32_t k_h = kFast ? 1u : F.k_h;
-    for (uint32_t a = 1; a <= k_h; a++) {
-        uint64_t word;
-        uint32_t l;
-        const uint64_t h = a == 1 ? c.h1 : hash_a(c.b0, c.b1, a);
-        if (kFast) {
-            l = (uint32_t)h & (F.eta - 1u);
-            word = (uint64_t)mod_small(h, (uint32_t)F.X, F.mX) * (uint32_t)F.Y +
-                   mod_small(h, (uint32_t)F.Y, F.mY);
-        } else {
-            slot_of(F, h, word, l);
-        }
-        const uint32_t r = (uint32_t)(word >> shift);
-        const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
-        const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
-        const uint64_t at = (uint64_t)(a - 1) * len + q;
-        slots[at] = id;
-        if (kParts) {
-            parts[at] = (uint8_t)(r >> B.part_log);
-            atomicAdd(&s_hist[r >> B.part_log], 1u);
-        } else {
-            atomicAdd(&s_hist[r], 1u);
-        }
-    }
-}
-
 // kParts: the partitioned path; the slot id holds the region within its
 // partition, parts[] the partition, and the histogram counts partitions.
-// kFast: see bin_window.
-// Each wavefront takes 64 positions at a time, their validity from the
-// valid-window bitmap (one 64-bit word), and queues the valid windows (key
-// and position) in an LDS ring of its own; it hashes 64 queued windows at a
-// time, so that no lane hashes an invalid window (the last K-1 positions of
-// every read, windows over 'N').
-template <bool kParts, bool kFast>
+// kFast: the fast layout (fast_layout); kWide: k-mers of 33..64 bases.
+// Every valid window of the workgroup's tile is hashed once (walk_windows);
+// slot ids are stored per (hash function, chunk-relative position), kNoSlot
+// for invalid windows.
+template <bool kParts, bool kFast, bool kWide>
 __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R, uint64_t c0,
                                                       uint64_t c1, BinPlan B,
                                                       uint32_t *__restrict__ slots,
@@ -146,10 +100,8 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
                                                       uint32_t *__restrict__ fine,
                                                       uint32_t *__restrict__ coarse,
                                                       unsigned long long *__restrict__ n_valid) {
-    constexpr uint32_t kRing = 128;  // queued windows per wavefront (< 64 + 64)
     extern __shared__ uint32_t s_hist[];  // n_regions region (n_parts partition) counts
-    __shared__ uint64_t s_key[kBinWG / 64][kRing];
-    __shared__ uint32_t s_pos[kBinWG / 64][kRing];
+    __shared__ uint32_t s_ring[kBinWG / 64][kWindowRing];
     __shared__ uint32_t s_valid;
     const uint32_t n_keys = kParts ? B.n_parts : B.n_regions;
     for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
@@ -157,176 +109,39 @@ __global__ void __launch_bounds__(kBinWG) k_bin_count(FilterArgs F, ReadsArgs R,
     if (threadIdx.x == 0)
         s_valid = 0;
     __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = wave_id();
     const uint64_t len = c1 - c0;
     const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
     const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
-    uint32_t nv = 0;
-    uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
     // chunk-relative 32-bit positions (a chunk is < 2^32 positions; c0 is a
     // multiple of 64, so the chunk's code words start at c0 / 16)
     const uint32_t *__restrict__ codes = R.codes + (c0 >> 4);
-    for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
-        // the wave's positions inside the tile and its valid windows (the
-        // bitmap), as wavefront-uniform masks
-        const uint64_t m_in = g1 - pb < 64u ? (1ull << (g1 - pb)) - 1ull : ~0ull;
-        const uint64_t m = wave_valid(R, pb) & m_in;
-        const uint64_t m_skip = m_in & ~m;
-        const uint32_t pos = (uint32_t)(pb - c0) + lane;
-        if ((m_skip >> lane) & 1ull)
-            for (uint32_t a = 1; a <= F.k_h; a++)
-                slots[(uint64_t)(a - 1) * len + pos] = kNoSlot;
-        if ((m >> lane) & 1ull) {
-            // the lane's three code words
-            const uint32_t w = pos >> 4;
-            const uint32_t sh = 2u * (pos & 15u);
-            const uint32_t w0 = codes[w], w1 = codes[w + 1], w2 = codes[w + 2];
-            const uint32_t top_hi = (uint32_t)(((((uint64_t)w0 << 32) | w1) << sh) >> 32);
-            const uint32_t top_lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32u - sh));
-            const uint64_t fwd = (((uint64_t)top_hi << 32) | top_lo) >> (64u - 2u * R.k);
-            nv++;
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const uint32_t at = (head + queued + rank) & (kRing - 1u);
-            s_key[wv][at] = fwd;
-            s_pos[wv][at] = pos;
-        }
-        queued += (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
-        if (queued >= 64u) {
-            const uint32_t at = (head + lane) & (kRing - 1u);
-            const uint64_t key = s_key[wv][at];
-            const uint32_t q = s_pos[wv][at];
-            __builtin_amdgcn_wave_barrier();
-            head = (head + 64u) & (kRing - 1u);
-            queued -= 64u;
-            bin_window<kParts, kFast>(F, B, key, R.k, q, len, slots, parts, s_hist);
-        }
-    }
-    if (lane < queued) {  // the last windows of the wavefront's positions
-        const uint32_t at = (head + lane) & (kRing - 1u);
-        bin_window<kParts, kFast>(F, B, s_key[wv][at], R.k, s_pos[wv][at], len, slots, parts,
-                                  s_hist);
-    }
-    atomicAdd(&s_valid, nv);
+    const uint32_t K = R.k, shift = B.region_shift, k_h = kFast ? 1u : F.k_h;
+    const uint32_t nv = walk_windows(
+        R, g0, g1, c0, s_ring[wave_id()],
+        [&](uint32_t q) {
+            for (uint32_t a = 0; a < k_h; a++)
+                slots[(uint64_t)a * len + q] = kNoSlot;
+        },
+        [&](uint32_t q) {
+            window_counters<kFast, kWide>(F, codes, q, K, shift, [&](uint32_t a, uint32_t r,
+                                                                       uint32_t local) {
+                const uint64_t at = (uint64_t)(a - 1) * len + q;
+                if (kParts) {
+                    slots[at] = ((r & ((1u << B.part_log) - 1u)) << kLocalBits) | local;
+                    parts[at] = (uint8_t)(r >> B.part_log);
+                    atomicAdd(&s_hist[r >> B.part_log], 1u);
+                } else {
+                    slots[at] = (r << kLocalBits) | local;
+                    atomicAdd(&s_hist[r], 1u);
+                }
+            });
+        });
+    if ((threadIdx.x & 63u) == 0)
+        atomicAdd(&s_valid, nv);
     __syncthreads();
     // binned path: the workgroup's region counts as one contiguous row
     // (transposed to region-major afterwards); partitioned path: partition
     // counts, few per workgroup, written partition-major directly
-    for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
-        fine[kParts ? (uint64_t)i * B.G + blockIdx.x : (uint64_t)blockIdx.x * n_keys + i] =
-            s_hist[i];
-    if (!kParts)
-        write_bucket_sums(s_hist, B.n_regions, B.n_buckets, B.bucket_shift, B.G, coarse,
-                          blockIdx.x);
-    if (threadIdx.x == 0)
-        atomicAdd(n_valid, (unsigned long long)s_valid);
-}
-
-// The same for k-mers of 33..64 bases (128-bit keys).
-template <bool kParts, bool kFast>
-__device__ __forceinline__ void bin_window_wide(const FilterArgs &F, const BinPlan &B,
-                                                Key128 fwd, uint32_t K, uint64_t q, uint64_t len,
-                                                uint32_t *__restrict__ slots,
-                                                uint8_t *__restrict__ parts, uint32_t *s_hist) {
-    const uint32_t shift = B.region_shift;
-    const uint64_t smask = (1ull << shift) - 1ull;
-    const CanonWide c = canonical_wide(fwd, K);
-    const uint32_t k_h = kFast ? 1u : F.k_h;
-    for (uint32_t a = 1; a <= k_h; a++) {
-        uint64_t word;
-        uint32_t l;
-        const uint64_t h = a == 1 ? c.h1 : hash_a_wide(c.b, a);
-        if (kFast) {
-            l = (uint32_t)h & (F.eta - 1u);
-            word = (uint64_t)mod_small(h, (uint32_t)F.X, F.mX) * (uint32_t)F.Y +
-                   mod_small(h, (uint32_t)F.Y, F.mY);
-        } else {
-            slot_of(F, h, word, l);
-        }
-        const uint32_t r = (uint32_t)(word >> shift);
-        const uint32_t rr = kParts ? (r & ((1u << B.part_log) - 1u)) : r;
-        const uint32_t id = (rr << kLocalBits) | (l << shift) | (uint32_t)(word & smask);
-        const uint64_t at = (uint64_t)(a - 1) * len + q;
-        slots[at] = id;
-        if (kParts) {
-            parts[at] = (uint8_t)(r >> B.part_log);
-            atomicAdd(&s_hist[r >> B.part_log], 1u);
-        } else {
-            atomicAdd(&s_hist[r], 1u);
-        }
-    }
-}
-
-// k_bin_count for k-mers of 33..64 bases: each lane reads its own window
-// (five code words) and the ring holds 128-bit keys; everything else is
-// k_bin_count's.
-template <bool kParts, bool kFast>
-__global__ void __launch_bounds__(kBinWG) k_bin_count_wide(FilterArgs F, ReadsArgs R, uint64_t c0,
-                                                           uint64_t c1, BinPlan B,
-                                                           uint32_t *__restrict__ slots,
-                                                           uint8_t *__restrict__ parts,
-                                                           uint32_t *__restrict__ fine,
-                                                           uint32_t *__restrict__ coarse,
-                                                           unsigned long long *__restrict__ n_valid) {
-    constexpr uint32_t kRing = 128;
-    extern __shared__ uint32_t s_hist[];
-    __shared__ uint64_t s_klo[kBinWG / 64][kRing];
-    __shared__ uint64_t s_khi[kBinWG / 64][kRing];
-    __shared__ uint32_t s_pos[kBinWG / 64][kRing];
-    __shared__ uint32_t s_valid;
-    const uint32_t n_keys = kParts ? B.n_parts : B.n_regions;
-    for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
-        s_hist[i] = 0;
-    if (threadIdx.x == 0)
-        s_valid = 0;
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = wave_id();
-    const uint64_t len = c1 - c0;
-    const uint64_t g0 = c0 + (uint64_t)blockIdx.x * B.tile;
-    const uint64_t g1 = g0 + B.tile < c1 ? g0 + B.tile : c1;
-    uint32_t nv = 0;
-    uint32_t head = 0, queued = 0;
-    const uint32_t *__restrict__ codes = R.codes + (c0 >> 4);  // as in k_bin_count
-    for (uint64_t pb = g0 + 64u * wv; pb < g1; pb += kBinWG) {
-        const uint64_t m_in = g1 - pb < 64u ? (1ull << (g1 - pb)) - 1ull : ~0ull;
-        const uint64_t m = wave_valid(R, pb) & m_in;  // the wave's valid windows
-        const uint64_t m_skip = m_in & ~m;
-        const uint32_t pos = (uint32_t)(pb - c0) + lane;
-        if ((m_skip >> lane) & 1ull)
-            for (uint32_t a = 1; a <= F.k_h; a++)
-                slots[(uint64_t)(a - 1) * len + pos] = kNoSlot;
-        if ((m >> lane) & 1ull) {
-            const Key128 fwd = window_key_wide(codes, pos, R.k);
-            nv++;
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const uint32_t at = (head + queued + rank) & (kRing - 1u);
-            s_klo[wv][at] = fwd.lo;
-            s_khi[wv][at] = fwd.hi;
-            s_pos[wv][at] = pos;
-        }
-        queued += (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
-        if (queued >= 64u) {
-            const uint32_t at = (head + lane) & (kRing - 1u);
-            const Key128 key{s_klo[wv][at], s_khi[wv][at]};
-            const uint32_t q = s_pos[wv][at];
-            __builtin_amdgcn_wave_barrier();
-            head = (head + 64u) & (kRing - 1u);
-            queued -= 64u;
-            bin_window_wide<kParts, kFast>(F, B, key, R.k, q, len, slots, parts, s_hist);
-        }
-    }
-    if (lane < queued) {
-        const uint32_t at = (head + lane) & (kRing - 1u);
-        bin_window_wide<kParts, kFast>(F, B, Key128{s_klo[wv][at], s_khi[wv][at]}, R.k,
-                                       s_pos[wv][at], len, slots, parts, s_hist);
-    }
-    atomicAdd(&s_valid, nv);
-    __syncthreads();
     for (uint32_t i = threadIdx.x; i < n_keys; i += kBinWG)
         fine[kParts ? (uint64_t)i * B.G + blockIdx.x : (uint64_t)blockIdx.x * n_keys + i] =
             s_hist[i];
@@ -1201,7 +1016,7 @@ constexpr uint32_t kWinA = 24;             // level-A digit: t >> 24 (256 bucket
 constexpr uint32_t kWinB = 19;             // level-B digit: (t >> 19) & 31 (2^19 positions)
 constexpr int kWinThreads = 1024;
 constexpr int kWinBatch = 8192;            // records per LDS batch
-constexpr uint32_t kWinRegions = 64;       // regions per level-A workgroup
+constexpr uint32_t kWinRegions = 32;       // regions per level-A workgroup
 constexpr uint32_t kWinSlices = 64;        // level-B workgroups per level-A bucket
 constexpr uint32_t kWinBuckets = 256;
 constexpr uint32_t kWinBlocksPerBucket = 1u << (kWinA - kWinB);
@@ -1492,9 +1307,13 @@ int pass_threads(const char *name, int dflt) {
     return std::atoi(e) == 1024 ? 1024 : kBinWG;
 }
 
-// The layout the hashing kernel's fast variant takes (bin_window).
-bool fast_layout(const FilterArgs &F) {
-    return F.k_h == 1 && F.eta_pow2 && F.small_dims;
+// The hashing kernel for a filter layout and k (partitioned or not).
+template <bool kParts>
+auto bin_count_kernel(const FilterArgs &F, uint32_t k) {
+    const bool fast = fast_layout(F);
+    if (k > 32)
+        return fast ? k_bin_count<kParts, true, true> : k_bin_count<kParts, false, true>;
+    return fast ? k_bin_count<kParts, true, false> : k_bin_count<kParts, false, false>;
 }
 
 // Partitioned chunk: hash + partition counts, partition lists, then the
@@ -1517,16 +1336,9 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     uint64_t *plist = W.entries;
     if (P)
         P->begin(kPhBinCount, s);
-    if (R.k > 32)
-        hipLaunchKernelGGL(
-            (fast_layout(F) ? k_bin_count_wide<true, true> : k_bin_count_wide<true, false>),
-            dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B,
-            slots, parts, W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
-    else
-        hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<true, true> : k_bin_count<true, false>),
-                           dim3(B.G), dim3(kBinWG), (size_t)B.n_parts * sizeof(uint32_t), s, F, R,
-                           c0, c1, B, slots, parts, W.pmat, nullptr,
-                           (unsigned long long *)(W.totals + 5));
+    hipLaunchKernelGGL(bin_count_kernel<true>(F, R.k), dim3(B.G), dim3(kBinWG),
+                       (size_t)B.n_parts * sizeof(uint32_t), s, F, R, c0, c1, B, slots, parts,
+                       W.pmat, nullptr, (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();
@@ -1672,15 +1484,9 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     const uint64_t n_coarse = (uint64_t)B.n_buckets * B.G;
     if (P)
         P->begin(kPhBinCount, s);
-    if (R.k > 32)
-        hipLaunchKernelGGL(
-            (fast_layout(F) ? k_bin_count_wide<false, true> : k_bin_count_wide<false, false>),
-            dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots, nullptr, W.matrix_t,
-            W.coarse, (unsigned long long *)(W.totals + 5));
-    else
-        hipLaunchKernelGGL((fast_layout(F) ? k_bin_count<false, true> : k_bin_count<false, false>),
-                           dim3(B.G), dim3(kBinWG), lds, s, F, R, c0, c1, B, W.slots, nullptr,
-                           W.matrix_t, W.coarse, (unsigned long long *)(W.totals + 5));
+    hipLaunchKernelGGL(bin_count_kernel<false>(F, R.k), dim3(B.G), dim3(kBinWG), lds, s, F, R,
+                       c0, c1, B, W.slots, nullptr, W.matrix_t, W.coarse,
+                       (unsigned long long *)(W.totals + 5));
     if (P)
         P->end(s);
     hipError_t e = hipGetLastError();

@@ -184,16 +184,28 @@ KC_HD uint32_t codes4(uint32_t x, uint32_t &valid4) {
 // Window extraction from the packed layout
 // ----------------------------------------------------------------------------
 
-// 2-bit reverse complement of a K-base key (K <= 32): complement every code
-// (x ^ 3 == ~x on 2 bits), reverse the order of the 32 2-bit groups, drop the
-// 32-K groups that came from the unused high end.  The group order is
-// reversed by a full bit reversal (one instruction per 32-bit half), which
-// also swaps the two bits inside every group; swapping them back restores
-// each code.
+// The 16 2-bit groups of x in reverse order, each code complemented.  A
+// full bit reversal (one instruction) reverses the group order but also
+// swaps the two bits inside every group; a shift each way and a bitwise
+// select swap them back, and complementing every bit complements every code
+// (c ^ 3 == ~c on 2 bits).  The select and the complement are one
+// three-input bitwise instruction on gfx950.
+KC_HD uint32_t revcomp16(uint32_t x) {
+    const uint32_t y = __builtin_bitreverse32(x);
+#if defined(__HIP_DEVICE_COMPILE__)
+    // bit i of the table is the result for (M, a, b) = bits of i (M high):
+    // ~(M ? a : b)
+    return __builtin_amdgcn_bitop3_b32(0x55555555u, y >> 1, y << 1, 0x35);
+#else
+    return ~(((y >> 1) & 0x55555555u) | ((y << 1) & 0xAAAAAAAAu));
+#endif
+}
+
+// 2-bit reverse complement of a K-base key (K <= 32): the reverse
+// complement of all 32 groups, then the 32-K groups that came from the
+// unused high end dropped.
 KC_HD uint64_t revcomp_key(uint64_t x, uint32_t K) {
-    const uint32_t lo = ~(uint32_t)x, hi = ~(uint32_t)(x >> 32);
-    uint64_t r = ((uint64_t)__builtin_bitreverse32(lo) << 32) | __builtin_bitreverse32(hi);
-    r = ((r >> 1) & 0x5555555555555555ull) | ((r & 0x5555555555555555ull) << 1);
+    const uint64_t r = ((uint64_t)revcomp16((uint32_t)x) << 32) | revcomp16((uint32_t)(x >> 32));
     return r >> (64u - 2u * K);
 }
 
@@ -408,14 +420,6 @@ struct Key128 {
     uint64_t lo, hi;
 };
 
-// The 32 2-bit groups of x in reverse order (a full bit reversal, then the
-// two bits of every group swapped back).
-KC_HD uint64_t reverse_groups(uint64_t x) {
-    uint64_t r = ((uint64_t)__builtin_bitreverse32((uint32_t)x) << 32) |
-                 __builtin_bitreverse32((uint32_t)(x >> 32));
-    return ((r >> 1) & 0x5555555555555555ull) | ((r & 0x5555555555555555ull) << 1);
-}
-
 // (hi:lo) >> sh for 0 <= sh < 64
 KC_HD Key128 shr128(uint64_t hi, uint64_t lo, uint32_t sh) {
     Key128 k;
@@ -424,10 +428,15 @@ KC_HD Key128 shr128(uint64_t hi, uint64_t lo, uint32_t sh) {
     return k;
 }
 
-// Reverse complement of a K-base key, 33 <= K <= 64: complement all 128 bits,
-// reverse the 64 groups, keep the K groups that came from the key.
+// Reverse complement of a K-base key, 33 <= K <= 64: the 64 groups reversed
+// and complemented (revcomp16 per 32-bit word, words in reverse order), the
+// K groups that came from the key kept.
 KC_HD Key128 revcomp_wide(Key128 x, uint32_t K) {
-    return shr128(reverse_groups(~x.lo), reverse_groups(~x.hi), 128u - 2u * K);
+    const uint64_t hi = ((uint64_t)revcomp16((uint32_t)x.lo) << 32) |
+                        revcomp16((uint32_t)(x.lo >> 32));
+    const uint64_t lo = ((uint64_t)revcomp16((uint32_t)x.hi) << 32) |
+                        revcomp16((uint32_t)(x.hi >> 32));
+    return shr128(hi, lo, 128u - 2u * K);
 }
 
 // Forward key of the K-base window at p (33 <= K <= 64): the 128 bits from
