@@ -98,10 +98,13 @@ def sha(t) -> str:
 
 def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
                       n_words: int, n_chunks: int = 1, partitioned: bool = False,
-                      binned: bool = True, key_bytes: int = 8, entry_bytes=None) -> float:
+                      binned: bool = True, key_bytes: int = 8, entry_bytes=None,
+                      classified=None) -> float:
     """Bytes one step's launches of `phase` must move by their definition
     (logical accesses, not cache lines), summed over the step's launches:
-    see the per-kernel table in the design notes."""
+    see the per-kernel table in the design notes.  classified: positions the
+    insert's classification covers in the position domain (None: the
+    classification of a key list)."""
     entries = n_windows * k_h
     if phase == "bin_count":         # packed input, a 4-byte slot id (+ partition byte)
         return n_bases * (0.5 + (5 if partitioned else 4) * k_h)
@@ -140,8 +143,10 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
         return n_bases * 3 / 8
     if phase == "scatter":           # flag byte + packed input, keys out (distinct + split)
         return n_bases * 1.5 + n_distinct * 2 * key_bytes
-    if phase == "classify_mark":     # key + cell per slot, mask out
-        return n_distinct * (key_bytes + 8 * k_h + 0.125)
+    if phase == "classify_mark":
+        if classified is not None:   # flag byte + packed codes per position, a cell per
+            return classified * 1.25 + n_distinct * classified / n_bases * 8 * k_h  # slot
+        return n_distinct * (key_bytes + 8 * k_h + 0.125)  # key + cell per slot, mask out
     if phase == "classify_scatter":  # key in, key out, mask
         return n_distinct * (2 * key_bytes + 0.125)
     return 0.0
@@ -261,7 +266,7 @@ def ops_per_window(k_h: int, alpha: int, k: int = 31) -> int:
 
 
 def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                n_chunks=1, partitioned=False, alpha=8, k=31, entry_bytes=None):
+                n_chunks=1, partitioned=False, alpha=8, k=31, entry_bytes=None, classified=None):
     """Roofline of the phase with the largest total time: the hashing kernel
     against the integer-VALU peak (algorithmic ops per window), the others
     against HBM (algorithmic bytes), per launch over the average launch."""
@@ -281,7 +286,7 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
                 "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": per_step}
     nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
                                partitioned, key_bytes=8 if k <= 32 else 16,
-                               entry_bytes=entry_bytes) / per_step
+                               entry_bytes=entry_bytes, classified=classified) / per_step
     achieved = nbytes / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -291,12 +296,13 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
 
 
 def hbm_rooflines(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                  n_chunks=1, partitioned=False, k=31):
+                  n_chunks=1, partitioned=False, k=31, classified=None):
     """The HBM roofline of every memory-bound phase (all but the hashing)."""
     out = {}
     for ph, (ms, launches) in phases.items():
         b = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                              partitioned, key_bytes=8 if k <= 32 else 16)
+                              partitioned, key_bytes=8 if k <= 32 else 16,
+                              classified=classified)
         if ph == "bin_count" or b <= 0:
             continue
         per_step = launches / max(1, steps)
@@ -593,8 +599,18 @@ def random_read_rate(words, n: int = 1 << 26, reps: int = 3) -> float:
     return n / best
 
 
+def classified_positions(plan, n_bases, k_h):
+    """Positions an insert's classification rereads against the final
+    countBF: with one hash function the binned paths' last region pass marks
+    the k-mers first seen in the last chunk, the earlier chunks' positions
+    are classified afterwards; otherwise every position."""
+    if plan["path"] != "direct" and k_h == 1:
+        return (plan["n_chunks"] - 1) * plan["chunk"]
+    return n_bases
+
+
 def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                  partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate):
+                  partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate, classified):
     """The whole step against two bounds.
     survey_model: the per-insertion byte model of a countBF insert (k_h
     random 64-bit read-modify-writes of 16 B, one 8 B pre-chunk counter read
@@ -603,7 +619,10 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
     design_bound: this design's own floor, each phase's algorithmic bytes at
     the copy bandwidth measured in this run, the hashing kernel's integer
     operations at the VALU peak, and the classification's random countBF
-    reads at the random-read rate measured over the countBF in this run."""
+    reads at the random-read rate measured over the countBF in this run (for
+    the classified share of the positions: distinct k-mers counted as spread
+    evenly over the positions, which front-loaded first occurrences make an
+    underestimate of the bound)."""
     secs = ms_per_step / 1e3
     f_new = n_distinct / max(1, n_windows)
     b_ins = 16 * k_h + 8 + 16 * f_new + n_bases / max(1, n_windows) + 0.125
@@ -614,7 +633,8 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
         if ph == "bin_count":
             t = n_windows * ops_per_window(k_h, alpha, k) / (ALU_PEAK_GOPS * 1e9)
         elif ph == "classify_mark":
-            t = n_distinct * k_h / rand_rate + n_distinct * (kb + 0.125) / copy_Bps
+            share = classified / max(1, n_bases)
+            t = share * n_distinct * k_h / rand_rate + classified * 1.25 / copy_Bps
         else:
             t = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
                                   partitioned, key_bytes=kb) / copy_Bps
@@ -734,10 +754,11 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
     ms_step = elapsed * 1e3 / steps
     partitioned = plan["path"] == "partitioned"
     n_chunks = plan["n_chunks"]
+    classified = classified_positions(plan, n_bases, k_h)
     per_phase = {p: {"avg_ms": v[0] / v[1], "launches": v[1]} for p, v in phases.items()}
     per_phase[dom]["timed_avg_ms"] = timed[dom][0] / timed[dom][1]
     roofline = roofline_of(timed, steps, n_bases, n_windows, n_distinct, k_h, X * Y, workload,
-                           n_chunks, partitioned, alpha, k)
+                           n_chunks, partitioned, alpha, k, classified=classified)
     copy_Bps = copy_bandwidth(dev)
     rand = random_read_rate(words)
     out = {
@@ -754,9 +775,10 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
         "roofline": roofline,
         "step_roofline": step_roofline(phases_per_step(phases, profile_steps), 1, n_bases,
                                        n_windows, n_distinct, k_h, X * Y, n_chunks, partitioned,
-                                       alpha, k, ms_step, copy_Bps, rand),
+                                       alpha, k, ms_step, copy_Bps, rand, classified),
         "hbm_rooflines": hbm_rooflines(phases, profile_steps, n_bases, n_windows, n_distinct,
-                                       k_h, X * Y, workload, n_chunks, partitioned, k),
+                                       k_h, X * Y, workload, n_chunks, partitioned, k,
+                                       classified),
         "input_generation_s": round(t_gen, 1),
     }
     if extras:

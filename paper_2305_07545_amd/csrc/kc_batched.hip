@@ -179,7 +179,6 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
     __shared__ uint64_t s_stage[kWriteStage];
     __shared__ uint32_t s_cnt[kBatchMaxRegions];
     __shared__ uint16_t s_start[kBatchMaxRegions];  // < kWriteStage
-    __shared__ uint32_t s_fill[kBatchMaxRegions];
     __shared__ uint32_t s_cursor[kBatchMaxRegions];
     __shared__ uint32_t s_wave[kBinWG / 64];
     __shared__ uint32_t s_total;
@@ -190,7 +189,6 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
     for (uint32_t r = threadIdx.x; r < kBatchMaxRegions; r += kBinWG) {
         s_cursor[r] = r < nr ? offsets[S.mat_base + (uint64_t)r * S.G + it.j] : 0u;
         s_cnt[r] = 0;
-        s_fill[r] = 0;
     }
     __syncthreads();
     uint32_t bl = 0;
@@ -237,10 +235,11 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
                 id[u] = (a < k_h && qq < nq) ? sl[a * nb + q0 + qq] : kNoSlot;
             }
         }
+        uint32_t rk[kPer];  // entry u's rank among its region's in the batch
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot)
-                atomicAdd(&s_cnt[id[u] >> kLocalBits], 1u);
+                rk[u] = atomicAdd(&s_cnt[id[u] >> kLocalBits], 1u);
         __syncthreads();
         {  // exclusive scan of the region counts: kScanPer per thread
             uint32_t v[kScanPer];
@@ -277,7 +276,7 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
                 const uint32_t i = pos_of(vec, u);
                 const uint32_t q = q0 + (i & (batch - 1u));
                 const uint32_t r = id[u] >> kLocalBits;
-                const uint32_t j = s_start[r] + atomicAdd(&s_fill[r], 1u);
+                const uint32_t j = s_start[r] + rk[u];
                 s_stage[j] = ((uint64_t)q << 32) | id[u];
             }
         __syncthreads();
@@ -293,7 +292,6 @@ __global__ void __launch_bounds__(kBinWG) kb_bin_write(const SetDesc *__restrict
         for (uint32_t r = threadIdx.x; r < kBatchMaxRegions; r += kBinWG) {
             s_cursor[r] += s_cnt[r];
             s_cnt[r] = 0;
-            s_fill[r] = 0;
         }
         __syncthreads();
     }

@@ -179,7 +179,6 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
     __shared__ uint64_t s_stage[kStage1];
     __shared__ uint32_t s_cnt[kMaxBuckets];
     __shared__ uint32_t s_start[kMaxBuckets];
-    __shared__ uint32_t s_fill[kMaxBuckets];
     __shared__ uint32_t s_cursor[kMaxBuckets];
     const uint32_t bshift = B.bucket_shift + kLocalBits;
     const uint32_t len = (uint32_t)(c1 - c0);
@@ -196,7 +195,6 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
     for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
         s_cursor[i] = i < B.n_buckets ? coarse_off[(uint64_t)i * B.G + blockIdx.x] : 0u;
         s_cnt[i] = 0;
-        s_fill[i] = 0;
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
@@ -245,10 +243,11 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
             id[u] = next[u];
         if (q0 + batch < g1)
             load(q0 + batch, next);
+        uint32_t rk[kPer];  // entry u's rank among its destination's in the batch
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (id[u] != kNoSlot)
-                atomicAdd(&s_cnt[id[u] >> bshift], 1u);
+                rk[u] = atomicAdd(&s_cnt[id[u] >> bshift], 1u);
         __syncthreads();
         if (threadIdx.x < 64) {  // one wavefront scans the 64 bucket counts
             uint32_t v = s_cnt[lane];
@@ -267,7 +266,7 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
                 const uint32_t i = pos_of(vec, u);
                 const uint32_t q = q0 - s0 + (i & (batch - 1u));  // ts: within the slice
                 const uint32_t b = id[u] >> bshift;
-                const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
+                const uint32_t j = s_start[b] + rk[u];
                 s_stage[j] = ((uint64_t)q << 32) | id[u];
             }
         __syncthreads();
@@ -286,7 +285,6 @@ __global__ void __launch_bounds__(kBinWG) k_bin_bucket(uint64_t c0, uint64_t c1,
         for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kBinWG) {
             s_cursor[i] += s_cnt[i];
             s_cnt[i] = 0;
-            s_fill[i] = 0;
         }
         __syncthreads();
     }
@@ -709,7 +707,6 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
     __shared__ uint64_t s_stage[kBatch];
     __shared__ uint32_t s_cnt[kMaxBuckets];
     __shared__ uint32_t s_start[kMaxBuckets];
-    __shared__ uint32_t s_fill[kMaxBuckets];
     __shared__ uint32_t s_cursor[kMaxBuckets];
     const uint32_t p = blockIdx.x / B.list_g, g = blockIdx.x % B.list_g;
     const uint32_t per = 1u << B.part_log;
@@ -721,7 +718,6 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
     for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kThreads) {
         s_cursor[i] = i < nbp ? coarse_off[((uint64_t)p * nbp + i) * B.list_g + g] : 0u;
         s_cnt[i] = 0;
-        s_fill[i] = 0;
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
@@ -743,10 +739,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
             v[u] = nv[u];
         if (q0 + kBatch < t.n)
             load(q0 + kBatch, nv);
+        uint32_t rk[kPer];  // entry u's rank among its destination's in the batch
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             if (v[u] != ~0ull)
-                atomicAdd(&s_cnt[((uint32_t)v[u] >> bshift) & (kMaxBuckets - 1u)], 1u);
+                rk[u] = atomicAdd(&s_cnt[((uint32_t)v[u] >> bshift) & (kMaxBuckets - 1u)], 1u);
         __syncthreads();
         if (threadIdx.x < 64) {
             uint32_t c = s_cnt[lane];
@@ -763,7 +760,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
         for (int u = 0; u < kPer; u++)
             if (v[u] != ~0ull) {
                 const uint32_t b = ((uint32_t)v[u] >> bshift) & (kMaxBuckets - 1u);
-                const uint32_t j = s_start[b] + atomicAdd(&s_fill[b], 1u);
+                const uint32_t j = s_start[b] + rk[u];
                 s_stage[j] = v[u];
             }
         __syncthreads();
@@ -779,7 +776,6 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
         for (uint32_t i = threadIdx.x; i < kMaxBuckets; i += kThreads) {
             s_cursor[i] += s_cnt[i];
             s_cnt[i] = 0;
-            s_fill[i] = 0;
         }
         __syncthreads();
     }
@@ -834,8 +830,11 @@ __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &
 
 // Region lists of 6-byte entries (both binned paths).  kCounters: the LDS
 // arrays' size, the plan's counters per region (16384: 144 KiB of LDS, one
-// workgroup per CU; 8192: 72 KiB, two per CU, so that one workgroup's loads
-// overlap the other's LDS work).
+// workgroup per CU; 8192: 72 KiB, two per CU).  The grid is persistent:
+// workgroup g takes regions g, g + gridDim.x, ...; the next region's bounds,
+// first batch of entries and cells are requested before the current one is
+// worked on, so that their latency overlaps its LDS work (a workgroup that
+// holds the CU's LDS alone has nobody else to hide it).
 template <int kCounters>
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
@@ -853,24 +852,19 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     __shared__ uint32_t first[kCounters];
     __shared__ unsigned long long s_cell[kSparseCells];
     __shared__ uint32_t s_nwin;
-    const uint32_t r = blockIdx.x;
     const uint32_t S = 1u << B.region_shift;
     const uint32_t n_ctr = S * F.eta;
-    const uint64_t e0 = offsets[(uint64_t)r * B.G];
-    uint64_t e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
-    if (e1 > B.entries_cap)
-        e1 = B.entries_cap;
-    const uint64_t wbase = (uint64_t)(B.region0 + r) << B.region_shift;
     const uint64_t n_words = F.X * F.Y;
-    const uint32_t nw = wbase + S <= n_words ? S : (uint32_t)(n_words - wbase);
     uint32_t *e_word = (uint32_t *)entries;
     uint16_t *e_half = (uint16_t *)(e_word + B.entries_cap);
-    if (threadIdx.x == 0)
-        s_nwin = 0;
-    const WinnerSink out{flags, c0, n_win ? e_word : nullptr, e_half, e0, &s_nwin};
-    // entry x as loaded (hi = ~0u past the end); decoded where it is used,
-    // so that prefetched loads stay in flight until then
-    auto fetch = [&](uint64_t x) -> RawEntry {
+    // a region's work: entries [e0, e1), cells [wbase, wbase + nw)
+    struct Region {
+        uint64_t e0, e1, wbase;
+        uint32_t nw;
+    };
+    // entry x of a region as loaded (hi = ~0u past its end); decoded where
+    // it is used, so that prefetched loads stay in flight until then
+    auto fetch = [&](uint64_t x, uint64_t e1) -> RawEntry {
         RawEntry e{~0u, ~0u};
         if (x < e1) {
             e.lo = e_word[x];
@@ -881,125 +875,173 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     auto t_of = [](RawEntry e) -> uint32_t {
         return (e.lo >> kLocalBits) | (e.hi << (32 - kLocalBits));
     };
-    // the first entries and the region's cells are requested before the LDS
-    // clear, so that their latency overlaps it (this workgroup alone writes
-    // these cells)
-    RawEntry v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; u++)
-        v[u] = fetch(e0 + threadIdx.x + (uint64_t)u * kRegionWG);
-    const bool hold = nw <= (uint32_t)kHold * kRegionWG;
-    uint64_t cell[kHold];
-#pragma unroll
-    for (int k = 0; k < kHold; k++) {
-        const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-        cell[k] = (hold && w < nw) ? F.words[wbase + w] : 0ull;
-    }
-    if (e1 - e0 <= (uint64_t)kUnroll * kRegionWG && nw <= kSparseCells) {
-        // Sparse region: every entry is in the register batch.  Only the
-        // counters the entries touch are cleared, and counters are updated
-        // per entry, not by a pass over all of them: the entry whose t is
-        // the counter's minimum applies min(2^alpha - 1, old + hits) to the
-        // staged cell (a 64-bit LDS add of the field's increase, which
-        // cannot carry into the next field) and flags its occurrence when
-        // the counter was zero.  atomicCAS(first, t, kDone) succeeds for
-        // exactly one entry holding the minimum (with k_h > 1 one window
-        // can put two entries on one counter).
+    auto hold_of = [&](const Region &R) { return R.nw <= (uint32_t)kHold * kRegionWG; };
+    // region r's bounds, first batch of entries and (when held) cells
+    auto request = [&](uint32_t r, Region &R, RawEntry(&v)[kUnroll], uint64_t(&cell)[kHold]) {
+        R.e0 = offsets[(uint64_t)r * B.G];
+        R.e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
+        if (R.e1 > B.entries_cap)
+            R.e1 = B.entries_cap;
+        R.wbase = (uint64_t)(B.region0 + r) << B.region_shift;
+        R.nw = R.wbase + S <= n_words ? S : (uint32_t)(n_words - R.wbase);
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
-            if (v[u].hi != ~0u) {
-                const uint32_t local = v[u].lo & (kRegionCounters - 1);
-                hits[local] = 0;
-                first[local] = kIdle;
-            }
+            v[u] = fetch(R.e0 + threadIdx.x + (uint64_t)u * kRegionWG, R.e1);
+        const bool hold = hold_of(R);
 #pragma unroll
         for (int k = 0; k < kHold; k++) {
             const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-            if (w < nw)
-                s_cell[w] = cell[k];
+            cell[k] = (hold && w < R.nw) ? F.words[R.wbase + w] : 0ull;
         }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++)
-            if (v[u].hi != ~0u) {
-                const uint32_t local = v[u].lo & (kRegionCounters - 1);
-                atomicAdd(&hits[local], 1u);
-                atomicMin(&first[local], t_of(v[u]));
-            }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++)
-            if (v[u].hi != ~0u) {
-                const uint32_t local = v[u].lo & (kRegionCounters - 1);
-                const uint32_t t = t_of(v[u]);
-                if (atomicCAS(&first[local], t, kDone) != t)
-                    continue;
-                const uint32_t w = local & (S - 1u);
-                const uint32_t sh = F.alpha * (local >> B.region_shift);
-                const uint64_t pf = (s_cell[w] >> sh) & F.field_max;
-                const uint64_t h = hits[local];
-                const uint64_t room = F.field_max - pf;
-                const uint64_t nf = pf + (h < room ? h : room);
-                if (nf != pf)
-                    atomicAdd(&s_cell[w], (unsigned long long)((nf - pf) << sh));
-                if (pf == 0)
-                    put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u);
-            }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kHold; k++) {
-            const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-            if (w < nw && s_cell[w] != cell[k])
-                F.words[wbase + w] = s_cell[w];
-        }
-        if (n_win && threadIdx.x == 0)
-            n_win[r] = s_nwin;  // its own atomics are done (the barrier above)
+    };
+    uint32_t r = blockIdx.x;
+    if (r >= B.n_regions)
         return;
-    }
-    for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
-        hits[i] = 0;
-        first[i] = kIdle;
-    }
-    __syncthreads();
-    for (uint64_t e = e0 + threadIdx.x;;) {
-        // the next entries are requested before this batch's LDS atomics
-        const uint64_t en = e + (uint64_t)kUnroll * kRegionWG;
-        RawEntry w[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++)
-            w[u] = fetch(en + (uint64_t)u * kRegionWG);
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-            if (v[u].hi == ~0u)
-                continue;
-            const uint32_t local = v[u].lo & (kRegionCounters - 1);
-            atomicAdd(&hits[local], 1u);
-            atomicMin(&first[local], t_of(v[u]));
-        }
-        if (en >= e1)
-            break;
-        e = en;
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++)
-            v[u] = w[u];
-    }
-    __syncthreads();
-    if (hold) {
-#pragma unroll
-        for (int k = 0; k < kHold; k++) {
-            const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-            if (w < nw)
-                region_cell(F, B, wbase, w, cell[k], hits, first, out, classify, tau);
-        }
-    } else {
-        for (uint32_t w = threadIdx.x; w < nw; w += kRegionWG)
-            region_cell(F, B, wbase, w, F.words[wbase + w], hits, first, out, classify, tau);
-    }
-    if (n_win) {
-        __syncthreads();
+    Region R;
+    RawEntry v[kUnroll];
+    uint64_t cell[kHold];
+    request(r, R, v, cell);
+    for (;;) {
+        const uint32_t rn = r + gridDim.x;
+        Region Rn{};
+        RawEntry vn[kUnroll];
+        uint64_t celln[kHold];
+        if (rn < B.n_regions)
+            request(rn, Rn, vn, celln);
         if (threadIdx.x == 0)
+            s_nwin = 0;
+        const WinnerSink out{flags, c0, n_win ? e_word : nullptr, e_half, R.e0, &s_nwin};
+        if (R.e1 - R.e0 <= (uint64_t)kUnroll * kRegionWG && R.nw <= kSparseCells) {
+            // Sparse region: every entry is in the register batch.  Only the
+            // counters the entries touch are cleared, and counters are
+            // updated per entry, not by a pass over all of them: the entry
+            // whose t is the counter's minimum applies min(2^alpha - 1, old +
+            // hits) to the staged cell (a 64-bit LDS add of the field's
+            // increase, which cannot carry into the next field) and flags its
+            // occurrence when the counter was zero.  atomicCAS(first, t,
+            // kDone) succeeds for exactly one entry holding the minimum (with
+            // k_h > 1 one window can put two entries on one counter).
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++)
+                if (v[u].hi != ~0u) {
+                    const uint32_t local = v[u].lo & (kRegionCounters - 1);
+                    hits[local] = 0;
+                    first[local] = kIdle;
+                }
+#pragma unroll
+            for (int k = 0; k < kHold; k++) {
+                const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+                if (w < R.nw)
+                    s_cell[w] = cell[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++)
+                if (v[u].hi != ~0u) {
+                    const uint32_t local = v[u].lo & (kRegionCounters - 1);
+                    atomicAdd(&hits[local], 1u);
+                    atomicMin(&first[local], t_of(v[u]));
+                }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++)
+                if (v[u].hi != ~0u) {
+                    const uint32_t local = v[u].lo & (kRegionCounters - 1);
+                    const uint32_t t = t_of(v[u]);
+                    if (atomicCAS(&first[local], t, kDone) != t)
+                        continue;
+                    const uint32_t w = local & (S - 1u);
+                    const uint32_t sh = F.alpha * (local >> B.region_shift);
+                    const uint64_t pf = (s_cell[w] >> sh) & F.field_max;
+                    const uint64_t h = hits[local];
+                    const uint64_t room = F.field_max - pf;
+                    const uint64_t nf = pf + (h < room ? h : room);
+                    if (nf != pf)
+                        atomicAdd(&s_cell[w], (unsigned long long)((nf - pf) << sh));
+                    if (pf == 0)
+                        put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u);
+                }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kHold; k++) {
+                const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+                if (w < R.nw && s_cell[w] != cell[k])
+                    F.words[R.wbase + w] = s_cell[w];
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
+                hits[i] = 0;
+                first[i] = kIdle;
+            }
+            __syncthreads();
+            for (uint64_t e = R.e0 + threadIdx.x;;) {
+                // the next entries are requested before this batch's LDS atomics
+                const uint64_t en = e + (uint64_t)kUnroll * kRegionWG;
+                RawEntry w[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++)
+                    w[u] = fetch(en + (uint64_t)u * kRegionWG, R.e1);
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    if (v[u].hi == ~0u)
+                        continue;
+                    const uint32_t local = v[u].lo & (kRegionCounters - 1);
+                    atomicAdd(&hits[local], 1u);
+                    atomicMin(&first[local], t_of(v[u]));
+                }
+                if (en >= R.e1)
+                    break;
+                e = en;
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++)
+                    v[u] = w[u];
+            }
+            __syncthreads();
+            if (hold_of(R)) {
+#pragma unroll
+                for (int k = 0; k < kHold; k++) {
+                    const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
+                    if (w < R.nw)
+                        region_cell(F, B, R.wbase, w, cell[k], hits, first, out, classify, tau);
+                }
+            } else {
+                for (uint32_t w = threadIdx.x; w < R.nw; w += kRegionWG)
+                    region_cell(F, B, R.wbase, w, F.words[R.wbase + w], hits, first, out,
+                                classify, tau);
+            }
+        }
+        __syncthreads();  // the region's LDS work and its winner count are complete
+        if (n_win && threadIdx.x == 0)
             n_win[r] = s_nwin;
+        if (rn >= B.n_regions)
+            break;
+        r = rn;
+        R = Rn;
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            v[u] = vn[u];
+#pragma unroll
+        for (int k = 0; k < kHold; k++)
+            cell[k] = celln[k];
     }
+}
+
+// Workgroups of the persistent region pass: as many as the CUs hold at once
+// (one per CU with the 144 KiB arrays, two with the 72 KiB ones), at most one
+// per region.
+uint32_t region_grid(uint32_t n_regions, uint32_t counters) {
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+            n_cu = v;
+        else
+            n_cu = 256;
+    }
+    const uint32_t g = (uint32_t)n_cu * (counters == (uint32_t)kSmallRegionCounters ? 2u : 1u);
+    return n_regions < g ? n_regions : g;
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,7 +1058,7 @@ constexpr uint32_t kWinA = 24;             // level-A digit: t >> 24 (256 bucket
 constexpr uint32_t kWinB = 19;             // level-B digit: (t >> 19) & 31 (2^19 positions)
 constexpr int kWinThreads = 1024;
 constexpr int kWinBatch = 8192;            // records per LDS batch
-constexpr uint32_t kWinRegions = 32;       // regions per level-A workgroup
+constexpr uint32_t kWinRegions = 64;       // regions per level-A workgroup
 constexpr uint32_t kWinSlices = 64;        // level-B workgroups per level-A bucket
 constexpr uint32_t kWinBuckets = 256;
 constexpr uint32_t kWinBlocksPerBucket = 1u << (kWinA - kWinB);
@@ -1053,44 +1095,58 @@ __device__ void win_flush(const Rec *s_rec, uint32_t n, uint32_t shift, uint32_t
 
 // Level A: the records of regions [kWinRegions * blockIdx.x, ...) (region r's
 // n_win[r] records start at its first entry) -> bucket t >> 24, record
-// (t & (2^24 - 1)) | mark << 24.
+// (t & (2^24 - 1)) | mark << 24.  The regions' record counts are scanned in
+// LDS first, so that the workgroup's records are one index range whose
+// batches are filled by all threads at once (record i is found in its
+// region by a binary search of the scan), not region after region.
 __global__ void __launch_bounds__(kWinThreads) k_win_a(BinPlan B, const uint32_t *__restrict__ offsets,
                                                        const uint32_t *__restrict__ n_win,
                                                        const uint64_t *__restrict__ entries,
                                                        uint32_t *__restrict__ cursor,
                                                        uint32_t *__restrict__ out) {
+    static_assert(kWinRegions == 64, "one wavefront scans the regions' counts");
     __shared__ uint64_t s_rec[kWinBatch];
     __shared__ uint32_t s_cnt[kWinBuckets], s_base[kWinBuckets];
+    __shared__ uint32_t s_first[kWinRegions];    // each region's first entry
+    __shared__ uint32_t s_pre[kWinRegions + 1];  // records before each region
     const uint32_t *e_word = (const uint32_t *)entries;
     const uint16_t *e_half = (const uint16_t *)(e_word + B.entries_cap);
     const uint32_t r0 = blockIdx.x * kWinRegions;
-    const uint32_t r1 = r0 + kWinRegions < B.n_regions ? r0 + kWinRegions : B.n_regions;
+    const uint32_t nr = r0 + kWinRegions < B.n_regions ? kWinRegions : B.n_regions - r0;
+    if (threadIdx.x < 64) {
+        const uint32_t i = threadIdx.x;
+        const uint32_t n = i < nr ? n_win[r0 + i] : 0u;
+        s_first[i] = i < nr ? offsets[(uint64_t)(r0 + i) * B.G] : 0u;
+        uint32_t incl = n;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (i >= d)
+                incl += o;
+        }
+        s_pre[i + 1] = incl;
+        if (i == 0)
+            s_pre[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t total = s_pre[kWinRegions];
     auto keep = [](uint64_t r) -> uint32_t {
         return ((uint32_t)r & ((1u << kWinA) - 1u)) | ((uint32_t)(r >> 32) << kWinA);
     };
-    uint32_t fill = 0;  // the same in every thread
-    for (uint32_t r = r0; r < r1; r++) {
-        const uint64_t base = offsets[(uint64_t)r * B.G];
-        const uint32_t n = n_win[r];
-        for (uint32_t done = 0; done < n;) {
-            const uint32_t take = n - done < kWinBatch - fill ? n - done : kWinBatch - fill;
-            for (uint32_t i = threadIdx.x; i < take; i += kWinThreads) {
-                const uint64_t x = base + done + i;
-                s_rec[fill + i] = ((uint64_t)e_half[x] << 32) | e_word[x];
-            }
-            fill += take;
-            done += take;
-            if (fill == kWinBatch) {
-                __syncthreads();
-                win_flush(s_rec, fill, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_base, cursor, out,
-                          keep);
-                fill = 0;
-            }
+    for (uint32_t q = 0; q < total; q += kWinBatch) {
+        const uint32_t m = total - q < (uint32_t)kWinBatch ? total - q : (uint32_t)kWinBatch;
+        for (uint32_t i = threadIdx.x; i < m; i += kWinThreads) {
+            const uint32_t idx = q + i;
+            uint32_t j = 0;  // the last region with s_pre[j] <= idx
+#pragma unroll
+            for (uint32_t step = kWinRegions / 2; step; step >>= 1)
+                if (s_pre[j + step] <= idx)
+                    j += step;
+            const uint64_t x = (uint64_t)s_first[j] + (idx - s_pre[j]);
+            s_rec[i] = ((uint64_t)e_half[x] << 32) | e_word[x];
         }
+        __syncthreads();
+        win_flush(s_rec, m, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_base, cursor, out, keep);
     }
-    __syncthreads();
-    if (fill)
-        win_flush(s_rec, fill, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_base, cursor, out, keep);
 }
 
 // Level B: slice blockIdx.y of level-A bucket a = blockIdx.x -> block
@@ -1446,7 +1502,8 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         hipLaunchKernelGGL((Q.region_counters == kSmallRegionCounters
                                 ? k_region<kSmallRegionCounters>
                                 : k_region<kRegionCounters>),
-                           dim3(Q.n_regions), dim3(kRegionWG), 0, s, F, c0, Q,
+                           dim3(region_grid(Q.n_regions, Q.region_counters)), dim3(kRegionWG),
+                           0, s, F, c0, Q,
                            (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
                            W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr);
         if (P)
@@ -1529,7 +1586,8 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     hipLaunchKernelGGL((B.region_counters == kSmallRegionCounters
                             ? k_region<kSmallRegionCounters>
                             : k_region<kRegionCounters>),
-                       dim3(B.n_regions), dim3(kRegionWG), 0, s, F, c0, B,
+                       dim3(region_grid(B.n_regions, B.region_counters)), dim3(kRegionWG), 0,
+                       s, F, c0, B,
                        (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
                        W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr);
     if (P)

@@ -420,7 +420,9 @@ __device__ __forceinline__ uint64_t query_canon_wide(const FilterArgs &F, const 
 // distinct list by the marks.  One wavefront per tile of 1024 flag bytes
 // (16 per lane): the flagged positions are listed in LDS, then each lane
 // takes one, rebuilds its canonical k-mer from the packed codes and reads
-// its k_h counters.
+// its k_h counters.  The marks go into an LDS copy of the tile, and a lane
+// whose 16 bytes changed writes them back as one 16-byte store (no single-
+// byte stores at scattered positions).
 template <bool kWide>
 __global__ void __launch_bounds__(kWG) k_classify_flags(FilterArgs F, ReadsArgs R,
                                                         uint8_t *__restrict__ flags,
@@ -428,12 +430,14 @@ __global__ void __launch_bounds__(kWG) k_classify_flags(FilterArgs F, ReadsArgs 
     static_assert(kTile == 64 * 16, "16 flag bytes per lane and tile");
     __shared__ uint16_t s_pos[kWG / 64][kTile];
     __shared__ uint16_t s_tb[kWG / 64][kTile];  // list_flags' second list (unused here)
+    __shared__ uint4 s_tile[kWG / 64][64];      // the tile's flag bytes, marked
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t n_waves = (uint64_t)gridDim.x * (kWG / 64);
-    const uint4 *f128 = reinterpret_cast<const uint4 *>(flags);
+    uint4 *f128 = reinterpret_cast<uint4 *>(flags);
     uint16_t *lpos = s_pos[wave];
     uint16_t *ltb = s_tb[wave];
+    uint8_t *lmark = reinterpret_cast<uint8_t *>(s_tile[wave]);
     for (uint64_t tile = (uint64_t)blockIdx.x * (kWG / 64) + wave; tile < n_tiles;
          tile += n_waves) {
         const uint4 x4 = f128[tile * 64 + lane];
@@ -447,17 +451,23 @@ __global__ void __launch_bounds__(kWG) k_classify_flags(FilterArgs F, ReadsArgs 
         if (tot_d == 0)
             continue;
         list_flags(x, lane, rd, 0, lpos, ltb);
+        s_tile[wave][lane] = x4;
         __builtin_amdgcn_wave_barrier();
         const uint64_t pos0 = tile * kTile;
         for (uint32_t i = lane; i < tot_d; i += 64) {
-            const uint64_t p = pos0 + lpos[i];
+            const uint32_t q = lpos[i];
+            const uint64_t p = pos0 + q;
             const uint64_t f =
                 kWide ? query_canon_wide(F, canonical_wide(window_key_wide(R.codes, p, R.k), R.k))
                       : query_canon(F, canonical_fast(window_key(R.codes, p, R.k), R.k));
             if (f > (uint64_t)tau)
-                flags[p] = 3;
+                lmark[q] = 3;
         }
-        __builtin_amdgcn_wave_barrier();  // the list is rewritten by the next tile
+        __builtin_amdgcn_wave_barrier();
+        const uint4 y4 = s_tile[wave][lane];
+        if (y4.x != x4.x || y4.y != x4.y || y4.z != x4.z || y4.w != x4.w)
+            f128[tile * 64 + lane] = y4;
+        __builtin_amdgcn_wave_barrier();  // the list and the tile are rewritten by the next tile
     }
 }
 
