@@ -99,7 +99,7 @@ def sha(t) -> str:
 def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int, k_h: int,
                       n_words: int, n_chunks: int = 1, partitioned: bool = False,
                       binned: bool = True, key_bytes: int = 8, entry_bytes=None,
-                      classified=None) -> float:
+                      classified=None, carried=0) -> float:
     """Bytes one step's launches of `phase` must move by their definition
     (logical accesses, not cache lines), summed over the step's launches:
     see the per-kernel table in the design notes.  classified: positions the
@@ -121,7 +121,10 @@ def algorithmic_bytes(phase: str, n_bases: int, n_windows: int, n_distinct: int,
     if phase == "bin_region":        # bucket-list entries in, region-list entries out
         return entries * (8 + ent) if partitioned else entries * 2 * ent
     if phase == "region":            # entries in, countBF cells read + written per chunk, flags
-        return entries * ent + n_chunks * n_words * 16 + n_distinct
+        b = entries * ent + n_chunks * n_words * 16 + n_distinct
+        if carried:                  # carried records: 6 B written, then 2 B read + 2 B marked
+            b += n_distinct * carried / n_bases * 10
+        return b
     if phase == "tile_count":        # flag byte per position (+ packed input when the
         return n_bases * (1.0 if binned else 1.5)  # insert passes did not count windows)
     if phase == "claim_increment":   # cell RMW + first-seen entry RMW per slot, packed input
@@ -171,7 +174,7 @@ def traffic_for(phase: str, workload: str):
 
 # the sources that define the kernels (host-only API code does not change
 # what a kernel moves)
-KERNEL_SOURCES = ["kc_batched.hip", "kc_batched.hpp", "kc_binned.hip", "kc_device.hpp",
+KERNEL_SOURCES = ["kc_batched.hip", "kc_batched.hpp", "kc_bin_hash.hpp", "kc_binned.hip", "kc_device.hpp",
                   "kc_kernels.hip", "kc_kernels.hpp", "kc_scan.hip"]
 
 
@@ -266,7 +269,8 @@ def ops_per_window(k_h: int, alpha: int, k: int = 31) -> int:
 
 
 def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                n_chunks=1, partitioned=False, alpha=8, k=31, entry_bytes=None, classified=None):
+                n_chunks=1, partitioned=False, alpha=8, k=31, entry_bytes=None, classified=None,
+                carried=0):
     """Roofline of the phase with the largest total time: the hashing kernel
     against the integer-VALU peak (algorithmic ops per window), the others
     against HBM (algorithmic bytes), per launch over the average launch."""
@@ -286,7 +290,8 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
                 "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": per_step}
     nbytes = algorithmic_bytes(dom, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
                                partitioned, key_bytes=8 if k <= 32 else 16,
-                               entry_bytes=entry_bytes, classified=classified) / per_step
+                               entry_bytes=entry_bytes, classified=classified,
+                               carried=carried) / per_step
     achieved = nbytes / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -296,13 +301,13 @@ def roofline_of(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, wor
 
 
 def hbm_rooflines(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, workload,
-                  n_chunks=1, partitioned=False, k=31, classified=None):
+                  n_chunks=1, partitioned=False, k=31, classified=None, carried=0):
     """The HBM roofline of every memory-bound phase (all but the hashing)."""
     out = {}
     for ph, (ms, launches) in phases.items():
         b = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
                               partitioned, key_bytes=8 if k <= 32 else 16,
-                              classified=classified)
+                              classified=classified, carried=carried)
         if ph == "bin_count" or b <= 0:
             continue
         per_step = launches / max(1, steps)
@@ -602,15 +607,24 @@ def random_read_rate(words, n: int = 1 << 26, reps: int = 3) -> float:
 def classified_positions(plan, n_bases, k_h):
     """Positions an insert's classification rereads against the final
     countBF: with one hash function the binned paths' last region pass marks
-    the k-mers first seen in the last chunk, the earlier chunks' positions
-    are classified afterwards; otherwise every position."""
+    the k-mers first seen in the last chunk, and with the carried
+    classification those of the earlier chunks too (none are reread);
+    otherwise the earlier chunks' positions are classified afterwards, and
+    every position with several hash functions or on the direct path."""
     if plan["path"] != "direct" and k_h == 1:
-        return (plan["n_chunks"] - 1) * plan["chunk"]
+        return 0 if plan.get("carried") else (plan["n_chunks"] - 1) * plan["chunk"]
     return n_bases
 
 
+def carried_positions(plan):
+    """Positions whose first-seen records the carried classification keeps
+    (the chunks before the last)."""
+    return (plan["n_chunks"] - 1) * plan["chunk"] if plan.get("carried") else 0
+
+
 def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                  partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate, classified):
+                  partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate, classified,
+                  carried=0):
     """The whole step against two bounds.
     survey_model: the per-insertion byte model of a countBF insert (k_h
     random 64-bit read-modify-writes of 16 B, one 8 B pre-chunk counter read
@@ -637,7 +651,7 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
             t = share * n_distinct * k_h / rand_rate + classified * 1.25 / copy_Bps
         else:
             t = algorithmic_bytes(ph, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
-                                  partitioned, key_bytes=kb) / copy_Bps
+                                  partitioned, key_bytes=kb, carried=carried) / copy_Bps
         per_phase[ph] = round(t * 1e3, 3)
     bound_ms = sum(per_phase.values())
     return {
@@ -755,10 +769,12 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
     partitioned = plan["path"] == "partitioned"
     n_chunks = plan["n_chunks"]
     classified = classified_positions(plan, n_bases, k_h)
+    carried = carried_positions(plan)
     per_phase = {p: {"avg_ms": v[0] / v[1], "launches": v[1]} for p, v in phases.items()}
     per_phase[dom]["timed_avg_ms"] = timed[dom][0] / timed[dom][1]
     roofline = roofline_of(timed, steps, n_bases, n_windows, n_distinct, k_h, X * Y, workload,
-                           n_chunks, partitioned, alpha, k, classified=classified)
+                           n_chunks, partitioned, alpha, k, classified=classified,
+                           carried=carried)
     copy_Bps = copy_bandwidth(dev)
     rand = random_read_rate(words)
     out = {
@@ -775,10 +791,11 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
         "roofline": roofline,
         "step_roofline": step_roofline(phases_per_step(phases, profile_steps), 1, n_bases,
                                        n_windows, n_distinct, k_h, X * Y, n_chunks, partitioned,
-                                       alpha, k, ms_step, copy_Bps, rand, classified),
+                                       alpha, k, ms_step, copy_Bps, rand, classified,
+                                       carried),
         "hbm_rooflines": hbm_rooflines(phases, profile_steps, n_bases, n_windows, n_distinct,
                                        k_h, X * Y, workload, n_chunks, partitioned, k,
-                                       classified),
+                                       classified, carried),
         "input_generation_s": round(t_gen, 1),
     }
     if extras:

@@ -285,7 +285,14 @@ kc_status kc_sync(kc_filter *f);
  * number of regions and partitions of the binned paths, and the positions
  * per chunk (the countBF's cells are read and written once per chunk) with
  * the chunks of this insert.  The batched form's tuner may change a
- * handle's chunk size; this reports the one in use. */
+ * handle's chunk size; this reports the one in use.  carried = 1: a split
+ * insert of this size (kc_insert_classify) classifies the first-seen k-mers
+ * of the chunks before the last in the last chunk's region pass, from the
+ * counters it holds (one hash function, at least 8 counters per cell, and
+ * the handle's workspace holds the carried records: 6 bytes per position
+ * before the last chunk, allocated by kc_reserve or the insert itself);
+ * 0: they are classified by a pass over their flags that rereads their
+ * counters. */
 #define KC_PATH_DIRECT 0u
 #define KC_PATH_BINNED 1u
 #define KC_PATH_PARTITIONED 2u
@@ -296,6 +303,8 @@ typedef struct {
     uint32_t n_parts;
     uint64_t chunk;
     uint64_t n_chunks;
+    uint32_t carried;
+    uint32_t reserved;
 } kc_plan;
 kc_status kc_get_plan(const kc_filter *f, uint64_t n_bases, kc_plan *out);
 

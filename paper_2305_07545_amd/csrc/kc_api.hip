@@ -274,6 +274,10 @@ void free_workspace(kc::Workspace &W) {
     dev_free(W.pbounds);
     dev_free(W.pdesc);
     W.slots_cap = W.entries_cap = W.matrix_cap = W.coarse_cap = W.pmat_cap = 0;
+    dev_free(W.carry);
+    dev_free(W.carry_off);
+    dev_free(W.carry_n);
+    W.carry_cap = W.carry_idx_cap = 0;
     dev_free(W.totals);
     dev_free(W.n_entries);
     dev_free(W.win_cursors);
@@ -358,6 +362,44 @@ kc_status ensure_plan(kc_filter *f, const kc::BinPlan &plan, uint64_t chunk) {
     return plan.n_parts ? ensure_parts(f, plan, chunk) : ensure_binned(f, plan, chunk);
 }
 
+// Whether an insert of n_bases in chunks of `chunk` takes the carried
+// classification (with a split: the last chunk's region pass classifies
+// the earlier chunks' first-seen k-mers).
+bool carries(const kc_filter *f, const kc::BinPlan &plan, uint64_t chunk, uint64_t n_bases) {
+    return f->carry && f->layout.k_h == 1 && n_bases > chunk && kc::carry_fits(plan);
+}
+
+// Its buffers: (chunks - 1) x chunk records of 6 bytes, (chunks - 1) x
+// regions offsets and counts.  A workspace carved from caller memory that
+// lacks them takes the classification pass instead.
+kc_status ensure_carry(kc_filter *f, const kc::BinPlan &plan, uint64_t chunk, uint64_t n_bases) {
+    if (!carries(f, plan, chunk, n_bases))
+        return KC_OK;
+    kc::Workspace &W = *f->W;
+    const uint64_t prev = (n_bases + chunk - 1) / chunk - 1;
+    const uint64_t cap = prev * chunk;
+    const uint64_t idx = prev * plan.n_regions;
+    if ((W.carry && cap <= W.carry_cap && idx <= W.carry_idx_cap) || W.fixed)
+        return KC_OK;
+    wait_idle(f);
+    dev_free(W.carry);
+    dev_free(W.carry_off);
+    dev_free(W.carry_n);
+    W.carry_cap = W.carry_idx_cap = 0;
+    if (!dev_alloc(&W.carry, 3 * cap) || !dev_alloc(&W.carry_off, idx) ||
+        !dev_alloc(&W.carry_n, idx))
+        return KC_ENOMEM;
+    W.carry_cap = cap;
+    W.carry_idx_cap = idx;
+    return KC_OK;
+}
+
+// Every binned-path buffer of an insert of n_bases.
+kc_status ensure_insert(kc_filter *f, const kc::BinPlan &plan, uint64_t chunk, uint64_t n_bases) {
+    kc_status st = ensure_plan(f, plan, chunk);
+    return st == KC_OK ? ensure_carry(f, plan, chunk, n_bases) : st;
+}
+
 uint64_t next_prime_after(uint64_t n) {
     for (uint64_t p = n + 1;; p++) {
         if (p < 2)
@@ -387,7 +429,7 @@ kc_status reserve_all(kc_filter *f, uint64_t max_bases) {
     kc::BinPlan plan{};
     uint64_t bchunk = 0;
     if (choose_plan(f, max_bases, plan, bchunk))
-        return ensure_plan(f, plan, bchunk);
+        return ensure_insert(f, plan, bchunk, max_bases);
     return ensure_aux(f, f->last);
 }
 
@@ -422,6 +464,7 @@ void init_filter(kc_filter *f, const kc_layout *layout) {
     f->part_chunk = chunk_size(kc::kPartChunk);
     f->part_log = part_log_from_env();
     f->region_counters = region_counters_from_env();
+    f->carry = env_u64("KMERCO_CARRY", 1) != 0;
     f->path = path_from_env();
     kc::FilterArgs &F = f->F;
     F.words = nullptr;
@@ -464,20 +507,38 @@ kc_status insert_core(kc_filter *f, const kc::Workspace &W, uint64_t n_bases, ui
     // chunks (and every flag with several hash functions or on the direct
     // path) are marked afterwards against the final countBF.
     const bool region_marks = split && binned && f->F.k_h == 1;
+    // With several chunks, the earlier chunks' first-seen k-mers either wait
+    // as records for the last chunk's region pass (carried) or are marked
+    // afterwards by a pass that rereads their counters.
+    const uint64_t n_chunks = (n_bases + chunk - 1) / chunk;
+    kc::Carry carry{};
+    if (region_marks && carries(f, plan, chunk, n_bases))
+        carry = kc::carry_of(W, plan, chunk, n_chunks);
     uint64_t last_c0 = 0;
-    for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk) {
+    uint32_t j = 0;
+    for (uint64_t c0 = 0; c0 < n_bases; c0 += chunk, j++) {
         uint64_t c1 = c0 + chunk < n_bases ? c0 + chunk : n_bases;
         last_c0 = c0;
-        if (binned)
+        if (binned) {
+            kc::Carry cj = carry;
+            if (carry.n_prev) {
+                cj.mode = c1 == n_bases ? kc::Carry::kIn : kc::Carry::kOut;
+                cj.chunk = j;
+            }
             e = kc::launch_binned_chunk(f->F, R, c0, c1, plan, W, region_marks && c1 == n_bases,
-                                        tau, s, P);
-        else
+                                        tau, cj, s, P);
+        } else {
             e = kc::launch_insert_chunk(f->F, R, c0, c1, f->zero, W, s, P);
+        }
         if (e != hipSuccess)
             return KC_EDEVICE;
         f->zero = false;
     }
-    if (split) {
+    for (uint32_t c = 0; c < carry.n_prev; c++)
+        if (kc::launch_carried_winners(plan, carry, c, (uint64_t)c * chunk, chunk, W, s, P) !=
+            hipSuccess)
+            return KC_EDEVICE;
+    if (split && !carry.n_prev) {
         const uint64_t unmarked = region_marks ? last_c0 : n_bases;
         if (kc::launch_classify_flags(f->F, R, W, unmarked, tau, s, P) != hipSuccess)
             return KC_EDEVICE;
@@ -515,7 +576,7 @@ kc_status insert_impl(kc_filter *f, const uint8_t *reads, const uint64_t *offset
     if (k > 32 && !binned)
         return KC_EINVAL;  // k-mers of 33..64 bases take the binned paths only
     if (binned) {
-        if ((st = ensure_plan(f, plan, bchunk)) != KC_OK)
+        if ((st = ensure_insert(f, plan, bchunk, n_bases)) != KC_OK)
             return st;
     } else if ((st = ensure_aux(f, s)) != KC_OK) {
         return st;
@@ -549,7 +610,7 @@ kc_status prepare_range(kc_filter *f, uint64_t n_bases) {
     kc::BinPlan plan{};
     uint64_t bchunk = 0;
     if (choose_plan(f, n_bases, plan, bchunk))
-        return ensure_plan(f, plan, bchunk);
+        return ensure_insert(f, plan, bchunk, n_bases);
     return ensure_aux(f, f->last);
 }
 
@@ -766,6 +827,11 @@ kc_status kc_get_plan(const kc_filter *f, uint64_t n_bases, kc_plan *out) {
         out->chunk = n_bases > 0 ? f->chunk : 0;
     }
     out->n_chunks = out->chunk ? (n_bases + out->chunk - 1) / out->chunk : 0;
+    if (out->path != KC_PATH_DIRECT && n_bases > 0 && carries(f, plan, chunk, n_bases)) {
+        // the insert allocates the records unless the workspace is fixed
+        const kc::Carry c = kc::carry_of(*f->W, plan, chunk, out->n_chunks);
+        out->carried = (c.n_prev || !f->W->fixed) ? 1u : 0u;
+    }
     return KC_OK;
 }
 

@@ -512,11 +512,12 @@ void workspace_pointers(const kc::Workspace &W, std::vector<uint64_t> &out) {
     const void *p[] = {W.codes, W.inv, W.rs, W.valid, W.flags8, W.tile_a, W.tile_b, W.tile_c,
                        W.off_a, W.off_b, W.off_c, W.tmask, W.partial64, W.matrix, W.matrix_t,
                        W.coarse, W.partial32, W.slots, W.bucketed, W.entries, W.pmat, W.pbounds,
-                       W.pdesc, W.totals, W.n_entries, W.win_cursors};
+                       W.pdesc, W.totals, W.n_entries, W.win_cursors, W.carry,
+                       W.carry_off, W.carry_n};
     for (const void *x : p)
         out.push_back((uint64_t)(uintptr_t)x);
     out.insert(out.end(), {W.cap, W.tile_cap, W.matrix_cap, W.coarse_cap, W.slots_cap,
-                           W.entries_cap, W.pmat_cap});
+                           W.entries_cap, W.pmat_cap, W.carry_cap, W.carry_idx_cap});
 }
 
 // Everything a captured graph depends on: the arguments, the work-item size

@@ -789,27 +789,31 @@ __global__ void __launch_bounds__(kThreads) k_bin_bucket_list(const uint64_t *__
 struct WinnerSink {
     uint8_t *flags;
     uint64_t c0;
-    uint32_t *rec_t;  // records mode: the entry lists' word array (null: flag mode)
-    uint16_t *rec_m;  // ... and half array
-    uint64_t e0;      // the region's first entry
+    uint32_t *rec_t;  // records or carry mode: the records' word array (null: flag mode)
+    uint16_t *rec_m;  // ... and half array: the mark, or in carry mode the local counter
+    uint64_t e0;      // the region's first record
     uint32_t *count;  // LDS: records written so far
+    bool carry;       // carry mode: the half is the local counter id
 };
 
-__device__ __forceinline__ void put_winner(const WinnerSink &o, uint32_t t, uint32_t mark) {
+__device__ __forceinline__ void put_winner(const WinnerSink &o, uint32_t t, uint32_t mark,
+                                           uint32_t local) {
     if (!o.rec_t) {
         o.flags[o.c0 + t] = (uint8_t)mark;
         return;
     }
     const uint32_t i = atomicAdd(o.count, 1u);
     o.rec_t[o.e0 + i] = t;
-    o.rec_m[o.e0 + i] = (uint16_t)mark;
+    o.rec_m[o.e0 + i] = (uint16_t)(o.carry ? local : mark);
 }
 
-// Counter update of cell w of the region (pre = its value before the chunk).
-__device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &B, uint64_t wbase,
-                                            uint32_t w, uint64_t pre, const uint32_t *hits,
-                                            const uint32_t *first, const WinnerSink &out,
-                                            int classify, uint32_t tau) {
+// Counter update of cell w of the region (pre = its value before the
+// chunk); returns the cell's new value.
+__device__ __forceinline__ uint64_t region_cell(const FilterArgs &F, const BinPlan &B,
+                                                uint64_t wbase, uint32_t w, uint64_t pre,
+                                                const uint32_t *hits, const uint32_t *first,
+                                                const WinnerSink &out, int classify,
+                                                uint32_t tau) {
     uint64_t next = pre;
     for (uint32_t l = 0; l < F.eta; l++) {
         const uint32_t idx = (l << B.region_shift) | w;
@@ -822,10 +826,11 @@ __device__ __forceinline__ void region_cell(const FilterArgs &F, const BinPlan &
         const uint64_t nf = pf + (h < room ? h : room);
         next = (next & ~(F.field_max << sh)) | (nf << sh);
         if (pf == 0)
-            put_winner(out, first[idx], (classify && nf > (uint64_t)tau) ? 3u : 1u);
+            put_winner(out, first[idx], (classify && nf > (uint64_t)tau) ? 3u : 1u, idx);
     }
     if (next != pre)
         F.words[wbase + w] = next;
+    return next;
 }
 
 // Region lists of 6-byte entries (both binned paths).  kCounters: the LDS
@@ -841,7 +846,8 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                                                       const uint32_t *__restrict__ n_entries,
                                                       uint64_t *__restrict__ entries,
                                                       uint8_t *__restrict__ flags, int classify,
-                                                      uint32_t tau, uint32_t *__restrict__ n_win) {
+                                                      uint32_t tau, uint32_t *__restrict__ n_win,
+                                                      Carry C) {
     constexpr int kUnroll = 8;
     constexpr int kHold = 4;  // cells per thread held in registers (regions <= 4096 cells)
     constexpr uint32_t kSparseCells = kCounters / 8;  // cells of a region the sparse path stages
@@ -910,7 +916,15 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             request(rn, Rn, vn, celln);
         if (threadIdx.x == 0)
             s_nwin = 0;
-        const WinnerSink out{flags, c0, n_win ? e_word : nullptr, e_half, R.e0, &s_nwin};
+        const bool carry_out = C.mode == Carry::kOut;
+        const WinnerSink out{flags,
+                             c0,
+                             carry_out ? C.word + (uint64_t)C.chunk * C.cap
+                                       : (n_win ? e_word : nullptr),
+                             carry_out ? C.half + (uint64_t)C.chunk * C.cap : e_half,
+                             R.e0,
+                             &s_nwin,
+                             carry_out};
         if (R.e1 - R.e0 <= (uint64_t)kUnroll * kRegionWG && R.nw <= kSparseCells) {
             // Sparse region: every entry is in the register batch.  Only the
             // counters the entries touch are cleared, and counters are
@@ -959,7 +973,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                     if (nf != pf)
                         atomicAdd(&s_cell[w], (unsigned long long)((nf - pf) << sh));
                     if (pf == 0)
-                        put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u);
+                        put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u, local);
                 }
             __syncthreads();
 #pragma unroll
@@ -1001,8 +1015,12 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
 #pragma unroll
                 for (int k = 0; k < kHold; k++) {
                     const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-                    if (w < R.nw)
-                        region_cell(F, B, R.wbase, w, cell[k], hits, first, out, classify, tau);
+                    if (w < R.nw) {
+                        const uint64_t next =
+                            region_cell(F, B, R.wbase, w, cell[k], hits, first, out, classify, tau);
+                        if (C.mode == Carry::kIn)  // the launcher checked nw <= kSparseCells
+                            s_cell[w] = next;
+                    }
                 }
             } else {
                 for (uint32_t w = threadIdx.x; w < R.nw; w += kRegionWG)
@@ -1011,8 +1029,30 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             }
         }
         __syncthreads();  // the region's LDS work and its winner count are complete
-        if (n_win && threadIdx.x == 0)
-            n_win[r] = s_nwin;
+        if (C.mode == Carry::kIn) {
+            // the carried records of this region: trustworthy (3) when the
+            // counter's final value, now staged in s_cell, is above tau
+            for (uint32_t j = 0; j < C.n_prev; j++) {
+                const uint64_t at = (uint64_t)j * C.stride + r;
+                const uint64_t x0 = (uint64_t)j * C.cap + C.off[at];
+                const uint32_t n = C.n[at];
+                for (uint32_t i = threadIdx.x; i < n; i += kRegionWG) {
+                    const uint32_t local = C.half[x0 + i];
+                    const uint64_t cv = s_cell[local & (S - 1u)];
+                    const uint64_t f = (cv >> (F.alpha * (local >> B.region_shift))) & F.field_max;
+                    C.half[x0 + i] = f > (uint64_t)tau ? 3u : 1u;
+                }
+            }
+            __syncthreads();  // s_cell is rewritten by the next region
+        }
+        if (threadIdx.x == 0) {
+            if (carry_out) {
+                C.off[(uint64_t)C.chunk * C.stride + r] = (uint32_t)R.e0;
+                C.n[(uint64_t)C.chunk * C.stride + r] = s_nwin;
+            } else if (n_win) {
+                n_win[r] = s_nwin;
+            }
+        }
         if (rn >= B.n_regions)
             break;
         r = rn;
@@ -1099,9 +1139,12 @@ __device__ void win_flush(const Rec *s_rec, uint32_t n, uint32_t shift, uint32_t
 // LDS first, so that the workgroup's records are one index range whose
 // batches are filled by all threads at once (record i is found in its
 // region by a binary search of the scan), not region after region.
-__global__ void __launch_bounds__(kWinThreads) k_win_a(BinPlan B, const uint32_t *__restrict__ offsets,
+__global__ void __launch_bounds__(kWinThreads) k_win_a(uint32_t n_regions,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       uint64_t off_stride,
                                                        const uint32_t *__restrict__ n_win,
-                                                       const uint64_t *__restrict__ entries,
+                                                       const uint32_t *__restrict__ e_word,
+                                                       const uint16_t *__restrict__ e_half,
                                                        uint32_t *__restrict__ cursor,
                                                        uint32_t *__restrict__ out) {
     static_assert(kWinRegions == 64, "one wavefront scans the regions' counts");
@@ -1109,14 +1152,12 @@ __global__ void __launch_bounds__(kWinThreads) k_win_a(BinPlan B, const uint32_t
     __shared__ uint32_t s_cnt[kWinBuckets], s_base[kWinBuckets];
     __shared__ uint32_t s_first[kWinRegions];    // each region's first entry
     __shared__ uint32_t s_pre[kWinRegions + 1];  // records before each region
-    const uint32_t *e_word = (const uint32_t *)entries;
-    const uint16_t *e_half = (const uint16_t *)(e_word + B.entries_cap);
     const uint32_t r0 = blockIdx.x * kWinRegions;
-    const uint32_t nr = r0 + kWinRegions < B.n_regions ? kWinRegions : B.n_regions - r0;
+    const uint32_t nr = r0 + kWinRegions < n_regions ? kWinRegions : n_regions - r0;
     if (threadIdx.x < 64) {
         const uint32_t i = threadIdx.x;
         const uint32_t n = i < nr ? n_win[r0 + i] : 0u;
-        s_first[i] = i < nr ? offsets[(uint64_t)(r0 + i) * B.G] : 0u;
+        s_first[i] = i < nr ? offsets[(uint64_t)(r0 + i) * off_stride] : 0u;
         uint32_t incl = n;
         for (uint32_t d = 1; d < 64; d <<= 1) {
             const uint32_t o = __shfl_up(incl, d, 64);
@@ -1238,9 +1279,12 @@ bool records_mode(uint64_t len) {
     return len > (1ull << 28);
 }
 
-// The winner passes of one chunk [c0, c0 + len) after its region pass.
-hipError_t launch_winner_passes(const BinPlan &Q, uint64_t c0, uint64_t len, const Workspace &W,
-                                const uint32_t *n_win, hipStream_t s, Profiler *P) {
+// The winner passes of one chunk [c0, c0 + len): its records, region r's
+// n_win[r] of them at offsets[r * off_stride] of the word and half arrays.
+hipError_t winner_passes(uint32_t n_regions, const uint32_t *offsets, uint64_t off_stride,
+                         const uint32_t *n_win, const uint32_t *rec_word,
+                         const uint16_t *rec_half, uint64_t c0, uint64_t len, const Workspace &W,
+                         hipStream_t s, Profiler *P) {
     uint32_t *cursors = W.win_cursors;  // kWinBuckets level-A, then the blocks' level-B cursors
     const uint32_t n_a = (uint32_t)((len + (1ull << kWinA) - 1) >> kWinA);
     const uint32_t n_blocks = (uint32_t)((len + (1ull << kWinB) - 1) >> kWinB);
@@ -1249,9 +1293,9 @@ hipError_t launch_winner_passes(const BinPlan &Q, uint64_t c0, uint64_t len, con
     static_assert(kWinBuckets + kWinBuckets * kWinBlocksPerBucket == kWinCursors, "cursors");
     hipError_t e = fill_u32(cursors, kWinCursors, 0u, s);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_win_a, dim3((Q.n_regions + kWinRegions - 1) / kWinRegions),
-                           dim3(kWinThreads), 0, s, Q, (const uint32_t *)W.matrix, n_win,
-                           (const uint64_t *)W.entries, cursors, (uint32_t *)W.bucketed);
+        hipLaunchKernelGGL(k_win_a, dim3((n_regions + kWinRegions - 1) / kWinRegions),
+                           dim3(kWinThreads), 0, s, n_regions, offsets, off_stride, n_win,
+                           rec_word, rec_half, cursors, (uint32_t *)W.bucketed);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -1269,6 +1313,48 @@ hipError_t launch_winner_passes(const BinPlan &Q, uint64_t c0, uint64_t len, con
     if (P)
         P->end(s);
     return e;
+}
+
+// The winner passes of one chunk after its region pass in records mode: the
+// records sit in the region lists' entry segments.
+hipError_t launch_winner_passes(const BinPlan &Q, uint64_t c0, uint64_t len, const Workspace &W,
+                                const uint32_t *n_win, hipStream_t s, Profiler *P) {
+    const uint32_t *e_word = (const uint32_t *)W.entries;
+    return winner_passes(Q.n_regions, (const uint32_t *)W.matrix, Q.G, n_win, e_word,
+                         (const uint16_t *)(e_word + Q.entries_cap), c0, len, W, s, P);
+}
+
+bool carry_fits(const BinPlan &plan) {
+    // the region's cells are staged in the region pass's s_cell array
+    // (kSparseCells = counters / 8 entries)
+    return (1u << plan.region_shift) <= plan.region_counters / 8u;
+}
+
+Carry carry_of(const Workspace &W, const BinPlan &plan, uint64_t chunk_positions,
+               uint64_t n_chunks) {
+    Carry c{};
+    if (n_chunks < 2 || !carry_fits(plan))
+        return c;
+    const uint64_t prev = n_chunks - 1;
+    if (!W.carry || W.carry_cap < prev * chunk_positions ||
+        W.carry_idx_cap < prev * plan.n_regions)
+        return c;
+    c.n_prev = (uint32_t)prev;
+    c.stride = plan.n_regions;
+    c.cap = chunk_positions;
+    c.word = (uint32_t *)W.carry;
+    c.half = W.carry + 2 * W.carry_cap;
+    c.off = W.carry_off;
+    c.n = W.carry_n;
+    return c;
+}
+
+hipError_t launch_carried_winners(const BinPlan &plan, const Carry &carry, uint32_t j, uint64_t c0,
+                                  uint64_t len, const Workspace &W, hipStream_t s, Profiler *P) {
+    const uint64_t at = (uint64_t)j * carry.stride;
+    return winner_passes(plan.n_regions, carry.off + at, 1, carry.n + at,
+                         carry.word + (uint64_t)j * carry.cap, carry.half + (uint64_t)j * carry.cap,
+                         c0, len, W, s, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -1378,7 +1464,7 @@ auto bin_count_kernel(const FilterArgs &F, uint32_t k) {
 // region pass over every region of the countBF.
 hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                               const BinPlan &plan, const Workspace &W, bool classify,
-                              uint32_t tau, hipStream_t s, Profiler *P) {
+                              uint32_t tau, const Carry &carry, hipStream_t s, Profiler *P) {
     BinPlan B = plan;
     B.G = (uint32_t)((c1 - c0 + B.tile - 1) / B.tile);
     B.n_slices = (B.G + B.slice - 1) / B.slice;
@@ -1498,14 +1584,14 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
     if (e == hipSuccess) {
         if (P)
             P->begin(kPhRegion, s);
-        const bool rec = records_mode(c1 - c0);
+        const bool rec = carry.mode != Carry::kOut && records_mode(c1 - c0);
         hipLaunchKernelGGL((Q.region_counters == kSmallRegionCounters
                                 ? k_region<kSmallRegionCounters>
                                 : k_region<kRegionCounters>),
                            dim3(region_grid(Q.n_regions, Q.region_counters)), dim3(kRegionWG),
                            0, s, F, c0, Q,
                            (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
-                           W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr);
+                           W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr, carry);
         if (P)
             P->end(s);
         e = hipGetLastError();
@@ -1519,11 +1605,13 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
 
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
-                               uint32_t tau, hipStream_t s, Profiler *P) {
+                               uint32_t tau, const Carry &carry, hipStream_t s, Profiler *P) {
     if ((c0 & 63u) || !R.valid)
         return hipErrorInvalidValue;  // waves read 64 bits of the valid-window bitmap
+    if (carry.mode != Carry::kNone && (!carry_fits(plan) || carry.stride != plan.n_regions))
+        return hipErrorInvalidValue;  // the region pass stages the cells it classifies against
     if (plan.n_parts)
-        return launch_parts_chunk(F, R, c0, c1, plan, W, classify, tau, s, P);
+        return launch_parts_chunk(F, R, c0, c1, plan, W, classify, tau, carry, s, P);
     if (c1 - c0 > kBinChunk || (c1 - c0) * F.k_h >= (1ull << 32))
         return hipErrorInvalidValue;  // the level-1 pass indexes in 32 bits
     BinPlan B = plan;
@@ -1582,14 +1670,14 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
         return e;
     if (P)
         P->begin(kPhRegion, s);
-    const bool rec = records_mode(c1 - c0);
+    const bool rec = carry.mode != Carry::kOut && records_mode(c1 - c0);
     hipLaunchKernelGGL((B.region_counters == kSmallRegionCounters
                             ? k_region<kSmallRegionCounters>
                             : k_region<kRegionCounters>),
                        dim3(region_grid(B.n_regions, B.region_counters)), dim3(kRegionWG), 0,
                        s, F, c0, B,
                        (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
-                       W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr);
+                       W.flags8, classify ? 1 : 0, tau, rec ? W.matrix_t : nullptr, carry);
     if (P)
         P->end(s);
     e = hipGetLastError();

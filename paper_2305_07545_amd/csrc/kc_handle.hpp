@@ -26,6 +26,7 @@ struct kc_filter {
     uint64_t part_chunk;   // partitioned binned path: positions per chunk
     uint32_t part_log;     // partitioned binned path: log2(regions per partition)
     uint32_t region_counters;  // binned paths: counters per region (the region pass's LDS)
+    bool carry;            // multi-chunk inserts classify in the last region pass
     KcPath path;
     kc::Profiler prof;     // optional per-kernel timing
     bool caller_scratch;   // status word and workspace live in the caller's buffer

@@ -103,6 +103,16 @@ struct Workspace {
     uint64_t *totals = nullptr;   // 8 scan totals / saved counters
     uint32_t *n_entries = nullptr;  // 4 entry totals
     uint32_t *win_cursors = nullptr;  // kWinCursors: the winner passes' bucket cursors
+    // carried first-seen records (classification by the last chunk's region
+    // pass): chunk j < last keeps its records (t, local counter) at
+    // [j * carry_cap + region offset) of two arrays, 32-bit t words then
+    // 16-bit halves, and each region's offset and record count at
+    // [j * carry_regions + region) of carry_off and carry_n
+    uint16_t *carry = nullptr;    // 3 * carry_cap halves: the words, then the halves
+    uint64_t carry_cap = 0;       // records per carried chunk x carried chunks
+    uint32_t *carry_off = nullptr;
+    uint32_t *carry_n = nullptr;
+    uint64_t carry_idx_cap = 0;   // regions x carried chunks
     // the buffers were carved from caller memory once: they never grow, and a
     // call that needs more than they hold fails instead
     bool fixed = false;
@@ -216,10 +226,39 @@ hipError_t launch_insert_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
 // partition size (regions) for countBFs of more than 2^part_log regions.
 bool bin_plan(const FilterArgs &F, uint64_t chunk_positions, BinPlan &B,
               uint32_t part_log = kPartLog, uint32_t region_counters = kRegionCounters);
+// Carried classification of a multi-chunk insert with one hash function:
+// the region passes of the chunks before the last keep their first-seen
+// records (Carry::kOut, chunk j of the carry arrays) instead of writing
+// flags; the last chunk's region pass (Carry::kIn, chunks 0 .. n_prev - 1)
+// marks each carried record trustworthy or not from its counter's final
+// value, and the winner passes then write every carried chunk's flags.
+struct Carry {
+    enum Mode : uint32_t { kNone = 0, kOut = 1, kIn = 2 };
+    uint32_t mode = kNone;
+    uint32_t chunk = 0;          // kOut: this chunk's index j
+    uint32_t n_prev = 0;         // kIn: carried chunks
+    uint32_t stride = 0;         // regions per carried chunk in carry_off / carry_n
+    uint64_t cap = 0;            // records per carried chunk
+    uint32_t *word = nullptr;    // t words of chunk 0 (chunk j at + j * cap)
+    uint16_t *half = nullptr;    // local counters, then marks, of chunk 0
+    uint32_t *off = nullptr;     // region offsets of chunk 0 (chunk j at + j * stride)
+    uint32_t *n = nullptr;       // region record counts of chunk 0
+};
+// The carry arrays of W viewed for n_chunks chunks of chunk_positions (k_h
+// = 1), or a kNone carry when W does not hold them.
+Carry carry_of(const Workspace &W, const BinPlan &plan, uint64_t chunk_positions,
+               uint64_t n_chunks);
+// Whether a plan's regions can take the carried classification: their cells
+// fit the region pass's staged-cell array (eta >= 8).
+bool carry_fits(const BinPlan &plan);
 // plan.n_parts > 0 takes the partitioned path
 hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t c0, uint64_t c1,
                                const BinPlan &plan, const Workspace &W, bool classify,
-                               uint32_t tau, hipStream_t s, Profiler *P);
+                               uint32_t tau, const Carry &carry, hipStream_t s, Profiler *P);
+// The winner passes of carried chunk j (positions [c0, c0 + len)) after the
+// last chunk's region pass has marked its records.
+hipError_t launch_carried_winners(const BinPlan &plan, const Carry &carry, uint32_t j, uint64_t c0,
+                                  uint64_t len, const Workspace &W, hipStream_t s, Profiler *P);
 // windows_counted: the insert passes already added this call's valid-window
 // count to W.totals[5] (else the tile pass counts them)
 hipError_t launch_distinct(const ReadsArgs &R, const Workspace &W, uint64_t *distinct,

@@ -50,7 +50,8 @@ SET_ALIGN = 4096
 class kc_plan(ctypes.Structure):
     _fields_ = [("path", ctypes.c_uint32), ("region_cells", ctypes.c_uint32),
                 ("n_regions", ctypes.c_uint32), ("n_parts", ctypes.c_uint32),
-                ("chunk", ctypes.c_uint64), ("n_chunks", ctypes.c_uint64)]
+                ("chunk", ctypes.c_uint64), ("n_chunks", ctypes.c_uint64),
+                ("carried", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 PATH_NAMES = {0: "direct", 1: "binned", 2: "partitioned"}

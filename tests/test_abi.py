@@ -92,11 +92,23 @@ def test_scratch_bytes_rounds_every_piece():
     """Every piece kc_scratch_bytes counts is rounded up to 256 bytes (the
     carving of a caller's scratch lays them out at that alignment), and the
     partitioned path's need per base (about 19 bytes) is below the
-    single-level path's (about 22)."""
+    single-level path's (about 22).  An insert of several chunks also holds
+    the carried first-seen records: 6 bytes per position before the last
+    chunk."""
     for X, Y, n in [(269, 281, 10**6), (2621, 2657, 10**7), (31627, 31657, 10**8)]:
         assert P.scratch_bytes(X, Y, n) % 256 == 0
-    big = P.scratch_bytes(31627, 31657, 2**32) / 2**32
+    one_chunk = 2**32 - 2**16  # the partitioned path's chunk
+    big = P.scratch_bytes(31627, 31657, one_chunk) / one_chunk
     assert 15 < big < 22, big
+
+    def second_chunk(**kw):  # bytes per base the second chunk adds
+        return (P.scratch_bytes(31627, 31657, 2 * one_chunk, **kw) -
+                P.scratch_bytes(31627, 31657, one_chunk, **kw)) / one_chunk
+
+    # eta = 4 (alpha = 16) and two hash functions carry nothing: the per-
+    # position buffers only; eta = 8 adds the 6-byte records
+    assert 1 < second_chunk(alpha=16) < 3 and 1 < second_chunk(k_h=2) < 3
+    assert 5.99 < second_chunk() - second_chunk(alpha=16) < 6.01
 
 
 def test_create_in_rejects_bad_arguments_on_the_host():

@@ -518,3 +518,49 @@ def test_winner_records_bacterial_and_wide(monkeypatch):
     check(rs, X, Y, k=45, what="records, bacterial x0.05, k=45")
     monkeypatch.setenv("KMERCO_PART_LOG", "3")
     check(rs, X, Y, what="records, bacterial x0.05, partitions of 8")
+
+
+# ---------------------------------------------------------------------------
+# carried classification: a multi-chunk split insert with one hash function
+# classifies the earlier chunks' first-seen k-mers in the last chunk's region
+# pass (KMERCO_CARRY=0: by the pass that rereads their counters instead)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,counters,part_log",
+                         [(8, "16384", "14"), (8, "16384", "2"), (5, "8192", "14"),
+                          (4, "8192", "2"), (16, "16384", "14")])
+def test_carried_classification(monkeypatch, alpha, counters, part_log):
+    monkeypatch.setenv("KMERCO_REGION_COUNTERS", counters)
+    monkeypatch.setenv("KMERCO_PART_LOG", part_log)
+    rnd = synth.random_reads(3100 + alpha, 700, 50, 300, k=23, tau=2, p_n=0.01)
+    extra = synth.reads_from_strings(["A" * 9000, "ACGT" * 2000, "GATTACA" * 500], k=23, tau=2)
+    rs = synth.concat_reads([rnd, extra], name="carried")
+    X, Y = (401, 409) if part_log == "2" else (1009, 1013)
+    for chunk in ("40000", "16384", "1024"):
+        monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", chunk)
+        bf = P.CountBF(X, Y, alpha, 1)
+        plan = bf.plan(rs.n_bases)
+        bf.close()
+        assert plan["n_chunks"] > 2
+        # eta >= 8 carries (the region's cells fit the staged-cell array)
+        assert plan["carried"] == (1 if 64 // alpha >= 8 else 0), plan
+        outs = []
+        for carry in ("1", "0"):
+            monkeypatch.setenv("KMERCO_CARRY", carry)
+            outs.append(check(rs, X, Y, alpha=alpha, what=f"carry={carry} chunks of {chunk}"))
+        for a, b in zip(outs[0][:4], outs[1][:4]):
+            assert np.array_equal(a, b)
+        monkeypatch.setenv("KMERCO_WINNER_RECORDS", "1")  # the last chunk's own records too
+        check(rs, X, Y, alpha=alpha, what=f"carried, records mode, chunks of {chunk}")
+        check(rs, X, Y, alpha=alpha, k=45, what=f"carried, k=45, chunks of {chunk}")
+        monkeypatch.delenv("KMERCO_WINNER_RECORDS")
+        monkeypatch.delenv("KMERCO_CARRY")
+
+
+def test_carried_classification_bacterial_sample(monkeypatch):
+    rs = synth.config("bacterial", scale=0.05)
+    X, Y = oracle.dims(rs.n_items)
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "1000000")
+    check(rs, X, Y, what="carried, bacterial x0.05, chunks of 1M")
+    monkeypatch.setenv("KMERCO_PART_LOG", "3")
+    check(rs, X, Y, what="carried, bacterial x0.05, partitions of 8, chunks of 1M")
