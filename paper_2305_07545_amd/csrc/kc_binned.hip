@@ -314,6 +314,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
     __shared__ uint32_t s_cnt[kMaxRegionsPerBucket];
     __shared__ uint32_t s_start[kMaxRegionsPerBucket];
     __shared__ uint32_t s_fill[kMaxRegionsPerBucket];
+    __shared__ uint32_t s_delta[kMaxRegionsPerBucket];  // output index - staged index, per region
     __shared__ uint32_t s_wave[kThreads / 64];
     const uint32_t b = blockIdx.x / B.n_slices;
     const uint32_t s = blockIdx.x % B.n_slices;
@@ -333,15 +334,18 @@ __global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
         s_fill[i] = 0;
     }
     __syncthreads();
-    const uint64_t e0 = coarse_off[(uint64_t)b * B.G + gs0];
-    uint64_t e1;
+    // entry indices are 32-bit: a chunk's entries (positions x hash
+    // functions) number less than 2^32 on both paths
+    const uint32_t e0 = coarse_off[(uint64_t)b * B.G + gs0];
+    uint32_t e1;
     if (gs1 < B.G)
         e1 = coarse_off[(uint64_t)b * B.G + gs1];
     else
         e1 = b + 1 < B.n_buckets ? coarse_off[(uint64_t)(b + 1) * B.G] : *n_entries;
     const uint64_t cap = B.entries_cap;
-    if (e1 > cap)
-        e1 = cap;
+    const uint32_t cap32 = cap < 0xFFFFFFFFull ? (uint32_t)cap : 0xFFFFFFFFu;
+    if (e1 > cap32)
+        e1 = cap32;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t *in_word = (const uint32_t *)bucketed;
@@ -353,10 +357,10 @@ __global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
     // words, or the 6-byte entry's word and half; hi = ~0u past the end);
     // the next batch's are requested before this one is sorted and decoded
     // only then, so that their loads stay in flight meanwhile
-    auto load = [&](uint64_t q0, RawEntry(&v)[kPer]) {
+    auto load = [&](uint32_t q0, RawEntry(&v)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
-            const uint64_t x = q0 + threadIdx.x + (uint64_t)u * kThreads;
+            const uint32_t x = q0 + threadIdx.x + (uint32_t)u * kThreads;
             v[u] = RawEntry{~0u, ~0u};
             if (x < e1) {
                 if (kCompact) {
@@ -373,14 +377,14 @@ __global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
     RawEntry next[kPer];
     if (e0 < e1)
         load(e0, next);
-    for (uint64_t q0 = e0; q0 < e1; q0 += kStage2) {
+    for (uint32_t q0 = e0; q0 < e1; q0 += kStage2) {
         uint64_t v[kPer];
         uint32_t ri[kPer];
         RawEntry raw[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; u++)
             raw[u] = next[u];
-        if (q0 + kStage2 < e1)
+        if (e1 - q0 > (uint32_t)kStage2)
             load(q0 + kStage2, next);
         // kCompact: t << 32 | region within the bucket << kLocalBits | counter
 #pragma unroll
@@ -425,8 +429,10 @@ __global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
             uint32_t before = 0;
             for (uint32_t w = 0; w < wave; w++)
                 before += s_wave[w];
-            if (threadIdx.x < kMaxRegionsPerBucket)
+            if (threadIdx.x < kMaxRegionsPerBucket) {
                 s_start[threadIdx.x] = before + incl - c;
+                s_delta[threadIdx.x] = s_cursor[threadIdx.x] - (before + incl - c);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -440,23 +446,14 @@ __global__ void __launch_bounds__(kThreads) k_bin_region(BinPlan B,
             s_start[kMaxRegionsPerBucket - 1] + s_cnt[kMaxRegionsPerBucket - 1];
         for (uint32_t j = threadIdx.x; j < n_stage; j += kThreads) {
             const uint64_t e = s_stage[j];
-            if (kCompact) {
-                const uint32_t r = (uint32_t)e >> kLocalBits;
-                const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
-                const uint32_t t = (uint32_t)(e >> 32);
-                if (dst < cap) {
-                    out_word[dst] = ((uint32_t)e & (kRegionCounters - 1u)) | (t << kLocalBits);
-                    out_half[dst] = (uint16_t)(t >> (32 - kLocalBits));
-                }
-            } else {
-                const uint32_t r =
-                    (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
-                const uint64_t dst = (uint64_t)s_cursor[r] + (j - s_start[r]);
-                const uint32_t t = (uint32_t)(e >> 32);  // chunk-relative: < 2^32 - 1
-                if (dst < cap) {
-                    out_word[dst] = ((uint32_t)e & (kRegionCounters - 1u)) | (t << kLocalBits);
-                    out_half[dst] = (uint16_t)(t >> (32 - kLocalBits));
-                }
+            const uint32_t r = kCompact
+                                   ? (uint32_t)e >> kLocalBits
+                                   : (((uint32_t)e >> kLocalBits) & ((1u << kLocalBits) - 1u)) - r0l;
+            const uint32_t dst = s_delta[r] + j;
+            const uint32_t t = (uint32_t)(e >> 32);  // chunk-relative: < 2^32 - 1
+            if (dst < cap32) {
+                out_word[dst] = ((uint32_t)e & (kRegionCounters - 1u)) | (t << kLocalBits);
+                out_half[dst] = (uint16_t)(t >> (32 - kLocalBits));
             }
         }
         __syncthreads();
