@@ -313,3 +313,26 @@ def test_side_lane_full_chunk_partitioned_digests():
     assert h(g["trust"]) == ref["trust_sha256"] and h(g["err"]) == ref["err_sha256"]
     want = oracle_each([small[0], small[1]])
     assert_sets_equal([got[0], got[2]], want, "small sets beside the large one")
+
+
+def test_side_lane_sets_in_several_chunks(monkeypatch):
+    """Side-lane sets inserted in several chunks (chunk size forced small):
+    their split takes the carried classification (the last chunk's region
+    pass marks the earlier chunks' first-seen k-mers from records kept in the
+    side lane's workspace), eager and graph-replayed, equal to the oracle."""
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "65536")
+    cases = side_lane_cases()
+    want = oracle_each(cases)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        run = BatchRun(cases, stream=stream)
+        plans = [e["filter"].plan(e["n_bases"]) for e in run.entries]
+        assert any(p["n_chunks"] > 1 and p["carried"] for p in plans), plans
+        b = P.Batch()
+        print("case side lanes in chunks: eager", flush=True)
+        b.insert(run.entries, run.reads, run.offs, reset=True, stream=stream)
+        assert_sets_equal(run.results(), want, "side lanes in chunks, eager")
+        for rep in range(2):
+            print(f"case side lanes in chunks: graph replay {rep}", flush=True)
+            b.insert(run.entries, run.reads, run.offs, reset=True, graph=True, stream=stream)
+            assert_sets_equal(run.results(), want, f"side lanes in chunks, graph {rep}")

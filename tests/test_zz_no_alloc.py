@@ -96,3 +96,26 @@ def test_noalloc_refuses_what_does_not_fit():
     bf.sync()
     assert int(c.abs().sum()) == 0 and not bool(bf.words.any())  # nothing was enqueued
     bf.close()
+
+
+def test_noalloc_in_several_chunks(monkeypatch):
+    """An insert of several chunks (chunk size forced small) through the
+    allocation-free entry point: its carried first-seen records are carved
+    from the fixed array too; equal to kc_insert_classify and the oracle."""
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", "131072")
+    a = synth.config("tiny", 1.0)
+    X, Y = 269, 281
+    bf = P.CountBF(X, Y)
+    plan = bf.plan(a.n_bases)
+    bf.close()
+    assert plan["n_chunks"] > 2 and plan["carried"] == 1, plan
+    print(f"case noalloc in {plan['n_chunks']} chunks", flush=True)
+    ref, ref_words = run([a], X, Y, 21, 2, noalloc=False)
+    got, got_words = run([a], X, Y, 21, 2, noalloc=True)
+    assert np.array_equal(got_words, ref_words)
+    (gw, gd, gt, ge), (rw, rd, rt, re) = got[0], ref[0]
+    assert gw == rw and np.array_equal(gd, rd)
+    assert np.array_equal(gt, rt) and np.array_equal(ge, re)
+    words, d, t, e, nw = oracle.run_kmerco(a.reads, a.offsets, 21, 2, X, Y)
+    assert np.array_equal(got_words, words) and gw == nw
+    assert np.array_equal(gd, d) and np.array_equal(gt, t) and np.array_equal(ge, e)
