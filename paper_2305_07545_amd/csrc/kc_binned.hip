@@ -860,18 +860,21 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     const uint64_t n_words = F.X * F.Y;
     uint32_t *e_word = (uint32_t *)entries;
     uint16_t *e_half = (uint16_t *)(e_word + B.entries_cap);
-    // a region's work: entries [e0, e1), cells [wbase, wbase + nw)
+    // a region's work: entries [e0, e0 + n), cells [wbase, wbase + nw);
+    // entry indices are 32-bit (a chunk's entries number less than 2^32)
     struct Region {
-        uint64_t e0, e1, wbase;
+        uint32_t e0, n;
+        uint64_t wbase;
         uint32_t nw;
     };
-    // entry x of a region as loaded (hi = ~0u past its end); decoded where
-    // it is used, so that prefetched loads stay in flight until then
-    auto fetch = [&](uint64_t x, uint64_t e1) -> RawEntry {
+    // entry e0 + off of a region of n entries as loaded (hi = ~0u past its
+    // end); decoded where it is used, so that prefetched loads stay in
+    // flight until then
+    auto fetch = [&](uint32_t e0, uint32_t off, uint32_t n) -> RawEntry {
         RawEntry e{~0u, ~0u};
-        if (x < e1) {
-            e.lo = e_word[x];
-            e.hi = e_half[x];
+        if (off < n) {
+            e.lo = e_word[e0 + off];
+            e.hi = e_half[e0 + off];
         }
         return e;
     };
@@ -881,15 +884,18 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     auto hold_of = [&](const Region &R) { return R.nw <= (uint32_t)kHold * kRegionWG; };
     // region r's bounds, first batch of entries and (when held) cells
     auto request = [&](uint32_t r, Region &R, RawEntry(&v)[kUnroll], uint64_t(&cell)[kHold]) {
-        R.e0 = offsets[(uint64_t)r * B.G];
-        R.e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
-        if (R.e1 > B.entries_cap)
-            R.e1 = B.entries_cap;
+        const uint32_t cap = B.entries_cap < 0xFFFFFFFFull ? (uint32_t)B.entries_cap : 0xFFFFFFFFu;
+        const uint32_t e0 = offsets[(uint64_t)r * B.G];
+        uint32_t e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
+        if (e1 > cap)
+            e1 = cap;
+        R.e0 = e0;
+        R.n = e1 > e0 ? e1 - e0 : 0u;
         R.wbase = (uint64_t)(B.region0 + r) << B.region_shift;
         R.nw = R.wbase + S <= n_words ? S : (uint32_t)(n_words - R.wbase);
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
-            v[u] = fetch(R.e0 + threadIdx.x + (uint64_t)u * kRegionWG, R.e1);
+            v[u] = fetch(R.e0, threadIdx.x + (uint32_t)u * kRegionWG, R.n);
         const bool hold = hold_of(R);
 #pragma unroll
         for (int k = 0; k < kHold; k++) {
@@ -922,7 +928,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                              R.e0,
                              &s_nwin,
                              carry_out};
-        if (R.e1 - R.e0 <= (uint64_t)kUnroll * kRegionWG && R.nw <= kSparseCells) {
+        if (R.n <= (uint32_t)(kUnroll * kRegionWG) && R.nw <= kSparseCells) {
             // Sparse region: every entry is in the register batch.  Only the
             // counters the entries touch are cleared, and counters are
             // updated per entry, not by a pass over all of them: the entry
@@ -985,13 +991,13 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                 first[i] = kIdle;
             }
             __syncthreads();
-            for (uint64_t e = R.e0 + threadIdx.x;;) {
+            for (uint32_t o = threadIdx.x;;) {
                 // the next entries are requested before this batch's LDS atomics
-                const uint64_t en = e + (uint64_t)kUnroll * kRegionWG;
+                const uint32_t on = o + (uint32_t)(kUnroll * kRegionWG);
                 RawEntry w[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++)
-                    w[u] = fetch(en + (uint64_t)u * kRegionWG, R.e1);
+                    w[u] = fetch(R.e0, on + (uint32_t)u * kRegionWG, R.n);
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
                     if (v[u].hi == ~0u)
@@ -1000,9 +1006,9 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                     atomicAdd(&hits[local], 1u);
                     atomicMin(&first[local], t_of(v[u]));
                 }
-                if (en >= R.e1)
+                if (on - threadIdx.x >= R.n)
                     break;
-                e = en;
+                o = on;
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++)
                     v[u] = w[u];
