@@ -604,6 +604,17 @@ def random_read_rate(words, n: int = 1 << 26, reps: int = 3) -> float:
     return n / best
 
 
+def survey_random_rates(footprint: int, ops: int = 1 << 27) -> dict:
+    """Uniform-random operations per second over a buffer of the countBF's
+    size, measured in this run by the library's microbenchmarks: 64-bit
+    load + compare-and-swap increments (a saturating counter update), 8-byte
+    reads and 32-bit atomicMin (a first-seen claim)."""
+    from paper_2305_07545_amd import microbench as mb
+    return {"rmw64_per_s": mb.rate("cas64", footprint, ops),
+            "read64_per_s": mb.rate("read64", footprint, ops),
+            "min32_per_s": mb.rate("min32", footprint, ops)}
+
+
 def classified_positions(plan, n_bases, k_h):
     """Positions an insert's classification rereads against the final
     countBF: with one hash function the binned paths' last region pass marks
@@ -624,12 +635,16 @@ def carried_positions(plan):
 
 def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n_chunks,
                   partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate, classified,
-                  carried=0):
-    """The whole step against two bounds.
+                  carried=0, rates=None):
+    """The whole step against three bounds.
     survey_model: the per-insertion byte model of a countBF insert (k_h
     random 64-bit read-modify-writes of 16 B, one 8 B pre-chunk counter read
     for first-seen, 16 B per new k-mer for its claim and its key, the input
     bytes per insertion and 1/8 B of flags) at the nominal 8 TB/s.
+    survey_model_measured_rates: the time the same operations take at the
+    uniform-random update, read and claim rates measured over the countBF's
+    footprint in this run (frac = that time / the measured step: above 1
+    when the step beats a random-access implementation of the operations).
     design_bound: this design's own floor, each phase's algorithmic bytes at
     the copy bandwidth measured in this run, the hashing kernel's integer
     operations at the VALU peak, and the classification's random countBF
@@ -654,10 +669,25 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
                                   partitioned, key_bytes=kb, carried=carried) / copy_Bps
         per_phase[ph] = round(t * 1e3, 3)
     bound_ms = sum(per_phase.values())
+    measured = None
+    if rates:
+        # the survey's per-insertion operations at the random-access rates
+        # measured over the countBF's footprint: a saturating 64-bit update
+        # per hash function, the pre-chunk counter read of first-seen, a
+        # 32-bit claim and its check read per new k-mer, and the streamed
+        # input, keys and flags at the copy rate
+        t = (n_windows * k_h / rates["rmw64_per_s"] + n_windows / rates["read64_per_s"] +
+             n_distinct * (1 / rates["min32_per_s"] + 1 / rates["read64_per_s"]) +
+             (n_bases + 8 * n_distinct + n_windows / 8) / copy_Bps)
+        measured = {"allowed_ms": round(t * 1e3, 3), "measured_ms": round(ms_per_step, 3),
+                    "frac": round(t * 1e3 / ms_per_step, 4),
+                    "rates": {k_: round(v / 1e9, 2) for k_, v in rates.items()},
+                    "rates_unit": "G ops/s"}
     return {
         "survey_model": {"bytes_per_insertion": round(b_ins, 3),
                          "achieved_GBps": round(achieved, 1), "peak_GBps": HBM_PEAK_GBS,
                          "frac": round(achieved / HBM_PEAK_GBS, 4)},
+        "survey_model_measured_rates": measured,
         "design_bound": {"bound_ms": round(bound_ms, 3), "measured_ms": round(ms_per_step, 3),
                          "frac": round(bound_ms / ms_per_step, 4),
                          "copy_GBps_measured": round(copy_Bps / 1e9, 1),
@@ -777,6 +807,7 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
                            carried=carried)
     copy_Bps = copy_bandwidth(dev)
     rand = random_read_rate(words)
+    rates = survey_random_rates(X * Y * 8)
     out = {
         "value": n_windows * steps / elapsed, "unit": "insertions/s", "ms_per_step": ms_step,
         "steps": steps, "warmup": warmup,
@@ -792,7 +823,7 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
         "step_roofline": step_roofline(phases_per_step(phases, profile_steps), 1, n_bases,
                                        n_windows, n_distinct, k_h, X * Y, n_chunks, partitioned,
                                        alpha, k, ms_step, copy_Bps, rand, classified,
-                                       carried),
+                                       carried, rates),
         "hbm_rooflines": hbm_rooflines(phases, profile_steps, n_bases, n_windows, n_distinct,
                                        k_h, X * Y, workload, n_chunks, partitioned, k,
                                        classified, carried),
