@@ -122,7 +122,10 @@ uint64_t kc_filter_bytes(const kc_layout *layout);
  * bases and classifications of up to max_bases keys: its status word and
  * what kc_reserve(max_bases) allocates on a new handle (the per-position and
  * per-tile buffers and the binned, partitioned or direct path's scratch, as
- * kc_insert would size them), each piece rounded up to 256 bytes.  It is the
+ * kc_insert would size them, and, for an insert of several chunks with one
+ * hash function, the carried first-seen records of kc_insert_classify: 6
+ * bytes per position before the last chunk, see kc_get_plan), each piece
+ * rounded up to 256 bytes.  It is the
  * scratch_bytes kc_create_in needs for that max_bases, and lets callers
  * budget HBM before creating handles.  0 for an invalid layout.  Host only,
  * pure: it counts the allocations without making them and touches no
