@@ -456,6 +456,52 @@ def _batched_leg(args, dev, sets, stream, t_gen):
     return res
 
 
+def serving_digests_ok(args, w, server, sessions, dims, res, outs):
+    """The paced run against the oracle's digests of the serving trace: every
+    request's counts, every session's final words and distinct list, and
+    each session's last classification (its outputs are the last written to
+    the session's lists).  None without digests for this trace."""
+    import hashlib
+
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "serving_digests.json")
+    if args.no_verify or not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    if ref["duration_s"] != args.serving_seconds or ref["n_requests"] != len(w.requests):
+        return None
+
+    def h(a):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
+
+    try:
+        for s in ref["sessions"]:
+            g = s["session"]
+            X, Y = dims[g]
+            if (s["X"], s["Y"], s["k"]) != (X, Y, w.ks[g]):
+                return False
+            for r in s["requests"]:
+                got = res[r["request"]]
+                if (got["n_windows"], got["n_new"]) != (r["n_windows"], r["n_new"]):
+                    return False
+                if "n_trust" in r and (got["n_trust"], got["n_err"]) != (r["n_trust"],
+                                                                         r["n_err"]):
+                    return False
+            if h(server.read_words(sessions[g], X * Y)) != s["words_sha256"]:
+                return False
+            if h(server.read_distinct(sessions[g], 0, s["n_distinct"])) != s["distinct_sha256"]:
+                return False
+            lc = s["last_classify"]
+            if lc:
+                nt, ne = res[lc["request"]]["n_trust"], res[lc["request"]]["n_err"]
+                if h(outs[g][0][:nt].cpu().numpy().view(np.uint64)) != lc["trust_sha256"] or \
+                        h(outs[g][1][:ne].cpu().numpy().view(np.uint64)) != lc["err_sha256"]:
+                    return False
+    except Exception:  # a list shorter than the oracle's cannot be read that far
+        return False
+    return True
+
+
 def serving_leg(args, dev):
     """The serving trace replayed in real time: Poisson arrivals (50/s) of
     insert / insert+classify requests on 16 device-resident sessions under a
@@ -512,6 +558,7 @@ def serving_leg(args, dev):
 
     res = serve.replay(server, [q.t for q in w.requests], submit)
     st = server.stats()
+    verified = serving_digests_ok(args, w, server, sessions, dims, res, outs)
     server.close_server()
 
     # capacity: the same requests all submitted at once to fresh sessions
@@ -543,6 +590,7 @@ def serving_leg(args, dev):
         "latency": serve.latency_summary(res),
         "checks": {"statuses_ok_and_lists_contiguous": bool(ok),
                    "windows_equal_sum_of_L_minus_k_plus_1": windows == expect_windows},
+        "verified_vs_oracle_digests": verified,
         "memory_budget_bytes": budget, "session_bytes": st["session_bytes"],
         "staging_bytes": st["staging_bytes"], "batches": st["batches"],
         "batched_requests": st["batched_requests"], "plain_requests": st["plain_requests"],

@@ -5,9 +5,17 @@ path's outputs against these stored digests.  Usage:
 
     python tests/golden/make_digests.py tiny bacterial batched bacterial_k55
     python tests/golden/make_digests.py fullchunk_4201x4211 fullchunk_2621x2657 fullchunk_5801x5807
+    python tests/golden/make_digests.py serving
 
 The batched workload (256 independent read sets, each with its own countBF)
-is stored set by set; its sets run in parallel host processes.
+is stored set by set; its sets run in parallel host processes.  The serving
+trace (16 sessions, 247 requests) is stored session by session: each
+session's requests in submission order (a request inserts its reads into
+its session's countBF, and a classify request then splits the session's
+whole distinct list at its tau), per request the k-mers inserted, the
+first-seen k-mers added and the classification's counts, per session the
+final countBF words, the distinct list and its last classification; the
+sessions run in parallel host processes.
 """
 import hashlib
 import json
@@ -105,6 +113,51 @@ def batched_digests(scale: float = 1.0, workers: int = 8) -> dict:
             "sets": per_set}
 
 
+_SERVING = []
+
+
+def _serving_session(g: int) -> dict:
+    w = _SERVING[0]
+    X, Y = oracle.dims(w.n_items[g], 0.001)
+    k = w.ks[g]
+    bf = oracle.CountBF(X, Y)
+    reqs, lists, last = [], [], None
+    for i, q in enumerate(w.requests):
+        if q.genome != g:
+            continue
+        reads, offs = w.request_reads(i)
+        d, nw = bf.insert(reads, offs, k)
+        lists.append(d)
+        r = {"request": i, "n_windows": nw, "n_new": len(d)}
+        if q.classify:
+            t, e = bf.classify(np.concatenate(lists), q.tau)
+            r.update({"tau": q.tau, "n_trust": len(t), "n_err": len(e)})
+            last = {"request": i, "trust_sha256": sha(t), "err_sha256": sha(e)}
+        reqs.append(r)
+    distinct = np.concatenate(lists) if lists else np.zeros(0, dtype=np.uint64)
+    return {"session": g, "k": k, "X": X, "Y": Y, "n_distinct": len(distinct),
+            "words_sha256": sha(bf.words), "distinct_sha256": sha(distinct),
+            "last_classify": last, "requests": reqs}
+
+
+def serving_digests(duration_s: float = 5.0, workers: int = 8) -> dict:
+    w = synth.serving_workload(duration_s=duration_s)
+    _SERVING[:] = [w]
+    vol = [0] * len(w.ks)
+    for i, q in enumerate(w.requests):
+        vol[q.genome] += w.request_bases(i)
+    order = sorted(range(len(w.ks)), key=lambda g: -vol[g])  # largest first
+    t = time.time()
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        done = pool.map(_serving_session, order, chunksize=1)
+    sessions = sorted(done, key=lambda d: d["session"])
+    return {"workload": "serving", "duration_s": duration_s, "alpha": 8, "k_h": 1,
+            "n_requests": len(w.requests), "n_bases": sum(vol),
+            "n_windows": sum(r["n_windows"] for s in sessions for r in s["requests"]),
+            "oracle_seconds_wall": round(time.time() - t, 2), "oracle_processes": workers,
+            "sessions": sessions}
+
+
 if __name__ == "__main__":
     oracle.build(force=False)
     # names: tiny, bacterial, batched, large, or <workload>_k<k> (another k)
@@ -112,6 +165,8 @@ if __name__ == "__main__":
         base, _, kk = name.partition("_k")
         if name == "batched":
             d = batched_digests()
+        elif name == "serving":
+            d = serving_digests()
         elif name in INPUTS:
             d = input_digests(name)
         else:
@@ -119,4 +174,4 @@ if __name__ == "__main__":
         path = os.path.join(HERE, f"{name}_digests.json")
         with open(path, "w") as f:
             json.dump(d, f, indent=1)
-        print(path, {k: v for k, v in d.items() if k != "sets"})
+        print(path, {k: v for k, v in d.items() if k not in ("sets", "sessions")})

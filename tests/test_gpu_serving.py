@@ -223,3 +223,68 @@ def test_request_errors(workload):
     with pytest.raises(P.KmercoError):
         server.submit(s, reads, offs)  # closed session
     server.close_server()
+
+
+def test_full_scale_trace_against_oracle_digests():
+    """The whole serving trace at full size (247 requests, 16.1 Gbases, 16
+    sessions of 75-505 MB), all requests submitted at once on two lanes:
+    every request's inserted and first-seen counts and classification
+    counts, every session's final countBF words and distinct list, and each
+    session's last classification equal the oracle's (digests written by
+    tests/golden/make_digests.py serving)."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "serving_digests.json")
+    if not os.path.exists(path):
+        pytest.skip("no oracle digests for the serving trace")
+    ref = json.load(open(path))
+
+    def sha(a):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=np.uint64).tobytes()).hexdigest()
+
+    print("case serving full scale: generating the trace", flush=True)
+    w = synth.serving_workload(duration_s=ref["duration_s"])
+    assert len(w.requests) == ref["n_requests"]
+    dims = [P.dims(n) for n in w.n_items]
+    cap = [int(math.ceil(1.2 * d)) + 4096 for d in w.expected_distinct]
+    server = P.Server(memory_budget=200 * 10**9,
+                      lane_bases=max(w.request_bases(i) for i in range(len(w.requests))),
+                      lane_reads=max(q.n_reads for q in w.requests), lane_requests=64, lanes=2)
+    sessions = [server.open(X, Y, w.ks[g], cap[g]) for g, (X, Y) in enumerate(dims)]
+    outs = [(torch.empty(c, dtype=torch.int64, device="cuda"),
+             torch.empty(c, dtype=torch.int64, device="cuda")) for c in cap]
+    bufs = [w.request_reads(i) for i in range(len(w.requests))]
+
+    def submit(i):
+        q = w.requests[i]
+        kw = {}
+        if q.classify:
+            kw = {"classify": True, "tau": q.tau, "trust": outs[q.genome][0],
+                  "err": outs[q.genome][1]}
+        return server.submit(sessions[q.genome], bufs[i][0], bufs[i][1], **kw)
+
+    print("case serving full scale: all requests at once", flush=True)
+    res = serve.replay(server, [0.0] * len(w.requests), submit)
+    for s in ref["sessions"]:
+        g = s["session"]
+        X, Y = dims[g]
+        assert (s["X"], s["Y"], s["k"]) == (X, Y, w.ks[g]), f"session {g}: layout"
+        for r in s["requests"]:
+            got = res[r["request"]]
+            assert got["status"] == 0, f"request {r['request']}: status"
+            assert (got["n_windows"], got["n_new"]) == (r["n_windows"], r["n_new"]), \
+                f"request {r['request']}: counts"
+            if "n_trust" in r:
+                assert (got["n_trust"], got["n_err"]) == (r["n_trust"], r["n_err"]), \
+                    f"request {r['request']}: classification counts"
+        assert sha(server.read_words(sessions[g], X * Y)) == s["words_sha256"], f"session {g}"
+        assert sha(server.read_distinct(sessions[g], 0, s["n_distinct"])) == \
+            s["distinct_sha256"], f"session {g}: distinct list"
+        lc = s["last_classify"]
+        if lc:
+            nt, ne = res[lc["request"]]["n_trust"], res[lc["request"]]["n_err"]
+            t, e = outs[g]
+            assert sha(t[:nt].cpu().numpy().view(np.uint64)) == lc["trust_sha256"], f"session {g}"
+            assert sha(e[:ne].cpu().numpy().view(np.uint64)) == lc["err_sha256"], f"session {g}"
+    server.close_server()
