@@ -19,10 +19,11 @@ form.  Every leg is checked against the oracle's digests.
 Kernel times: a few untimed steps with every kernel bracketed by HIP events
 give the per-phase breakdown ("phases"); during the timed steps the library
 records events around the dominant kernel only, whose average launch gives
-the roofline.  "step_roofline" prices the whole step: the survey's per-
-insertion byte model against 8 TB/s, and this design's own bound (each
-phase's algorithmic bytes at the copy bandwidth measured in the same run,
-plus the hashing kernel's integer operations at the VALU peak).
+the roofline.  "step_roofline" prices the whole step: the per-insertion
+byte model of a random-access countBF insert against 8 TB/s and at the
+random-access rates measured in the same run, and this design's own bound
+(each phase's algorithmic bytes at the copy bandwidth measured in the same
+run, plus the hashing kernel's integer operations at the VALU peak).
 
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
@@ -652,7 +653,7 @@ def random_read_rate(words, n: int = 1 << 26, reps: int = 3) -> float:
     return n / best
 
 
-def survey_random_rates(footprint: int, ops: int = 1 << 27) -> dict:
+def random_access_rates(footprint: int, ops: int = 1 << 27) -> dict:
     """Uniform-random operations per second over a buffer of the countBF's
     size, measured in this run by the library's microbenchmarks: 64-bit
     load + compare-and-swap increments (a saturating counter update), 8-byte
@@ -685,11 +686,11 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
                   partitioned, alpha, k, ms_per_step, copy_Bps, rand_rate, classified,
                   carried=0, rates=None):
     """The whole step against three bounds.
-    survey_model: the per-insertion byte model of a countBF insert (k_h
+    random_access_model: the per-insertion byte model of a countBF insert (k_h
     random 64-bit read-modify-writes of 16 B, one 8 B pre-chunk counter read
     for first-seen, 16 B per new k-mer for its claim and its key, the input
     bytes per insertion and 1/8 B of flags) at the nominal 8 TB/s.
-    survey_model_measured_rates: the time the same operations take at the
+    random_access_model_measured_rates: the time the same operations take at the
     uniform-random update, read and claim rates measured over the countBF's
     footprint in this run (frac = that time / the measured step: above 1
     when the step beats a random-access implementation of the operations).
@@ -719,7 +720,7 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
     bound_ms = sum(per_phase.values())
     measured = None
     if rates:
-        # the survey's per-insertion operations at the random-access rates
+        # the model's per-insertion operations at the random-access rates
         # measured over the countBF's footprint: a saturating 64-bit update
         # per hash function, the pre-chunk counter read of first-seen, a
         # 32-bit claim and its check read per new k-mer, and the streamed
@@ -732,10 +733,10 @@ def step_roofline(phases, steps, n_bases, n_windows, n_distinct, k_h, n_words, n
                     "rates": {k_: round(v / 1e9, 2) for k_, v in rates.items()},
                     "rates_unit": "G ops/s"}
     return {
-        "survey_model": {"bytes_per_insertion": round(b_ins, 3),
+        "random_access_model": {"bytes_per_insertion": round(b_ins, 3),
                          "achieved_GBps": round(achieved, 1), "peak_GBps": HBM_PEAK_GBS,
                          "frac": round(achieved / HBM_PEAK_GBS, 4)},
-        "survey_model_measured_rates": measured,
+        "random_access_model_measured_rates": measured,
         "design_bound": {"bound_ms": round(bound_ms, 3), "measured_ms": round(ms_per_step, 3),
                          "frac": round(bound_ms / ms_per_step, 4),
                          "copy_GBps_measured": round(copy_Bps / 1e9, 1),
@@ -855,7 +856,7 @@ def plain_leg(args, dev, workload, steps, warmup, profile_steps, keep=False, ext
                            carried=carried)
     copy_Bps = copy_bandwidth(dev)
     rand = random_read_rate(words)
-    rates = survey_random_rates(X * Y * 8)
+    rates = random_access_rates(X * Y * 8)
     out = {
         "value": n_windows * steps / elapsed, "unit": "insertions/s", "ms_per_step": ms_step,
         "steps": steps, "warmup": warmup,
