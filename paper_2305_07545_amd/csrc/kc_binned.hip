@@ -830,14 +830,28 @@ __device__ __forceinline__ uint64_t region_cell(const FilterArgs &F, const BinPl
     return next;
 }
 
+// s_waitcnt vmcnt(0) in the gfx9 encoding, with expcnt and lgkmcnt left
+// open: a wavefront's vector loads and stores all complete.
+constexpr int kWaitVmem = 0x0F70;
+
 // Region lists of 6-byte entries (both binned paths).  kCounters: the LDS
 // arrays' size, the plan's counters per region (16384: 144 KiB of LDS, one
-// workgroup per CU; 8192: 72 KiB, two per CU).  The grid is persistent:
-// workgroup g takes regions g, g + gridDim.x, ...; the next region's bounds,
-// first batch of entries and cells are requested before the current one is
-// worked on, so that their latency overlaps its LDS work (a workgroup that
-// holds the CU's LDS alone has nobody else to hide it).
-template <int kCounters>
+// workgroup per CU; 8192: 72 KiB, two per CU).  kHold: cells per thread held
+// in registers; regions of up to kHold x kRegionWG cells take the held paths
+// (the launcher picks the fewest that hold the plan's regions, which leaves
+// registers for the prefetch).
+//
+// The grid is persistent: workgroup g takes regions g, g + gridDim.x, ....
+// A workgroup that holds the CU's LDS alone has nobody else to hide its
+// memory latency, so the next region's first batch of entries and cells
+// (and first carried records) are requested before the current region is
+// worked on, and the bounds that give their addresses one region earlier
+// still.  A wavefront's loads and stores share one completion counter, and
+// the wait for loads issued before a store must wait for the store too: the
+// region's own stores (cell write-back, winner count) are therefore issued
+// after the next region's requests, and the only wait for memory is where
+// the next region's data moves into the current one's registers.
+template <int kCounters, int kHold>
 __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0, BinPlan B,
                                                       const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ n_entries,
@@ -846,7 +860,6 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                                                       uint32_t tau, uint32_t *__restrict__ n_win,
                                                       Carry C) {
     constexpr int kUnroll = 8;
-    constexpr int kHold = 4;  // cells per thread held in registers (regions <= 4096 cells)
     constexpr uint32_t kSparseCells = kCounters / 8;  // cells of a region the sparse path stages
     constexpr uint32_t kDone = 0xFFFFFFFEu;  // first[] of a counter already updated
     static_assert(kSparseCells <= (uint32_t)kHold * kRegionWG, "sparse cells are held");
@@ -866,6 +879,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         uint32_t e0, n;
         uint64_t wbase;
         uint32_t nw;
+        uint32_t c_off, c_n;  // carried chunk 0's records of the region
     };
     // entry e0 + off of a region of n entries as loaded (hi = ~0u past its
     // end); decoded where it is used, so that prefetched loads stay in
@@ -882,17 +896,51 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         return (e.lo >> kLocalBits) | (e.hi << (32 - kLocalBits));
     };
     auto hold_of = [&](const Region &R) { return R.nw <= (uint32_t)kHold * kRegionWG; };
-    // region r's bounds, first batch of entries and (when held) cells
-    auto request = [&](uint32_t r, Region &R, RawEntry(&v)[kUnroll], uint64_t(&cell)[kHold]) {
+    // Carried records are classified only where the regions fit the sparse
+    // tile (the launcher rejects a carry otherwise): in the instance that
+    // holds the tile's cells.
+    constexpr bool kTile = (uint32_t)kHold * kRegionWG == kSparseCells;
+    const bool carry_in = kTile && C.mode == Carry::kIn && C.n_prev > 0;
+    struct Bounds {
+        uint32_t e0, e1;      // the region's entries
+        uint32_t c_off, c_n;  // carried chunk 0's records of the region
+    };
+    // region r's bounds, requested as vector loads by lanes 0 (entry start)
+    // and 1 (entry end) of every wavefront, and with carried records by
+    // lanes 2 (record offset) and 3 (record count); bounds_of reads them out
+    auto bounds = [&](uint32_t r) -> uint32_t {
+        const uint32_t lane = threadIdx.x & 63u;
+        uint32_t x = 0;
+        if (r < B.n_regions && lane < 2u) {
+            const uint32_t rr = r + lane;
+            x = rr < B.n_regions ? offsets[(uint64_t)rr * B.G] : *n_entries;
+        } else if (r < B.n_regions && carry_in && lane < 4u) {
+            x = lane == 2u ? C.off[r] : C.n[r];
+        }
+        return x;
+    };
+    auto bounds_of = [](uint32_t x) -> Bounds {
+        return Bounds{(uint32_t)__builtin_amdgcn_readlane((int)x, 0),
+                      (uint32_t)__builtin_amdgcn_readlane((int)x, 1),
+                      (uint32_t)__builtin_amdgcn_readlane((int)x, 2),
+                      (uint32_t)__builtin_amdgcn_readlane((int)x, 3)};
+    };
+    // region r's first batch of entries and (when held) cells
+    auto request = [&](uint32_t r, Bounds b, Region &R, RawEntry(&v)[kUnroll],
+                       uint64_t(&cell)[kHold], uint32_t &ch) {
         const uint32_t cap = B.entries_cap < 0xFFFFFFFFull ? (uint32_t)B.entries_cap : 0xFFFFFFFFu;
-        const uint32_t e0 = offsets[(uint64_t)r * B.G];
-        uint32_t e1 = r + 1 < B.n_regions ? offsets[(uint64_t)(r + 1) * B.G] : *n_entries;
+        const uint32_t e0 = b.e0;
+        uint32_t e1 = b.e1;
         if (e1 > cap)
             e1 = cap;
         R.e0 = e0;
         R.n = e1 > e0 ? e1 - e0 : 0u;
         R.wbase = (uint64_t)(B.region0 + r) << B.region_shift;
         R.nw = R.wbase + S <= n_words ? S : (uint32_t)(n_words - R.wbase);
+        R.c_off = b.c_off;
+        R.c_n = carry_in ? b.c_n : 0u;
+        // the first carried record of each thread
+        ch = threadIdx.x < R.c_n ? C.half[(uint64_t)R.c_off + threadIdx.x] : 0u;
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
             v[u] = fetch(R.e0, threadIdx.x + (uint32_t)u * kRegionWG, R.n);
@@ -909,17 +957,50 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     Region R;
     RawEntry v[kUnroll];
     uint64_t cell[kHold];
-    request(r, R, v, cell);
+    uint32_t ch;
+    request(r, bounds_of(bounds(r)), R, v, cell, ch);
+    uint32_t bn = bounds(r + gridDim.x);
+    // the first region's data in place before the loop, so that no path
+    // into the loop head has loads in flight
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    // stores deferred from the previous region to just after the next
+    // region's requests: its changed cells (sparse path) and its winner
+    // count
+    constexpr int kSparseHold = (int)(kSparseCells / kRegionWG);
+    static_assert(kSparseHold >= 1 && kSparseHold <= kHold, "sparse cells per thread");
+    uint64_t pc[kSparseHold];
+    uint32_t pmask = 0;  // bit k: pc[k] is to be written (per thread)
+    uint64_t pbase = 0;
+    uint32_t p_r = ~0u, p_e0 = 0, p_n = 0;  // region, first entry, winner count
+    const bool carry_out = C.mode == Carry::kOut;
+    auto flush = [&]() {
+#pragma unroll
+        for (int k = 0; k < kSparseHold; k++)
+            if (pmask & (1u << k))
+                F.words[pbase + threadIdx.x + (uint32_t)k * kRegionWG] = pc[k];
+        pmask = 0;
+        if (threadIdx.x == 0 && p_r != ~0u) {
+            if (carry_out) {
+                C.off[(uint64_t)C.chunk * C.stride + p_r] = p_e0;
+                C.n[(uint64_t)C.chunk * C.stride + p_r] = p_n;
+            } else if (n_win) {
+                n_win[p_r] = p_n;
+            }
+        }
+        p_r = ~0u;
+    };
     for (;;) {
         const uint32_t rn = r + gridDim.x;
         Region Rn{};
         RawEntry vn[kUnroll];
         uint64_t celln[kHold];
+        uint32_t chn = 0;
         if (rn < B.n_regions)
-            request(rn, Rn, vn, celln);
+            request(rn, bounds_of(bn), Rn, vn, celln, chn);
+        const uint32_t bn2 = bounds(rn + gridDim.x);
+        flush();
         if (threadIdx.x == 0)
             s_nwin = 0;
-        const bool carry_out = C.mode == Carry::kOut;
         const WinnerSink out{flags,
                              c0,
                              carry_out ? C.word + (uint64_t)C.chunk * C.cap
@@ -979,11 +1060,13 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                         put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u, local);
                 }
             __syncthreads();
+            pbase = R.wbase;
 #pragma unroll
-            for (int k = 0; k < kHold; k++) {
+            for (int k = 0; k < kSparseHold; k++) {
                 const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-                if (w < R.nw && s_cell[w] != cell[k])
-                    F.words[R.wbase + w] = s_cell[w];
+                pc[k] = s_cell[w];
+                if (w < R.nw && pc[k] != cell[k])
+                    pmask |= 1u << k;
             }
         } else {
             for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
@@ -1013,6 +1096,10 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                 for (int u = 0; u < kUnroll; u++)
                     v[u] = w[u];
             }
+            // none of this path's loads in flight where it joins the sparse
+            // path, whose registers it shares: the compiler would otherwise
+            // wait for every load and store there, the next region's too
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
             __syncthreads();
             if (hold_of(R)) {
 #pragma unroll
@@ -1021,7 +1108,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                     if (w < R.nw) {
                         const uint64_t next =
                             region_cell(F, B, R.wbase, w, cell[k], hits, first, out, classify, tau);
-                        if (C.mode == Carry::kIn)  // the launcher checked nw <= kSparseCells
+                        if (kTile && C.mode == Carry::kIn)
                             s_cell[w] = next;
                     }
                 }
@@ -1032,41 +1119,66 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             }
         }
         __syncthreads();  // the region's LDS work and its winner count are complete
-        if (C.mode == Carry::kIn) {
+        if (kTile && C.mode == Carry::kIn) {
             // the carried records of this region: trustworthy (3) when the
-            // counter's final value, now staged in s_cell, is above tau
-            for (uint32_t j = 0; j < C.n_prev; j++) {
+            // counter's final value, now staged in s_cell, is above tau.
+            // Chunk 0's records were requested with the region (the first
+            // per thread) and its offset and count a region earlier, so that
+            // in the common case nothing here waits for memory.
+            auto mark = [&](uint32_t local) -> uint16_t {
+                const uint64_t cv = s_cell[local & (S - 1u)];
+                const uint64_t f = (cv >> (F.alpha * (local >> B.region_shift))) & F.field_max;
+                return f > (uint64_t)tau ? 3u : 1u;
+            };
+            if (threadIdx.x < R.c_n)
+                C.half[(uint64_t)R.c_off + threadIdx.x] = mark(ch);
+            for (uint32_t i = threadIdx.x + kRegionWG; i < R.c_n; i += kRegionWG)
+                C.half[(uint64_t)R.c_off + i] = mark(C.half[(uint64_t)R.c_off + i]);
+            for (uint32_t j = 1; j < C.n_prev; j++) {
                 const uint64_t at = (uint64_t)j * C.stride + r;
                 const uint64_t x0 = (uint64_t)j * C.cap + C.off[at];
                 const uint32_t n = C.n[at];
-                for (uint32_t i = threadIdx.x; i < n; i += kRegionWG) {
-                    const uint32_t local = C.half[x0 + i];
-                    const uint64_t cv = s_cell[local & (S - 1u)];
-                    const uint64_t f = (cv >> (F.alpha * (local >> B.region_shift))) & F.field_max;
-                    C.half[x0 + i] = f > (uint64_t)tau ? 3u : 1u;
-                }
+                for (uint32_t i = threadIdx.x; i < n; i += kRegionWG)
+                    C.half[x0 + i] = mark(C.half[x0 + i]);
             }
             __syncthreads();  // s_cell is rewritten by the next region
         }
-        if (threadIdx.x == 0) {
-            if (carry_out) {
-                C.off[(uint64_t)C.chunk * C.stride + r] = (uint32_t)R.e0;
-                C.n[(uint64_t)C.chunk * C.stride + r] = s_nwin;
-            } else if (n_win) {
-                n_win[r] = s_nwin;
-            }
-        }
-        if (rn >= B.n_regions)
-            break;
+        // the region's winner count (wavefront-uniform; thread 0 writes it)
+        p_r = r;
+        p_e0 = R.e0;
+        p_n = __builtin_amdgcn_readfirstlane(s_nwin);
+        // the next region's data moves in on every path (also past the last
+        // region): a path that skipped it would leave loads in flight at the
+        // loop head, and the compiler would wait for them (and for every
+        // store) at the head of the next region
         r = rn;
         R = Rn;
+        bn = bn2;
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
             v[u] = vn[u];
 #pragma unroll
         for (int k = 0; k < kHold; k++)
             cell[k] = celln[k];
+        ch = chn;
+        if (r >= B.n_regions)
+            break;
     }
+    flush();
+}
+
+// The region pass's instance for a plan: the plan's counters per region,
+// and two cells per thread (one with 8192 counters) where the regions fit the
+// sparse tile, else four.
+using RegionKernel = void (*)(FilterArgs, uint64_t, BinPlan, const uint32_t *, const uint32_t *,
+                              uint64_t *, uint8_t *, int, uint32_t, uint32_t *, Carry);
+RegionKernel region_kernel(const BinPlan &B) {
+    const bool sparse_tile = carry_fits(B);
+    if (B.region_counters == kSmallRegionCounters)
+        return sparse_tile ? k_region<kSmallRegionCounters, kSmallRegionCounters / 8 / kRegionWG>
+                           : k_region<kSmallRegionCounters, 4>;
+    return sparse_tile ? k_region<kRegionCounters, kRegionCounters / 8 / kRegionWG>
+                       : k_region<kRegionCounters, 4>;
 }
 
 // Workgroups of the persistent region pass: as many as the CUs hold at once
@@ -1588,9 +1700,7 @@ hipError_t launch_parts_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t 
         if (P)
             P->begin(kPhRegion, s);
         const bool rec = carry.mode != Carry::kOut && records_mode(c1 - c0);
-        hipLaunchKernelGGL((Q.region_counters == kSmallRegionCounters
-                                ? k_region<kSmallRegionCounters>
-                                : k_region<kRegionCounters>),
+        hipLaunchKernelGGL(region_kernel(Q),
                            dim3(region_grid(Q.n_regions, Q.region_counters)), dim3(kRegionWG),
                            0, s, F, c0, Q,
                            (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
@@ -1674,9 +1784,7 @@ hipError_t launch_binned_chunk(const FilterArgs &F, const ReadsArgs &R, uint64_t
     if (P)
         P->begin(kPhRegion, s);
     const bool rec = carry.mode != Carry::kOut && records_mode(c1 - c0);
-    hipLaunchKernelGGL((B.region_counters == kSmallRegionCounters
-                            ? k_region<kSmallRegionCounters>
-                            : k_region<kRegionCounters>),
+    hipLaunchKernelGGL(region_kernel(B),
                        dim3(region_grid(B.n_regions, B.region_counters)), dim3(kRegionWG), 0,
                        s, F, c0, B,
                        (const uint32_t *)W.matrix, (const uint32_t *)W.n_entries, W.entries,
