@@ -1218,32 +1218,65 @@ constexpr uint32_t kWinSlices = 64;        // level-B workgroups per level-A buc
 constexpr uint32_t kWinBuckets = 256;
 constexpr uint32_t kWinBlocksPerBucket = 1u << (kWinA - kWinB);
 
-// The batch s_rec[0..n) appended to buckets by digit (rec >> shift) & (nd - 1)
-// (nd <= kWinThreads): counted in LDS, one cursor bump per digit, then each
-// record written at its digit's base plus its rank (the records of a digit
-// fill one run; their order inside it does not matter).  keep(rec) is the
-// record written.  Ends with a barrier, so that the batch can be refilled.
+constexpr int kWinPer = kWinBatch / kWinThreads;  // records per thread and batch
+static_assert(kWinBuckets <= 256 && kWinBlocksPerBucket <= 256, "digits are staged as bytes");
+
+// A batch of records appended to buckets by digit d = (rec >> shift) & (nd
+// - 1): record u of this thread is v[u] (present where bit u of ok is set).
+// The records are ranked within their digit by LDS atomics, the digit
+// counts scanned and each digit's run reserved at its bucket's cursor; the
+// kept records (keep(rec)) are then staged in LDS in digit order and written
+// out in that order, consecutive threads to consecutive addresses of a run
+// (the order of records inside a run does not matter).  Ends with a barrier.
 template <typename Rec, typename Keep>
-__device__ void win_flush(const Rec *s_rec, uint32_t n, uint32_t shift, uint32_t nd,
-                          uint32_t bucket0, uint32_t area_log, uint32_t *s_cnt, uint32_t *s_base,
-                          uint32_t *__restrict__ cursor, uint32_t *__restrict__ out, Keep keep) {
+__device__ void win_append(const Rec (&v)[kWinPer], uint32_t ok, uint32_t n, uint32_t shift,
+                           uint32_t nd, uint32_t bucket0, uint32_t area_log, uint32_t *s_cnt,
+                           uint32_t *s_start, uint32_t *s_base, uint32_t *s_wave,
+                           uint32_t *s_stage, uint8_t *s_tag, uint32_t *__restrict__ cursor,
+                           uint32_t *__restrict__ out, Keep keep) {
     for (uint32_t i = threadIdx.x; i < nd; i += kWinThreads)
         s_cnt[i] = 0;
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < n; j += kWinThreads)
-        atomicAdd(&s_cnt[(uint32_t)(s_rec[j] >> shift) & (nd - 1u)], 1u);
+    uint32_t rk[kWinPer];
+#pragma unroll
+    for (int u = 0; u < kWinPer; u++)
+        if (ok & (1u << u))
+            rk[u] = atomicAdd(&s_cnt[(uint32_t)(v[u] >> shift) & (nd - 1u)], 1u);
     __syncthreads();
+    // exclusive scan of the nd (<= 256) counts, 64 per wavefront
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t c = threadIdx.x < nd ? s_cnt[threadIdx.x] : 0u;
+    uint32_t incl = c;
     if (threadIdx.x < nd) {
-        const uint32_t c = s_cnt[threadIdx.x];
-        s_base[threadIdx.x] = c ? atomicAdd(&cursor[bucket0 + threadIdx.x], c) : 0u;
-        s_cnt[threadIdx.x] = 0;  // reused as each digit's rank counter
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d)
+                incl += o;
+        }
+        if (lane == 63 || threadIdx.x == nd - 1)
+            s_wave[wave] = incl;
     }
     __syncthreads();
+    if (threadIdx.x < nd) {
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < wave; w++)
+            before += s_wave[w];
+        s_start[threadIdx.x] = before + incl - c;
+        s_base[threadIdx.x] = c ? atomicAdd(&cursor[bucket0 + threadIdx.x], c) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kWinPer; u++)
+        if (ok & (1u << u)) {
+            const uint32_t d = (uint32_t)(v[u] >> shift) & (nd - 1u);
+            const uint32_t j = s_start[d] + rk[u];
+            s_stage[j] = keep(v[u]);
+            s_tag[j] = (uint8_t)d;
+        }
+    __syncthreads();
     for (uint32_t j = threadIdx.x; j < n; j += kWinThreads) {
-        const Rec r = s_rec[j];
-        const uint32_t d = (uint32_t)(r >> shift) & (nd - 1u);
-        const uint32_t rank = atomicAdd(&s_cnt[d], 1u);
-        out[((uint64_t)(bucket0 + d) << area_log) + s_base[d] + rank] = keep(r);
+        const uint32_t d = s_tag[j];
+        out[((uint64_t)(bucket0 + d) << area_log) + s_base[d] + (j - s_start[d])] = s_stage[j];
     }
     __syncthreads();
 }
@@ -1263,8 +1296,10 @@ __global__ void __launch_bounds__(kWinThreads) k_win_a(uint32_t n_regions,
                                                        uint32_t *__restrict__ cursor,
                                                        uint32_t *__restrict__ out) {
     static_assert(kWinRegions == 64, "one wavefront scans the regions' counts");
-    __shared__ uint64_t s_rec[kWinBatch];
-    __shared__ uint32_t s_cnt[kWinBuckets], s_base[kWinBuckets];
+    __shared__ uint32_t s_stage[kWinBatch];
+    __shared__ uint8_t s_tag[kWinBatch];
+    __shared__ uint32_t s_cnt[kWinBuckets], s_start[kWinBuckets], s_base[kWinBuckets];
+    __shared__ uint32_t s_wave[kWinThreads / 64];
     __shared__ uint32_t s_first[kWinRegions];    // each region's first entry
     __shared__ uint32_t s_pre[kWinRegions + 1];  // records before each region
     const uint32_t r0 = blockIdx.x * kWinRegions;
@@ -1290,18 +1325,26 @@ __global__ void __launch_bounds__(kWinThreads) k_win_a(uint32_t n_regions,
     };
     for (uint32_t q = 0; q < total; q += kWinBatch) {
         const uint32_t m = total - q < (uint32_t)kWinBatch ? total - q : (uint32_t)kWinBatch;
-        for (uint32_t i = threadIdx.x; i < m; i += kWinThreads) {
-            const uint32_t idx = q + i;
-            uint32_t j = 0;  // the last region with s_pre[j] <= idx
+        uint64_t v[kWinPer];
+        uint32_t ok = 0;
 #pragma unroll
-            for (uint32_t step = kWinRegions / 2; step; step >>= 1)
-                if (s_pre[j + step] <= idx)
-                    j += step;
-            const uint64_t x = (uint64_t)s_first[j] + (idx - s_pre[j]);
-            s_rec[i] = ((uint64_t)e_half[x] << 32) | e_word[x];
+        for (int u = 0; u < kWinPer; u++) {
+            const uint32_t i = threadIdx.x + (uint32_t)u * kWinThreads;
+            v[u] = 0;
+            if (i < m) {
+                const uint32_t idx = q + i;
+                uint32_t j = 0;  // the last region with s_pre[j] <= idx
+#pragma unroll
+                for (uint32_t step = kWinRegions / 2; step; step >>= 1)
+                    if (s_pre[j + step] <= idx)
+                        j += step;
+                const uint64_t x = (uint64_t)s_first[j] + (idx - s_pre[j]);
+                v[u] = ((uint64_t)e_half[x] << 32) | e_word[x];
+                ok |= 1u << u;
+            }
         }
-        __syncthreads();
-        win_flush(s_rec, m, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_base, cursor, out, keep);
+        win_append(v, ok, m, kWinA, kWinBuckets, 0, kWinA, s_cnt, s_start, s_base, s_wave,
+                   s_stage, s_tag, cursor, out, keep);
     }
 }
 
@@ -1311,8 +1354,11 @@ __global__ void __launch_bounds__(kWinThreads) k_win_b(const uint32_t *__restric
                                                        const uint32_t *__restrict__ cursor_a,
                                                        uint32_t *__restrict__ cursor_b,
                                                        uint32_t *__restrict__ out) {
-    __shared__ uint32_t s_rec[kWinBatch];
-    __shared__ uint32_t s_cnt[kWinBlocksPerBucket], s_base[kWinBlocksPerBucket];
+    __shared__ uint32_t s_stage[kWinBatch];
+    __shared__ uint8_t s_tag[kWinBatch];
+    __shared__ uint32_t s_cnt[kWinBlocksPerBucket], s_start[kWinBlocksPerBucket],
+        s_base[kWinBlocksPerBucket];
+    __shared__ uint32_t s_wave[kWinThreads / 64];
     const uint32_t a = blockIdx.x;
     const uint32_t n = cursor_a[a];
     const uint32_t per = ((1u << kWinA) + kWinSlices - 1) / kWinSlices;
@@ -1324,12 +1370,18 @@ __global__ void __launch_bounds__(kWinThreads) k_win_b(const uint32_t *__restric
     };
     for (uint32_t q = q0; q < q1; q += kWinBatch) {
         const uint32_t m = q1 - q < (uint32_t)kWinBatch ? q1 - q : (uint32_t)kWinBatch;
-        for (uint32_t i = threadIdx.x; i < m; i += kWinThreads)
-            s_rec[i] = src[q + i];
-        __syncthreads();
+        uint32_t v[kWinPer];
+        uint32_t ok = 0;
+#pragma unroll
+        for (int u = 0; u < kWinPer; u++) {
+            const uint32_t i = threadIdx.x + (uint32_t)u * kWinThreads;
+            v[u] = i < m ? src[q + i] : 0u;
+            if (i < m)
+                ok |= 1u << u;
+        }
         // digit (t24 >> 19) & 31 of the record (t24 | mark << 24)
-        win_flush(s_rec, m, kWinB, kWinBlocksPerBucket, a * kWinBlocksPerBucket, kWinB, s_cnt,
-                  s_base, cursor_b, out, keep);
+        win_append(v, ok, m, kWinB, kWinBlocksPerBucket, a * kWinBlocksPerBucket, kWinB, s_cnt,
+                   s_start, s_base, s_wave, s_stage, s_tag, cursor_b, out, keep);
     }
 }
 
