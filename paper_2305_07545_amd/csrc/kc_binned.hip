@@ -79,6 +79,14 @@ static_assert((32 - kLocalBits) + 16 >= 32, "level-2 entries hold any 32-bit t")
 struct RawEntry {
     uint32_t lo, hi;
 };
+
+// Element at a 32-bit byte offset from a wavefront-uniform base: the address
+// is the base's scalar registers plus one 32-bit vector register, not a
+// 64-bit address per thread.
+template <typename T>
+__device__ __forceinline__ T &at_byte(T *base, uint32_t byte_off) {
+    return *(T *)((char *)base + byte_off);
+}
 static_assert(kStage == (1 << kStageLog), "stage size");
 static_assert(kRegionCounters == (1 << kLocalBits), "region size");
 static_assert(kMaxRegions == (1u << kPartLog), "partition size");
@@ -799,9 +807,9 @@ __device__ __forceinline__ void put_winner(const WinnerSink &o, uint32_t t, uint
         o.flags[o.c0 + t] = (uint8_t)mark;
         return;
     }
-    const uint32_t i = atomicAdd(o.count, 1u);
-    o.rec_t[o.e0 + i] = t;
-    o.rec_m[o.e0 + i] = (uint16_t)(o.carry ? local : mark);
+    const uint32_t i = atomicAdd(o.count, 1u);  // < the region's entries
+    at_byte(o.rec_t + o.e0, 4u * i) = t;
+    at_byte(o.rec_m + o.e0, 2u * i) = (uint16_t)(o.carry ? local : mark);
 }
 
 // Counter update of cell w of the region (pre = its value before the
@@ -811,19 +819,21 @@ __device__ __forceinline__ uint64_t region_cell(const FilterArgs &F, const BinPl
                                                 const uint32_t *hits, const uint32_t *first,
                                                 const WinnerSink &out, int classify,
                                                 uint32_t tau) {
+    // counters are at most 32 bits wide: the field arithmetic is 32-bit
+    const uint32_t fm = (uint32_t)F.field_max;
     uint64_t next = pre;
     for (uint32_t l = 0; l < F.eta; l++) {
         const uint32_t idx = (l << B.region_shift) | w;
-        const uint64_t h = hits[idx];
+        const uint32_t h = hits[idx];
         if (h == 0)
             continue;
         const uint32_t sh = F.alpha * l;
-        const uint64_t pf = (pre >> sh) & F.field_max;
-        const uint64_t room = F.field_max - pf;
-        const uint64_t nf = pf + (h < room ? h : room);
-        next = (next & ~(F.field_max << sh)) | (nf << sh);
+        const uint32_t pf = (uint32_t)(pre >> sh) & fm;
+        const uint32_t room = fm - pf;
+        const uint32_t nf = pf + (h < room ? h : room);
+        next += (uint64_t)(nf - pf) << sh;  // the field grows without carrying out
         if (pf == 0)
-            put_winner(out, first[idx], (classify && nf > (uint64_t)tau) ? 3u : 1u, idx);
+            put_winner(out, first[idx], (classify && nf > tau) ? 3u : 1u, idx);
     }
     if (next != pre)
         F.words[wbase + w] = next;
@@ -884,11 +894,11 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     // entry e0 + off of a region of n entries as loaded (hi = ~0u past its
     // end); decoded where it is used, so that prefetched loads stay in
     // flight until then
-    auto fetch = [&](uint32_t e0, uint32_t off, uint32_t n) -> RawEntry {
+    auto fetch = [&](uint32_t e0, uint32_t ob, uint32_t n) -> RawEntry {  // entry ob + thread
         RawEntry e{~0u, ~0u};
-        if (off < n) {
-            e.lo = e_word[e0 + off];
-            e.hi = e_half[e0 + off];
+        if (ob + threadIdx.x < n) {
+            e.lo = at_byte(e_word + e0 + ob, 4u * threadIdx.x);
+            e.hi = at_byte(e_half + e0 + ob, 2u * threadIdx.x);
         }
         return e;
     };
@@ -943,12 +953,14 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         ch = threadIdx.x < R.c_n ? C.half[(uint64_t)R.c_off + threadIdx.x] : 0u;
 #pragma unroll
         for (int u = 0; u < kUnroll; u++)
-            v[u] = fetch(R.e0, threadIdx.x + (uint32_t)u * kRegionWG, R.n);
+            v[u] = fetch(R.e0, (uint32_t)u * kRegionWG, R.n);
         const bool hold = hold_of(R);
 #pragma unroll
         for (int k = 0; k < kHold; k++) {
             const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
-            cell[k] = (hold && w < R.nw) ? F.words[R.wbase + w] : 0ull;
+            cell[k] = (hold && w < R.nw)
+                          ? at_byte(F.words + R.wbase + (uint32_t)k * kRegionWG, 8u * threadIdx.x)
+                          : 0ull;
         }
     };
     uint32_t r = blockIdx.x;
@@ -977,7 +989,7 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
 #pragma unroll
         for (int k = 0; k < kSparseHold; k++)
             if (pmask & (1u << k))
-                F.words[pbase + threadIdx.x + (uint32_t)k * kRegionWG] = pc[k];
+                at_byte(F.words + pbase + (uint32_t)k * kRegionWG, 8u * threadIdx.x) = pc[k];
         pmask = 0;
         if (threadIdx.x == 0 && p_r != ~0u) {
             if (carry_out) {
@@ -1050,14 +1062,15 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                         continue;
                     const uint32_t w = local & (S - 1u);
                     const uint32_t sh = F.alpha * (local >> B.region_shift);
-                    const uint64_t pf = (s_cell[w] >> sh) & F.field_max;
-                    const uint64_t h = hits[local];
-                    const uint64_t room = F.field_max - pf;
-                    const uint64_t nf = pf + (h < room ? h : room);
-                    if (nf != pf)
-                        atomicAdd(&s_cell[w], (unsigned long long)((nf - pf) << sh));
+                    const uint32_t fm = (uint32_t)F.field_max;  // counters <= 32 bits
+                    const uint32_t pf = (uint32_t)(s_cell[w] >> sh) & fm;
+                    const uint32_t h = hits[local];
+                    const uint32_t room = fm - pf;
+                    const uint32_t inc = h < room ? h : room;
+                    if (inc)
+                        atomicAdd(&s_cell[w], (unsigned long long)inc << sh);
                     if (pf == 0)
-                        put_winner(out, t, (classify && nf > (uint64_t)tau) ? 3u : 1u, local);
+                        put_winner(out, t, (classify && pf + inc > tau) ? 3u : 1u, local);
                 }
             __syncthreads();
             pbase = R.wbase;
@@ -1074,9 +1087,9 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                 first[i] = kIdle;
             }
             __syncthreads();
-            for (uint32_t o = threadIdx.x;;) {
+            for (uint32_t ob = 0;;) {  // the batch's first entry (uniform)
                 // the next entries are requested before this batch's LDS atomics
-                const uint32_t on = o + (uint32_t)(kUnroll * kRegionWG);
+                const uint32_t on = ob + (uint32_t)(kUnroll * kRegionWG);
                 RawEntry w[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++)
@@ -1089,9 +1102,9 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                     atomicAdd(&hits[local], 1u);
                     atomicMin(&first[local], t_of(v[u]));
                 }
-                if (on - threadIdx.x >= R.n)
+                if (on >= R.n)
                     break;
-                o = on;
+                ob = on;
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++)
                     v[u] = w[u];
@@ -1127,8 +1140,9 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
             // in the common case nothing here waits for memory.
             auto mark = [&](uint32_t local) -> uint16_t {
                 const uint64_t cv = s_cell[local & (S - 1u)];
-                const uint64_t f = (cv >> (F.alpha * (local >> B.region_shift))) & F.field_max;
-                return f > (uint64_t)tau ? 3u : 1u;
+                const uint32_t f =
+                    (uint32_t)(cv >> (F.alpha * (local >> B.region_shift))) & (uint32_t)F.field_max;
+                return f > tau ? 3u : 1u;
             };
             if (threadIdx.x < R.c_n)
                 C.half[(uint64_t)R.c_off + threadIdx.x] = mark(ch);
