@@ -813,10 +813,11 @@ __device__ __forceinline__ void put_winner(const WinnerSink &o, uint32_t t, uint
 }
 
 // Counter update of cell w of the region (pre = its value before the
-// chunk); returns the cell's new value.
+// chunk); returns the cell's new value.  Leaves the cell's counters clean
+// (hits 0, first kIdle) for the next region.
 __device__ __forceinline__ uint64_t region_cell(const FilterArgs &F, const BinPlan &B,
                                                 uint64_t wbase, uint32_t w, uint64_t pre,
-                                                const uint32_t *hits, const uint32_t *first,
+                                                uint32_t *hits, uint32_t *first,
                                                 const WinnerSink &out, int classify,
                                                 uint32_t tau) {
     // counters are at most 32 bits wide: the field arithmetic is 32-bit
@@ -827,13 +828,16 @@ __device__ __forceinline__ uint64_t region_cell(const FilterArgs &F, const BinPl
         const uint32_t h = hits[idx];
         if (h == 0)
             continue;
+        const uint32_t t = first[idx];
+        hits[idx] = 0;
+        first[idx] = kIdle;
         const uint32_t sh = F.alpha * l;
         const uint32_t pf = (uint32_t)(pre >> sh) & fm;
         const uint32_t room = fm - pf;
         const uint32_t nf = pf + (h < room ? h : room);
         next += (uint64_t)(nf - pf) << sh;  // the field grows without carrying out
         if (pf == 0)
-            put_winner(out, first[idx], (classify && nf > tau) ? 3u : 1u, idx);
+            put_winner(out, t, (classify && nf > tau) ? 3u : 1u, idx);
     }
     if (next != pre)
         F.words[wbase + w] = next;
@@ -871,7 +875,6 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                                                       Carry C) {
     constexpr int kUnroll = 8;
     constexpr uint32_t kSparseCells = kCounters / 8;  // cells of a region the sparse path stages
-    constexpr uint32_t kDone = 0xFFFFFFFEu;  // first[] of a counter already updated
     static_assert(kSparseCells <= (uint32_t)kHold * kRegionWG, "sparse cells are held");
     static_assert(kCounters <= kRegionCounters, "local counter ids are 14-bit");
     __shared__ uint32_t hits[kCounters];
@@ -879,7 +882,6 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     __shared__ unsigned long long s_cell[kSparseCells];
     __shared__ uint32_t s_nwin;
     const uint32_t S = 1u << B.region_shift;
-    const uint32_t n_ctr = S * F.eta;
     const uint64_t n_words = F.X * F.Y;
     uint32_t *e_word = (uint32_t *)entries;
     uint16_t *e_half = (uint16_t *)(e_word + B.entries_cap);
@@ -975,6 +977,14 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
     // the first region's data in place before the loop, so that no path
     // into the loop head has loads in flight
     __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    // Counters start every region clean (hits 0, first kIdle): cleared once
+    // here, and each region leaves the counters it touched clean (the entry
+    // that updates a counter resets it), so no region clears its own.
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kCounters; i += kRegionWG) {
+        hits[i] = 0;
+        first[i] = kIdle;
+    }
+    __syncthreads();
     // stores deferred from the previous region to just after the next
     // region's requests: its changed cells (sparse path) and its winner
     // count
@@ -1022,29 +1032,22 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                              &s_nwin,
                              carry_out};
         if (R.n <= (uint32_t)(kUnroll * kRegionWG) && R.nw <= kSparseCells) {
-            // Sparse region: every entry is in the register batch.  Only the
-            // counters the entries touch are cleared, and counters are
-            // updated per entry, not by a pass over all of them: the entry
-            // whose t is the counter's minimum applies min(2^alpha - 1, old +
-            // hits) to the staged cell (a 64-bit LDS add of the field's
-            // increase, which cannot carry into the next field) and flags its
-            // occurrence when the counter was zero.  atomicCAS(first, t,
-            // kDone) succeeds for exactly one entry holding the minimum (with
-            // k_h > 1 one window can put two entries on one counter).
-#pragma unroll
-            for (int u = 0; u < kUnroll; u++)
-                if (v[u].hi != ~0u) {
-                    const uint32_t local = v[u].lo & (kRegionCounters - 1);
-                    hits[local] = 0;
-                    first[local] = kIdle;
-                }
+            // Sparse region: every entry is in the register batch, and
+            // counters are updated per entry, not by a pass over all of
+            // them: the entry whose t is the counter's minimum applies
+            // min(2^alpha - 1, old + hits) to the staged cell (a 64-bit LDS
+            // add of the field's increase, which cannot carry into the next
+            // field), flags its occurrence when the counter was zero and
+            // resets the counter.  atomicCAS(first, t, kIdle) succeeds for
+            // exactly one entry holding the minimum (with k_h > 1 one window
+            // can put two entries on one counter).  The staged cells are
+            // first read after the barrier that follows the atomics.
 #pragma unroll
             for (int k = 0; k < kHold; k++) {
                 const uint32_t w = threadIdx.x + (uint32_t)k * kRegionWG;
                 if (w < R.nw)
                     s_cell[w] = cell[k];
             }
-            __syncthreads();
 #pragma unroll
             for (int u = 0; u < kUnroll; u++)
                 if (v[u].hi != ~0u) {
@@ -1058,13 +1061,14 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                 if (v[u].hi != ~0u) {
                     const uint32_t local = v[u].lo & (kRegionCounters - 1);
                     const uint32_t t = t_of(v[u]);
-                    if (atomicCAS(&first[local], t, kDone) != t)
+                    if (atomicCAS(&first[local], t, kIdle) != t)
                         continue;
                     const uint32_t w = local & (S - 1u);
                     const uint32_t sh = F.alpha * (local >> B.region_shift);
                     const uint32_t fm = (uint32_t)F.field_max;  // counters <= 32 bits
                     const uint32_t pf = (uint32_t)(s_cell[w] >> sh) & fm;
                     const uint32_t h = hits[local];
+                    hits[local] = 0;
                     const uint32_t room = fm - pf;
                     const uint32_t inc = h < room ? h : room;
                     if (inc)
@@ -1082,11 +1086,6 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
                     pmask |= 1u << k;
             }
         } else {
-            for (uint32_t i = threadIdx.x; i < n_ctr; i += kRegionWG) {
-                hits[i] = 0;
-                first[i] = kIdle;
-            }
-            __syncthreads();
             for (uint32_t ob = 0;;) {  // the batch's first entry (uniform)
                 // the next entries are requested before this batch's LDS atomics
                 const uint32_t on = ob + (uint32_t)(kUnroll * kRegionWG);

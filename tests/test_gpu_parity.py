@@ -557,6 +557,30 @@ def test_carried_classification(monkeypatch, alpha, counters, part_log):
         monkeypatch.delenv("KMERCO_CARRY")
 
 
+@pytest.mark.parametrize("X,Y,chunk", [(211, 223, 40000), (101, 103, 65536)])
+def test_carried_classification_many_records_per_region(monkeypatch, X, Y, chunk):
+    """More than 1024 first-seen records of an earlier chunk in one region
+    (sparse regions at 211 x 223, dense ones at 101 x 103): the last chunk's
+    region pass marks the first 1024 from the records it requested with the
+    region and the others in a loop."""
+    n_first = chunk // 300 - 1  # reads wholly inside the first chunk
+    first = synth.random_reads(3300 + X, n_first, 300, 300, k=23, tau=2)
+    rest = synth.random_reads(3400 + X, 3 * n_first, 300, 300, k=23, tau=2)
+    rs = synth.concat_reads([first, rest], name="carried, many records")
+    monkeypatch.setenv("KMERCO_CHUNK_POSITIONS", str(chunk))
+    bf = P.CountBF(X, Y, 8, 1)
+    plan = bf.plan(rs.n_bases)
+    bf.close()
+    assert plan["carried"] == 1 and plan["n_chunks"] >= 3, plan
+    # the first chunk's first-seen k-mers (those of the reads inside it, a
+    # lower bound) average more than 1024 per region
+    n_first_seen = len(cpu_run(first, X, Y)[1])
+    assert n_first_seen > 1024 * plan["n_regions"], (n_first_seen, plan)
+    check(rs, X, Y, what=f"carried, many records per region, {X}x{Y}, chunks of {chunk}")
+    monkeypatch.setenv("KMERCO_WINNER_RECORDS", "1")
+    check(rs, X, Y, what=f"carried, many records per region, records mode, {X}x{Y}")
+
+
 def test_carried_classification_bacterial_sample(monkeypatch):
     rs = synth.config("bacterial", scale=0.05)
     X, Y = oracle.dims(rs.n_items)
