@@ -179,14 +179,41 @@ KERNEL_SOURCES = ["kc_batched.hip", "kc_batched.hpp", "kc_bin_hash.hpp", "kc_bin
                   "kc_kernels.hip", "kc_kernels.hpp", "kc_scan.hip"]
 
 
+def code_text(src: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed:
+    what decides the compiled code (a comment edit keeps the counters).
+    String and character literals are kept whole."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_digest() -> str:
-    """Digest of the kernel sources the committed traffic counters belong to."""
+    """Digest of the kernel sources (their code, comments aside) the
+    committed traffic counters belong to."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2305_07545_amd", "csrc")
     for name in KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()
 
 
@@ -984,8 +1011,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                          "--gpus must be 1 (no multi-GPU path is built)"}), flush=True)
+        print(json.dumps({"error": "the library runs on one GPU only; "
+                          "--gpus must be 1 (no multi-GPU path is implemented)"}), flush=True)
         sys.exit(2)
 
     import torch

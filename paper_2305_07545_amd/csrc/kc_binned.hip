@@ -893,10 +893,10 @@ __global__ void __launch_bounds__(kRegionWG) k_region(FilterArgs F, uint64_t c0,
         uint32_t nw;
         uint32_t c_off, c_n;  // carried chunk 0's records of the region
     };
-    // entry e0 + off of a region of n entries as loaded (hi = ~0u past its
-    // end); decoded where it is used, so that prefetched loads stay in
-    // flight until then
-    auto fetch = [&](uint32_t e0, uint32_t ob, uint32_t n) -> RawEntry {  // entry ob + thread
+    // entry ob + threadIdx.x (ob uniform) of a region of n entries from e0,
+    // as loaded (hi = ~0u past its end); decoded where it is used, so that
+    // prefetched loads stay in flight until then
+    auto fetch = [&](uint32_t e0, uint32_t ob, uint32_t n) -> RawEntry {
         RawEntry e{~0u, ~0u};
         if (ob + threadIdx.x < n) {
             e.lo = at_byte(e_word + e0 + ob, 4u * threadIdx.x);
