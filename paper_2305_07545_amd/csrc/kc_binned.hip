@@ -15,7 +15,7 @@
 //               LDS and written as contiguous runs: entry = t << 32 | slot id
 //   bin_region  one workgroup per (bucket, slice of bin workgroups): move the
 //               slice's entries to their regions' segments
-//   region      one workgroup per region: in LDS, hits[c] += 1 and
+//   region      each region by one workgroup of a persistent grid: in LDS, hits[c] += 1 and
 //               first[c] = min(first[c], t) over the region's entries; then
 //               counter = min(2^alpha - 1, old + hits) per counter, and the
 //               occurrence first[c] is distinct when the counter was zero
